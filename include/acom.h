@@ -1,0 +1,227 @@
+/* acom.h — C ABI of the MI355X (gfx950) sparse-correlation orientation matcher.
+ *
+ * Method: Ophus et al., "Automated crystal orientation mapping in py4DSTEM using
+ * sparse correlation matching" (arXiv 2111.00171).  Every call names the passage
+ * of the paper that defines the operation it performs.
+ *
+ * Conventions
+ *   - Pointers are DEVICE pointers unless marked [host].  Device buffers are
+ *     plain global memory (hipMalloc or a framework allocator); the library
+ *     never retains a caller pointer after a call returns.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the default stream.
+ *     acom_match, acom_polar_*, acom_correlate, acom_score, acom_score_grad and
+ *     acom_refine are asynchronous on `stream` and allocate nothing: scratch
+ *     memory is the caller's workspace.  acom_build_plan allocates the plan and
+ *     synchronises `stream` before returning.
+ *   - Every entry point returns an acom_status_t.  Problems the host can see
+ *     (null pointers, sizes, workspace too small) return ACOM_E_INVALID or
+ *     ACOM_E_WORKSPACE synchronously with a message in acom_last_error()
+ *     (thread-local).  Data problems inside the peak lists (non-finite values,
+ *     negative intensity, an empty pattern) are never fatal: that pattern gets
+ *     zone = -1 and score = 0.  No C++ exception crosses this boundary.
+ *   - Reciprocal-space quantities are spatial frequencies in 1/Angstrom (no 2 pi),
+ *     angles are radians unless the name says _deg.
+ *   - Orientation matrices m are 3x3 row-major with d = m d0 (sample -> crystal);
+ *     columns u, v, w are the in-plane x, y axes and the zone axis
+ *     (Methods > Generation of an Orientation Plan, Eq. rotation_matrices).
+ */
+#ifndef ACOM_H
+#define ACOM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ACOM_OK = 0,
+  ACOM_E_INVALID = 1,     /* bad argument (see acom_last_error) */
+  ACOM_E_NOMEM = 2,       /* device allocation failed (acom_build_plan only) */
+  ACOM_E_HIP = 3,         /* a HIP runtime call failed */
+  ACOM_E_UNSUPPORTED = 4, /* valid request this build does not support */
+  ACOM_E_WORKSPACE = 5    /* workspace smaller than acom_*_workspace_size */
+} acom_status_t;
+
+/* Correlation kernel K(d) shared by the plan and the image.
+ * CONE is the paper's max(1 - d/delta, 0) (plan expression and Eq. image_polar);
+ * GAUSS is exp(-d^2 / 2 sigma^2) cut at d < 3 sigma (an option, not the paper's). */
+typedef enum { ACOM_KERNEL_CONE = 0, ACOM_KERNEL_GAUSS = 1 } acom_kernel_t;
+
+/* Radial axis q_s.  SHELLS: the unique |g| of the phases (the paper's radii);
+ * UNIFORM: bin centres (s + 1/2) k_max / n_radial, each g reaching the bins
+ * near |g| through rho = |g| - q_s inside the kernel distance. */
+typedef enum { ACOM_RADIAL_UNIFORM = 0, ACOM_RADIAL_SHELLS = 1 } acom_radial_t;
+
+/* Precision of the plan-image contraction operands (accumulation is FP32). */
+typedef enum { ACOM_FP32 = 0, ACOM_BF16 = 1, ACOM_FP16 = 2 } acom_precision_t;
+
+/* One crystal phase (Methods > Structure Factor Calculations): unit cell and
+ * atomic basis, plus the zone axes to sample (Methods > Generation of an
+ * Orientation Plan: a SLERP grid over one or two spherical triangles, or an
+ * explicit list). */
+typedef struct {
+  double lattice[3][3];        /* rows a, b, c in Cartesian Angstrom */
+  int32_t n_atoms;
+  const double* frac_xyz;      /* [host] n_atoms x 3 fractional positions in [0,1) */
+  const int32_t* species;      /* [host] n_atoms rows into f_tab, or NULL (all 0) */
+  int32_t n_f;                 /* number of f_q knots; 0 -> f_n == 1 for every atom */
+  const double* f_q;           /* [host] n_f knots (1/A), increasing */
+  const double* f_tab;         /* [host] n_species x n_f scattering factors, linear interp. */
+  int32_t n_triangles;         /* 1 or 2 (ignored when n_zones_explicit > 0) */
+  double triangles[2][3][3];   /* per triangle the corner directions v0, v1, v2 (crystal Cartesian) */
+  int32_t n_zones_explicit;    /* > 0: use zones_explicit instead of the triangles */
+  const double* zones_explicit;/* [host] n x 3 zone-axis directions */
+} acom_phase_t;
+
+typedef struct {
+  double k_max;          /* maximum scattering vector, 1/A (reflections with 0 < |g| < k_max) */
+  double delta;          /* correlation kernel size delta, 1/A (paper: 0.08) */
+  double gamma;          /* radial power-law weight (paper default 1) */
+  double omega;          /* amplitude power-law weight (paper default 1) */
+  double accel_kV;       /* beam energy for the Ewald sphere (300) */
+  double zone_step_deg;  /* SLERP angular step between zone axes */
+  double gauss_sigma;    /* GAUSS kernel sigma; <= 0 -> delta / 2 */
+  double sigma_exc;      /* excitation tolerance of the continuous score, 1/A; <= 0 -> 0.02 */
+  int32_t n_radial;      /* N_r for UNIFORM (ignored for SHELLS) */
+  int32_t n_angular;     /* N_phi: even, >= 8, only prime factors 2, 3, 5, <= 1024 */
+  int32_t radial;        /* acom_radial_t */
+  int32_t kernel;        /* acom_kernel_t */
+  int32_t precisions;    /* bit mask of (1 << acom_precision_t) operand copies to build; FP32 is always built */
+  int32_t keep_f64;      /* nonzero: keep the FP64 angular plan for acom_plan_copy_f64 */
+} acom_plan_params_t;
+
+typedef struct acom_plan_s* acom_plan_t;
+
+/* Ragged peak lists, CSR (the py4DSTEM PointListArray as one flat array):
+ * pattern p owns peaks offsets[p] .. offsets[p+1]-1.  (qx, qy) in 1/A with the
+ * pattern centre at the origin, intensity >= 0 (Methods > Correlation Pattern
+ * Matching: the M peaks (q_m, gamma_m, I_m)). */
+typedef struct {
+  int64_t n_patterns;    /* [host] value */
+  int64_t total_peaks;   /* [host] value; must equal offsets[n_patterns] */
+  const int64_t* offsets;/* n_patterns + 1, offsets[0] = 0, nondecreasing */
+  const float* qx;
+  const float* qy;
+  const float* intensity;
+} acom_peaks_t;
+
+/* Per pattern, top_k entries ordered by decreasing score (ties: smaller zone).
+ * zone is the global zone index over the concatenated phases, -1 for no match. */
+typedef struct {
+  int32_t* zone;         /* n x top_k */
+  int32_t* phase;        /* n x top_k */
+  int32_t* bin;          /* n x top_k: winning in-plane bin n (phi3 = -n 2pi/N_phi before refinement) */
+  int32_t* mirror;       /* n x top_k: 1 when the mirror correlogram won */
+  float* score;          /* n x top_k: correlation value C at the winning bin */
+  float* phi3;           /* n x top_k: -(n + parabolic offset) 2 pi / N_phi */
+  float* orient;         /* n x top_k x 9, or NULL */
+  int32_t* n_evaluated;  /* n, or NULL: zones whose correlogram was evaluated exactly */
+} acom_matches_t;
+
+/* ---------------------------------------------------------------- plan ---- */
+
+/* Build the orientation plan (Methods > Structure Factor Calculations; Methods >
+ * Generation of an Orientation Plan): reflections and structure factors F_hkl,
+ * zone-axis grid and rotations, P0 from the excitation error (Eq. excitation
+ * error) and the kernel, per-zone normalisation A = 1/sqrt(sum P0^2) (A = 0 for a
+ * zone with no excited reflection), and the 1-D FFT of P along phi3.  FP64 on
+ * the GPU; the frequency-domain plan is kept in FP32 plus the requested
+ * low-precision copies.  Phases are concatenated in order.  Synchronous. */
+acom_status_t acom_build_plan(const acom_phase_t* phases, int32_t n_phases,
+                              const acom_plan_params_t* params, void* stream, acom_plan_t* out);
+
+/* Sizes of a built plan.  q_s [host, N_r] (the radial axis), zones [host, Z x 3],
+ * zone_phase [host, Z] and norm_A [host, Z] may each be NULL. */
+acom_status_t acom_plan_info(acom_plan_t plan, int32_t* n_zones, int32_t* n_radial,
+                             int32_t* n_angular, int32_t* n_phases, double* q_s, double* zones,
+                             int32_t* zone_phase, double* norm_A);
+
+/* Copy the FP64 angular plan P[z][a][s] (Z x N_phi x N_r) to host memory.
+ * Requires keep_f64 at build time, else ACOM_E_UNSUPPORTED. */
+acom_status_t acom_plan_copy_f64(acom_plan_t plan, double* host_P);
+
+acom_status_t acom_plan_destroy(acom_plan_t plan);
+
+/* --------------------------------------------------------------- match ---- */
+
+/* Workspace bytes for acom_match with this many patterns per internal chunk
+ * (<= 0 -> default 16384).  The size does not depend on n_patterns. */
+acom_status_t acom_match_workspace_size(acom_plan_t plan, int32_t precision, int32_t chunk,
+                                        size_t* bytes);
+
+/* Match every pattern against the plan (Methods > Correlation Pattern Matching):
+ * sparse polar image X (Eq. image_polar), its FFT along phi3, the per-frequency
+ * contraction sum_s FFT{P}^* FFT{X} for C and FFT{P}^* FFT{X}^* for C_mirror, the
+ * inverse FFT, and the maximum over zones, in-plane bins and the two branches.
+ * The contraction runs in `precision`; every reported score is recomputed in
+ * FP32 from the FP32 plan, and a zone is skipped only when the upper bound
+ * (1/N) sum_k |G_k| of its correlogram (computed in `precision`, widened by a
+ * precision-dependent margin) is below the current top_k-th exact score.
+ * Adds a 3-point parabolic sub-bin offset and the orientation matrix.
+ * top_k in [1, 16]; `chunk` must equal the value given to the size query. */
+acom_status_t acom_match(acom_plan_t plan, const acom_peaks_t* peaks, int32_t top_k,
+                         int32_t precision, int32_t chunk, void* workspace, size_t workspace_bytes,
+                         const acom_matches_t* out, void* stream);
+
+/* Intermediate outputs, for verification (same arithmetic as acom_match).
+ * acom_polar_image: X[p][a][s] (n x N_phi x N_r, FP32), Eq. image_polar.
+ * acom_polar_spectrum: FFT of X along phi3, Xr/Xi[p][k][s] (n x (N_phi/2+1) x N_r).
+ * acom_correlate: C[p][z][b][n] (n x Z x 2 x N_phi, FP32), b = 0 correlogram,
+ *   b = 1 mirror, computed by the FFT route in FP32.
+ * All three need workspace >= acom_debug_workspace_size(plan, n_patterns). */
+acom_status_t acom_debug_workspace_size(acom_plan_t plan, int64_t n_patterns, size_t* bytes);
+acom_status_t acom_polar_image(acom_plan_t plan, const acom_peaks_t* peaks, float* X,
+                               void* workspace, size_t workspace_bytes, void* stream);
+acom_status_t acom_polar_spectrum(acom_plan_t plan, const acom_peaks_t* peaks, float* Xr, float* Xi,
+                                  void* workspace, size_t workspace_bytes, void* stream);
+acom_status_t acom_correlate(acom_plan_t plan, const acom_peaks_t* peaks, float* C,
+                             void* workspace, size_t workspace_bytes, void* stream);
+/* Upper bounds U[p][z] = (1/N) max(sum_k w_k |G_k|, sum_k w_k |G_m,k|) as computed by
+ * the contraction pass in `precision` (n x Z, FP32), without margin. */
+acom_status_t acom_bound(acom_plan_t plan, const acom_peaks_t* peaks, int32_t precision, float* U,
+                         void* workspace, size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------ score / refine ---- */
+
+/* Continuous correlation score of pattern p at orientation m = base_orient[p]
+ * Exp(theta[p]) with respect to the reflections of phase[p] (an extension of the
+ * polar correlation, not in the paper):
+ *   S = sum_m sum_g w_m v_g K_mg / sqrt(sum_g v_g^2),
+ *   w_m = q_m^gamma I_m^(omega/2) (Eq. image_polar),
+ *   v_g = |g|^gamma (|F_g|^2 exp(-s_g^2 / 2 sigma_exc^2))^(omega/2)
+ *         (Eq. excitation error, Eq. shape_gaussian),
+ *   K_mg = exp(-|q_m - (x_g, y_g)|^2 / (2 (delta/2)^2)), (x_g, y_g, z_g) = m^T g.
+ * For omega > 0, reflections whose |s_g| at base_orient is at least
+ * 10 sigma_exc / sqrt(omega) + 0.035 1/A are left out (v_g below exp(-25) of its
+ * peak value even after a 1 degree rotation); at most 1024 reflections per phase
+ * take part.
+ * base_orient n x 9, theta n x 3, phase n (int32) or NULL (phase 0); S n. */
+acom_status_t acom_score(acom_plan_t plan, const acom_peaks_t* peaks, const float* base_orient,
+                         const float* theta, const int32_t* phase, float* S, void* stream);
+
+/* Backward of acom_score: given dS (n), dtheta = dS dS/dtheta (n x 3) and, when
+ * dqx / dqy are not NULL, dS dS/dqx and dS dS/dqy per peak (total_peaks). */
+acom_status_t acom_score_grad(acom_plan_t plan, const acom_peaks_t* peaks, const float* base_orient,
+                              const float* theta, const int32_t* phase, const float* dS,
+                              float* dtheta, float* dqx, float* dqy, void* stream);
+
+/* Gradient-ascent refinement of n_cand candidate orientations per pattern
+ * (init_orient n x n_cand x 9, cand_phase n x n_cand or NULL): per candidate,
+ * steps of length l along grad S / |grad S| from the current orientation (l starts
+ * at 0.25 deg, doubles after an improving step up to 0.5 deg, halves otherwise),
+ * at most max_iter trials or until l < 1e-4 deg; the best candidate wins.
+ * out_orient n x 9, out_score n, out_cand n (index of the winner) or NULL. */
+acom_status_t acom_refine(acom_plan_t plan, const acom_peaks_t* peaks, int32_t n_cand,
+                          const float* init_orient, const int32_t* cand_phase, int32_t max_iter,
+                          float* out_orient, float* out_score, int32_t* out_cand, void* stream);
+
+/* ------------------------------------------------------------- errors ---- */
+const char* acom_status_string(acom_status_t s);
+const char* acom_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ACOM_H */

@@ -1,0 +1,79 @@
+// Internal declarations shared by the HIP translation units of libacom.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/acom.h"
+
+namespace acom {
+
+// ------------------------------------------------------------------ errors --
+acom_status_t fail(acom_status_t s, const std::string& msg);
+acom_status_t hip_fail(hipError_t e, const char* what);
+#define ACOM_HIP(call)                                   \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ != hipSuccess) return acom::hip_fail(e_, #call); \
+  } while (0)
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Tile sizes of the contraction pass (patterns x zones per workgroup) and the
+// radial padding unit (one s-chunk of the MFMA K loop).
+constexpr int kTileP = 64;
+constexpr int kTileZ = 64;
+constexpr int kSChunk = 32;
+constexpr int kMaxRadices = 12;
+constexpr int kMaxAngular = 1024;
+constexpr int kMaxTopK = 16;
+constexpr int kMaxZonesExact = 16384;  // per-pattern bound row held in LDS by the exact pass
+
+// Mixed-radix factorisation of the angular length (radices 4, 2, 3, 5).
+struct Radices {
+  int n = 0;
+  int r[kMaxRadices] = {0};
+};
+bool factor_angular(int N, Radices* out);
+
+// Device-resident plan.
+struct PlanDev {
+  // sizes
+  int Z = 0, Zp = 0;        // zones, zones padded to kTileZ
+  int R = 0, Rp = 0;        // radial bins, padded to kSChunk
+  int N = 0, Nk = 0;        // angular bins, N/2 + 1
+  int n_phases = 0;
+  Radices rad;
+  // parameters
+  double k_max = 0, delta = 0, gamma = 1, omega = 1, k0 = 0, gauss_sigma = 0, sigma_exc = 0.02;
+  int kernel = 0, radial = 0;
+  int precisions = 1;
+  // host copies
+  std::vector<double> q_s, zones, normA;  // R, Z*3, Z
+  std::vector<int32_t> zone_phase;        // Z
+  std::vector<int32_t> refl_off;          // n_phases + 1
+  // device arrays
+  float* d_qs = nullptr;        // Rp (padding columns carry q = -1: no peak reaches them)
+  float2* d_tw = nullptr;       // N twiddles (cos, sin)(2 pi m / N)
+  float* d_M12 = nullptr;       // Z x 9 (row-major, float)
+  int32_t* d_zone_phase = nullptr;
+  float* d_PR = nullptr;        // Nk x Zp x Rp  (FP32 real part of FFT{P})
+  float* d_PI = nullptr;        // Nk x Zp x Rp  (imaginary part)
+  uint16_t* d_PR16[3] = {nullptr, nullptr, nullptr};  // per precision (index = acom_precision_t)
+  uint16_t* d_PI16[3] = {nullptr, nullptr, nullptr};
+  double* d_Pang = nullptr;     // optional FP64 angular plan Z x N x R
+  // reflections for the continuous score (all phases concatenated)
+  int G = 0;
+  float4* d_refl = nullptr;     // (gx, gy, gz, |g|)
+  float* d_reflF2 = nullptr;    // |F|^2
+  int32_t* d_refl_off = nullptr;
+};
+
+}  // namespace acom
+
+struct acom_plan_s {
+  acom::PlanDev d;
+};

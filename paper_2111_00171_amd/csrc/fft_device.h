@@ -1,0 +1,112 @@
+// Block-cooperative mixed-radix Stockham FFT in LDS (radices 2, 3, 4, 5).
+//
+// The angular axis phi3 is transformed many sequences at a time: element a of
+// sequence q lives at buf[a * nseq + q], so consecutive threads touch
+// consecutive LDS words.  One stage of radix R with partial length Ns reads
+// R inputs spaced N/R apart, multiplies by w^(r * (j mod Ns) * N / (Ns R)),
+// applies an R-point DFT and writes R outputs spaced Ns apart at
+// (j / Ns) Ns R + j mod Ns; the stages leave the result in natural order.
+// Twiddles come from a table tw[m] = (cos, sin)(2 pi m / N).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace acom {
+
+struct cf {
+  float x, y;
+};
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+// multiply by -i*sg  (sg = +1: forward transform sign e^{-i...})
+__device__ __forceinline__ float2 rot_mi(float2 a, float sg) { return make_float2(sg * a.y, -sg * a.x); }
+
+// In-register R-point DFT, sign sg = +1 for exp(-2 pi i r k / R), -1 for exp(+...).
+__device__ __forceinline__ void dft_small(float2* v, int R, float sg) {
+  if (R == 2) {
+    float2 a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  } else if (R == 3) {
+    const float c = -0.5f, s = 0.866025403784438647f;
+    float2 a = v[0], b = v[1], d = v[2];
+    float2 t = cadd(b, d);
+    float2 m = make_float2(a.x + c * t.x, a.y + c * t.y);
+    float2 u = rot_mi(csub(b, d), sg);  // -i sg (b - d)
+    v[0] = cadd(a, t);
+    v[1] = make_float2(m.x + s * u.x, m.y + s * u.y);
+    v[2] = make_float2(m.x - s * u.x, m.y - s * u.y);
+  } else if (R == 4) {
+    float2 a = v[0], b = v[1], c = v[2], d = v[3];
+    float2 s0 = cadd(a, c), d0 = csub(a, c), s1 = cadd(b, d);
+    float2 d1 = rot_mi(csub(b, d), sg);
+    v[0] = cadd(s0, s1);
+    v[2] = csub(s0, s1);
+    v[1] = cadd(d0, d1);
+    v[3] = csub(d0, d1);
+  } else {  // R == 5
+    const float c1 = 0.309016994374947424f, c2 = -0.809016994374947424f;
+    const float s1 = 0.951056516295153572f, s2 = 0.587785252292473129f;
+    float2 a0 = v[0];
+    float2 p1 = cadd(v[1], v[4]), m1 = csub(v[1], v[4]);
+    float2 p2 = cadd(v[2], v[3]), m2 = csub(v[2], v[3]);
+    float2 r1 = make_float2(a0.x + c1 * p1.x + c2 * p2.x, a0.y + c1 * p1.y + c2 * p2.y);
+    float2 r2 = make_float2(a0.x + c2 * p1.x + c1 * p2.x, a0.y + c2 * p1.y + c1 * p2.y);
+    float2 i1 = rot_mi(make_float2(s1 * m1.x + s2 * m2.x, s1 * m1.y + s2 * m2.y), sg);
+    float2 i2 = rot_mi(make_float2(s2 * m1.x - s1 * m2.x, s2 * m1.y - s1 * m2.y), sg);
+    v[0] = make_float2(a0.x + p1.x + p2.x, a0.y + p1.y + p2.y);
+    v[1] = cadd(r1, i1);
+    v[4] = csub(r1, i1);
+    v[2] = cadd(r2, i2);
+    v[3] = csub(r2, i2);
+  }
+}
+
+// Transform `nseq` interleaved sequences of length N held in `a`; `b` is the
+// ping-pong buffer.  sg = +1 forward, -1 inverse (unnormalised).  Returns the
+// buffer holding the result.  All threads of the block must call it.
+__device__ inline float2* block_fft(float2* a, float2* b, const float2* tw, int N, int nseq,
+                                   const int* radix, int nrad, float sg) {
+  int Ns = 1;
+  for (int st = 0; st < nrad; ++st) {
+    const int R = radix[st];
+    const int NR = N / R;
+    const int step = N / (Ns * R);
+    const int items = NR * nseq;
+    for (int it = threadIdx.x; it < items; it += blockDim.x) {
+      const int q = it % nseq;
+      const int j = it / nseq;
+      const int jm = j % Ns;
+      float2 v[5];
+#pragma unroll
+      for (int r = 0; r < 5; ++r) {
+        if (r < R) {
+          float2 x = a[(j + r * NR) * nseq + q];
+          if (r > 0 && jm > 0) {
+            float2 w = tw[(r * jm * step) % N];
+            w.y *= -sg;  // forward uses conj(w)
+            x = cmul(x, w);
+          }
+          v[r] = x;
+        }
+      }
+      dft_small(v, R, sg);
+      const int d0 = (j / Ns) * Ns * R + jm;
+#pragma unroll
+      for (int r = 0; r < 5; ++r)
+        if (r < R) b[(d0 + r * Ns) * nseq + q] = v[r];
+    }
+    __syncthreads();
+    float2* t = a;
+    a = b;
+    b = t;
+    Ns *= R;
+  }
+  return a;
+}
+
+}  // namespace acom

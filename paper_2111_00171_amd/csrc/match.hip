@@ -1,0 +1,1096 @@
+// Pattern matching against a built plan (Methods > Correlation Pattern Matching).
+//
+// Per chunk of patterns, three launches on the caller's stream:
+//  1. polar_kernel   - sparse polar image X(phi_a, q_s) (Eq. image_polar) by a
+//                      deterministic per-column splat in LDS, then the FFT of X
+//                      along phi3 (block Stockham FFT, two real columns packed
+//                      in one complex sequence); writes FFT{X} in FP32 and, for
+//                      the low-precision contraction, BF16/FP16 copies.
+//  2. bound_kernel   - the per-frequency contraction G_k = sum_s FFT{P}^* FFT{X}
+//                      (and the mirror with FFT{X}^*) on MFMA for a 64x64
+//                      (pattern x zone) tile, streaming over k and accumulating
+//                      U = (1/N) sum_k w_k |G_k| (an upper bound of max_n C by the
+//                      triangle inequality on the inverse DFT) for both branches.
+//  3. exact_kernel   - per pattern, zones in decreasing U are evaluated exactly
+//                      in FP32 (contraction over s, inverse FFT along phi3 of
+//                      C + i C_mirror, argmax over (n, branch)) until no remaining
+//                      zone's widened bound can beat the top_k-th exact score;
+//                      parabolic sub-bin offset and the orientation matrix.
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+#include <climits>
+#include <cmath>
+
+#include "acom_internal.h"
+#include "fft_device.h"
+
+namespace acom {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kPolarCols = 32;   // radial columns per polar block (16 complex sequences)
+constexpr int kPeakCache = 256;
+constexpr int kBatch = 8;        // zones evaluated together by the exact pass
+constexpr int kDefaultChunk = 16384;
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8;
+
+__device__ __forceinline__ float powe(float x, float e) {
+  if (e == 1.0f) return x;
+  if (e == 0.5f) return sqrtf(x);
+  if (e == 0.0f) return 1.0f;
+  if (e == 2.0f) return x * x;
+  return powf(x, e);
+}
+
+__device__ __forceinline__ double wrap_pi64(double x) {
+  const double tp = 6.283185307179586476925286766559;
+  return x - tp * rint(x / tp);
+}
+
+__device__ __forceinline__ float kern32(float d, float delta, float sigma, int kind) {
+  if (kind == ACOM_KERNEL_CONE) return d < delta ? 1.0f - d / delta : 0.0f;
+  return d < 3.0f * sigma ? expf(-d * d / (2.0f * sigma * sigma)) : 0.0f;
+}
+
+__device__ __forceinline__ uint16_t to_bf16_bits(float v) {
+  __hip_bfloat16 b = __float2bfloat16(v);
+  return *reinterpret_cast<uint16_t*>(&b);
+}
+__device__ __forceinline__ uint16_t to_f16_bits(float v) {
+  __half h = __float2half(v);
+  return *reinterpret_cast<uint16_t*>(&h);
+}
+
+// ------------------------------------------------------------ 1. polar ----
+
+struct PolarArgs {
+  int N, R, Rp, Nk, nrad;
+  int rad[kMaxRadices];
+  const float* qs;
+  const float2* tw;
+  float delta, rk, sigma, gamma, omega;
+  int kernel;
+  const int64_t* offsets;
+  const float *qx, *qy, *I;
+  int64_t total_peaks;
+  int64_t p_begin;
+  int np;
+  float *xr, *xi;          // FFT{X} at k * ldk + p * ldp + s (p local), columns s < out_cols
+  size_t ldk;
+  int ldp, out_cols;
+  uint16_t *lr, *li;       // low-precision copies (same layout) or null
+  int lowp;                // 0 none, ACOM_BF16, ACOM_FP16
+  float* scale;            // np: factor applied before the FP16 cast (else 1)
+  float* xnorm2;           // np x ntiles: sum of X^2 of each radial tile
+  int* flags;              // np: 0 ok, 1 invalid data, 2 no peaks
+  float* Ximg;             // optional X[p][a][s] (np x N x R)
+  int do_fft;
+};
+
+__global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  float2* b0 = reinterpret_cast<float2*>(smem_raw);
+  float2* b1 = b0 + a.N * (kPolarCols / 2);
+  float2* tw = b1 + a.N * (kPolarCols / 2);
+  double* pg = reinterpret_cast<double*>(tw + a.N);
+  float* pq = reinterpret_cast<float*>(pg + kPeakCache);
+  float* pw = pq + kPeakCache;
+  __shared__ int s_bad;
+  __shared__ float s_red[kThreads];
+  __shared__ double s_red64[kThreads];
+
+  const int tid = threadIdx.x;
+  const int p = blockIdx.x;
+  const int tile = blockIdx.y;
+  const int col0 = tile * kPolarCols;
+  const int64_t P = a.p_begin + p;
+  int64_t m0 = a.offsets[P], m1 = a.offsets[P + 1];
+  const bool bad_range = m0 < 0 || m1 < m0 || m1 > a.total_peaks;
+  if (bad_range) m0 = m1 = 0;  // malformed CSR row: a data error, nothing is read
+  float* X = reinterpret_cast<float*>(b0);  // [a][kPolarCols]
+  for (int i = tid; i < a.N * kPolarCols; i += kThreads) X[i] = 0.0f;
+  for (int i = tid; i < a.N; i += kThreads) tw[i] = a.tw[i];
+  if (tid == 0) s_bad = bad_range ? 1 : 0;
+  __syncthreads();
+
+  const double dphi = 6.283185307179586476925286766559 / a.N;
+  double wsum = 0.0;
+  for (int64_t c0 = m0; c0 < m1; c0 += kPeakCache) {
+    const int cnt = (int)min((int64_t)kPeakCache, m1 - c0);
+    if (tid < cnt) {
+      const float x = a.qx[c0 + tid], y = a.qy[c0 + tid], in = a.I[c0 + tid];
+      const bool bad = !isfinite(x) || !isfinite(y) || !isfinite(in) || in < 0.0f;
+      if (bad) atomicOr(&s_bad, 1);
+      const double q = sqrt((double)x * x + (double)y * y);
+      pg[tid] = atan2((double)y, (double)x);
+      pq[tid] = (float)q;
+      const float w = bad ? 0.0f : powe((float)q, a.gamma) * powe(in, 0.5f * a.omega);
+      pw[tid] = w;
+      wsum += w;
+    }
+    __syncthreads();
+    const int col = col0 + tid;
+    if (tid < kPolarCols && col < a.R) {
+      const float qs = a.qs[col];
+      for (int j = 0; j < cnt; ++j) {
+        const float dq = pq[j] - qs;
+        const float w = pw[j];
+        if (fabsf(dq) >= a.rk || w == 0.0f) continue;
+        const double g = pg[j];
+        int hw = a.N;
+        if (qs > 0.0f) {
+          const float h = a.rk / (qs * (float)dphi) + 1.0f;
+          hw = h > (float)a.N ? a.N : (int)ceilf(h);
+        }
+        if (2 * hw + 1 >= a.N) {
+          for (int ai = 0; ai < a.N; ++ai) {
+            const float dp = (float)wrap_pi64(ai * dphi - g) * qs;
+            const float k = kern32(sqrtf(dq * dq + dp * dp), a.delta, a.sigma, a.kernel);
+            if (k > 0.0f) X[ai * kPolarCols + tid] += w * k;
+          }
+        } else {
+          const int ac = (int)floor(g / dphi + 0.5);
+          for (int jj = -hw; jj <= hw; ++jj) {
+            int ai = (ac + jj) % a.N;
+            if (ai < 0) ai += a.N;
+            const float dp = (float)wrap_pi64(ai * dphi - g) * qs;
+            const float k = kern32(sqrtf(dq * dq + dp * dp), a.delta, a.sigma, a.kernel);
+            if (k > 0.0f) X[ai * kPolarCols + tid] += w * k;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // block sums: peak weights (FP16 scale) and sum of X^2 of this tile
+  float xx = 0.0f;
+  for (int i = tid; i < a.N * kPolarCols; i += kThreads) xx += X[i] * X[i];
+  s_red[tid] = xx;
+  s_red64[tid] = wsum;
+  __syncthreads();
+  for (int off = kThreads / 2; off > 0; off >>= 1) {
+    if (tid < off) {
+      s_red[tid] += s_red[tid + off];
+      s_red64[tid] += s_red64[tid + off];
+    }
+    __syncthreads();
+  }
+  const bool bad = s_bad != 0;
+  const bool empty = (m1 <= m0);
+  float sc = 1.0f;
+  if (a.lowp == ACOM_FP16) {
+    // |FFT{X}| <= sum_a X <= N * sum_m w_m; map that bound below 2^14.
+    const double bound = s_red64[0] * a.N;
+    if (bound > 0.0) {
+      int e = (int)floor(log2(16384.0 / bound));
+      e = max(-60, min(60, e));
+      sc = ldexpf(1.0f, e);
+    }
+  }
+  if (tid == 0) {
+    a.xnorm2[(size_t)p * gridDim.y + tile] = bad ? 0.0f : s_red[0];
+    if (tile == 0) {
+      a.flags[p] = bad ? 1 : (empty ? 2 : 0);
+      a.scale[p] = sc;
+    }
+  }
+  if (a.Ximg) {
+    for (int i = tid; i < a.N * kPolarCols; i += kThreads) {
+      const int ai = i / kPolarCols, c = i % kPolarCols;
+      if (col0 + c < a.R) a.Ximg[((size_t)p * a.N + ai) * a.R + col0 + c] = bad ? 0.0f : X[i];
+    }
+  }
+  if (!a.do_fft) return;
+  __syncthreads();
+  constexpr int NS = kPolarCols / 2;
+  const float2* F = block_fft(b0, b1, tw, a.N, NS, a.rad, a.nrad, 1.0f);
+  // unpack: column 2q = (Z_k + conj Z_{N-k}) / 2, column 2q+1 = -i (Z_k - conj Z_{N-k}) / 2
+  for (int it = tid; it < a.Nk * NS; it += kThreads) {
+    const int k = it / NS, q = it % NS;
+    const float2 Zk = F[k * NS + q];
+    const float2 Zn = F[((a.N - k) % a.N) * NS + q];
+    float2 E = make_float2(0.5f * (Zk.x + Zn.x), 0.5f * (Zk.y - Zn.y));
+    float2 O = make_float2(0.5f * (Zk.y + Zn.y), -0.5f * (Zk.x - Zn.x));
+    if (bad) E = O = make_float2(0.0f, 0.0f);
+    const int s0 = col0 + 2 * q;
+    const size_t o = (size_t)k * a.ldk + (size_t)p * a.ldp + s0;
+    if (s0 < a.out_cols) {
+      a.xr[o] = E.x;
+      a.xi[o] = E.y;
+    }
+    if (s0 + 1 < a.out_cols) {
+      a.xr[o + 1] = O.x;
+      a.xi[o + 1] = O.y;
+    }
+    if (a.lowp == ACOM_BF16) {
+      a.lr[o] = to_bf16_bits(E.x);
+      a.li[o] = to_bf16_bits(E.y);
+      a.lr[o + 1] = to_bf16_bits(O.x);
+      a.li[o + 1] = to_bf16_bits(O.y);
+    } else if (a.lowp == ACOM_FP16) {
+      a.lr[o] = to_f16_bits(E.x * sc);
+      a.li[o] = to_f16_bits(E.y * sc);
+      a.lr[o + 1] = to_f16_bits(O.x * sc);
+      a.li[o + 1] = to_f16_bits(O.y * sc);
+    }
+  }
+}
+
+// ------------------------------------------------------------ 2. bound ----
+
+struct BoundArgs {
+  int Nk, Rp, N;
+  const void *xr, *xi;     // [k][p][s]
+  size_t x_ldk;
+  int x_ldp;
+  const void *pr, *pi;     // [k][z][s]
+  size_t p_ldk;
+  int p_ldz;
+  const float* scale;      // per local pattern
+  float* U;
+  int ldU, np, Zvalid;
+};
+
+template <int KIND>  // 0: FP32 operands, 1: BF16, 2: FP16
+struct BoundTraits;
+
+template <>
+struct BoundTraits<0> {
+  typedef float T;
+  static constexpr int kPad = 4;  // row stride 36 floats
+};
+template <>
+struct BoundTraits<1> {
+  typedef uint16_t T;
+  static constexpr int kPad = 8;  // row stride 40 elements
+};
+template <>
+struct BoundTraits<2> {
+  typedef uint16_t T;
+  static constexpr int kPad = 8;
+};
+
+// One workgroup: 64 patterns x 64 zones, 4 waves of 32 x 32 (2 x 2 MFMA blocks
+// of 16 x 16).  For each frequency k the K loop runs over s in chunks of 32
+// staged through LDS; four accumulators per block give the real products
+// A = Xr Pr, B = Xi Pi, C = Xi Pr, D = Xr Pi, so G = (A + B) + i (C - D) and
+// G_mirror = (A - B) - i (C + D).  Lanes of a quarter-wave (l / 16) take the
+// contiguous s-range 8 (l / 16) .. +7 of a chunk for both operands, which is
+// the same permutation of the contraction index on both sides.
+template <int KIND>
+__global__ void __launch_bounds__(kThreads) bound_kernel(BoundArgs a) {
+  typedef typename BoundTraits<KIND>::T T;
+  constexpr int LD = kSChunk + BoundTraits<KIND>::kPad;
+  __shared__ __align__(16) T sXr[kTileP * LD];
+  __shared__ __align__(16) T sXi[kTileP * LD];
+  __shared__ __align__(16) T sPr[kTileZ * LD];
+  __shared__ __align__(16) T sPi[kTileZ * LD];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int p0 = blockIdx.x * kTileP;
+  const int z0 = blockIdx.y * kTileZ;
+  const int li = lane & 15;  // row within a 16-block
+  const int lg = lane >> 4;  // quarter-wave: s sub-range / output row group
+
+  float U[2][2][4], Um[2][2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) U[i][j][r] = Um[i][j][r] = 0.0f;
+
+  const T* gxr = reinterpret_cast<const T*>(a.xr);
+  const T* gxi = reinterpret_cast<const T*>(a.xi);
+  const T* gpr = reinterpret_cast<const T*>(a.pr);
+  const T* gpi = reinterpret_cast<const T*>(a.pi);
+
+  for (int k = 0; k < a.Nk; ++k) {
+    f32x4 acc[2][2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[i][j][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+
+    const T* xrk = gxr + (size_t)k * a.x_ldk + (size_t)p0 * a.x_ldp;
+    const T* xik = gxi + (size_t)k * a.x_ldk + (size_t)p0 * a.x_ldp;
+    const T* prk = gpr + (size_t)k * a.p_ldk + (size_t)z0 * a.p_ldz;
+    const T* pik = gpi + (size_t)k * a.p_ldk + (size_t)z0 * a.p_ldz;
+
+    for (int s0 = 0; s0 < a.Rp; s0 += kSChunk) {
+      // stage 64 rows x 32 elements of each operand (16-byte vectors)
+      constexpr int VEC = 16 / sizeof(T);           // elements per 16 bytes
+      constexpr int PER_ROW = kSChunk / VEC;        // vectors per row
+      for (int v = tid; v < kTileP * PER_ROW; v += kThreads) {
+        const int row = v / PER_ROW, cv = v % PER_ROW;
+        const size_t gx = (size_t)row * a.x_ldp + s0 + cv * VEC;
+        const size_t gp = (size_t)row * a.p_ldz + s0 + cv * VEC;
+        const int l = row * LD + cv * VEC;
+        *reinterpret_cast<uint4*>(&sXr[l]) = *reinterpret_cast<const uint4*>(xrk + gx);
+        *reinterpret_cast<uint4*>(&sXi[l]) = *reinterpret_cast<const uint4*>(xik + gx);
+        *reinterpret_cast<uint4*>(&sPr[l]) = *reinterpret_cast<const uint4*>(prk + gp);
+        *reinterpret_cast<uint4*>(&sPi[l]) = *reinterpret_cast<const uint4*>(pik + gp);
+      }
+      __syncthreads();
+      if constexpr (KIND == 0) {
+        float fxr[2][8], fxi[2][8], fpr[2][8], fpi[2][8];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const int rx = (wr * 32 + i * 16 + li) * LD + lg * 8;
+          const int rp = (wc * 32 + i * 16 + li) * LD + lg * 8;
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            float4 t;
+            t = *reinterpret_cast<const float4*>(&sXr[rx + 4 * h]);
+            fxr[i][4 * h] = t.x; fxr[i][4 * h + 1] = t.y; fxr[i][4 * h + 2] = t.z; fxr[i][4 * h + 3] = t.w;
+            t = *reinterpret_cast<const float4*>(&sXi[rx + 4 * h]);
+            fxi[i][4 * h] = t.x; fxi[i][4 * h + 1] = t.y; fxi[i][4 * h + 2] = t.z; fxi[i][4 * h + 3] = t.w;
+            t = *reinterpret_cast<const float4*>(&sPr[rp + 4 * h]);
+            fpr[i][4 * h] = t.x; fpr[i][4 * h + 1] = t.y; fpr[i][4 * h + 2] = t.z; fpr[i][4 * h + 3] = t.w;
+            t = *reinterpret_cast<const float4*>(&sPi[rp + 4 * h]);
+            fpi[i][4 * h] = t.x; fpi[i][4 * h + 1] = t.y; fpi[i][4 * h + 2] = t.z; fpi[i][4 * h + 3] = t.w;
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+              acc[i][j][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxr[i][t], fpr[j][t], acc[i][j][0], 0, 0, 0);
+              acc[i][j][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxi[i][t], fpi[j][t], acc[i][j][1], 0, 0, 0);
+              acc[i][j][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxi[i][t], fpr[j][t], acc[i][j][2], 0, 0, 0);
+              acc[i][j][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxr[i][t], fpi[j][t], acc[i][j][3], 0, 0, 0);
+            }
+      } else {
+        typedef typename std::conditional<KIND == 1, bf16x8, f16x8>::type V8;
+        V8 fxr[2], fxi[2], fpr[2], fpi[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const int rx = (wr * 32 + i * 16 + li) * LD + lg * 8;
+          const int rp = (wc * 32 + i * 16 + li) * LD + lg * 8;
+          fxr[i] = *reinterpret_cast<const V8*>(&sXr[rx]);
+          fxi[i] = *reinterpret_cast<const V8*>(&sXi[rx]);
+          fpr[i] = *reinterpret_cast<const V8*>(&sPr[rp]);
+          fpi[i] = *reinterpret_cast<const V8*>(&sPi[rp]);
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            if constexpr (KIND == 1) {
+              acc[i][j][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fxr[i], fpr[j], acc[i][j][0], 0, 0, 0);
+              acc[i][j][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fxi[i], fpi[j], acc[i][j][1], 0, 0, 0);
+              acc[i][j][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fxi[i], fpr[j], acc[i][j][2], 0, 0, 0);
+              acc[i][j][3] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fxr[i], fpi[j], acc[i][j][3], 0, 0, 0);
+            } else {
+              acc[i][j][0] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fxr[i], fpr[j], acc[i][j][0], 0, 0, 0);
+              acc[i][j][1] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fxi[i], fpi[j], acc[i][j][1], 0, 0, 0);
+              acc[i][j][2] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fxi[i], fpr[j], acc[i][j][2], 0, 0, 0);
+              acc[i][j][3] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fxr[i], fpi[j], acc[i][j][3], 0, 0, 0);
+            }
+          }
+      }
+      __syncthreads();
+    }
+    const float wk = (k == 0 || 2 * k == a.N) ? 1.0f : 2.0f;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float A = acc[i][j][0][r], B = acc[i][j][1][r], C = acc[i][j][2][r], D = acc[i][j][3][r];
+          const float re = A + B, im = C - D, rm = A - B, imm = C + D;
+          U[i][j][r] += wk * sqrtf(re * re + im * im);
+          Um[i][j][r] += wk * sqrtf(rm * rm + imm * imm);
+        }
+  }
+  const float invN = 1.0f / (float)a.N;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int p = p0 + wr * 32 + i * 16 + lg * 4 + r;
+      if (p >= a.np) continue;
+      const float inv = invN / a.scale[p];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int z = z0 + wc * 32 + j * 16 + li;
+        if (z < a.Zvalid) a.U[(size_t)p * a.ldU + z] = fmaxf(U[i][j][r], Um[i][j][r]) * inv;
+      }
+    }
+}
+
+// ------------------------------------------------------------ 3. exact ----
+
+struct ExactArgs {
+  int N, Nk, Rp, Z, nrad;
+  int rad[kMaxRadices];
+  const float2* tw;
+  const float *xr, *xi;
+  size_t x_ldk;
+  int x_ldp;
+  const float *pr, *pi;
+  size_t p_ldk;
+  int p_ldz;
+  const float* U;
+  int ldU;
+  const float* xnorm2;
+  int ntiles;
+  const int* flags;
+  const float* M12;
+  const int* zone_phase;
+  float eps_rel, eps_abs;
+  int top_k;
+  int64_t p_begin;
+  int np;
+  int *zone, *phase, *bin, *mirror, *n_eval;
+  float *score, *phi3, *orient;
+  float* C;  // correlate mode: C[p][z][2][N] for every zone (no selection)
+};
+
+// H for nb zones of local pattern p: H_k = G_k + i G_mirror,k (k <= N/2) and
+// H_{N-k} = conj(G_k) + i conj(G_mirror,k), stored as H[n * nb + b].
+__device__ void contract_exact(const ExactArgs& a, int p, const int* bz, int nb, float2* H) {
+  for (int k = threadIdx.x; k < a.Nk; k += blockDim.x) {
+    float acc[kBatch][4];
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) acc[b][0] = acc[b][1] = acc[b][2] = acc[b][3] = 0.0f;
+    const float* xr = a.xr + (size_t)k * a.x_ldk + (size_t)p * a.x_ldp;
+    const float* xi = a.xi + (size_t)k * a.x_ldk + (size_t)p * a.x_ldp;
+    for (int s = 0; s < a.Rp; s += 4) {
+      const float4 vr = *reinterpret_cast<const float4*>(xr + s);
+      const float4 vi = *reinterpret_cast<const float4*>(xi + s);
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) {
+        if (b < nb) {
+          const size_t o = (size_t)k * a.p_ldk + (size_t)bz[b] * a.p_ldz + s;
+          const float4 wr = *reinterpret_cast<const float4*>(a.pr + o);
+          const float4 wi = *reinterpret_cast<const float4*>(a.pi + o);
+          acc[b][0] += vr.x * wr.x + vr.y * wr.y + vr.z * wr.z + vr.w * wr.w;
+          acc[b][1] += vi.x * wi.x + vi.y * wi.y + vi.z * wi.z + vi.w * wi.w;
+          acc[b][2] += vi.x * wr.x + vi.y * wr.y + vi.z * wr.z + vi.w * wr.w;
+          acc[b][3] += vr.x * wi.x + vr.y * wi.y + vr.z * wi.z + vr.w * wi.w;
+        }
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      if (b < nb) {
+        const float A = acc[b][0], B = acc[b][1], C = acc[b][2], D = acc[b][3];
+        H[k * nb + b] = make_float2((A + B) + (C + D), (C - D) + (A - B));
+        if (k > 0 && 2 * k < a.N) H[(a.N - k) * nb + b] = make_float2((A + B) - (C + D), (A - B) - (C - D));
+      }
+    }
+  }
+}
+
+__device__ void block_argmax(const float* v, int n, float* out_v, int* out_i, float* sv, int* si) {
+  float bv = -INFINITY;
+  int bi = INT_MAX;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const float x = v[i];
+    if (x > bv || (x == bv && i < bi)) {
+      bv = x;
+      bi = i;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const float ov = __shfl_xor(bv, off, 64);
+    const int oi = __shfl_xor(bi, off, 64);
+    if (ov > bv || (ov == bv && oi < bi)) {
+      bv = ov;
+      bi = oi;
+    }
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sv[threadIdx.x >> 6] = bv;
+    si[threadIdx.x >> 6] = bi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float b = sv[0];
+    int ix = si[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+      if (sv[w] > b || (sv[w] == b && si[w] < ix)) {
+        b = sv[w];
+        ix = si[w];
+      }
+    *out_v = b;
+    *out_i = ix;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ float parabolic(float cm1, float c0, float cp1) {
+  const float den = cm1 - 2.0f * c0 + cp1;
+  if (!(den < 0.0f)) return 0.0f;
+  return fminf(0.5f, fmaxf(-0.5f, 0.5f * (cm1 - cp1) / den));
+}
+
+__global__ void __launch_bounds__(kThreads) exact_kernel(ExactArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  float2* H0 = reinterpret_cast<float2*>(smem_raw);
+  float2* H1 = H0 + kBatch * a.N;
+  float2* tw = H1 + kBatch * a.N;
+  float* Ul = reinterpret_cast<float*>(tw + a.N);
+  __shared__ float sv[4];
+  __shared__ int si[4];
+  __shared__ float s_topv[kMaxTopK], s_tcm[kMaxTopK], s_tcp[kMaxTopK];
+  __shared__ int s_topz[kMaxTopK], s_topn[kMaxTopK], s_topm[kMaxTopK];
+  __shared__ int s_cnt, s_nb, s_done, s_eval;
+  __shared__ int s_bz[kBatch];
+  __shared__ float s_rv[kBatch], s_rcm[kBatch], s_rcp[kBatch];
+  __shared__ int s_rn[kBatch], s_rm[kBatch];
+  __shared__ float s_bv;
+  __shared__ int s_bi;
+
+  const int p = blockIdx.x;
+  const int64_t P = a.p_begin + p;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const float invN = 1.0f / (float)a.N;
+  for (int i = tid; i < a.N; i += kThreads) tw[i] = a.tw[i];
+
+  if (a.C) {  // full correlogram of zones blockIdx.y * kBatch ..
+    __syncthreads();
+    int bz[kBatch];
+    const int zb = blockIdx.y * kBatch;
+    const int nb = min(kBatch, a.Z - zb);
+    for (int b = 0; b < kBatch; ++b) bz[b] = zb + min(b, nb - 1);
+    contract_exact(a, p, bz, nb, H0);
+    __syncthreads();
+    const float2* Fr = block_fft(H0, H1, tw, a.N, nb, a.rad, a.nrad, -1.0f);
+    for (int it = tid; it < nb * a.N; it += kThreads) {
+      const int b = it / a.N, n = it % a.N;
+      const float2 v = Fr[n * nb + b];
+      float* out = a.C + (((size_t)p * a.Z + zb + b) * 2) * a.N;
+      out[n] = v.x * invN;
+      out[a.N + n] = v.y * invN;
+    }
+    return;
+  }
+
+  const int fl = a.flags[p];
+  if (fl != 0) {
+    for (int t = tid; t < a.top_k; t += kThreads) {
+      const size_t o = (size_t)P * a.top_k + t;
+      a.zone[o] = -1;
+      if (a.phase) a.phase[o] = -1;
+      if (a.bin) a.bin[o] = 0;
+      if (a.mirror) a.mirror[o] = 0;
+      a.score[o] = 0.0f;
+      if (a.phi3) a.phi3[o] = 0.0f;
+      if (a.orient)
+        for (int i = 0; i < 9; ++i) a.orient[o * 9 + i] = 0.0f;
+    }
+    if (a.n_eval && tid == 0) a.n_eval[P] = 0;
+    return;
+  }
+  float xn2 = 0.0f;
+  for (int t = 0; t < a.ntiles; ++t) xn2 += a.xnorm2[(size_t)p * a.ntiles + t];
+  const float margin_abs = a.eps_abs * sqrtf(xn2);
+  for (int z = tid; z < a.Z; z += kThreads) Ul[z] = a.U[(size_t)p * a.ldU + z];
+  if (tid == 0) {
+    s_cnt = 0;
+    s_done = 0;
+    s_eval = 0;
+  }
+  __syncthreads();
+
+  while (true) {
+    // ---- select the next batch in decreasing bound order
+    if (tid == 0) s_nb = 0;
+    __syncthreads();
+    for (int b = 0; b < kBatch; ++b) {
+      block_argmax(Ul, a.Z, &s_bv, &s_bi, sv, si);
+      if (tid == 0) {
+        const float v = s_bv;
+        const float kth = s_cnt >= a.top_k ? s_topv[a.top_k - 1] : -INFINITY;
+        bool stop = !(v > 0.0f) || (v * (1.0f + a.eps_rel) + margin_abs < kth);
+        if (stop) {
+          if (s_nb == 0) s_done = 1;
+        } else {
+          s_bz[s_nb] = s_bi;
+          Ul[s_bi] = -1.0f;
+          s_nb = s_nb + 1;
+        }
+        s_bv = stop ? -1.0f : 0.0f;  // broadcast: stop selecting
+      }
+      __syncthreads();
+      if (s_bv < 0.0f) break;
+    }
+    const int nb = s_nb;
+    if (s_done || nb == 0) break;
+    // ---- exact correlograms of the batch
+    int bz[kBatch];
+    for (int b = 0; b < kBatch; ++b) bz[b] = s_bz[min(b, nb - 1)];
+    contract_exact(a, p, bz, nb, H0);
+    __syncthreads();
+    const float2* Fr = block_fft(H0, H1, tw, a.N, nb, a.rad, a.nrad, -1.0f);
+    for (int b = wave; b < nb; b += kThreads / 64) {
+      float bv = -INFINITY;
+      int bi = INT_MAX;
+      for (int t = lane; t < 2 * a.N; t += 64) {
+        const float2 v = Fr[(t >> 1) * nb + b];
+        const float x = ((t & 1) ? v.y : v.x) * invN;
+        if (x > bv || (x == bv && t < bi)) {
+          bv = x;
+          bi = t;
+        }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const float ov = __shfl_xor(bv, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ov > bv || (ov == bv && oi < bi)) {
+          bv = ov;
+          bi = oi;
+        }
+      }
+      if (lane == 0) {
+        const int n = bi >> 1, m = bi & 1;
+        const float2 vm = Fr[((n + a.N - 1) % a.N) * nb + b];
+        const float2 vp = Fr[((n + 1) % a.N) * nb + b];
+        s_rv[b] = bv;
+        s_rn[b] = n;
+        s_rm[b] = m;
+        s_rcm[b] = (m ? vm.y : vm.x) * invN;
+        s_rcp[b] = (m ? vp.y : vp.x) * invN;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      s_eval += nb;
+      for (int b = 0; b < nb; ++b) {
+        const float v = s_rv[b];
+        const int z = s_bz[b];
+        if (!(v > 0.0f)) continue;
+        int pos = s_cnt;  // insertion point: after all entries that beat (v, z)
+        while (pos > 0 && (s_topv[pos - 1] < v || (s_topv[pos - 1] == v && s_topz[pos - 1] > z))) --pos;
+        if (pos >= a.top_k) continue;
+        const int last = min(s_cnt, a.top_k - 1);
+        for (int q = last; q > pos; --q) {
+          s_topv[q] = s_topv[q - 1];
+          s_topz[q] = s_topz[q - 1];
+          s_topn[q] = s_topn[q - 1];
+          s_topm[q] = s_topm[q - 1];
+          s_tcm[q] = s_tcm[q - 1];
+          s_tcp[q] = s_tcp[q - 1];
+        }
+        s_topv[pos] = v;
+        s_topz[pos] = z;
+        s_topn[pos] = s_rn[b];
+        s_topm[pos] = s_rm[b];
+        s_tcm[pos] = s_rcm[b];
+        s_tcp[pos] = s_rcp[b];
+        s_cnt = min(s_cnt + 1, a.top_k);
+      }
+    }
+    __syncthreads();
+  }
+  // ---- outputs
+  const float two_pi = 6.283185307179586f;
+  for (int t = tid; t < a.top_k; t += kThreads) {
+    const size_t o = (size_t)P * a.top_k + t;
+    if (t < s_cnt) {
+      const int z = s_topz[t], n = s_topn[t], m = s_topm[t];
+      const float off = parabolic(s_tcm[t], s_topv[t], s_tcp[t]);
+      const float ph3 = -((float)n + off) * two_pi / (float)a.N;
+      a.zone[o] = z;
+      if (a.phase) a.phase[o] = a.zone_phase[z];
+      if (a.bin) a.bin[o] = n;
+      if (a.mirror) a.mirror[o] = m;
+      a.score[o] = s_topv[t];
+      if (a.phi3) a.phi3[o] = ph3;
+      if (a.orient) {
+        float cs, sn;
+        sincosf(ph3, &sn, &cs);
+        const float* M = a.M12 + (size_t)z * 9;
+        for (int i = 0; i < 3; ++i) {
+          float c0 = M[3 * i] * cs + M[3 * i + 1] * sn;
+          const float c1 = -M[3 * i] * sn + M[3 * i + 1] * cs;
+          float c2 = M[3 * i + 2];
+          if (m) {
+            c0 = -c0;
+            c2 = -c2;
+          }
+          a.orient[o * 9 + 3 * i] = c0;
+          a.orient[o * 9 + 3 * i + 1] = c1;
+          a.orient[o * 9 + 3 * i + 2] = c2;
+        }
+      }
+    } else {
+      a.zone[o] = -1;
+      if (a.phase) a.phase[o] = -1;
+      if (a.bin) a.bin[o] = 0;
+      if (a.mirror) a.mirror[o] = 0;
+      a.score[o] = 0.0f;
+      if (a.phi3) a.phi3[o] = 0.0f;
+      if (a.orient)
+        for (int i = 0; i < 9; ++i) a.orient[o * 9 + i] = 0.0f;
+    }
+  }
+  if (a.n_eval && tid == 0) a.n_eval[P] = s_eval;
+}
+
+// ------------------------------------------------------------- host -------
+
+struct WsLayout {
+  size_t xr = 0, xi = 0, lr = 0, li = 0, scale = 0, xn2 = 0, flags = 0, U = 0, total = 0;
+  int Pc = 0, ntiles = 0;
+  bool lowp = false;
+};
+
+WsLayout layout(const PlanDev& d, bool lowp, int Pc) {
+  WsLayout L;
+  L.Pc = Pc;
+  L.lowp = lowp;
+  L.ntiles = d.Rp / kPolarCols;
+  const size_t nx = (size_t)d.Nk * Pc * d.Rp;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + bytes, 256);
+    return at;
+  };
+  L.xr = take(nx * 4);
+  L.xi = take(nx * 4);
+  if (lowp) {
+    L.lr = take(nx * 2);
+    L.li = take(nx * 2);
+  }
+  L.scale = take((size_t)Pc * 4);
+  L.xn2 = take((size_t)Pc * L.ntiles * 4);
+  L.flags = take((size_t)Pc * 4);
+  L.U = take((size_t)Pc * d.Zp * 4);
+  L.total = o;
+  return L;
+}
+
+size_t polar_lds(const PlanDev& d) {
+  return (size_t)(2 * d.N * (kPolarCols / 2) + d.N) * sizeof(float2) + kPeakCache * (8 + 4 + 4);
+}
+size_t exact_lds(const PlanDev& d) { return (size_t)(2 * kBatch * d.N + d.N) * sizeof(float2) + (size_t)d.Z * 4; }
+
+template <class K>
+acom_status_t ensure_lds(K kernel, size_t bytes) {
+  if (bytes > 160 * 1024) return fail(ACOM_E_UNSUPPORTED, "plan too large for the LDS budget of one workgroup");
+  ACOM_HIP(hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  return ACOM_OK;
+}
+
+acom_status_t check_peaks(const acom_peaks_t* pk) {
+  if (!pk) return fail(ACOM_E_INVALID, "peaks is null");
+  if (pk->n_patterns < 0 || pk->total_peaks < 0) return fail(ACOM_E_INVALID, "negative pattern or peak count");
+  if (pk->n_patterns > 0 && !pk->offsets) return fail(ACOM_E_INVALID, "offsets is null");
+  if (pk->total_peaks > 0 && (!pk->qx || !pk->qy || !pk->intensity)) return fail(ACOM_E_INVALID, "peak arrays are null");
+  if (pk->total_peaks > INT_MAX) return fail(ACOM_E_UNSUPPORTED, "more than 2^31-1 peaks in one call");
+  return ACOM_OK;
+}
+
+PolarArgs polar_args(const PlanDev& d, const acom_peaks_t* pk, int64_t p_begin, int np, int lowp) {
+  PolarArgs a;
+  a.N = d.N;
+  a.R = d.R;
+  a.Rp = d.Rp;
+  a.Nk = d.Nk;
+  a.nrad = d.rad.n;
+  for (int i = 0; i < kMaxRadices; ++i) a.rad[i] = d.rad.r[i];
+  a.qs = d.d_qs;
+  a.tw = d.d_tw;
+  a.delta = (float)d.delta;
+  a.sigma = (float)d.gauss_sigma;
+  a.rk = d.kernel == ACOM_KERNEL_CONE ? (float)d.delta : (float)(3.0 * d.gauss_sigma);
+  a.gamma = (float)d.gamma;
+  a.omega = (float)d.omega;
+  a.kernel = d.kernel;
+  a.offsets = pk->offsets;
+  a.qx = pk->qx;
+  a.qy = pk->qy;
+  a.I = pk->intensity;
+  a.total_peaks = pk->total_peaks;
+  a.p_begin = p_begin;
+  a.np = np;
+  a.lowp = lowp;
+  a.Ximg = nullptr;
+  a.do_fft = 1;
+  return a;
+}
+
+void set_ws(PolarArgs& a, const WsLayout& L, unsigned char* ws, const PlanDev& d) {
+  a.xr = reinterpret_cast<float*>(ws + L.xr);
+  a.xi = reinterpret_cast<float*>(ws + L.xi);
+  a.ldk = (size_t)L.Pc * d.Rp;
+  a.ldp = d.Rp;
+  a.out_cols = d.Rp;
+  a.lr = L.lowp ? reinterpret_cast<uint16_t*>(ws + L.lr) : nullptr;
+  a.li = L.lowp ? reinterpret_cast<uint16_t*>(ws + L.li) : nullptr;
+  a.scale = reinterpret_cast<float*>(ws + L.scale);
+  a.xnorm2 = reinterpret_cast<float*>(ws + L.xn2);
+  a.flags = reinterpret_cast<int*>(ws + L.flags);
+}
+
+acom_status_t launch_polar(const PlanDev& d, const PolarArgs& a, hipStream_t s) {
+  acom_status_t st = ensure_lds(polar_kernel, polar_lds(d));
+  if (st != ACOM_OK) return st;
+  dim3 grid(a.np, d.Rp / kPolarCols);
+  polar_kernel<<<grid, kThreads, polar_lds(d), s>>>(a);
+  ACOM_HIP(hipGetLastError());
+  return ACOM_OK;
+}
+
+acom_status_t launch_bound(const PlanDev& d, int precision, const WsLayout& L, unsigned char* ws, int np,
+                           float* U, int ldU, int Zvalid, hipStream_t s) {
+  BoundArgs b;
+  b.Nk = d.Nk;
+  b.Rp = d.Rp;
+  b.N = d.N;
+  b.x_ldk = (size_t)L.Pc * d.Rp;
+  b.x_ldp = d.Rp;
+  b.p_ldk = (size_t)d.Zp * d.Rp;
+  b.p_ldz = d.Rp;
+  b.scale = reinterpret_cast<const float*>(ws + L.scale);
+  b.U = U;
+  b.ldU = ldU;
+  b.np = np;
+  b.Zvalid = Zvalid;
+  dim3 grid((np + kTileP - 1) / kTileP, d.Zp / kTileZ);
+  if (precision == ACOM_FP32) {
+    b.xr = ws + L.xr;
+    b.xi = ws + L.xi;
+    b.pr = d.d_PR;
+    b.pi = d.d_PI;
+    bound_kernel<0><<<grid, kThreads, 0, s>>>(b);
+  } else {
+    b.xr = ws + L.lr;
+    b.xi = ws + L.li;
+    b.pr = d.d_PR16[precision];
+    b.pi = d.d_PI16[precision];
+    if (precision == ACOM_BF16)
+      bound_kernel<1><<<grid, kThreads, 0, s>>>(b);
+    else
+      bound_kernel<2><<<grid, kThreads, 0, s>>>(b);
+  }
+  ACOM_HIP(hipGetLastError());
+  return ACOM_OK;
+}
+
+ExactArgs exact_args(const PlanDev& d, const WsLayout& L, unsigned char* ws, int64_t p_begin, int np) {
+  ExactArgs e;
+  e.N = d.N;
+  e.Nk = d.Nk;
+  e.Rp = d.Rp;
+  e.Z = d.Z;
+  e.nrad = d.rad.n;
+  for (int i = 0; i < kMaxRadices; ++i) e.rad[i] = d.rad.r[i];
+  e.tw = d.d_tw;
+  e.xr = reinterpret_cast<const float*>(ws + L.xr);
+  e.xi = reinterpret_cast<const float*>(ws + L.xi);
+  e.x_ldk = (size_t)L.Pc * d.Rp;
+  e.x_ldp = d.Rp;
+  e.pr = d.d_PR;
+  e.pi = d.d_PI;
+  e.p_ldk = (size_t)d.Zp * d.Rp;
+  e.p_ldz = d.Rp;
+  e.U = reinterpret_cast<const float*>(ws + L.U);
+  e.ldU = d.Zp;
+  e.xnorm2 = reinterpret_cast<const float*>(ws + L.xn2);
+  e.ntiles = L.ntiles;
+  e.flags = reinterpret_cast<const int*>(ws + L.flags);
+  e.M12 = d.d_M12;
+  e.zone_phase = d.d_zone_phase;
+  e.eps_rel = 1e-5f;
+  e.eps_abs = 1e-5f;
+  e.top_k = 1;
+  e.p_begin = p_begin;
+  e.np = np;
+  e.zone = e.phase = e.bin = e.mirror = e.n_eval = nullptr;
+  e.score = e.phi3 = e.orient = nullptr;
+  e.C = nullptr;
+  return e;
+}
+
+// Rigorous widening of the bound for operand rounding: |dU| <= 2 u ||X|| with
+// u the unit roundoff of the operand format, plus FP32 accumulation slack.
+float eps_abs_for(int precision) {
+  if (precision == ACOM_BF16) return 0.0078125f + 1e-5f;   // 2 * 2^-8
+  if (precision == ACOM_FP16) return 0.0009765625f + 1e-5f; // 2 * 2^-11
+  return 1e-5f;
+}
+
+acom_status_t check_plan_precision(acom_plan_t plan, int precision) {
+  if (!plan) return fail(ACOM_E_INVALID, "plan is null");
+  if (precision < 0 || precision > 2) return fail(ACOM_E_INVALID, "precision must be ACOM_FP32, ACOM_BF16 or ACOM_FP16");
+  if (precision != ACOM_FP32 && !plan->d.d_PR16[precision])
+    return fail(ACOM_E_INVALID, "plan was built without this precision (acom_plan_params_t.precisions)");
+  if (plan->d.Z > kMaxZonesExact) return fail(ACOM_E_UNSUPPORTED, "more than 16384 zones");
+  return ACOM_OK;
+}
+
+int chunk_of(int chunk) {
+  int c = chunk <= 0 ? kDefaultChunk : chunk;
+  return (int)align_up(c, kTileP);
+}
+
+}  // namespace
+}  // namespace acom
+
+using namespace acom;
+
+extern "C" acom_status_t acom_match_workspace_size(acom_plan_t plan, int32_t precision, int32_t chunk,
+                                                   size_t* bytes) {
+  acom_status_t st = check_plan_precision(plan, precision);
+  if (st != ACOM_OK) return st;
+  if (!bytes) return fail(ACOM_E_INVALID, "bytes is null");
+  *bytes = layout(plan->d, precision != ACOM_FP32, chunk_of(chunk)).total;
+  return ACOM_OK;
+}
+
+extern "C" acom_status_t acom_match(acom_plan_t plan, const acom_peaks_t* peaks, int32_t top_k, int32_t precision,
+                                    int32_t chunk, void* workspace, size_t workspace_bytes,
+                                    const acom_matches_t* out, void* stream_v) {
+  acom_status_t st = check_plan_precision(plan, precision);
+  if (st != ACOM_OK) return st;
+  if ((st = check_peaks(peaks)) != ACOM_OK) return st;
+  if (top_k < 1 || top_k > kMaxTopK) return fail(ACOM_E_INVALID, "top_k must be in [1, 16]");
+  if (!out) return fail(ACOM_E_INVALID, "matches is null");
+  if (peaks->n_patterns == 0) return ACOM_OK;
+  if (!out->zone || !out->score) return fail(ACOM_E_INVALID, "matches: zone and score outputs are required");
+  const PlanDev& d = plan->d;
+  const int Pc = chunk_of(chunk);
+  const WsLayout L = layout(d, precision != ACOM_FP32, Pc);
+  if (!workspace || workspace_bytes < L.total)
+    return fail(ACOM_E_WORKSPACE, "workspace smaller than acom_match_workspace_size");
+  hipStream_t s = (hipStream_t)stream_v;
+  unsigned char* ws = reinterpret_cast<unsigned char*>(workspace);
+  if ((st = ensure_lds(exact_kernel, exact_lds(d))) != ACOM_OK) return st;
+  for (int64_t c0 = 0; c0 < peaks->n_patterns; c0 += Pc) {
+    const int np = (int)std::min<int64_t>(Pc, peaks->n_patterns - c0);
+    PolarArgs pa = polar_args(d, peaks, c0, np, precision);
+    set_ws(pa, L, ws, d);
+    if ((st = launch_polar(d, pa, s)) != ACOM_OK) return st;
+    if ((st = launch_bound(d, precision, L, ws, np, reinterpret_cast<float*>(ws + L.U), d.Zp, d.Zp, s)) != ACOM_OK)
+      return st;
+    ExactArgs e = exact_args(d, L, ws, c0, np);
+    e.eps_abs = eps_abs_for(precision);
+    e.top_k = top_k;
+    e.zone = out->zone;
+    e.phase = out->phase;
+    e.bin = out->bin;
+    e.mirror = out->mirror;
+    e.score = out->score;
+    e.phi3 = out->phi3;
+    e.orient = out->orient;
+    e.n_eval = out->n_evaluated;
+    exact_kernel<<<np, kThreads, exact_lds(d), s>>>(e);
+    ACOM_HIP(hipGetLastError());
+  }
+  return ACOM_OK;
+}
+
+extern "C" acom_status_t acom_debug_workspace_size(acom_plan_t plan, int64_t n_patterns, size_t* bytes) {
+  if (!plan || !bytes) return fail(ACOM_E_INVALID, "null argument");
+  if (n_patterns < 0 || n_patterns > (1 << 20)) return fail(ACOM_E_INVALID, "n_patterns must be in [0, 2^20]");
+  *bytes = layout(plan->d, true, chunk_of((int)std::max<int64_t>(1, n_patterns))).total;
+  return ACOM_OK;
+}
+
+namespace {
+acom_status_t debug_prep(acom_plan_t plan, const acom_peaks_t* peaks, void* ws, size_t wsb, WsLayout* L) {
+  if (!plan) return fail(ACOM_E_INVALID, "plan is null");
+  acom_status_t st = check_peaks(peaks);
+  if (st != ACOM_OK) return st;
+  if (peaks->n_patterns > (1 << 20)) return fail(ACOM_E_INVALID, "debug calls take at most 2^20 patterns");
+  *L = layout(plan->d, true, chunk_of((int)std::max<int64_t>(1, peaks->n_patterns)));
+  if (!ws || wsb < L->total) return fail(ACOM_E_WORKSPACE, "workspace smaller than acom_debug_workspace_size");
+  return ACOM_OK;
+}
+}  // namespace
+
+extern "C" acom_status_t acom_polar_image(acom_plan_t plan, const acom_peaks_t* peaks, float* X, void* workspace,
+                                          size_t workspace_bytes, void* stream_v) {
+  WsLayout L;
+  acom_status_t st = debug_prep(plan, peaks, workspace, workspace_bytes, &L);
+  if (st != ACOM_OK) return st;
+  if (!X) return fail(ACOM_E_INVALID, "X is null");
+  if (peaks->n_patterns == 0) return ACOM_OK;
+  const PlanDev& d = plan->d;
+  unsigned char* ws = reinterpret_cast<unsigned char*>(workspace);
+  PolarArgs pa = polar_args(d, peaks, 0, (int)peaks->n_patterns, 0);
+  set_ws(pa, L, ws, d);
+  pa.Ximg = X;
+  pa.do_fft = 0;
+  return launch_polar(d, pa, (hipStream_t)stream_v);
+}
+
+extern "C" acom_status_t acom_polar_spectrum(acom_plan_t plan, const acom_peaks_t* peaks, float* Xr, float* Xi,
+                                             void* workspace, size_t workspace_bytes, void* stream_v) {
+  WsLayout L;
+  acom_status_t st = debug_prep(plan, peaks, workspace, workspace_bytes, &L);
+  if (st != ACOM_OK) return st;
+  if (!Xr || !Xi) return fail(ACOM_E_INVALID, "Xr/Xi is null");
+  if (peaks->n_patterns == 0) return ACOM_OK;
+  const PlanDev& d = plan->d;
+  unsigned char* ws = reinterpret_cast<unsigned char*>(workspace);
+  PolarArgs pa = polar_args(d, peaks, 0, (int)peaks->n_patterns, 0);
+  set_ws(pa, L, ws, d);
+  pa.xr = Xr;
+  pa.xi = Xi;
+  pa.ldk = d.R;
+  pa.ldp = d.Nk * d.R;
+  pa.out_cols = d.R;
+  return launch_polar(d, pa, (hipStream_t)stream_v);
+}
+
+extern "C" acom_status_t acom_correlate(acom_plan_t plan, const acom_peaks_t* peaks, float* C, void* workspace,
+                                        size_t workspace_bytes, void* stream_v) {
+  WsLayout L;
+  acom_status_t st = debug_prep(plan, peaks, workspace, workspace_bytes, &L);
+  if (st != ACOM_OK) return st;
+  if (!C) return fail(ACOM_E_INVALID, "C is null");
+  if (peaks->n_patterns == 0) return ACOM_OK;
+  const PlanDev& d = plan->d;
+  hipStream_t s = (hipStream_t)stream_v;
+  unsigned char* ws = reinterpret_cast<unsigned char*>(workspace);
+  const int np = (int)peaks->n_patterns;
+  PolarArgs pa = polar_args(d, peaks, 0, np, 0);
+  set_ws(pa, L, ws, d);
+  if ((st = launch_polar(d, pa, s)) != ACOM_OK) return st;
+  ExactArgs e = exact_args(d, L, ws, 0, np);
+  e.C = C;
+  if ((st = ensure_lds(exact_kernel, exact_lds(d))) != ACOM_OK) return st;
+  dim3 grid(np, (d.Z + kBatch - 1) / kBatch);
+  exact_kernel<<<grid, kThreads, exact_lds(d), s>>>(e);
+  ACOM_HIP(hipGetLastError());
+  return ACOM_OK;
+}
+
+extern "C" acom_status_t acom_bound(acom_plan_t plan, const acom_peaks_t* peaks, int32_t precision, float* U,
+                                    void* workspace, size_t workspace_bytes, void* stream_v) {
+  acom_status_t st = check_plan_precision(plan, precision);
+  if (st != ACOM_OK) return st;
+  WsLayout L;
+  if ((st = debug_prep(plan, peaks, workspace, workspace_bytes, &L)) != ACOM_OK) return st;
+  if (!U) return fail(ACOM_E_INVALID, "U is null");
+  if (peaks->n_patterns == 0) return ACOM_OK;
+  const PlanDev& d = plan->d;
+  hipStream_t s = (hipStream_t)stream_v;
+  unsigned char* ws = reinterpret_cast<unsigned char*>(workspace);
+  const int np = (int)peaks->n_patterns;
+  PolarArgs pa = polar_args(d, peaks, 0, np, precision);
+  set_ws(pa, L, ws, d);
+  if ((st = launch_polar(d, pa, s)) != ACOM_OK) return st;
+  return launch_bound(d, precision, L, ws, np, U, d.Z, d.Z, s);
+}

@@ -1,0 +1,474 @@
+// Continuous correlation score, its backward, and gradient-ascent refinement.
+//
+// The continuous analogue of the paper's normalised polar correlation (an
+// extension, not in the paper):
+//   S = sum_m sum_g w_m v_g K_mg / sqrt(sum_g v_g^2)
+//   w_m = q_m^gamma I_m^(omega/2)                               (Eq. image_polar)
+//   v_g = |g|^gamma (|F_g|^2 exp(-s_g^2 / 2 sigma_e^2))^(omega/2) (Eq. excitation
+//         error with the Gaussian shape factor of Eq. shape_gaussian)
+//   K_mg = exp(-|q_m - (x_g, y_g)|^2 / (2 sigma_c^2)), sigma_c = delta / 2,
+//   (x_g, y_g, z_g) = m^T g with m = base Exp(theta).
+// dS/dtheta uses d(Exp(theta)^T u)/dtheta = [r]x J_r(theta) (SO(3) right Jacobian).
+// One wavefront per pattern; lanes own reflections, peaks are streamed from
+// LDS.  For omega > 0, reflections with |s_g| >= 10 sigma_e / sqrt(omega) + 0.035
+// 1/A at the base orientation are dropped once per call: v_g is then below
+// exp(-25) of |g|^gamma |F_g|^omega even after a 1 degree rotation (which moves
+// s_g by at most 0.035 1/A for |g| < 2 1/A).  For omega = 0 all are kept.
+#include <cmath>
+
+#include "acom_internal.h"
+
+namespace acom {
+namespace {
+
+constexpr int kW = 64;         // one wavefront per pattern
+constexpr int kMaxKept = 1024;  // kept reflections per pattern
+constexpr int kPeakChunk = 256;
+
+struct ScoreArgs {
+  const int64_t* offsets;
+  const float *qx, *qy, *I;
+  int64_t total_peaks;
+  const float4* refl;
+  const float* F2;
+  const int* refl_off;
+  int n_phases;
+  float k0, delta, gamma, omega, sigma_e;
+  int n;
+  // score / grad
+  const float* base;
+  const float* theta;
+  const int* phase;
+  float* S;
+  const float* dS;
+  float* dtheta;
+  float *dqx, *dqy;
+  // refine
+  int n_cand, max_iter;
+  const float* init;
+  const int* cand_phase;
+  float* out_orient;
+  float* out_score;
+  int* out_cand;
+};
+
+__device__ __forceinline__ float wsum(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ float powe(float x, float e) {
+  if (e == 1.0f) return x;
+  if (e == 0.5f) return sqrtf(x);
+  if (e == 0.0f) return 1.0f;
+  if (e == 2.0f) return x * x;
+  return powf(x, e);
+}
+
+// Rodrigues Exp(theta) into E (row-major).
+__device__ void expm3(const float* th, float* E) {
+  const float t2 = th[0] * th[0] + th[1] * th[1] + th[2] * th[2];
+  const float t = sqrtf(t2);
+  float a, b;
+  if (t < 1e-4f) {
+    a = 1.0f - t2 / 6.0f;
+    b = 0.5f - t2 / 24.0f;
+  } else {
+    a = sinf(t) / t;
+    b = (1.0f - cosf(t)) / t2;
+  }
+  const float K[9] = {0, -th[2], th[1], th[2], 0, -th[0], -th[1], th[0], 0};
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      float kk = 0.0f;
+      for (int l = 0; l < 3; ++l) kk += K[3 * i + l] * K[3 * l + j];
+      E[3 * i + j] = (i == j ? 1.0f : 0.0f) + a * K[3 * i + j] + b * kk;
+    }
+}
+
+__device__ void right_jac(const float* th, float* J) {
+  const float t2 = th[0] * th[0] + th[1] * th[1] + th[2] * th[2];
+  const float t = sqrtf(t2);
+  float a, b;
+  if (t < 1e-3f) {
+    a = 0.5f - t2 / 24.0f;
+    b = 1.0f / 6.0f - t2 / 120.0f;
+  } else {
+    a = (1.0f - cosf(t)) / t2;
+    b = (t - sinf(t)) / (t2 * t);
+  }
+  const float K[9] = {0, -th[2], th[1], th[2], 0, -th[0], -th[1], th[0], 0};
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      float kk = 0.0f;
+      for (int l = 0; l < 3; ++l) kk += K[3 * i + l] * K[3 * l + j];
+      J[3 * i + j] = (i == j ? 1.0f : 0.0f) - a * K[3 * i + j] + b * kk;
+    }
+}
+
+__device__ void matmul3(const float* A, const float* B, float* C) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) C[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
+}
+
+__device__ __forceinline__ float excitation(float x, float y, float z, float k0) {
+  return -(2.0f * k0 * z + (x * x + y * y + z * z)) / (2.0f * sqrtf(x * x + y * y + (k0 + z) * (k0 + z)));
+}
+
+struct Shared {
+  float qx[kPeakChunk], qy[kPeakChunk], w[kPeakChunk], q[kPeakChunk];
+  int kept[kMaxKept];
+  float rx[kMaxKept], ry[kMaxKept], v[kMaxKept];
+  int nkept;
+};
+
+// Kept reflections of `ph` at orientation m (lane-cooperative, ascending order).
+__device__ void select_kept(const ScoreArgs& a, int ph, const float* m, Shared& sh) {
+  const int lane = threadIdx.x;
+  const int g0 = a.refl_off[ph], g1 = a.refl_off[ph + 1];
+  const float lim = a.omega > 0.0f ? 10.0f * a.sigma_e / sqrtf(a.omega) + 0.035f : INFINITY;
+  int base = 0;
+  for (int c = g0; c < g1; c += kW) {
+    const int g = c + lane;
+    bool keep = false;
+    if (g < g1) {
+      const float4 r = a.refl[g];
+      const float x = m[0] * r.x + m[3] * r.y + m[6] * r.z;
+      const float y = m[1] * r.x + m[4] * r.y + m[7] * r.z;
+      const float z = m[2] * r.x + m[5] * r.y + m[8] * r.z;
+      keep = fabsf(excitation(x, y, z, a.k0)) < lim;
+    }
+    const unsigned long long bal = __ballot(keep);
+    const int before = __popcll(bal & ((1ull << lane) - 1ull));
+    if (keep && base + before < kMaxKept) sh.kept[base + before] = g;
+    base += __popcll(bal);
+  }
+  if (lane == 0) sh.nkept = base < kMaxKept ? base : kMaxKept;
+  __syncthreads();
+}
+
+// S, and optionally dS/dtheta (theta-Jacobian J) and the per-reflection
+// arrays needed for peak gradients, at orientation R = m (row-major).
+struct Eval {
+  float S, N, nv;
+  float g[3];
+};
+
+__device__ Eval evaluate(const ScoreArgs& a, int64_t m0, int64_t m1, const float* R, const float* J, bool grad,
+                         bool keep_arrays, Shared& sh) {
+  const int lane = threadIdx.x;
+  const float sig2 = 0.25f * a.delta * a.delta;
+  const float inv2sc = 1.0f / (2.0f * sig2);
+  const float inv2se = 1.0f / (2.0f * a.sigma_e * a.sigma_e);
+  const int nk = sh.nkept;
+  constexpr int PER = kMaxKept / kW;
+  float rx[PER], ry[PER], rz[PER], s[PER], v[PER], ag[PER], bx[PER], by[PER];
+#pragma unroll
+  for (int t = 0; t < PER; ++t) {
+    const int j = lane + t * kW;
+    ag[t] = bx[t] = by[t] = 0.0f;
+    v[t] = 0.0f;
+    rx[t] = ry[t] = rz[t] = s[t] = 0.0f;
+    if (j < nk) {
+      const int g = sh.kept[j];
+      const float4 r = a.refl[g];
+      rx[t] = R[0] * r.x + R[3] * r.y + R[6] * r.z;
+      ry[t] = R[1] * r.x + R[4] * r.y + R[7] * r.z;
+      rz[t] = R[2] * r.x + R[5] * r.y + R[8] * r.z;
+      s[t] = excitation(rx[t], ry[t], rz[t], a.k0);
+      v[t] = powe(r.w, a.gamma) * powe(a.F2[g] * expf(-s[t] * s[t] * inv2se), 0.5f * a.omega);
+    }
+  }
+  for (int64_t c0 = m0; c0 < m1; c0 += kPeakChunk) {
+    const int cnt = (int)min((int64_t)kPeakChunk, m1 - c0);
+    __syncthreads();
+    for (int i = lane; i < cnt; i += kW) {
+      const float x = a.qx[c0 + i], y = a.qy[c0 + i], in = a.I[c0 + i];
+      const float q = sqrtf(x * x + y * y);
+      sh.qx[i] = x;
+      sh.qy[i] = y;
+      sh.q[i] = q;
+      sh.w[i] = powe(q, a.gamma) * powe(in, 0.5f * a.omega);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      if (lane + t * kW >= nk) continue;
+      for (int i = 0; i < cnt; ++i) {
+        const float dx = sh.qx[i] - rx[t], dy = sh.qy[i] - ry[t];
+        const float wk = sh.w[i] * expf(-(dx * dx + dy * dy) * inv2sc);
+        ag[t] += wk;
+        if (grad) {
+          bx[t] += wk * dx;
+          by[t] += wk * dy;
+        }
+      }
+    }
+  }
+  float Np = 0.0f, V2 = 0.0f;
+#pragma unroll
+  for (int t = 0; t < PER; ++t) {
+    Np += ag[t] * v[t];
+    V2 += v[t] * v[t];
+  }
+  Eval e;
+  e.N = wsum(Np);
+  const float v2 = wsum(V2);
+  e.nv = sqrtf(v2);
+  e.S = e.nv > 0.0f ? e.N / e.nv : 0.0f;
+  e.g[0] = e.g[1] = e.g[2] = 0.0f;
+  if (keep_arrays) {
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const int j = lane + t * kW;
+      if (j < nk) {
+        sh.rx[j] = rx[t];
+        sh.ry[j] = ry[t];
+        sh.v[j] = v[t];
+      }
+    }
+  }
+  if (!grad || !(e.nv > 0.0f)) return e;
+  const float inv_se2 = 1.0f / (a.sigma_e * a.sigma_e);
+  const float c1 = 1.0f / e.nv, c2 = e.N / (e.nv * e.nv * e.nv);
+  float gd[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int t = 0; t < PER; ++t) {
+    if (lane + t * kW >= nk) continue;
+    const float x = rx[t], y = ry[t], z = rz[t], st = s[t];
+    const float D = sqrtf(x * x + y * y + (a.k0 + z) * (a.k0 + z));
+    const float f = v[t] * 0.5f * a.omega * (-st * inv_se2);
+    const float dvx = f * (-x / D - st * x / (D * D));
+    const float dvy = f * (-y / D - st * y / (D * D));
+    const float dvz = f * (-(a.k0 + z) / D - st * (a.k0 + z) / (D * D));
+    const float dNx = ag[t] * dvx + v[t] * bx[t] / sig2;
+    const float dNy = ag[t] * dvy + v[t] * by[t] / sig2;
+    const float dNz = ag[t] * dvz;
+    const float dx = c1 * dNx - c2 * v[t] * dvx;
+    const float dy = c1 * dNy - c2 * v[t] * dvy;
+    const float dz = c1 * dNz - c2 * v[t] * dvz;
+    // (dS/dr x r)
+    const float cx = dy * z - dz * y, cy = dz * x - dx * z, cz = dx * y - dy * x;
+    gd[0] += cx * J[0] + cy * J[3] + cz * J[6];
+    gd[1] += cx * J[1] + cy * J[4] + cz * J[7];
+    gd[2] += cx * J[2] + cy * J[5] + cz * J[8];
+  }
+  e.g[0] = wsum(gd[0]);
+  e.g[1] = wsum(gd[1]);
+  e.g[2] = wsum(gd[2]);
+  return e;
+}
+
+__global__ void __launch_bounds__(kW) score_kernel(ScoreArgs a) {
+  __shared__ Shared sh;
+  const int p = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int64_t m0 = a.offsets[p], m1 = a.offsets[p + 1];
+  const int ph = a.phase ? a.phase[p] : 0;
+  float base[9], th[3], E[9], R[9], J[9];
+  for (int i = 0; i < 9; ++i) base[i] = a.base[(size_t)p * 9 + i];
+  for (int i = 0; i < 3; ++i) th[i] = a.theta[(size_t)p * 3 + i];
+  if (ph < 0 || ph >= a.n_phases || m0 < 0 || m1 < m0 || m1 > a.total_peaks) {
+    if (lane == 0) {
+      if (a.S) a.S[p] = NAN;
+      if (a.dtheta)
+        for (int i = 0; i < 3; ++i) a.dtheta[(size_t)p * 3 + i] = NAN;
+    }
+    return;
+  }
+  expm3(th, E);
+  matmul3(base, E, R);
+  right_jac(th, J);
+  select_kept(a, ph, base, sh);
+  const bool grad = a.dtheta != nullptr;
+  const bool peak_grad = a.dqx != nullptr || a.dqy != nullptr;
+  Eval e = evaluate(a, m0, m1, R, J, grad, peak_grad, sh);
+  if (!grad) {
+    if (lane == 0) a.S[p] = e.S;
+    return;
+  }
+  const float ds = a.dS ? a.dS[p] : 1.0f;
+  if (lane == 0) {
+    for (int i = 0; i < 3; ++i) a.dtheta[(size_t)p * 3 + i] = ds * e.g[i];
+    if (a.S) a.S[p] = e.S;
+  }
+  if (!peak_grad) return;
+  __syncthreads();
+  // per-peak gradient: (dw/dq K.v - w sum_g K v d / sig2) / nv
+  const float sig2 = 0.25f * a.delta * a.delta;
+  const float inv2sc = 1.0f / (2.0f * sig2);
+  const int nk = sh.nkept;
+  for (int64_t m = m0 + lane; m < m1; m += kW) {
+    const float x = a.qx[m], y = a.qy[m], in = a.I[m];
+    const float q = sqrtf(x * x + y * y);
+    const float w = powe(q, a.gamma) * powe(in, 0.5f * a.omega);
+    float kv = 0.0f, kdx = 0.0f, kdy = 0.0f;
+    for (int j = 0; j < nk; ++j) {
+      const float dx = x - sh.rx[j], dy = y - sh.ry[j];
+      const float kvj = expf(-(dx * dx + dy * dy) * inv2sc) * sh.v[j];
+      kv += kvj;
+      kdx += kvj * dx;
+      kdy += kvj * dy;
+    }
+    float gx = 0.0f, gy = 0.0f;
+    if (e.nv > 0.0f) {
+      const float inv_q2 = q > 0.0f ? 1.0f / (q * q) : 0.0f;
+      gx = (a.gamma * w * x * inv_q2 * kv - w * kdx / sig2) / e.nv;
+      gy = (a.gamma * w * y * inv_q2 * kv - w * kdy / sig2) / e.nv;
+    }
+    if (a.dqx) a.dqx[m] = ds * gx;
+    if (a.dqy) a.dqy[m] = ds * gy;
+  }
+}
+
+__global__ void __launch_bounds__(kW) refine_kernel(ScoreArgs a) {
+  __shared__ Shared sh;
+  const int p = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int64_t m0 = a.offsets[p], m1 = a.offsets[p + 1];
+  const float deg = 0.017453292519943295f;
+  const float lmax = 0.5f * deg, lmin = 1e-4f * deg;
+  float best[9];
+  float bestS = -INFINITY;
+  int bestc = -1;
+  for (int i = 0; i < 9; ++i) best[i] = 0.0f;
+  const float I3[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+  for (int c = 0; c < a.n_cand; ++c) {
+    const size_t ci = (size_t)p * a.n_cand + c;
+    const int ph = a.cand_phase ? a.cand_phase[ci] : 0;
+    float m[9];
+    for (int i = 0; i < 9; ++i) m[i] = a.init[ci * 9 + i];
+    bool ok = ph >= 0 && ph < a.n_phases && m0 >= 0 && m1 >= m0 && m1 <= a.total_peaks;
+    for (int i = 0; i < 9; ++i) ok = ok && isfinite(m[i]);
+    if (!ok) continue;
+    __syncthreads();
+    select_kept(a, ph, m, sh);
+    Eval e = evaluate(a, m0, m1, m, I3, true, false, sh);
+    float S = e.S;
+    float g[3] = {e.g[0], e.g[1], e.g[2]};
+    float l = 0.25f * deg;
+    int it = 0;
+    while (it < a.max_iter && l >= lmin) {
+      const float gn = sqrtf(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+      if (!(gn > 0.0f)) break;
+      float th[3] = {l * g[0] / gn, l * g[1] / gn, l * g[2] / gn};
+      float E[9], mt[9];
+      expm3(th, E);
+      matmul3(m, E, mt);
+      Eval et = evaluate(a, m0, m1, mt, I3, false, false, sh);
+      ++it;
+      if (et.S > S) {
+        for (int i = 0; i < 9; ++i) m[i] = mt[i];
+        S = et.S;
+        l = fminf(2.0f * l, lmax);
+        Eval eg = evaluate(a, m0, m1, m, I3, true, false, sh);
+        g[0] = eg.g[0];
+        g[1] = eg.g[1];
+        g[2] = eg.g[2];
+      } else {
+        l *= 0.5f;
+      }
+    }
+    if (S > bestS) {
+      bestS = S;
+      bestc = c;
+      for (int i = 0; i < 9; ++i) best[i] = m[i];
+    }
+  }
+  if (lane == 0) {
+    for (int i = 0; i < 9; ++i) a.out_orient[(size_t)p * 9 + i] = bestc >= 0 ? best[i] : 0.0f;
+    if (a.out_score) a.out_score[p] = bestc >= 0 ? bestS : 0.0f;
+    if (a.out_cand) a.out_cand[p] = bestc;
+  }
+}
+
+acom_status_t common_args(acom_plan_t plan, const acom_peaks_t* pk, ScoreArgs* a) {
+  if (!plan) return fail(ACOM_E_INVALID, "plan is null");
+  if (!pk) return fail(ACOM_E_INVALID, "peaks is null");
+  if (pk->n_patterns < 0 || pk->total_peaks < 0) return fail(ACOM_E_INVALID, "negative sizes");
+  if (pk->n_patterns > INT_MAX) return fail(ACOM_E_UNSUPPORTED, "too many patterns");
+  if (pk->n_patterns > 0 && !pk->offsets) return fail(ACOM_E_INVALID, "offsets is null");
+  if (pk->total_peaks > 0 && (!pk->qx || !pk->qy || !pk->intensity)) return fail(ACOM_E_INVALID, "peak arrays are null");
+  const PlanDev& d = plan->d;
+  *a = ScoreArgs();
+  a->offsets = pk->offsets;
+  a->qx = pk->qx;
+  a->qy = pk->qy;
+  a->I = pk->intensity;
+  a->total_peaks = pk->total_peaks;
+  a->refl = d.d_refl;
+  a->F2 = d.d_reflF2;
+  a->refl_off = d.d_refl_off;
+  a->n_phases = d.n_phases;
+  a->k0 = (float)d.k0;
+  a->delta = (float)d.delta;
+  a->gamma = (float)d.gamma;
+  a->omega = (float)d.omega;
+  a->sigma_e = (float)d.sigma_exc;
+  a->n = (int)pk->n_patterns;
+  return ACOM_OK;
+}
+
+}  // namespace
+}  // namespace acom
+
+using namespace acom;
+
+extern "C" acom_status_t acom_score(acom_plan_t plan, const acom_peaks_t* peaks, const float* base_orient,
+                                    const float* theta, const int32_t* phase, float* S, void* stream) {
+  ScoreArgs a;
+  acom_status_t st = common_args(plan, peaks, &a);
+  if (st != ACOM_OK) return st;
+  if (a.n == 0) return ACOM_OK;
+  if (!base_orient || !theta || !S) return fail(ACOM_E_INVALID, "acom_score: null argument");
+  a.base = base_orient;
+  a.theta = theta;
+  a.phase = phase;
+  a.S = S;
+  score_kernel<<<a.n, kW, 0, (hipStream_t)stream>>>(a);
+  ACOM_HIP(hipGetLastError());
+  return ACOM_OK;
+}
+
+extern "C" acom_status_t acom_score_grad(acom_plan_t plan, const acom_peaks_t* peaks, const float* base_orient,
+                                         const float* theta, const int32_t* phase, const float* dS, float* dtheta,
+                                         float* dqx, float* dqy, void* stream) {
+  ScoreArgs a;
+  acom_status_t st = common_args(plan, peaks, &a);
+  if (st != ACOM_OK) return st;
+  if (a.n == 0) return ACOM_OK;
+  if (!base_orient || !theta || !dtheta) return fail(ACOM_E_INVALID, "acom_score_grad: null argument");
+  a.base = base_orient;
+  a.theta = theta;
+  a.phase = phase;
+  a.dS = dS;
+  a.dtheta = dtheta;
+  a.dqx = dqx;
+  a.dqy = dqy;
+  score_kernel<<<a.n, kW, 0, (hipStream_t)stream>>>(a);
+  ACOM_HIP(hipGetLastError());
+  return ACOM_OK;
+}
+
+extern "C" acom_status_t acom_refine(acom_plan_t plan, const acom_peaks_t* peaks, int32_t n_cand,
+                                     const float* init_orient, const int32_t* cand_phase, int32_t max_iter,
+                                     float* out_orient, float* out_score, int32_t* out_cand, void* stream) {
+  ScoreArgs a;
+  acom_status_t st = common_args(plan, peaks, &a);
+  if (st != ACOM_OK) return st;
+  if (n_cand < 1 || n_cand > 64) return fail(ACOM_E_INVALID, "n_cand must be in [1, 64]");
+  if (max_iter < 0 || max_iter > 100000) return fail(ACOM_E_INVALID, "max_iter must be in [0, 100000]");
+  if (a.n == 0) return ACOM_OK;
+  if (!init_orient || !out_orient) return fail(ACOM_E_INVALID, "acom_refine: null argument");
+  a.n_cand = n_cand;
+  a.max_iter = max_iter;
+  a.init = init_orient;
+  a.cand_phase = cand_phase;
+  a.out_orient = out_orient;
+  a.out_score = out_score;
+  a.out_cand = out_cand;
+  refine_kernel<<<a.n, kW, 0, (hipStream_t)stream>>>(a);
+  ACOM_HIP(hipGetLastError());
+  return ACOM_OK;
+}
