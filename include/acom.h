@@ -217,6 +217,20 @@ acom_status_t acom_refine(acom_plan_t plan, const acom_peaks_t* peaks, int32_t n
                           const float* init_orient, const int32_t* cand_phase, int32_t max_iter,
                           float* out_orient, float* out_score, int32_t* out_cand, void* stream);
 
+/* ------------------------------------------------------------ profile ---- */
+
+/* Kernel timing with HIP events recorded on the launch stream around every
+ * kernel that acom_match launches (measurement support; not thread-safe).
+ * acom_profile_begin creates `capacity` event pairs and starts recording;
+ * acom_profile_read synchronises the recorded events and returns, for kernel
+ * kind 0 (polar image + FFT), 1 (bound contraction) or 2 (exact pass), the
+ * summed duration in milliseconds and the number of launches; records beyond
+ * the capacity are dropped.  acom_profile_end stops recording and frees the
+ * events. */
+acom_status_t acom_profile_begin(int32_t capacity);
+acom_status_t acom_profile_read(int32_t kind, double* total_ms, int32_t* launches);
+acom_status_t acom_profile_end(void);
+
 /* ------------------------------------------------------------- errors ---- */
 const char* acom_status_string(acom_status_t s);
 const char* acom_last_error(void);

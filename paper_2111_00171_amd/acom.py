@@ -82,6 +82,11 @@ def lib():
             f = getattr(L, name)
             f.argtypes = args
             f.restype = st
+        L.acom_profile_begin.argtypes = [c_int32]
+        L.acom_profile_read.argtypes = [c_int32, P(c_double), P(c_int32)]
+        L.acom_profile_end.argtypes = []
+        for f in (L.acom_profile_begin, L.acom_profile_read, L.acom_profile_end):
+            f.restype = st
         L.acom_status_string.argtypes = [ctypes.c_int]
         L.acom_status_string.restype = ctypes.c_char_p
         L.acom_last_error.restype = ctypes.c_char_p
@@ -421,6 +426,28 @@ class Plan:
                                  _ptr(out, torch.float32, "out"), _ptr(S, torch.float32, "S"),
                                  _ptr(cand, torch.int32, "cand"), _stream(stream)), "acom_refine")
         return out, S, cand
+
+
+KERNEL_KINDS = {"polar": 0, "bound": 1, "exact": 2}
+
+
+def profile_begin(capacity=4096):
+    """Start recording HIP events around every kernel acom_match launches."""
+    _check(lib().acom_profile_begin(int(capacity)), "acom_profile_begin")
+
+
+def profile_read():
+    """{kernel: (total_ms, launches)} of the records so far (synchronises them)."""
+    out = {}
+    for name, k in KERNEL_KINDS.items():
+        t, n = c_double(), c_int32()
+        _check(lib().acom_profile_read(k, ctypes.byref(t), ctypes.byref(n)), "acom_profile_read")
+        out[name] = (t.value, n.value)
+    return out
+
+
+def profile_end():
+    _check(lib().acom_profile_end(), "acom_profile_end")
 
 
 class ContinuousScore(torch.autograd.Function):

@@ -21,6 +21,7 @@
 
 #include <climits>
 #include <cmath>
+#include <vector>
 
 #include "acom_internal.h"
 #include "fft_device.h"
@@ -747,6 +748,30 @@ __global__ void __launch_bounds__(kThreads) exact_kernel(ExactArgs a) {
 
 // ------------------------------------------------------------- host -------
 
+// ---------------------------------------------------------- profiling ----
+
+struct Profiler {
+  bool on = false;
+  std::vector<hipEvent_t> ev;   // 2 per record
+  std::vector<int> kind;
+  int used = 0;
+};
+Profiler g_prof;
+
+struct ProfScope {
+  int slot = -1;
+  hipStream_t s;
+  ProfScope(int kind, hipStream_t st) : s(st) {
+    if (!g_prof.on || g_prof.used >= (int)g_prof.kind.size()) return;
+    slot = g_prof.used++;
+    g_prof.kind[slot] = kind;
+    (void)hipEventRecord(g_prof.ev[2 * slot], s);
+  }
+  ~ProfScope() {
+    if (slot >= 0) (void)hipEventRecord(g_prof.ev[2 * slot + 1], s);
+  }
+};
+
 struct WsLayout {
   size_t xr = 0, xi = 0, lr = 0, li = 0, scale = 0, xn2 = 0, flags = 0, U = 0, total = 0;
   int Pc = 0, ntiles = 0;
@@ -846,6 +871,7 @@ acom_status_t launch_polar(const PlanDev& d, const PolarArgs& a, hipStream_t s) 
   acom_status_t st = ensure_lds(polar_kernel, polar_lds(d));
   if (st != ACOM_OK) return st;
   dim3 grid(a.np, d.Rp / kPolarCols);
+  ProfScope prof(0, s);
   polar_kernel<<<grid, kThreads, polar_lds(d), s>>>(a);
   ACOM_HIP(hipGetLastError());
   return ACOM_OK;
@@ -867,6 +893,7 @@ acom_status_t launch_bound(const PlanDev& d, int precision, const WsLayout& L, u
   b.np = np;
   b.Zvalid = Zvalid;
   dim3 grid((np + kTileP - 1) / kTileP, d.Zp / kTileZ);
+  ProfScope prof(1, s);
   if (precision == ACOM_FP32) {
     b.xr = ws + L.xr;
     b.xi = ws + L.xi;
@@ -994,7 +1021,10 @@ extern "C" acom_status_t acom_match(acom_plan_t plan, const acom_peaks_t* peaks,
     e.phi3 = out->phi3;
     e.orient = out->orient;
     e.n_eval = out->n_evaluated;
-    exact_kernel<<<np, kThreads, exact_lds(d), s>>>(e);
+    {
+      ProfScope prof(2, s);
+      exact_kernel<<<np, kThreads, exact_lds(d), s>>>(e);
+    }
     ACOM_HIP(hipGetLastError());
   }
   return ACOM_OK;
@@ -1093,4 +1123,42 @@ extern "C" acom_status_t acom_bound(acom_plan_t plan, const acom_peaks_t* peaks,
   set_ws(pa, L, ws, d);
   if ((st = launch_polar(d, pa, s)) != ACOM_OK) return st;
   return launch_bound(d, precision, L, ws, np, U, d.Z, d.Z, s);
+}
+
+extern "C" acom_status_t acom_profile_begin(int32_t capacity) {
+  if (capacity < 1 || capacity > (1 << 20)) return fail(ACOM_E_INVALID, "capacity must be in [1, 2^20]");
+  acom_profile_end();
+  g_prof.ev.assign(2 * (size_t)capacity, nullptr);
+  for (auto& e : g_prof.ev) ACOM_HIP(hipEventCreate(&e));
+  g_prof.kind.assign(capacity, -1);
+  g_prof.used = 0;
+  g_prof.on = true;
+  return ACOM_OK;
+}
+
+extern "C" acom_status_t acom_profile_read(int32_t kind, double* total_ms, int32_t* launches) {
+  if (!total_ms || !launches) return fail(ACOM_E_INVALID, "null argument");
+  double t = 0.0;
+  int n = 0;
+  for (int i = 0; i < g_prof.used; ++i) {
+    if (g_prof.kind[i] != kind) continue;
+    ACOM_HIP(hipEventSynchronize(g_prof.ev[2 * i + 1]));
+    float ms = 0.0f;
+    ACOM_HIP(hipEventElapsedTime(&ms, g_prof.ev[2 * i], g_prof.ev[2 * i + 1]));
+    t += ms;
+    ++n;
+  }
+  *total_ms = t;
+  *launches = n;
+  return ACOM_OK;
+}
+
+extern "C" acom_status_t acom_profile_end(void) {
+  for (auto e : g_prof.ev)
+    if (e) (void)hipEventDestroy(e);
+  g_prof.ev.clear();
+  g_prof.kind.clear();
+  g_prof.used = 0;
+  g_prof.on = false;
+  return ACOM_OK;
 }
