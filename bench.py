@@ -106,6 +106,9 @@ def main():
     ap.add_argument("--precisions", default="fp32,bf16,fp16")
     ap.add_argument("--chunk", type=int, default=16384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
+                    help="first copy this many GiB device-to-device (a plain copy kernel of known size, "
+                         "for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); patterns are independent, so a "
@@ -119,6 +122,13 @@ def main():
     from paper_2111_00171_amd import acom
 
     precs = [p for p in args.precisions.split(",") if p]
+    if args.calibrate_copy_gib > 0:
+        nb = int(args.calibrate_copy_gib * (1 << 30))
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     t0 = time.perf_counter()
     d = synth.make("scan")
     t_gen = time.perf_counter() - t0

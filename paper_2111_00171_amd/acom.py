@@ -82,6 +82,8 @@ def lib():
             f = getattr(L, name)
             f.argtypes = args
             f.restype = st
+        L.acom_set_tuning.argtypes = [c_int32, c_int32]
+        L.acom_set_tuning.restype = st
         L.acom_profile_begin.argtypes = [c_int32]
         L.acom_profile_read.argtypes = [c_int32, P(c_double), P(c_int32)]
         L.acom_profile_end.argtypes = []
@@ -429,6 +431,14 @@ class Plan:
 
 
 KERNEL_KINDS = {"polar": 0, "bound": 1, "exact": 2}
+TUNING_KEYS = {"bound_order": 0, "bound_kch16": 1, "exact_xcd": 2}
+
+
+def set_tuning(**kw):
+    """Launch-shape knobs (results do not depend on them): bound_order (0/1),
+    bound_kch16 (32/64/128), exact_xcd (0/1)."""
+    for k, v in kw.items():
+        _check(lib().acom_set_tuning(TUNING_KEYS[k], int(v)), "acom_set_tuning")
 
 
 def profile_begin(capacity=4096):

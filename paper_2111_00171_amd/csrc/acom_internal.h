@@ -22,6 +22,14 @@ acom_status_t hip_fail(hipError_t e, const char* what);
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Tile-major layout of a set of spectra [rows][Nk][Rp]: rows (patterns or
+// zones) grouped in tiles of 64, so that the 64 x Rp block a contraction tile
+// reads for one frequency k is contiguous and every row of a tile lies in one
+// Nk x 64 x Rp slab:  ((i / 64) * Nk + k) * 64 * Rp + (i % 64) * Rp + s.
+__host__ __device__ inline size_t tile_off(int i, int k, int s, int Nk, int Rp) {
+  return ((size_t)(i >> 6) * Nk + k) * (size_t)(64 * Rp) + (size_t)(i & 63) * Rp + s;
+}
+
 // Tile sizes of the contraction pass (patterns x zones per workgroup) and the
 // radial padding unit (one s-chunk of the MFMA K loop).
 constexpr int kTileP = 64;
@@ -58,11 +66,14 @@ struct PlanDev {
   // device arrays
   float* d_qs = nullptr;        // Rp (padding columns carry q = -1: no peak reaches them)
   float2* d_tw = nullptr;       // N twiddles (cos, sin)(2 pi m / N)
+  int32_t* d_rev = nullptr;     // N: digit-reversed position of index n (in-place FFT input order)
   float* d_M12 = nullptr;       // Z x 9 (row-major, float)
   int32_t* d_zone_phase = nullptr;
-  float* d_PR = nullptr;        // Nk x Zp x Rp  (FP32 real part of FFT{P})
-  float* d_PI = nullptr;        // Nk x Zp x Rp  (imaginary part)
-  uint16_t* d_PR16[3] = {nullptr, nullptr, nullptr};  // per precision (index = acom_precision_t)
+  float* d_PR = nullptr;        // FFT{P} real part, FP32, tile-major over Zp zones
+  float* d_PI = nullptr;        // imaginary part
+  float* d_PRz = nullptr;       // FP32 real part, zone-major [Z][Nk][Rp] (exact pass)
+  float* d_PIz = nullptr;
+  uint16_t* d_PR16[3] = {nullptr, nullptr, nullptr};  // tile-major 16-bit copies (index = acom_precision_t)
   uint16_t* d_PI16[3] = {nullptr, nullptr, nullptr};
   double* d_Pang = nullptr;     // optional FP64 angular plan Z x N x R
   // reflections for the continuous score (all phases concatenated)

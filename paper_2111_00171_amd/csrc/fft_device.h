@@ -1,21 +1,27 @@
-// Block-cooperative mixed-radix Stockham FFT in LDS (radices 2, 3, 4, 5).
+// Block-cooperative mixed-radix FFTs in LDS (radices 2, 3, 4, 5).
 //
 // The angular axis phi3 is transformed many sequences at a time: element a of
 // sequence q lives at buf[a * nseq + q], so consecutive threads touch
-// consecutive LDS words.  One stage of radix R with partial length Ns reads
-// R inputs spaced N/R apart, multiplies by w^(r * (j mod Ns) * N / (Ns R)),
-// applies an R-point DFT and writes R outputs spaced Ns apart at
-// (j / Ns) Ns R + j mod Ns; the stages leave the result in natural order.
-// Twiddles come from a table tw[m] = (cos, sin)(2 pi m / N).
+// consecutive LDS words.  Twiddles come from a table tw[m] = (cos, sin)(2 pi m / N).
+//
+// block_fft_inplace: in-place decimation in time.  With N = R_1 R_2 ... R_m, the
+// transform of length L at level i splits into R_i transforms of length
+// S = L / R_i over the inputs r + R_i n'' (r < R_i), stored contiguously, and
+// combines them: X[k'' + S r'] = sum_r w_R^(r r') w_L^(r k'') Y_r[k''].  Levels
+// run from the innermost (shortest) outwards, every butterfly reading and
+// writing the same R positions, so one buffer suffices.  The input must be
+// stored in digit-reversed order, x[n] at rev[n] with
+// rev[n] = sum_i (N / (R_1 .. R_i)) * digit_i(n), digit_i the mixed-radix digits
+// of n (least significant first); the output is in natural order.
+//
+// block_fft (Stockham, two buffers) keeps natural order on both sides.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 namespace acom {
 
-struct cf {
-  float x, y;
-};
+constexpr int kMaxRadicesDev = 12;
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -66,28 +72,95 @@ __device__ __forceinline__ void dft_small(float2* v, int R, float sg) {
   }
 }
 
+// q = n / d and r = n % d for 0 <= n < 2^20, 0 < d < 2^12, using a float
+// reciprocal inv_d = 1/d and one correction step (exact in that range).
+__device__ __forceinline__ int fdivmod(int n, int d, float inv_d, int* r) {
+  int q = (int)((float)n * inv_d);
+  int rem = n - q * d;
+  if (rem < 0) {
+    --q;
+    rem += d;
+  } else if (rem >= d) {
+    ++q;
+    rem -= d;
+  }
+  *r = rem;
+  return q;
+}
+
+// In-place transform of `nseq` interleaved sequences of length N (input in
+// digit-reversed order, output natural).  sg = +1 forward, -1 inverse
+// (unnormalised).  All threads of the block must call it.
+__device__ inline void block_fft_inplace(float2* buf, const float2* tw, int N, int nseq, const int* radix,
+                                         int nrad, float sg) {
+  int Ls[kMaxRadicesDev];
+  int L = N;
+  for (int i = 0; i < nrad; ++i) {
+    Ls[i] = L;
+    L /= radix[i];
+  }
+  const float inv_nseq = 1.0f / (float)nseq;
+  for (int i = nrad - 1; i >= 0; --i) {
+    const int R = radix[i];
+    const int Li = Ls[i];
+    const int S = Li / R;
+    const int step = N / Li;
+    const int items = (N / R) * nseq;
+    const float inv_s = 1.0f / (float)S;
+    for (int it = threadIdx.x; it < items; it += blockDim.x) {
+      int q;
+      const int t = fdivmod(it, nseq, inv_nseq, &q);
+      int kk;
+      const int b = fdivmod(t, S, inv_s, &kk);
+      const int base = b * Li + kk;
+      float2 v[5];
+#pragma unroll
+      for (int r = 0; r < 5; ++r) {
+        if (r < R) {
+          float2 x = buf[(base + S * r) * nseq + q];
+          if (r > 0 && kk > 0) {
+            float2 w = tw[step * r * kk];  // step * r * kk < N
+            w.y *= -sg;                    // forward uses conj(w)
+            x = cmul(x, w);
+          }
+          v[r] = x;
+        }
+      }
+      dft_small(v, R, sg);
+#pragma unroll
+      for (int r = 0; r < 5; ++r)
+        if (r < R) buf[(base + S * r) * nseq + q] = v[r];
+    }
+    __syncthreads();
+  }
+}
+
 // Transform `nseq` interleaved sequences of length N held in `a`; `b` is the
 // ping-pong buffer.  sg = +1 forward, -1 inverse (unnormalised).  Returns the
 // buffer holding the result.  All threads of the block must call it.
+// The twiddle exponent r * (j mod Ns) * N / (Ns R) is always below N.
 __device__ inline float2* block_fft(float2* a, float2* b, const float2* tw, int N, int nseq,
                                    const int* radix, int nrad, float sg) {
   int Ns = 1;
+  const float inv_nseq = 1.0f / (float)nseq;
   for (int st = 0; st < nrad; ++st) {
     const int R = radix[st];
     const int NR = N / R;
     const int step = N / (Ns * R);
     const int items = NR * nseq;
+    const float inv_ns = 1.0f / (float)Ns;
     for (int it = threadIdx.x; it < items; it += blockDim.x) {
-      const int q = it % nseq;
-      const int j = it / nseq;
-      const int jm = j % Ns;
+      int q;
+      const int j = fdivmod(it, nseq, inv_nseq, &q);
+      int jm;
+      const int jq = fdivmod(j, Ns, inv_ns, &jm);
       float2 v[5];
 #pragma unroll
       for (int r = 0; r < 5; ++r) {
         if (r < R) {
           float2 x = a[(j + r * NR) * nseq + q];
           if (r > 0 && jm > 0) {
-            float2 w = tw[(r * jm * step) % N];
+            float2 w = tw[r * jm * step];
             w.y *= -sg;  // forward uses conj(w)
             x = cmul(x, w);
           }
@@ -95,7 +168,7 @@ __device__ inline float2* block_fft(float2* a, float2* b, const float2* tw, int 
         }
       }
       dft_small(v, R, sg);
-      const int d0 = (j / Ns) * Ns * R + jm;
+      const int d0 = jq * Ns * R + jm;
 #pragma unroll
       for (int r = 0; r < 5; ++r)
         if (r < R) b[(d0 + r * Ns) * nseq + q] = v[r];

@@ -21,6 +21,7 @@
 
 #include <climits>
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "acom_internal.h"
@@ -30,7 +31,7 @@ namespace acom {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kPolarCols = 32;   // radial columns per polar block (16 complex sequences)
+constexpr int kPolarCols = 16;   // radial columns per polar block (8 complex sequences)
 constexpr int kPeakCache = 256;
 constexpr int kBatch = 8;        // zones evaluated together by the exact pass
 constexpr int kDefaultChunk = 16384;
@@ -66,13 +67,27 @@ __device__ __forceinline__ uint16_t to_f16_bits(float v) {
   return *reinterpret_cast<uint16_t*>(&h);
 }
 
+// XCD-aware block order: the hardware deals workgroup b to XCD b % 8, so
+// logical work item w = (b % 8) * per + b / 8 gives every XCD a contiguous range
+// of logical items (neighbouring tiles then share that XCD's L2).  The grid has
+// 8 * per blocks; blocks with w >= total exit at once.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_item(int per) { return (blockIdx.x % kXcds) * per + blockIdx.x / kXcds; }
+inline int xcd_blocks(int total, int* per) {
+  *per = (total + kXcds - 1) / kXcds;
+  return *per * kXcds;
+}
+
 // ------------------------------------------------------------ 1. polar ----
+
+constexpr int kPolarParts = kThreads / kPolarCols;  // angular partitions of the splat
 
 struct PolarArgs {
   int N, R, Rp, Nk, nrad;
   int rad[kMaxRadices];
   const float* qs;
   const float2* tw;
+  const int* rev;
   float delta, rk, sigma, gamma, omega;
   int kernel;
   const int64_t* offsets;
@@ -80,8 +95,10 @@ struct PolarArgs {
   int64_t total_peaks;
   int64_t p_begin;
   int np;
-  float *xr, *xi;          // FFT{X} at k * ldk + p * ldp + s (p local), columns s < out_cols
-  size_t ldk;
+  // FFT{X}[p][k][s] at (p / 64) * ld_tile + k * ldk + (p % 64) * ldp + s (p local),
+  // columns s < out_cols
+  float *xr, *xi;
+  size_t ld_tile, ldk;
   int ldp, out_cols;
   uint16_t *lr, *li;       // low-precision copies (same layout) or null
   int lowp;                // 0 none, ACOM_BF16, ACOM_FP16
@@ -92,12 +109,17 @@ struct PolarArgs {
   int do_fft;
 };
 
+// Block (pattern, tile of kPolarCols radial columns).  Splat: thread
+// (column c, part t) owns the angular bins [t L, (t + 1) L) of column c and adds
+// every peak's kernel there in peak order (no atomics, deterministic).  Then
+// the FFT along phi3 of the columns packed in pairs as complex sequences.
 __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  float2* b0 = reinterpret_cast<float2*>(smem_raw);
-  float2* b1 = b0 + a.N * (kPolarCols / 2);
-  float2* tw = b1 + a.N * (kPolarCols / 2);
-  double* pg = reinterpret_cast<double*>(tw + a.N);
+  constexpr int NS = kPolarCols / 2;
+  float2* b0 = reinterpret_cast<float2*>(smem_raw);   // [rev(a)][NS] complex: columns packed in pairs
+  float2* tw = b0 + a.N * NS;
+  int* rev = reinterpret_cast<int*>(tw + a.N);
+  double* pg = reinterpret_cast<double*>(rev + a.N + (a.N & 1));
   float* pq = reinterpret_cast<float*>(pg + kPeakCache);
   float* pw = pq + kPeakCache;
   __shared__ int s_bad;
@@ -112,13 +134,22 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
   int64_t m0 = a.offsets[P], m1 = a.offsets[P + 1];
   const bool bad_range = m0 < 0 || m1 < m0 || m1 > a.total_peaks;
   if (bad_range) m0 = m1 = 0;  // malformed CSR row: a data error, nothing is read
-  float* X = reinterpret_cast<float*>(b0);  // [a][kPolarCols]
+  float* X = reinterpret_cast<float*>(b0);  // X(phi_a, column) at [rev(a)][kPolarCols]
   for (int i = tid; i < a.N * kPolarCols; i += kThreads) X[i] = 0.0f;
-  for (int i = tid; i < a.N; i += kThreads) tw[i] = a.tw[i];
+  for (int i = tid; i < a.N; i += kThreads) {
+    tw[i] = a.tw[i];
+    rev[i] = a.rev[i];
+  }
   if (tid == 0) s_bad = bad_range ? 1 : 0;
   __syncthreads();
 
   const double dphi = 6.283185307179586476925286766559 / a.N;
+  const double inv_dphi = a.N / 6.283185307179586476925286766559;
+  const int c = tid % kPolarCols, part = tid / kPolarCols;
+  const int L = (a.N + kPolarParts - 1) / kPolarParts;
+  const int lo = part * L, hi = min(a.N, lo + L);
+  const int col = col0 + c;
+  const float qs = col < a.R ? a.qs[col] : -1.0f;
   double wsum = 0.0;
   for (int64_t c0 = m0; c0 < m1; c0 += kPeakCache) {
     const int cnt = (int)min((int64_t)kPeakCache, m1 - c0);
@@ -134,9 +165,7 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
       wsum += w;
     }
     __syncthreads();
-    const int col = col0 + tid;
-    if (tid < kPolarCols && col < a.R) {
-      const float qs = a.qs[col];
+    if (qs >= 0.0f && lo < hi) {
       for (int j = 0; j < cnt; ++j) {
         const float dq = pq[j] - qs;
         const float w = pw[j];
@@ -147,20 +176,23 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
           const float h = a.rk / (qs * (float)dphi) + 1.0f;
           hw = h > (float)a.N ? a.N : (int)ceilf(h);
         }
+        int wlo, whi;  // window [wlo, whi) in unwrapped bin units
         if (2 * hw + 1 >= a.N) {
-          for (int ai = 0; ai < a.N; ++ai) {
-            const float dp = (float)wrap_pi64(ai * dphi - g) * qs;
-            const float k = kern32(sqrtf(dq * dq + dp * dp), a.delta, a.sigma, a.kernel);
-            if (k > 0.0f) X[ai * kPolarCols + tid] += w * k;
-          }
+          wlo = 0;
+          whi = a.N;
         } else {
-          const int ac = (int)floor(g / dphi + 0.5);
-          for (int jj = -hw; jj <= hw; ++jj) {
-            int ai = (ac + jj) % a.N;
-            if (ai < 0) ai += a.N;
+          const int ac = (int)floor(g * inv_dphi + 0.5);
+          wlo = ac - hw;
+          whi = ac + hw + 1;
+        }
+        // the window has < N bins: each bin of [lo, hi) is met by at most one shift
+        for (int sh = -a.N; sh <= a.N; sh += a.N) {
+          const int u0 = max(wlo, lo + sh), u1 = min(whi, hi + sh);
+          for (int u = u0; u < u1; ++u) {
+            const int ai = u - sh;
             const float dp = (float)wrap_pi64(ai * dphi - g) * qs;
             const float k = kern32(sqrtf(dq * dq + dp * dp), a.delta, a.sigma, a.kernel);
-            if (k > 0.0f) X[ai * kPolarCols + tid] += w * k;
+            if (k > 0.0f) X[rev[ai] * kPolarCols + c] += w * k;
           }
         }
       }
@@ -201,24 +233,25 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
   }
   if (a.Ximg) {
     for (int i = tid; i < a.N * kPolarCols; i += kThreads) {
-      const int ai = i / kPolarCols, c = i % kPolarCols;
-      if (col0 + c < a.R) a.Ximg[((size_t)p * a.N + ai) * a.R + col0 + c] = bad ? 0.0f : X[i];
+      const int ai = i / kPolarCols, cc = i % kPolarCols;
+      if (col0 + cc < a.R) a.Ximg[((size_t)p * a.N + ai) * a.R + col0 + cc] = bad ? 0.0f : X[rev[ai] * kPolarCols + cc];
     }
   }
   if (!a.do_fft) return;
   __syncthreads();
-  constexpr int NS = kPolarCols / 2;
-  const float2* F = block_fft(b0, b1, tw, a.N, NS, a.rad, a.nrad, 1.0f);
+  block_fft_inplace(b0, tw, a.N, NS, a.rad, a.nrad, 1.0f);
+  const float2* F = b0;
   // unpack: column 2q = (Z_k + conj Z_{N-k}) / 2, column 2q+1 = -i (Z_k - conj Z_{N-k}) / 2
+  const size_t pbase = (size_t)(p >> 6) * a.ld_tile + (size_t)(p & 63) * a.ldp;
   for (int it = tid; it < a.Nk * NS; it += kThreads) {
     const int k = it / NS, q = it % NS;
     const float2 Zk = F[k * NS + q];
-    const float2 Zn = F[((a.N - k) % a.N) * NS + q];
+    const float2 Zn = F[(k == 0 ? 0 : a.N - k) * NS + q];
     float2 E = make_float2(0.5f * (Zk.x + Zn.x), 0.5f * (Zk.y - Zn.y));
     float2 O = make_float2(0.5f * (Zk.y + Zn.y), -0.5f * (Zk.x - Zn.x));
     if (bad) E = O = make_float2(0.0f, 0.0f);
     const int s0 = col0 + 2 * q;
-    const size_t o = (size_t)k * a.ldk + (size_t)p * a.ldp + s0;
+    const size_t o = pbase + (size_t)k * a.ldk + s0;
     if (s0 < a.out_cols) {
       a.xr[o] = E.x;
       a.xi[o] = E.y;
@@ -245,60 +278,64 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
 
 struct BoundArgs {
   int Nk, Rp, N;
-  const void *xr, *xi;     // [k][p][s]
-  size_t x_ldk;
-  int x_ldp;
-  const void *pr, *pi;     // [k][z][s]
-  size_t p_ldk;
-  int p_ldz;
-  const float* scale;      // per local pattern
+  int nP, nZ, per;          // pattern tiles, zone tiles, XCD items per XCD
+  int order;                // block order (see bound_kernel)
+  const void *xr, *xi;      // tile-major over patterns (local to the chunk)
+  const void *pr, *pi;      // tile-major over zones
+  const float* scale;       // per local pattern
   float* U;
   int ldU, np, Zvalid;
 };
 
-template <int KIND>  // 0: FP32 operands, 1: BF16, 2: FP16
-struct BoundTraits;
-
+// Operand element type per kind (0: FP32, 1: BF16, 2: FP16) and LDS row padding.
+template <int KIND>
+struct BoundTraits {
+  typedef uint16_t T;
+  static constexpr int PAD = 8;
+};
 template <>
 struct BoundTraits<0> {
   typedef float T;
-  static constexpr int kPad = 4;  // row stride 36 floats
-};
-template <>
-struct BoundTraits<1> {
-  typedef uint16_t T;
-  static constexpr int kPad = 8;  // row stride 40 elements
-};
-template <>
-struct BoundTraits<2> {
-  typedef uint16_t T;
-  static constexpr int kPad = 8;
+  static constexpr int PAD = 4;
 };
 
 // One workgroup: 64 patterns x 64 zones, 4 waves of 32 x 32 (2 x 2 MFMA blocks
-// of 16 x 16).  For each frequency k the K loop runs over s in chunks of 32
-// staged through LDS; four accumulators per block give the real products
-// A = Xr Pr, B = Xi Pi, C = Xi Pr, D = Xr Pi, so G = (A + B) + i (C - D) and
-// G_mirror = (A - B) - i (C + D).  Lanes of a quarter-wave (l / 16) take the
-// contiguous s-range 8 (l / 16) .. +7 of a chunk for both operands, which is
-// the same permutation of the contraction index on both sides.
-template <int KIND>
+// of 16 x 16).  For each frequency k the K loop runs over s in steps of KCH
+// radii (KCH divides Rp) staged through LDS; four accumulators per block
+// give the real products A = Xr Pr, B = Xi Pi, C = Xi Pr, D = Xr Pi, so
+// G = (A + B) + i (C - D) and G_mirror = (A - B) - i (C + D).  Lanes of a
+// quarter-wave (l / 16) take the contiguous s-range 8 (l / 16) .. +7 of every
+// 32 radii for both operands: the same permutation of the contraction index on
+// both sides.
+template <int KIND, int KCH>
 __global__ void __launch_bounds__(kThreads) bound_kernel(BoundArgs a) {
+  static_assert(KIND != 0 || KCH == 32, "FP32 operands use 32-radius steps");
   typedef typename BoundTraits<KIND>::T T;
-  constexpr int LD = kSChunk + BoundTraits<KIND>::kPad;
+  constexpr int LD = KCH + BoundTraits<KIND>::PAD;
+  constexpr int VEC = 16 / sizeof(T);        // elements per 16-byte vector
+  constexpr int PER_ROW = KCH / VEC;         // vectors per row per step
+  constexpr int NV = kTileP * PER_ROW / kThreads;  // vectors per thread per array
   __shared__ __align__(16) T sXr[kTileP * LD];
   __shared__ __align__(16) T sXi[kTileP * LD];
   __shared__ __align__(16) T sPr[kTileZ * LD];
   __shared__ __align__(16) T sPi[kTileZ * LD];
 
+  int tp, tz;
+  if (a.order == 0) {  // pattern tiles fastest: concurrent blocks share one zone tile
+    tp = blockIdx.x % a.nP;
+    tz = blockIdx.x / a.nP;
+  } else {             // XCD-grouped, zone tiles fastest: concurrent blocks share pattern tiles
+    const int w = xcd_item(a.per);
+    if (w >= a.nP * a.nZ) return;
+    tp = w / a.nZ;
+    tz = w % a.nZ;
+  }
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
-  const int p0 = blockIdx.x * kTileP;
-  const int z0 = blockIdx.y * kTileZ;
   const int li = lane & 15;  // row within a 16-block
-  const int lg = lane >> 4;  // quarter-wave: s sub-range / output row group
+  const int lg = lane >> 4;  // quarter-wave
 
   float U[2][2][4], Um[2][2][4];
 #pragma unroll
@@ -308,77 +345,79 @@ __global__ void __launch_bounds__(kThreads) bound_kernel(BoundArgs a) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) U[i][j][r] = Um[i][j][r] = 0.0f;
 
-  const T* gxr = reinterpret_cast<const T*>(a.xr);
-  const T* gxi = reinterpret_cast<const T*>(a.xi);
-  const T* gpr = reinterpret_cast<const T*>(a.pr);
-  const T* gpi = reinterpret_cast<const T*>(a.pi);
+  const size_t slab = (size_t)a.Nk * 64 * a.Rp;
+  const T* gxr = reinterpret_cast<const T*>(a.xr) + (size_t)tp * slab;
+  const T* gxi = reinterpret_cast<const T*>(a.xi) + (size_t)tp * slab;
+  const T* gpr = reinterpret_cast<const T*>(a.pr) + (size_t)tz * slab;
+  const T* gpi = reinterpret_cast<const T*>(a.pi) + (size_t)tz * slab;
+  const int steps_per_k = a.Rp / KCH;
+  const int nsteps = a.Nk * steps_per_k;
 
-  for (int k = 0; k < a.Nk; ++k) {
-    f32x4 acc[2][2][4];
+  f32x4 acc[2][2][4];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < 2; ++j)
 #pragma unroll
-        for (int t = 0; t < 4; ++t) acc[i][j][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+      for (int t = 0; t < 4; ++t) acc[i][j][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 
-    const T* xrk = gxr + (size_t)k * a.x_ldk + (size_t)p0 * a.x_ldp;
-    const T* xik = gxi + (size_t)k * a.x_ldk + (size_t)p0 * a.x_ldp;
-    const T* prk = gpr + (size_t)k * a.p_ldk + (size_t)z0 * a.p_ldz;
-    const T* pik = gpi + (size_t)k * a.p_ldk + (size_t)z0 * a.p_ldz;
-
-    for (int s0 = 0; s0 < a.Rp; s0 += kSChunk) {
-      // stage 64 rows x 32 elements of each operand (16-byte vectors)
-      constexpr int VEC = 16 / sizeof(T);           // elements per 16 bytes
-      constexpr int PER_ROW = kSChunk / VEC;        // vectors per row
-      for (int v = tid; v < kTileP * PER_ROW; v += kThreads) {
-        const int row = v / PER_ROW, cv = v % PER_ROW;
-        const size_t gx = (size_t)row * a.x_ldp + s0 + cv * VEC;
-        const size_t gp = (size_t)row * a.p_ldz + s0 + cv * VEC;
+  for (int stp = 0; stp < nsteps; ++stp) {
+    {  // stage KCH radii of frequency k: 64 rows of each operand, 16-byte vectors
+      const int k = stp / steps_per_k;
+      const int s0 = (stp - k * steps_per_k) * KCH;
+      const size_t base = (size_t)k * 64 * a.Rp + s0;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const int idx = tid + v * kThreads;
+        const int row = idx / PER_ROW, cv = idx % PER_ROW;
+        const size_t g = base + (size_t)row * a.Rp + cv * VEC;
         const int l = row * LD + cv * VEC;
-        *reinterpret_cast<uint4*>(&sXr[l]) = *reinterpret_cast<const uint4*>(xrk + gx);
-        *reinterpret_cast<uint4*>(&sXi[l]) = *reinterpret_cast<const uint4*>(xik + gx);
-        *reinterpret_cast<uint4*>(&sPr[l]) = *reinterpret_cast<const uint4*>(prk + gp);
-        *reinterpret_cast<uint4*>(&sPi[l]) = *reinterpret_cast<const uint4*>(pik + gp);
+        *reinterpret_cast<uint4*>(&sXr[l]) = *reinterpret_cast<const uint4*>(gxr + g);
+        *reinterpret_cast<uint4*>(&sXi[l]) = *reinterpret_cast<const uint4*>(gxi + g);
+        *reinterpret_cast<uint4*>(&sPr[l]) = *reinterpret_cast<const uint4*>(gpr + g);
+        *reinterpret_cast<uint4*>(&sPi[l]) = *reinterpret_cast<const uint4*>(gpi + g);
       }
-      __syncthreads();
-      if constexpr (KIND == 0) {
-        float fxr[2][8], fxi[2][8], fpr[2][8], fpi[2][8];
+    }
+    __syncthreads();
+    if constexpr (KIND == 0) {
+      float fxr[2][8], fxi[2][8], fpr[2][8], fpi[2][8];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          const int rx = (wr * 32 + i * 16 + li) * LD + lg * 8;
-          const int rp = (wc * 32 + i * 16 + li) * LD + lg * 8;
+      for (int i = 0; i < 2; ++i) {
+        const int rx = (wr * 32 + i * 16 + li) * LD + lg * 8;
+        const int rp = (wc * 32 + i * 16 + li) * LD + lg * 8;
 #pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            float4 t;
-            t = *reinterpret_cast<const float4*>(&sXr[rx + 4 * h]);
-            fxr[i][4 * h] = t.x; fxr[i][4 * h + 1] = t.y; fxr[i][4 * h + 2] = t.z; fxr[i][4 * h + 3] = t.w;
-            t = *reinterpret_cast<const float4*>(&sXi[rx + 4 * h]);
-            fxi[i][4 * h] = t.x; fxi[i][4 * h + 1] = t.y; fxi[i][4 * h + 2] = t.z; fxi[i][4 * h + 3] = t.w;
-            t = *reinterpret_cast<const float4*>(&sPr[rp + 4 * h]);
-            fpr[i][4 * h] = t.x; fpr[i][4 * h + 1] = t.y; fpr[i][4 * h + 2] = t.z; fpr[i][4 * h + 3] = t.w;
-            t = *reinterpret_cast<const float4*>(&sPi[rp + 4 * h]);
-            fpi[i][4 * h] = t.x; fpi[i][4 * h + 1] = t.y; fpi[i][4 * h + 2] = t.z; fpi[i][4 * h + 3] = t.w;
-          }
+        for (int h = 0; h < 2; ++h) {
+          float4 t;
+          t = *reinterpret_cast<const float4*>(&sXr[rx + 4 * h]);
+          fxr[i][4 * h] = t.x; fxr[i][4 * h + 1] = t.y; fxr[i][4 * h + 2] = t.z; fxr[i][4 * h + 3] = t.w;
+          t = *reinterpret_cast<const float4*>(&sXi[rx + 4 * h]);
+          fxi[i][4 * h] = t.x; fxi[i][4 * h + 1] = t.y; fxi[i][4 * h + 2] = t.z; fxi[i][4 * h + 3] = t.w;
+          t = *reinterpret_cast<const float4*>(&sPr[rp + 4 * h]);
+          fpr[i][4 * h] = t.x; fpr[i][4 * h + 1] = t.y; fpr[i][4 * h + 2] = t.z; fpr[i][4 * h + 3] = t.w;
+          t = *reinterpret_cast<const float4*>(&sPi[rp + 4 * h]);
+          fpi[i][4 * h] = t.x; fpi[i][4 * h + 1] = t.y; fpi[i][4 * h + 2] = t.z; fpi[i][4 * h + 3] = t.w;
         }
+      }
 #pragma unroll
-        for (int t = 0; t < 8; ++t)
+      for (int t = 0; t < 8; ++t)
 #pragma unroll
-          for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-              acc[i][j][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxr[i][t], fpr[j][t], acc[i][j][0], 0, 0, 0);
-              acc[i][j][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxi[i][t], fpi[j][t], acc[i][j][1], 0, 0, 0);
-              acc[i][j][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxi[i][t], fpr[j][t], acc[i][j][2], 0, 0, 0);
-              acc[i][j][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxr[i][t], fpi[j][t], acc[i][j][3], 0, 0, 0);
-            }
-      } else {
-        typedef typename std::conditional<KIND == 1, bf16x8, f16x8>::type V8;
+          for (int j = 0; j < 2; ++j) {
+            acc[i][j][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxr[i][t], fpr[j][t], acc[i][j][0], 0, 0, 0);
+            acc[i][j][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxi[i][t], fpi[j][t], acc[i][j][1], 0, 0, 0);
+            acc[i][j][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxi[i][t], fpr[j][t], acc[i][j][2], 0, 0, 0);
+            acc[i][j][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxr[i][t], fpi[j][t], acc[i][j][3], 0, 0, 0);
+          }
+    } else {
+      typedef typename std::conditional<KIND == 1, bf16x8, f16x8>::type V8;
+#pragma unroll
+      for (int sub = 0; sub < KCH / 32; ++sub) {
         V8 fxr[2], fxi[2], fpr[2], fpi[2];
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
-          const int rx = (wr * 32 + i * 16 + li) * LD + lg * 8;
-          const int rp = (wc * 32 + i * 16 + li) * LD + lg * 8;
+          const int rx = (wr * 32 + i * 16 + li) * LD + sub * 32 + lg * 8;
+          const int rp = (wc * 32 + i * 16 + li) * LD + sub * 32 + lg * 8;
           fxr[i] = *reinterpret_cast<const V8*>(&sXr[rx]);
           fxi[i] = *reinterpret_cast<const V8*>(&sXi[rx]);
           fpr[i] = *reinterpret_cast<const V8*>(&sPr[rp]);
@@ -401,32 +440,38 @@ __global__ void __launch_bounds__(kThreads) bound_kernel(BoundArgs a) {
             }
           }
       }
-      __syncthreads();
     }
-    const float wk = (k == 0 || 2 * k == a.N) ? 1.0f : 2.0f;
+    const int k = stp / steps_per_k;
+    if (stp - k * steps_per_k == steps_per_k - 1) {  // last radii of frequency k
+      const float wk = (k == 0 || 2 * k == a.N) ? 1.0f : 2.0f;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < 2; ++j) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const float A = acc[i][j][0][r], B = acc[i][j][1][r], C = acc[i][j][2][r], D = acc[i][j][3][r];
-          const float re = A + B, im = C - D, rm = A - B, imm = C + D;
-          U[i][j][r] += wk * sqrtf(re * re + im * im);
-          Um[i][j][r] += wk * sqrtf(rm * rm + imm * imm);
+          for (int r = 0; r < 4; ++r) {
+            const float A = acc[i][j][0][r], B = acc[i][j][1][r], C = acc[i][j][2][r], D = acc[i][j][3][r];
+            const float re = A + B, im = C - D, rm = A - B, imm = C + D;
+            U[i][j][r] += wk * sqrtf(re * re + im * im);
+            Um[i][j][r] += wk * sqrtf(rm * rm + imm * imm);
+          }
+#pragma unroll
+          for (int t = 0; t < 4; ++t) acc[i][j][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
         }
+    }
+    __syncthreads();
   }
   const float invN = 1.0f / (float)a.N;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int p = p0 + wr * 32 + i * 16 + lg * 4 + r;
+      const int p = tp * kTileP + wr * 32 + i * 16 + lg * 4 + r;
       if (p >= a.np) continue;
       const float inv = invN / a.scale[p];
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        const int z = z0 + wc * 32 + j * 16 + li;
+        const int z = tz * kTileZ + wc * 32 + j * 16 + li;
         if (z < a.Zvalid) a.U[(size_t)p * a.ldU + z] = fmaxf(U[i][j][r], Um[i][j][r]) * inv;
       }
     }
@@ -438,12 +483,9 @@ struct ExactArgs {
   int N, Nk, Rp, Z, nrad;
   int rad[kMaxRadices];
   const float2* tw;
-  const float *xr, *xi;
-  size_t x_ldk;
-  int x_ldp;
-  const float *pr, *pi;
-  size_t p_ldk;
-  int p_ldz;
+  const int* rev;
+  const float *xr, *xi;     // tile-major over the chunk's patterns (FP32)
+  const float *pr, *pi;     // zone-major [Z][Nk][Rp] (FP32)
   const float* U;
   int ldU;
   const float* xnorm2;
@@ -452,7 +494,7 @@ struct ExactArgs {
   const float* M12;
   const int* zone_phase;
   float eps_rel, eps_abs;
-  int top_k;
+  int top_k, per;
   int64_t p_begin;
   int np;
   int *zone, *phase, *bin, *mirror, *n_eval;
@@ -461,38 +503,34 @@ struct ExactArgs {
 };
 
 // H for nb zones of local pattern p: H_k = G_k + i G_mirror,k (k <= N/2) and
-// H_{N-k} = conj(G_k) + i conj(G_mirror,k), stored as H[n * nb + b].
-__device__ void contract_exact(const ExactArgs& a, int p, const int* bz, int nb, float2* H) {
-  for (int k = threadIdx.x; k < a.Nk; k += blockDim.x) {
-    float acc[kBatch][4];
-#pragma unroll
-    for (int b = 0; b < kBatch; ++b) acc[b][0] = acc[b][1] = acc[b][2] = acc[b][3] = 0.0f;
-    const float* xr = a.xr + (size_t)k * a.x_ldk + (size_t)p * a.x_ldp;
-    const float* xi = a.xi + (size_t)k * a.x_ldk + (size_t)p * a.x_ldp;
+// H_{N-k} = conj(G_k) + i conj(G_mirror,k), stored in digit-reversed order for
+// the in-place inverse FFT: H[rev(n) * nb + b].  Work items are (frequency k,
+// zone b) pairs.
+__device__ void contract_exact(const ExactArgs& a, int p, const int* bz, int nb, const int* rev, float2* H) {
+  const size_t xbase = tile_off(p, 0, 0, a.Nk, a.Rp);
+  const size_t xk = (size_t)64 * a.Rp;
+  const float inv_nb = 1.0f / (float)nb;
+  for (int it = threadIdx.x; it < a.Nk * nb; it += blockDim.x) {
+    int b;
+    const int k = fdivmod(it, nb, inv_nb, &b);
+    const float* xr = a.xr + xbase + (size_t)k * xk;
+    const float* xi = a.xi + xbase + (size_t)k * xk;
+    const size_t po = ((size_t)bz[b] * a.Nk + k) * a.Rp;
+    const float* pr = a.pr + po;
+    const float* pi = a.pi + po;
+    float A = 0.0f, B = 0.0f, C = 0.0f, D = 0.0f;
     for (int s = 0; s < a.Rp; s += 4) {
       const float4 vr = *reinterpret_cast<const float4*>(xr + s);
       const float4 vi = *reinterpret_cast<const float4*>(xi + s);
-#pragma unroll
-      for (int b = 0; b < kBatch; ++b) {
-        if (b < nb) {
-          const size_t o = (size_t)k * a.p_ldk + (size_t)bz[b] * a.p_ldz + s;
-          const float4 wr = *reinterpret_cast<const float4*>(a.pr + o);
-          const float4 wi = *reinterpret_cast<const float4*>(a.pi + o);
-          acc[b][0] += vr.x * wr.x + vr.y * wr.y + vr.z * wr.z + vr.w * wr.w;
-          acc[b][1] += vi.x * wi.x + vi.y * wi.y + vi.z * wi.z + vi.w * wi.w;
-          acc[b][2] += vi.x * wr.x + vi.y * wr.y + vi.z * wr.z + vi.w * wr.w;
-          acc[b][3] += vr.x * wi.x + vr.y * wi.y + vr.z * wi.z + vr.w * wi.w;
-        }
-      }
+      const float4 wr = *reinterpret_cast<const float4*>(pr + s);
+      const float4 wi = *reinterpret_cast<const float4*>(pi + s);
+      A += vr.x * wr.x + vr.y * wr.y + vr.z * wr.z + vr.w * wr.w;
+      B += vi.x * wi.x + vi.y * wi.y + vi.z * wi.z + vi.w * wi.w;
+      C += vi.x * wr.x + vi.y * wr.y + vi.z * wr.z + vi.w * wr.w;
+      D += vr.x * wi.x + vr.y * wi.y + vr.z * wi.z + vr.w * wi.w;
     }
-#pragma unroll
-    for (int b = 0; b < kBatch; ++b) {
-      if (b < nb) {
-        const float A = acc[b][0], B = acc[b][1], C = acc[b][2], D = acc[b][3];
-        H[k * nb + b] = make_float2((A + B) + (C + D), (C - D) + (A - B));
-        if (k > 0 && 2 * k < a.N) H[(a.N - k) * nb + b] = make_float2((A + B) - (C + D), (A - B) - (C - D));
-      }
-    }
+    H[rev[k] * nb + b] = make_float2((A + B) + (C + D), (C - D) + (A - B));
+    if (k > 0 && 2 * k < a.N) H[rev[a.N - k] * nb + b] = make_float2((A + B) - (C + D), (A - B) - (C - D));
   }
 }
 
@@ -543,36 +581,39 @@ __device__ __forceinline__ float parabolic(float cm1, float c0, float cp1) {
 __global__ void __launch_bounds__(kThreads) exact_kernel(ExactArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   float2* H0 = reinterpret_cast<float2*>(smem_raw);
-  float2* H1 = H0 + kBatch * a.N;
-  float2* tw = H1 + kBatch * a.N;
-  float* Ul = reinterpret_cast<float*>(tw + a.N);
+  float2* tw = H0 + kBatch * a.N;
+  int* rev = reinterpret_cast<int*>(tw + a.N);
+  float* Ul = reinterpret_cast<float*>(rev + a.N);
   __shared__ float sv[4];
   __shared__ int si[4];
   __shared__ float s_topv[kMaxTopK], s_tcm[kMaxTopK], s_tcp[kMaxTopK];
   __shared__ int s_topz[kMaxTopK], s_topn[kMaxTopK], s_topm[kMaxTopK];
-  __shared__ int s_cnt, s_nb, s_done, s_eval;
+  __shared__ int s_cnt, s_nb, s_done, s_eval, s_batches;
   __shared__ int s_bz[kBatch];
   __shared__ float s_rv[kBatch], s_rcm[kBatch], s_rcp[kBatch];
   __shared__ int s_rn[kBatch], s_rm[kBatch];
   __shared__ float s_bv;
   __shared__ int s_bi;
 
-  const int p = blockIdx.x;
-  const int64_t P = a.p_begin + p;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const float invN = 1.0f / (float)a.N;
-  for (int i = tid; i < a.N; i += kThreads) tw[i] = a.tw[i];
+  for (int i = tid; i < a.N; i += kThreads) {
+    tw[i] = a.tw[i];
+    rev[i] = a.rev[i];
+  }
 
   if (a.C) {  // full correlogram of zones blockIdx.y * kBatch ..
+    const int p = blockIdx.x;
     __syncthreads();
     int bz[kBatch];
     const int zb = blockIdx.y * kBatch;
     const int nb = min(kBatch, a.Z - zb);
     for (int b = 0; b < kBatch; ++b) bz[b] = zb + min(b, nb - 1);
-    contract_exact(a, p, bz, nb, H0);
+    contract_exact(a, p, bz, nb, rev, H0);
     __syncthreads();
-    const float2* Fr = block_fft(H0, H1, tw, a.N, nb, a.rad, a.nrad, -1.0f);
+    block_fft_inplace(H0, tw, a.N, nb, a.rad, a.nrad, -1.0f);
+    const float2* Fr = H0;
     for (int it = tid; it < nb * a.N; it += kThreads) {
       const int b = it / a.N, n = it % a.N;
       const float2 v = Fr[n * nb + b];
@@ -583,6 +624,9 @@ __global__ void __launch_bounds__(kThreads) exact_kernel(ExactArgs a) {
     return;
   }
 
+  const int p = a.per < 0 ? (int)blockIdx.x : xcd_item(a.per);
+  if (p >= a.np) return;
+  const int64_t P = a.p_begin + p;
   const int fl = a.flags[p];
   if (fl != 0) {
     for (int t = tid; t < a.top_k; t += kThreads) {
@@ -607,19 +651,22 @@ __global__ void __launch_bounds__(kThreads) exact_kernel(ExactArgs a) {
     s_cnt = 0;
     s_done = 0;
     s_eval = 0;
+    s_batches = 0;
   }
   __syncthreads();
 
   while (true) {
-    // ---- select the next batch in decreasing bound order
+    // ---- select the next batch in decreasing bound order; the first batch
+    // holds top_k + 1 zones, later ones kBatch
+    const int want = s_batches == 0 ? min(kBatch, a.top_k + 1) : kBatch;
     if (tid == 0) s_nb = 0;
     __syncthreads();
-    for (int b = 0; b < kBatch; ++b) {
+    for (int b = 0; b < want; ++b) {
       block_argmax(Ul, a.Z, &s_bv, &s_bi, sv, si);
       if (tid == 0) {
         const float v = s_bv;
         const float kth = s_cnt >= a.top_k ? s_topv[a.top_k - 1] : -INFINITY;
-        bool stop = !(v > 0.0f) || (v * (1.0f + a.eps_rel) + margin_abs < kth);
+        const bool stop = !(v > 0.0f) || (v * (1.0f + a.eps_rel) + margin_abs < kth);
         if (stop) {
           if (s_nb == 0) s_done = 1;
         } else {
@@ -637,9 +684,10 @@ __global__ void __launch_bounds__(kThreads) exact_kernel(ExactArgs a) {
     // ---- exact correlograms of the batch
     int bz[kBatch];
     for (int b = 0; b < kBatch; ++b) bz[b] = s_bz[min(b, nb - 1)];
-    contract_exact(a, p, bz, nb, H0);
+    contract_exact(a, p, bz, nb, rev, H0);
     __syncthreads();
-    const float2* Fr = block_fft(H0, H1, tw, a.N, nb, a.rad, a.nrad, -1.0f);
+    block_fft_inplace(H0, tw, a.N, nb, a.rad, a.nrad, -1.0f);
+    const float2* Fr = H0;
     for (int b = wave; b < nb; b += kThreads / 64) {
       float bv = -INFINITY;
       int bi = INT_MAX;
@@ -662,8 +710,8 @@ __global__ void __launch_bounds__(kThreads) exact_kernel(ExactArgs a) {
       }
       if (lane == 0) {
         const int n = bi >> 1, m = bi & 1;
-        const float2 vm = Fr[((n + a.N - 1) % a.N) * nb + b];
-        const float2 vp = Fr[((n + 1) % a.N) * nb + b];
+        const float2 vm = Fr[(n == 0 ? a.N - 1 : n - 1) * nb + b];
+        const float2 vp = Fr[(n == a.N - 1 ? 0 : n + 1) * nb + b];
         s_rv[b] = bv;
         s_rn[b] = n;
         s_rm[b] = m;
@@ -674,6 +722,7 @@ __global__ void __launch_bounds__(kThreads) exact_kernel(ExactArgs a) {
     __syncthreads();
     if (tid == 0) {
       s_eval += nb;
+      s_batches += 1;
       for (int b = 0; b < nb; ++b) {
         const float v = s_rv[b];
         const int z = s_bz[b];
@@ -746,7 +795,14 @@ __global__ void __launch_bounds__(kThreads) exact_kernel(ExactArgs a) {
   if (a.n_eval && tid == 0) a.n_eval[P] = s_eval;
 }
 
-// ------------------------------------------------------------- host -------
+// ------------------------------------------------------------- tuning ----
+
+struct Tuning {
+  int bound_order = 1;    // 0: pattern tiles fastest, 1: XCD-grouped zone tiles fastest
+  int bound_kch16 = 64;   // radii per LDS step of the 16-bit contraction (32, 64 or 128)
+  int exact_xcd = 1;      // exact pass: XCD-grouped pattern order
+};
+Tuning g_tune;
 
 // ---------------------------------------------------------- profiling ----
 
@@ -805,9 +861,12 @@ WsLayout layout(const PlanDev& d, bool lowp, int Pc) {
 }
 
 size_t polar_lds(const PlanDev& d) {
-  return (size_t)(2 * d.N * (kPolarCols / 2) + d.N) * sizeof(float2) + kPeakCache * (8 + 4 + 4);
+  return (size_t)(d.N * (kPolarCols / 2) + d.N) * sizeof(float2) + (size_t)(d.N + (d.N & 1)) * 4 +
+         kPeakCache * (8 + 4 + 4);
 }
-size_t exact_lds(const PlanDev& d) { return (size_t)(2 * kBatch * d.N + d.N) * sizeof(float2) + (size_t)d.Z * 4; }
+size_t exact_lds(const PlanDev& d) {
+  return (size_t)(kBatch * d.N + d.N) * sizeof(float2) + (size_t)d.N * 4 + (size_t)d.Z * 4;
+}
 
 template <class K>
 acom_status_t ensure_lds(K kernel, size_t bytes) {
@@ -835,6 +894,7 @@ PolarArgs polar_args(const PlanDev& d, const acom_peaks_t* pk, int64_t p_begin, 
   for (int i = 0; i < kMaxRadices; ++i) a.rad[i] = d.rad.r[i];
   a.qs = d.d_qs;
   a.tw = d.d_tw;
+  a.rev = d.d_rev;
   a.delta = (float)d.delta;
   a.sigma = (float)d.gauss_sigma;
   a.rk = d.kernel == ACOM_KERNEL_CONE ? (float)d.delta : (float)(3.0 * d.gauss_sigma);
@@ -857,7 +917,8 @@ PolarArgs polar_args(const PlanDev& d, const acom_peaks_t* pk, int64_t p_begin, 
 void set_ws(PolarArgs& a, const WsLayout& L, unsigned char* ws, const PlanDev& d) {
   a.xr = reinterpret_cast<float*>(ws + L.xr);
   a.xi = reinterpret_cast<float*>(ws + L.xi);
-  a.ldk = (size_t)L.Pc * d.Rp;
+  a.ld_tile = (size_t)d.Nk * 64 * d.Rp;   // tile-major, as tile_off
+  a.ldk = (size_t)64 * d.Rp;
   a.ldp = d.Rp;
   a.out_cols = d.Rp;
   a.lr = L.lowp ? reinterpret_cast<uint16_t*>(ws + L.lr) : nullptr;
@@ -883,32 +944,40 @@ acom_status_t launch_bound(const PlanDev& d, int precision, const WsLayout& L, u
   b.Nk = d.Nk;
   b.Rp = d.Rp;
   b.N = d.N;
-  b.x_ldk = (size_t)L.Pc * d.Rp;
-  b.x_ldp = d.Rp;
-  b.p_ldk = (size_t)d.Zp * d.Rp;
-  b.p_ldz = d.Rp;
+  b.nP = (np + kTileP - 1) / kTileP;
+  b.nZ = d.Zp / kTileZ;
+  b.order = g_tune.bound_order;
+  const int nblocks = b.order == 0 ? b.nP * b.nZ : xcd_blocks(b.nP * b.nZ, &b.per);
+  if (b.order == 0) b.per = 0;
   b.scale = reinterpret_cast<const float*>(ws + L.scale);
   b.U = U;
   b.ldU = ldU;
   b.np = np;
   b.Zvalid = Zvalid;
-  dim3 grid((np + kTileP - 1) / kTileP, d.Zp / kTileZ);
+  dim3 grid(nblocks);
   ProfScope prof(1, s);
   if (precision == ACOM_FP32) {
     b.xr = ws + L.xr;
     b.xi = ws + L.xi;
     b.pr = d.d_PR;
     b.pi = d.d_PI;
-    bound_kernel<0><<<grid, kThreads, 0, s>>>(b);
+    bound_kernel<0, 32><<<grid, kThreads, 0, s>>>(b);
   } else {
     b.xr = ws + L.lr;
     b.xi = ws + L.li;
     b.pr = d.d_PR16[precision];
     b.pi = d.d_PI16[precision];
-    if (precision == ACOM_BF16)
-      bound_kernel<1><<<grid, kThreads, 0, s>>>(b);
-    else
-      bound_kernel<2><<<grid, kThreads, 0, s>>>(b);
+    int kch = g_tune.bound_kch16;
+    while (d.Rp % kch) kch /= 2;
+    if (precision == ACOM_BF16) {
+      if (kch == 128) bound_kernel<1, 128><<<grid, kThreads, 0, s>>>(b);
+      else if (kch == 64) bound_kernel<1, 64><<<grid, kThreads, 0, s>>>(b);
+      else bound_kernel<1, 32><<<grid, kThreads, 0, s>>>(b);
+    } else {
+      if (kch == 128) bound_kernel<2, 128><<<grid, kThreads, 0, s>>>(b);
+      else if (kch == 64) bound_kernel<2, 64><<<grid, kThreads, 0, s>>>(b);
+      else bound_kernel<2, 32><<<grid, kThreads, 0, s>>>(b);
+    }
   }
   ACOM_HIP(hipGetLastError());
   return ACOM_OK;
@@ -923,14 +992,11 @@ ExactArgs exact_args(const PlanDev& d, const WsLayout& L, unsigned char* ws, int
   e.nrad = d.rad.n;
   for (int i = 0; i < kMaxRadices; ++i) e.rad[i] = d.rad.r[i];
   e.tw = d.d_tw;
+  e.rev = d.d_rev;
   e.xr = reinterpret_cast<const float*>(ws + L.xr);
   e.xi = reinterpret_cast<const float*>(ws + L.xi);
-  e.x_ldk = (size_t)L.Pc * d.Rp;
-  e.x_ldp = d.Rp;
-  e.pr = d.d_PR;
-  e.pi = d.d_PI;
-  e.p_ldk = (size_t)d.Zp * d.Rp;
-  e.p_ldz = d.Rp;
+  e.pr = d.d_PRz;
+  e.pi = d.d_PIz;
   e.U = reinterpret_cast<const float*>(ws + L.U);
   e.ldU = d.Zp;
   e.xnorm2 = reinterpret_cast<const float*>(ws + L.xn2);
@@ -1021,9 +1087,14 @@ extern "C" acom_status_t acom_match(acom_plan_t plan, const acom_peaks_t* peaks,
     e.phi3 = out->phi3;
     e.orient = out->orient;
     e.n_eval = out->n_evaluated;
+    int nblk = np;
+    if (g_tune.exact_xcd)
+      nblk = xcd_blocks(np, &e.per);
+    else
+      e.per = -1;
     {
       ProfScope prof(2, s);
-      exact_kernel<<<np, kThreads, exact_lds(d), s>>>(e);
+      exact_kernel<<<nblk, kThreads, exact_lds(d), s>>>(e);
     }
     ACOM_HIP(hipGetLastError());
   }
@@ -1078,6 +1149,7 @@ extern "C" acom_status_t acom_polar_spectrum(acom_plan_t plan, const acom_peaks_
   set_ws(pa, L, ws, d);
   pa.xr = Xr;
   pa.xi = Xi;
+  pa.ld_tile = (size_t)64 * d.Nk * d.R;
   pa.ldk = d.R;
   pa.ldp = d.Nk * d.R;
   pa.out_cols = d.R;
@@ -1161,4 +1233,22 @@ extern "C" acom_status_t acom_profile_end(void) {
   g_prof.used = 0;
   g_prof.on = false;
   return ACOM_OK;
+}
+
+extern "C" acom_status_t acom_set_tuning(int32_t key, int32_t value) {
+  switch (key) {
+    case 0:
+      if (value != 0 && value != 1) return fail(ACOM_E_INVALID, "bound order must be 0 or 1");
+      g_tune.bound_order = value;
+      return ACOM_OK;
+    case 1:
+      if (value != 32 && value != 64 && value != 128) return fail(ACOM_E_INVALID, "16-bit step must be 32, 64 or 128");
+      g_tune.bound_kch16 = value;
+      return ACOM_OK;
+    case 2:
+      if (value != 0 && value != 1) return fail(ACOM_E_INVALID, "exact order must be 0 or 1");
+      g_tune.exact_xcd = value;
+      return ACOM_OK;
+  }
+  return fail(ACOM_E_INVALID, "unknown tuning key");
 }

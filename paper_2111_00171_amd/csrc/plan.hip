@@ -252,10 +252,12 @@ __global__ void __launch_bounds__(kPlanThreads) plan_zone_kernel(PlanKernelArgs 
   if (threadIdx.x == 0) a.normA[z] = A;
 }
 
-// FFT{P} along phi3 by a direct FP64 DFT: block (z, k-group), threads over s.
-__global__ void plan_dft_kernel(int Z, int Zp, int N, int Nk, int R, int Rp, const double* P,
-                                const double2* tw64, float* PR, float* PI, uint16_t* PRb,
-                                uint16_t* PIb, uint16_t* PRh, uint16_t* PIh) {
+// FFT{P} along phi3 by a direct FP64 DFT: block (z, k), threads over s.
+// Writes the FP32 operand in tile-major and zone-major layouts and the
+// requested 16-bit copies (tile-major).
+__global__ void plan_dft_kernel(int Z, int N, int Nk, int R, int Rp, const double* P, const double2* tw64,
+                                float* PR, float* PI, float* PRz, float* PIz, uint16_t* PRb, uint16_t* PIb,
+                                uint16_t* PRh, uint16_t* PIh) {
   const int z = blockIdx.x;
   const int k = blockIdx.y;
   const double* Pz = P + (size_t)z * N * R;
@@ -267,9 +269,12 @@ __global__ void plan_dft_kernel(int Z, int Zp, int N, int Nk, int R, int Rp, con
       re += v * w.x;
       im -= v * w.y;
     }
-    const size_t o = ((size_t)k * Zp + z) * Rp + s;
+    const size_t o = tile_off(z, k, s, Nk, Rp);
+    const size_t oz = ((size_t)z * Nk + k) * Rp + s;
     PR[o] = (float)re;
     PI[o] = (float)im;
+    PRz[oz] = (float)re;
+    PIz[oz] = (float)im;
     if (PRb) {
       __hip_bfloat16 br = __float2bfloat16((float)re), bi = __float2bfloat16((float)im);
       PRb[o] = *reinterpret_cast<uint16_t*>(&br);
@@ -298,10 +303,13 @@ acom_status_t dalloc(T** p, size_t n) {
 void free_plan(PlanDev& d) {
   (void)hipFree(d.d_qs);
   (void)hipFree(d.d_tw);
+  (void)hipFree(d.d_rev);
   (void)hipFree(d.d_M12);
   (void)hipFree(d.d_zone_phase);
   (void)hipFree(d.d_PR);
   (void)hipFree(d.d_PI);
+  (void)hipFree(d.d_PRz);
+  (void)hipFree(d.d_PIz);
   for (int i = 0; i < 3; ++i) {
     (void)hipFree(d.d_PR16[i]);
     (void)hipFree(d.d_PI16[i]);
@@ -588,8 +596,12 @@ extern "C" acom_status_t acom_build_plan(const acom_phase_t* phases, int32_t n_p
 
   // frequency-domain operands
   const size_t nfreq = (size_t)d.Nk * d.Zp * d.Rp;
-  if ((st = dalloc(&d.d_PR, nfreq)) || (st = dalloc(&d.d_PI, nfreq))) return bail(st);
-  if (hipMemsetAsync(d.d_PR, 0, nfreq * 4, stream) != hipSuccess || hipMemsetAsync(d.d_PI, 0, nfreq * 4, stream) != hipSuccess)
+  const size_t nfz = (size_t)d.Nk * d.Z * d.Rp;
+  if ((st = dalloc(&d.d_PR, nfreq)) || (st = dalloc(&d.d_PI, nfreq)) || (st = dalloc(&d.d_PRz, nfz)) ||
+      (st = dalloc(&d.d_PIz, nfz)))
+    return bail(st);
+  if (hipMemsetAsync(d.d_PR, 0, nfreq * 4, stream) != hipSuccess || hipMemsetAsync(d.d_PI, 0, nfreq * 4, stream) != hipSuccess ||
+      hipMemsetAsync(d.d_PRz, 0, nfz * 4, stream) != hipSuccess || hipMemsetAsync(d.d_PIz, 0, nfz * 4, stream) != hipSuccess)
     return bail(fail(ACOM_E_HIP, "memset plan"));
   for (int p = 1; p <= 2; ++p)
     if (d.precisions & (1 << p)) {
@@ -599,8 +611,8 @@ extern "C" acom_status_t acom_build_plan(const acom_phase_t* phases, int32_t n_p
         return bail(fail(ACOM_E_HIP, "memset plan16"));
     }
   dim3 gdft(d.Z, d.Nk);
-  plan_dft_kernel<<<gdft, 128, 0, stream>>>(d.Z, d.Zp, d.N, d.Nk, d.R, d.Rp, d_P, d_tw64, d.d_PR, d.d_PI,
-                                            d.d_PR16[ACOM_BF16], d.d_PI16[ACOM_BF16], d.d_PR16[ACOM_FP16],
+  plan_dft_kernel<<<gdft, 128, 0, stream>>>(d.Z, d.N, d.Nk, d.R, d.Rp, d_P, d_tw64, d.d_PR, d.d_PI, d.d_PRz,
+                                            d.d_PIz, d.d_PR16[ACOM_BF16], d.d_PI16[ACOM_BF16], d.d_PR16[ACOM_FP16],
                                             d.d_PI16[ACOM_FP16]);
   if (hipGetLastError() != hipSuccess) return bail(fail(ACOM_E_HIP, "plan_dft_kernel launch"));
 
@@ -612,16 +624,27 @@ extern "C" acom_status_t acom_build_plan(const acom_phase_t* phases, int32_t n_p
       hipMemcpy(d.normA.data(), d_A, sizeof(double) * d.Z, hipMemcpyDeviceToHost) != hipSuccess)
     return bail(fail(ACOM_E_HIP, "copy zone tables"));
   std::vector<float> M12f(M12.begin(), M12.end());
+  std::vector<int32_t> rev(d.N);
+  for (int n = 0; n < d.N; ++n) {
+    int pos = 0, S = d.N, m = n;
+    for (int i = 0; i < d.rad.n; ++i) {
+      S /= d.rad.r[i];
+      pos += S * (m % d.rad.r[i]);
+      m /= d.rad.r[i];
+    }
+    rev[n] = pos;
+  }
   std::vector<float> qsf(d.Rp, -1.0f);
   for (int s = 0; s < d.R; ++s) qsf[s] = (float)d.q_s[s];
   if ((st = dalloc(&d.d_M12, M12f.size())) || (st = dalloc(&d.d_zone_phase, d.Z)) || (st = dalloc(&d.d_qs, d.Rp)) ||
-      (st = dalloc(&d.d_tw, d.N)) || (st = dalloc(&d.d_refl, std::max(1, d.G))) ||
+      (st = dalloc(&d.d_tw, d.N)) || (st = dalloc(&d.d_rev, d.N)) || (st = dalloc(&d.d_refl, std::max(1, d.G))) ||
       (st = dalloc(&d.d_reflF2, std::max(1, d.G))) || (st = dalloc(&d.d_refl_off, n_phases + 1)))
     return bail(st);
   if (hipMemcpy(d.d_M12, M12f.data(), sizeof(float) * M12f.size(), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(d.d_zone_phase, d.zone_phase.data(), sizeof(int) * d.Z, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(d.d_qs, qsf.data(), sizeof(float) * d.Rp, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(d.d_tw, tw32.data(), sizeof(float2) * d.N, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(d.d_rev, rev.data(), sizeof(int32_t) * d.N, hipMemcpyHostToDevice) != hipSuccess ||
       (d.G && hipMemcpy(d.d_refl, refl_f.data(), sizeof(float4) * d.G, hipMemcpyHostToDevice) != hipSuccess) ||
       (d.G && hipMemcpy(d.d_reflF2, F2_all.data(), sizeof(float) * d.G, hipMemcpyHostToDevice) != hipSuccess) ||
       hipMemcpy(d.d_refl_off, d.refl_off.data(), sizeof(int) * (n_phases + 1), hipMemcpyHostToDevice) != hipSuccess)

@@ -243,3 +243,17 @@ def test_full_scan_sampled_against_oracle(acom, scan, precision):
     G = metrics.cubic_rotations()
     mis = [metrics.misorientation_deg(res["orient"][p, 0], d["truth"][p], G) for p in idx[:16]]
     assert np.median(mis) < 1.0
+
+
+@pytest.mark.parametrize("n_radial", [20, 48])
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp16"])
+def test_match_ragged_radial_padding(acom, n_radial, precision):
+    """Radial counts that are not multiples of the 32 / 64 / 128-radius steps."""
+    cfg = dict(k_max=1.2, n_radial=n_radial, n_angular=90, zone_step_deg=5.0)
+    opl = helpers.oracle_plan(["fcc"], **cfg)
+    gpl = helpers.gpu_plan(["fcc"], **cfg)
+    d = synth.subset(synth.make("small"), np.arange(40))
+    res = gpl.match(acom.Peaks.from_host(d), top_k=2, precision=precision)
+    torch.cuda.synchronize()
+    res = {k: v.cpu().numpy() for k, v in res.items() if v is not None}
+    _check_decisions(opl, d, res, range(40), top_k=2)
