@@ -1,0 +1,95 @@
+"""Multi-phase plans (concatenated phases, argmax over all of them), the
+hexagonal two-triangle zone set, and capture of acom_match in a HIP graph."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import correlate
+from tests import helpers
+
+pytestmark = pytest.mark.gpu
+
+MULTI = dict(k_max=2.0, n_radial=64, n_angular=180, zone_step_deg=5.0)
+
+
+@pytest.fixture(scope="module")
+def acom():
+    from paper_2111_00171_amd import acom as a
+    a.lib()
+    return a
+
+
+def test_hcp_two_triangle_plan_matches_oracle(acom):
+    cfg = dict(k_max=1.6, n_radial=32, n_angular=120, zone_step_deg=10.0)
+    opl = helpers.oracle_plan(["hcp"], **cfg)
+    gpl = helpers.gpu_plan(["hcp"], keep_f64=True, precisions=("fp32",), **cfg)
+    assert gpl.n_zones == len(opl["zones"]) == 2 * 55 - 10
+    assert np.allclose(gpl.info()["zones"], opl["zones"], atol=1e-14)
+    P = gpl.angular_f64()
+    assert np.abs(P - opl["P"]).max() < 1e-12 * np.abs(opl["P"]).max()
+
+
+@pytest.fixture(scope="module")
+def multi(acom):
+    d = synth.multi(ny=16, nx=16, n_grains=12)
+    opl = helpers.oracle_plan(["fcc", "bcc", "hcp"], **MULTI)
+    gpl = helpers.gpu_plan(["fcc", "bcc", "hcp"], **MULTI)
+    return d, opl, gpl
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_multiphase_match(acom, multi, precision):
+    d, opl, gpl = multi
+    assert gpl.n_phases == 3 and gpl.n_zones == len(opl["zones"])
+    info = gpl.info()
+    assert np.array_equal(info["zone_phase"], opl["zone_phase"])
+    res = gpl.match(acom.Peaks.from_host(d), top_k=2, precision=precision)
+    torch.cuda.synchronize()
+    res = {k: v.cpu().numpy() for k, v in res.items() if v is not None}
+    pats = list(range(0, 256, 7))
+    for p in pats:
+        Xo = helpers.oracle_image(opl, d, p)
+        Co, Cmo = correlate.correlate_direct(opl["P"], Xo)
+        sc, _, _ = correlate.zone_best(Co, Cmo)
+        mx = sc.max()
+        z = int(res["zone"][p, 0])
+        assert sc[z] >= mx - 1e-5 * mx
+        assert res["phase"][p, 0] == opl["zone_phase"][z]
+    # phase identification against the generator's truth (patterns with >= 8 peaks)
+    cnt = np.diff(d["offsets"])
+    ok = [res["phase"][p, 0] == d["phase"][p] for p in range(256) if cnt[p] >= 8]
+    assert np.mean(ok) > 0.9
+
+
+def test_match_in_hip_graph(acom, multi):
+    """acom_match allocates nothing and never synchronises: captured once, the
+    graph replays on new peak data and reproduces eager results bit for bit."""
+    d, opl, gpl = multi
+    pk = acom.Peaks.from_host(d)
+    n = pk.n_patterns
+    ws = torch.empty(gpl.match_workspace_bytes("bf16", 128), dtype=torch.uint8, device="cuda")
+    out = gpl.empty_matches(n, 2, True, "cuda")
+    gpl.match(pk, 2, "bf16", 128, ws, out=out)       # warm-up outside the capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        gpl.match(pk, 2, "bf16", 128, ws, out=out)
+    rng = np.random.default_rng(3)
+    for rep in range(3):
+        ang = rng.uniform(-0.3, 0.3)
+        qx = d["qx"] * np.cos(ang) - d["qy"] * np.sin(ang)
+        qy = d["qx"] * np.sin(ang) + d["qy"] * np.cos(ang)
+        I = d["I"] * rng.uniform(0.8, 1.2, len(d["I"]))
+        pk.qx.copy_(torch.tensor(qx, dtype=torch.float32))
+        pk.qy.copy_(torch.tensor(qy, dtype=torch.float32))
+        pk.intensity.copy_(torch.tensor(I, dtype=torch.float32))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = {k: v.clone() for k, v in out.items() if v is not None}
+        fresh = acom.Peaks(d["offsets"], qx, qy, I)
+        ref = gpl.match(fresh, 2, "bf16", 128)
+        torch.cuda.synchronize()
+        for k in ("zone", "bin", "mirror", "score", "phi3", "orient", "n_evaluated"):
+            assert torch.equal(got[k], ref[k]), (rep, k)
