@@ -234,7 +234,7 @@ acom_status_t acom_profile_end(void);
 /* Launch-shape tuning (process-wide; results do not depend on it):
  * key 0: contraction block order, 0 = pattern tiles fastest,
  *        1 = zone tiles fastest with the tiles of one pattern group on one XCD (default);
- * key 1: radii staged per LDS step by the BF16/FP16 contraction: 32, 64 (default), 128;
+ * key 1: radii staged per LDS step by the BF16/FP16 contraction: 32, 64, 128 (default; the largest dividing Rp is used);
  * key 2: exact-pass pattern order, 1 = XCD-grouped (default), 0 = plain. */
 acom_status_t acom_set_tuning(int32_t key, int32_t value);
 

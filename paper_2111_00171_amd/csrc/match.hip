@@ -53,9 +53,10 @@ __device__ __forceinline__ double wrap_pi64(double x) {
   return x - tp * rint(x / tp);
 }
 
-__device__ __forceinline__ float kern32(float d, float delta, float sigma, int kind) {
-  if (kind == ACOM_KERNEL_CONE) return d < delta ? 1.0f - d / delta : 0.0f;
-  return d < 3.0f * sigma ? expf(-d * d / (2.0f * sigma * sigma)) : 0.0f;
+// Correlation kernel of distance d with inv = 1/delta (cone) or 1/(2 sigma^2) (Gaussian).
+__device__ __forceinline__ float kern32(float d, float delta, float inv, float sigma3, int kind) {
+  if (kind == ACOM_KERNEL_CONE) return d < delta ? 1.0f - d * inv : 0.0f;
+  return d < sigma3 ? expf(-d * d * inv) : 0.0f;
 }
 
 __device__ __forceinline__ uint16_t to_bf16_bits(float v) {
@@ -123,8 +124,8 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
   float* pq = reinterpret_cast<float*>(pg + kPeakCache);
   float* pw = pq + kPeakCache;
   __shared__ int s_bad;
-  __shared__ float s_red[kThreads];
-  __shared__ double s_red64[kThreads];
+  __shared__ float s_red[kThreads / 64];
+  __shared__ double s_red64[kThreads / 64];
 
   const int tid = threadIdx.x;
   const int p = blockIdx.x;
@@ -146,6 +147,8 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
   const double dphi = 6.283185307179586476925286766559 / a.N;
   const double inv_dphi = a.N / 6.283185307179586476925286766559;
   const int c = tid % kPolarCols, part = tid / kPolarCols;
+  const float kinv = a.kernel == ACOM_KERNEL_CONE ? 1.0f / a.delta : 1.0f / (2.0f * a.sigma * a.sigma);
+  const float sig3 = 3.0f * a.sigma;
   const int L = (a.N + kPolarParts - 1) / kPolarParts;
   const int lo = part * L, hi = min(a.N, lo + L);
   const int col = col0 + c;
@@ -191,7 +194,7 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
           for (int u = u0; u < u1; ++u) {
             const int ai = u - sh;
             const float dp = (float)wrap_pi64(ai * dphi - g) * qs;
-            const float k = kern32(sqrtf(dq * dq + dp * dp), a.delta, a.sigma, a.kernel);
+            const float k = kern32(__builtin_amdgcn_sqrtf(dq * dq + dp * dp), a.delta, kinv, sig3, a.kernel);
             if (k > 0.0f) X[rev[ai] * kPolarCols + c] += w * k;
           }
         }
@@ -199,19 +202,30 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
     }
     __syncthreads();
   }
-  // block sums: peak weights (FP16 scale) and sum of X^2 of this tile
+  // block sums (fixed order): peak weights (FP16 scale) and sum of X^2 of this tile
   float xx = 0.0f;
   for (int i = tid; i < a.N * kPolarCols; i += kThreads) xx += X[i] * X[i];
-  s_red[tid] = xx;
-  s_red64[tid] = wsum;
-  __syncthreads();
-  for (int off = kThreads / 2; off > 0; off >>= 1) {
-    if (tid < off) {
-      s_red[tid] += s_red[tid + off];
-      s_red64[tid] += s_red64[tid + off];
-    }
-    __syncthreads();
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    xx += __shfl_xor(xx, off, 64);
+    wsum += __shfl_xor(wsum, off, 64);
   }
+  if ((tid & 63) == 0) {
+    s_red[tid >> 6] = xx;
+    s_red64[tid >> 6] = wsum;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    float t = 0.0f;
+    double u = 0.0;
+    for (int w = 0; w < kThreads / 64; ++w) {
+      t += s_red[w];
+      u += s_red64[w];
+    }
+    s_red[0] = t;
+    s_red64[0] = u;
+  }
+  __syncthreads();
   const bool bad = s_bad != 0;
   const bool empty = (m1 <= m0);
   float sc = 1.0f;
@@ -354,13 +368,6 @@ __global__ void __launch_bounds__(kThreads) bound_kernel(BoundArgs a) {
   const int nsteps = a.Nk * steps_per_k;
 
   f32x4 acc[2][2][4];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int t = 0; t < 4; ++t) acc[i][j][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-
   for (int stp = 0; stp < nsteps; ++stp) {
     {  // stage KCH radii of frequency k: 64 rows of each operand, 16-byte vectors
       const int k = stp / steps_per_k;
@@ -379,68 +386,77 @@ __global__ void __launch_bounds__(kThreads) bound_kernel(BoundArgs a) {
       }
     }
     __syncthreads();
-    if constexpr (KIND == 0) {
-      float fxr[2][8], fxi[2][8], fpr[2][8], fpi[2][8];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int rx = (wr * 32 + i * 16 + li) * LD + lg * 8;
-        const int rp = (wc * 32 + i * 16 + li) * LD + lg * 8;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          float4 t;
-          t = *reinterpret_cast<const float4*>(&sXr[rx + 4 * h]);
-          fxr[i][4 * h] = t.x; fxr[i][4 * h + 1] = t.y; fxr[i][4 * h + 2] = t.z; fxr[i][4 * h + 3] = t.w;
-          t = *reinterpret_cast<const float4*>(&sXi[rx + 4 * h]);
-          fxi[i][4 * h] = t.x; fxi[i][4 * h + 1] = t.y; fxi[i][4 * h + 2] = t.z; fxi[i][4 * h + 3] = t.w;
-          t = *reinterpret_cast<const float4*>(&sPr[rp + 4 * h]);
-          fpr[i][4 * h] = t.x; fpr[i][4 * h + 1] = t.y; fpr[i][4 * h + 2] = t.z; fpr[i][4 * h + 3] = t.w;
-          t = *reinterpret_cast<const float4*>(&sPi[rp + 4 * h]);
-          fpi[i][4 * h] = t.x; fpi[i][4 * h + 1] = t.y; fpi[i][4 * h + 2] = t.z; fpi[i][4 * h + 3] = t.w;
-        }
-      }
-#pragma unroll
-      for (int t = 0; t < 8; ++t)
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j) {
-            acc[i][j][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxr[i][t], fpr[j][t], acc[i][j][0], 0, 0, 0);
-            acc[i][j][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxi[i][t], fpi[j][t], acc[i][j][1], 0, 0, 0);
-            acc[i][j][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxi[i][t], fpr[j][t], acc[i][j][2], 0, 0, 0);
-            acc[i][j][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxr[i][t], fpi[j][t], acc[i][j][3], 0, 0, 0);
-          }
-    } else {
-      typedef typename std::conditional<KIND == 1, bf16x8, f16x8>::type V8;
-#pragma unroll
-      for (int sub = 0; sub < KCH / 32; ++sub) {
-        V8 fxr[2], fxi[2], fpr[2], fpi[2];
-#pragma unroll
+    // MFMAs of this step; the first step of a frequency starts its accumulators at 0
+    auto step_mfma = [&](auto zc) {
+      constexpr bool Z = decltype(zc)::value;
+      const f32x4 zero4 = {0.0f, 0.0f, 0.0f, 0.0f};
+      if constexpr (KIND == 0) {
+        float fxr[2][8], fxi[2][8], fpr[2][8], fpi[2][8];
+  #pragma unroll
         for (int i = 0; i < 2; ++i) {
-          const int rx = (wr * 32 + i * 16 + li) * LD + sub * 32 + lg * 8;
-          const int rp = (wc * 32 + i * 16 + li) * LD + sub * 32 + lg * 8;
-          fxr[i] = *reinterpret_cast<const V8*>(&sXr[rx]);
-          fxi[i] = *reinterpret_cast<const V8*>(&sXi[rx]);
-          fpr[i] = *reinterpret_cast<const V8*>(&sPr[rp]);
-          fpi[i] = *reinterpret_cast<const V8*>(&sPi[rp]);
-        }
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j) {
-            if constexpr (KIND == 1) {
-              acc[i][j][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fxr[i], fpr[j], acc[i][j][0], 0, 0, 0);
-              acc[i][j][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fxi[i], fpi[j], acc[i][j][1], 0, 0, 0);
-              acc[i][j][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fxi[i], fpr[j], acc[i][j][2], 0, 0, 0);
-              acc[i][j][3] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fxr[i], fpi[j], acc[i][j][3], 0, 0, 0);
-            } else {
-              acc[i][j][0] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fxr[i], fpr[j], acc[i][j][0], 0, 0, 0);
-              acc[i][j][1] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fxi[i], fpi[j], acc[i][j][1], 0, 0, 0);
-              acc[i][j][2] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fxi[i], fpr[j], acc[i][j][2], 0, 0, 0);
-              acc[i][j][3] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fxr[i], fpi[j], acc[i][j][3], 0, 0, 0);
-            }
+          const int rx = (wr * 32 + i * 16 + li) * LD + lg * 8;
+          const int rp = (wc * 32 + i * 16 + li) * LD + lg * 8;
+  #pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            float4 t;
+            t = *reinterpret_cast<const float4*>(&sXr[rx + 4 * h]);
+            fxr[i][4 * h] = t.x; fxr[i][4 * h + 1] = t.y; fxr[i][4 * h + 2] = t.z; fxr[i][4 * h + 3] = t.w;
+            t = *reinterpret_cast<const float4*>(&sXi[rx + 4 * h]);
+            fxi[i][4 * h] = t.x; fxi[i][4 * h + 1] = t.y; fxi[i][4 * h + 2] = t.z; fxi[i][4 * h + 3] = t.w;
+            t = *reinterpret_cast<const float4*>(&sPr[rp + 4 * h]);
+            fpr[i][4 * h] = t.x; fpr[i][4 * h + 1] = t.y; fpr[i][4 * h + 2] = t.z; fpr[i][4 * h + 3] = t.w;
+            t = *reinterpret_cast<const float4*>(&sPi[rp + 4 * h]);
+            fpi[i][4 * h] = t.x; fpi[i][4 * h + 1] = t.y; fpi[i][4 * h + 2] = t.z; fpi[i][4 * h + 3] = t.w;
           }
+        }
+  #pragma unroll
+        for (int t = 0; t < 8; ++t)
+  #pragma unroll
+          for (int i = 0; i < 2; ++i)
+  #pragma unroll
+            for (int j = 0; j < 2; ++j) {
+              acc[i][j][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxr[i][t], fpr[j][t], Z && t == 0 ? zero4 : acc[i][j][0], 0, 0, 0);
+              acc[i][j][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxi[i][t], fpi[j][t], Z && t == 0 ? zero4 : acc[i][j][1], 0, 0, 0);
+              acc[i][j][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxi[i][t], fpr[j][t], Z && t == 0 ? zero4 : acc[i][j][2], 0, 0, 0);
+              acc[i][j][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxr[i][t], fpi[j][t], Z && t == 0 ? zero4 : acc[i][j][3], 0, 0, 0);
+            }
+      } else {
+        typedef typename std::conditional<KIND == 1, bf16x8, f16x8>::type V8;
+  #pragma unroll
+        for (int sub = 0; sub < KCH / 32; ++sub) {
+          V8 fxr[2], fxi[2], fpr[2], fpi[2];
+  #pragma unroll
+          for (int i = 0; i < 2; ++i) {
+            const int rx = (wr * 32 + i * 16 + li) * LD + sub * 32 + lg * 8;
+            const int rp = (wc * 32 + i * 16 + li) * LD + sub * 32 + lg * 8;
+            fxr[i] = *reinterpret_cast<const V8*>(&sXr[rx]);
+            fxi[i] = *reinterpret_cast<const V8*>(&sXi[rx]);
+            fpr[i] = *reinterpret_cast<const V8*>(&sPr[rp]);
+            fpi[i] = *reinterpret_cast<const V8*>(&sPi[rp]);
+          }
+  #pragma unroll
+          for (int i = 0; i < 2; ++i)
+  #pragma unroll
+            for (int j = 0; j < 2; ++j) {
+              if constexpr (KIND == 1) {
+                acc[i][j][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fxr[i], fpr[j], Z && sub == 0 ? zero4 : acc[i][j][0], 0, 0, 0);
+                acc[i][j][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fxi[i], fpi[j], Z && sub == 0 ? zero4 : acc[i][j][1], 0, 0, 0);
+                acc[i][j][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fxi[i], fpr[j], Z && sub == 0 ? zero4 : acc[i][j][2], 0, 0, 0);
+                acc[i][j][3] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fxr[i], fpi[j], Z && sub == 0 ? zero4 : acc[i][j][3], 0, 0, 0);
+              } else {
+                acc[i][j][0] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fxr[i], fpr[j], Z && sub == 0 ? zero4 : acc[i][j][0], 0, 0, 0);
+                acc[i][j][1] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fxi[i], fpi[j], Z && sub == 0 ? zero4 : acc[i][j][1], 0, 0, 0);
+                acc[i][j][2] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fxi[i], fpr[j], Z && sub == 0 ? zero4 : acc[i][j][2], 0, 0, 0);
+                acc[i][j][3] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fxr[i], fpi[j], Z && sub == 0 ? zero4 : acc[i][j][3], 0, 0, 0);
+              }
+            }
+        }
       }
-    }
+    };
+    if (stp % steps_per_k == 0)
+      step_mfma(std::true_type{});
+    else
+      step_mfma(std::false_type{});
     const int k = stp / steps_per_k;
     if (stp - k * steps_per_k == steps_per_k - 1) {  // last radii of frequency k
       const float wk = (k == 0 || 2 * k == a.N) ? 1.0f : 2.0f;
@@ -452,11 +468,10 @@ __global__ void __launch_bounds__(kThreads) bound_kernel(BoundArgs a) {
           for (int r = 0; r < 4; ++r) {
             const float A = acc[i][j][0][r], B = acc[i][j][1][r], C = acc[i][j][2][r], D = acc[i][j][3][r];
             const float re = A + B, im = C - D, rm = A - B, imm = C + D;
-            U[i][j][r] += wk * sqrtf(re * re + im * im);
-            Um[i][j][r] += wk * sqrtf(rm * rm + imm * imm);
+            // hardware square root (<= 1 ulp): the certificate's relative slack covers it
+            U[i][j][r] += wk * __builtin_amdgcn_sqrtf(re * re + im * im);
+            Um[i][j][r] += wk * __builtin_amdgcn_sqrtf(rm * rm + imm * imm);
           }
-#pragma unroll
-          for (int t = 0; t < 4; ++t) acc[i][j][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
         }
     }
     __syncthreads();
@@ -507,30 +522,48 @@ struct ExactArgs {
 // the in-place inverse FFT: H[rev(n) * nb + b].  Work items are (frequency k,
 // zone b) pairs.
 __device__ void contract_exact(const ExactArgs& a, int p, const int* bz, int nb, const int* rev, float2* H) {
+  // four consecutive lanes share an item, each summing a quarter of the radii
   const size_t xbase = tile_off(p, 0, 0, a.Nk, a.Rp);
   const size_t xk = (size_t)64 * a.Rp;
   const float inv_nb = 1.0f / (float)nb;
-  for (int it = threadIdx.x; it < a.Nk * nb; it += blockDim.x) {
-    int b;
-    const int k = fdivmod(it, nb, inv_nb, &b);
-    const float* xr = a.xr + xbase + (size_t)k * xk;
-    const float* xi = a.xi + xbase + (size_t)k * xk;
-    const size_t po = ((size_t)bz[b] * a.Nk + k) * a.Rp;
-    const float* pr = a.pr + po;
-    const float* pi = a.pi + po;
+  const int sub = threadIdx.x & 3;
+  const int rq = a.Rp >> 2;  // multiple of 8
+  const int nitems = a.Nk * nb;
+  for (int base = 0; base < nitems; base += (int)(blockDim.x >> 2)) {
+    const int it = base + (int)(threadIdx.x >> 2);
     float A = 0.0f, B = 0.0f, C = 0.0f, D = 0.0f;
-    for (int s = 0; s < a.Rp; s += 4) {
-      const float4 vr = *reinterpret_cast<const float4*>(xr + s);
-      const float4 vi = *reinterpret_cast<const float4*>(xi + s);
-      const float4 wr = *reinterpret_cast<const float4*>(pr + s);
-      const float4 wi = *reinterpret_cast<const float4*>(pi + s);
-      A += vr.x * wr.x + vr.y * wr.y + vr.z * wr.z + vr.w * wr.w;
-      B += vi.x * wi.x + vi.y * wi.y + vi.z * wi.z + vi.w * wi.w;
-      C += vi.x * wr.x + vi.y * wr.y + vi.z * wr.z + vi.w * wr.w;
-      D += vr.x * wi.x + vr.y * wi.y + vr.z * wi.z + vr.w * wi.w;
+    int k = 0, b = 0;
+    if (it < nitems) {
+      k = fdivmod(it, nb, inv_nb, &b);
+      const int s0 = sub * rq;
+      const float* xr = a.xr + xbase + (size_t)k * xk + s0;
+      const float* xi = a.xi + xbase + (size_t)k * xk + s0;
+      const size_t po = ((size_t)bz[b] * a.Nk + k) * a.Rp + s0;
+      const float* pr = a.pr + po;
+      const float* pi = a.pi + po;
+#pragma unroll 8
+      for (int s = 0; s < rq; s += 4) {
+        const float4 vr = *reinterpret_cast<const float4*>(xr + s);
+        const float4 vi = *reinterpret_cast<const float4*>(xi + s);
+        const float4 wr = *reinterpret_cast<const float4*>(pr + s);
+        const float4 wi = *reinterpret_cast<const float4*>(pi + s);
+        A += vr.x * wr.x + vr.y * wr.y + vr.z * wr.z + vr.w * wr.w;
+        B += vi.x * wi.x + vi.y * wi.y + vi.z * wi.z + vi.w * wi.w;
+        C += vi.x * wr.x + vi.y * wr.y + vi.z * wr.z + vi.w * wr.w;
+        D += vr.x * wi.x + vr.y * wi.y + vr.z * wi.z + vr.w * wi.w;
+      }
     }
-    H[rev[k] * nb + b] = make_float2((A + B) + (C + D), (C - D) + (A - B));
-    if (k > 0 && 2 * k < a.N) H[rev[a.N - k] * nb + b] = make_float2((A + B) - (C + D), (A - B) - (C - D));
+#pragma unroll
+    for (int off = 1; off <= 2; off <<= 1) {
+      A += __shfl_xor(A, off, 64);
+      B += __shfl_xor(B, off, 64);
+      C += __shfl_xor(C, off, 64);
+      D += __shfl_xor(D, off, 64);
+    }
+    if (it < nitems && sub == 0) {
+      H[rev[k] * nb + b] = make_float2((A + B) + (C + D), (C - D) + (A - B));
+      if (k > 0 && 2 * k < a.N) H[rev[a.N - k] * nb + b] = make_float2((A + B) - (C + D), (A - B) - (C - D));
+    }
   }
 }
 
@@ -799,7 +832,7 @@ __global__ void __launch_bounds__(kThreads) exact_kernel(ExactArgs a) {
 
 struct Tuning {
   int bound_order = 1;    // 0: pattern tiles fastest, 1: XCD-grouped zone tiles fastest
-  int bound_kch16 = 64;   // radii per LDS step of the 16-bit contraction (32, 64 or 128)
+  int bound_kch16 = 128;  // radii per LDS step of the 16-bit contraction (32, 64 or 128)
   int exact_xcd = 1;      // exact pass: XCD-grouped pattern order
 };
 Tuning g_tune;
@@ -1249,6 +1282,7 @@ extern "C" acom_status_t acom_set_tuning(int32_t key, int32_t value) {
       if (value != 0 && value != 1) return fail(ACOM_E_INVALID, "exact order must be 0 or 1");
       g_tune.exact_xcd = value;
       return ACOM_OK;
+
   }
   return fail(ACOM_E_INVALID, "unknown tuning key");
 }
