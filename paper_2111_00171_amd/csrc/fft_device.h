@@ -14,6 +14,10 @@
 // rev[n] = sum_i (N / (R_1 .. R_i)) * digit_i(n), digit_i the mixed-radix digits
 // of n (least significant first); the output is in natural order.
 //
+// block_fft_inplace_ct<N, NSEQ> is the same transform with the length and the
+// (power-of-two) sequence count known at compile time, so every index
+// computation folds to shifts and constant divisions.
+//
 // block_fft (Stockham, two buffers) keeps natural order on both sides.
 #pragma once
 
@@ -133,6 +137,73 @@ __device__ inline void block_fft_inplace(float2* buf, const float2* tw, int N, i
     }
     __syncthreads();
   }
+}
+
+struct RadixPlan {
+  int n;
+  int rest;  // 1 when N factors completely into 2, 3, 5
+  int r[kMaxRadicesDev];
+  int L[kMaxRadicesDev];
+};
+
+// Radices 4, 2, 3, 5 in that order (the same factorisation the host uses for
+// the digit-reversal table) and the level lengths L_0 = N, L_{i+1} = L_i / R_i.
+__host__ __device__ constexpr RadixPlan make_radix_plan(int N) {
+  RadixPlan p{};
+  int m = N;
+  const int fs[4] = {4, 2, 3, 5};
+  for (int f = 0; f < 4; ++f)
+    while (m % fs[f] == 0 && p.n < kMaxRadicesDev) {
+      p.r[p.n++] = fs[f];
+      m /= fs[f];
+    }
+  p.rest = m;
+  int L = N;
+  for (int i = 0; i < p.n; ++i) {
+    p.L[i] = L;
+    L /= p.r[i];
+  }
+  return p;
+}
+
+template <int N, int NSEQ, int LEVEL>
+__device__ __forceinline__ void fft_level_ct(float2* buf, const float2* tw, float sg) {
+  constexpr RadixPlan P = make_radix_plan(N);
+  constexpr int R = P.r[LEVEL];
+  constexpr int Li = P.L[LEVEL];
+  constexpr int S = Li / R;
+  constexpr int step = N / Li;
+  constexpr int items = (N / R) * NSEQ;
+  static_assert((NSEQ & (NSEQ - 1)) == 0, "power-of-two sequence count");
+  for (int it = threadIdx.x; it < items; it += blockDim.x) {
+    const int q = it % NSEQ;
+    const int t = it / NSEQ;
+    const int b = t / S, kk = t % S;
+    const int base = b * Li + kk;
+    float2 v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      float2 x = buf[(base + S * r) * NSEQ + q];
+      if (r > 0 && kk > 0) {
+        float2 w = tw[step * r * kk];
+        w.y *= -sg;
+        x = cmul(x, w);
+      }
+      v[r] = x;
+    }
+    dft_small(v, R, sg);
+#pragma unroll
+    for (int r = 0; r < R; ++r) buf[(base + S * r) * NSEQ + q] = v[r];
+  }
+  __syncthreads();
+  if constexpr (LEVEL > 0) fft_level_ct<N, NSEQ, LEVEL - 1>(buf, tw, sg);
+}
+
+template <int N, int NSEQ>
+__device__ __forceinline__ void block_fft_inplace_ct(float2* buf, const float2* tw, float sg) {
+  constexpr RadixPlan P = make_radix_plan(N);
+  static_assert(P.n > 0 && P.rest == 1, "length must factor into 2, 3, 5");
+  fft_level_ct<N, NSEQ, P.n - 1>(buf, tw, sg);
 }
 
 // Transform `nseq` interleaved sequences of length N held in `a`; `b` is the

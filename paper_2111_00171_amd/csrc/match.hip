@@ -33,7 +33,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kPolarCols = 16;   // radial columns per polar block (8 complex sequences)
 constexpr int kPeakCache = 256;
-constexpr int kBatch = 8;        // zones evaluated together by the exact pass
+constexpr int kBatch = 4;        // zones evaluated together by the exact pass
 constexpr int kDefaultChunk = 16384;
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -108,51 +108,76 @@ struct PolarArgs {
   int* flags;              // np: 0 ok, 1 invalid data, 2 no peaks
   float* Ximg;             // optional X[p][a][s] (np x N x R)
   int do_fft;
+  int ntiles;              // radial tiles of kPolarCols columns
+  int per;                 // > 0: XCD-grouped block order with this many items per XCD
 };
 
 // Block (pattern, tile of kPolarCols radial columns).  Splat: thread
 // (column c, part t) owns the angular bins [t L, (t + 1) L) of column c and adds
-// every peak's kernel there in peak order (no atomics, deterministic).  Then
-// the FFT along phi3 of the columns packed in pairs as complex sequences.
+// every peak's kernel there in peak order (no atomics, deterministic).  A peak
+// at angle gamma sits at t = gamma / dphi = ac + f (ac the nearest bin); the
+// angle from bin ac + jj is then (jj - f) dphi, already wrapped while the window
+// is shorter than the circle, so cells need only FP32 arithmetic.  Then the
+// FFT along phi3 of the columns packed in pairs as complex sequences.
+// NT > 0: angular length known at compile time (FFT specialised); NT = 0: any.
+template <int NT>
 __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int NS = kPolarCols / 2;
+  const int N = NT > 0 ? NT : a.N;
   float2* b0 = reinterpret_cast<float2*>(smem_raw);   // [rev(a)][NS] complex: columns packed in pairs
-  float2* tw = b0 + a.N * NS;
-  int* rev = reinterpret_cast<int*>(tw + a.N);
-  double* pg = reinterpret_cast<double*>(rev + a.N + (a.N & 1));
-  float* pq = reinterpret_cast<float*>(pg + kPeakCache);
+  float2* tw = b0 + N * NS;
+  int* rev = reinterpret_cast<int*>(tw + N);
+  int* pac = rev + N;
+  float* pf = reinterpret_cast<float*>(pac + kPeakCache);
+  float* pq = pf + kPeakCache;
   float* pw = pq + kPeakCache;
   __shared__ int s_bad;
   __shared__ float s_red[kThreads / 64];
   __shared__ double s_red64[kThreads / 64];
 
   const int tid = threadIdx.x;
-  const int p = blockIdx.x;
-  const int tile = blockIdx.y;
+  int p, tile;
+  if (a.per > 0) {  // XCD-grouped: the radial tiles of one pattern run back to back on one XCD
+    const int w = xcd_item(a.per);
+    if (w >= a.np * a.ntiles) return;
+    p = w / a.ntiles;
+    tile = w - p * a.ntiles;
+  } else {
+    p = blockIdx.x % a.np;
+    tile = blockIdx.x / a.np;
+  }
   const int col0 = tile * kPolarCols;
   const int64_t P = a.p_begin + p;
   int64_t m0 = a.offsets[P], m1 = a.offsets[P + 1];
   const bool bad_range = m0 < 0 || m1 < m0 || m1 > a.total_peaks;
   if (bad_range) m0 = m1 = 0;  // malformed CSR row: a data error, nothing is read
   float* X = reinterpret_cast<float*>(b0);  // X(phi_a, column) at [rev(a)][kPolarCols]
-  for (int i = tid; i < a.N * kPolarCols; i += kThreads) X[i] = 0.0f;
-  for (int i = tid; i < a.N; i += kThreads) {
+  for (int i = tid; i < N * kPolarCols; i += kThreads) X[i] = 0.0f;
+  for (int i = tid; i < N; i += kThreads) {
     tw[i] = a.tw[i];
     rev[i] = a.rev[i];
   }
   if (tid == 0) s_bad = bad_range ? 1 : 0;
   __syncthreads();
 
-  const double dphi = 6.283185307179586476925286766559 / a.N;
-  const double inv_dphi = a.N / 6.283185307179586476925286766559;
+  const double inv_dphi = N / 6.283185307179586476925286766559;
+  const float dphi = (float)(6.283185307179586476925286766559 / N);
+  const float pi_f = 3.14159265358979323846f;
   const int c = tid % kPolarCols, part = tid / kPolarCols;
   const float kinv = a.kernel == ACOM_KERNEL_CONE ? 1.0f / a.delta : 1.0f / (2.0f * a.sigma * a.sigma);
   const float sig3 = 3.0f * a.sigma;
-  const int L = (a.N + kPolarParts - 1) / kPolarParts;
-  const int lo = part * L, hi = min(a.N, lo + L);
+  const int L = (N + kPolarParts - 1) / kPolarParts;
+  const int lo = part * L, hi = min(N, lo + L);
   const int col = col0 + c;
   const float qs = col < a.R ? a.qs[col] : -1.0f;
+  const float dqs = dphi * qs;
+  int hw = N;  // half-width of the angular window of this column
+  if (qs > 0.0f) {
+    const float h = a.rk / dqs + 1.0f;
+    hw = h > (float)N ? N : (int)ceilf(h);
+  }
+  const bool full = 2 * hw + 1 >= N;
   double wsum = 0.0;
   for (int64_t c0 = m0; c0 < m1; c0 += kPeakCache) {
     const int cnt = (int)min((int64_t)kPeakCache, m1 - c0);
@@ -161,7 +186,10 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
       const bool bad = !isfinite(x) || !isfinite(y) || !isfinite(in) || in < 0.0f;
       if (bad) atomicOr(&s_bad, 1);
       const double q = sqrt((double)x * x + (double)y * y);
-      pg[tid] = atan2((double)y, (double)x);
+      const double t = atan2((double)y, (double)x) * inv_dphi;
+      const double tr = floor(t + 0.5);
+      pac[tid] = (int)tr;
+      pf[tid] = (float)(t - tr);
       pq[tid] = (float)q;
       const float w = bad ? 0.0f : powe((float)q, a.gamma) * powe(in, 0.5f * a.omega);
       pw[tid] = w;
@@ -173,29 +201,32 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
         const float dq = pq[j] - qs;
         const float w = pw[j];
         if (fabsf(dq) >= a.rk || w == 0.0f) continue;
-        const double g = pg[j];
-        int hw = a.N;
-        if (qs > 0.0f) {
-          const float h = a.rk / (qs * (float)dphi) + 1.0f;
-          hw = h > (float)a.N ? a.N : (int)ceilf(h);
-        }
-        int wlo, whi;  // window [wlo, whi) in unwrapped bin units
-        if (2 * hw + 1 >= a.N) {
-          wlo = 0;
-          whi = a.N;
-        } else {
-          const int ac = (int)floor(g * inv_dphi + 0.5);
-          wlo = ac - hw;
-          whi = ac + hw + 1;
-        }
-        // the window has < N bins: each bin of [lo, hi) is met by at most one shift
-        for (int sh = -a.N; sh <= a.N; sh += a.N) {
-          const int u0 = max(wlo, lo + sh), u1 = min(whi, hi + sh);
-          for (int u = u0; u < u1; ++u) {
-            const int ai = u - sh;
-            const float dp = (float)wrap_pi64(ai * dphi - g) * qs;
-            const float k = kern32(__builtin_amdgcn_sqrtf(dq * dq + dp * dp), a.delta, kinv, sig3, a.kernel);
+        const int ac = pac[j];
+        const float f = pf[j];
+        const float dq2 = dq * dq;
+        if (full) {
+          for (int ai = lo; ai < hi; ++ai) {
+            int u = ai - ac;  // in (-3N/2, 3N/2): bring to [-N/2, N/2)
+            if (u >= N / 2) u -= N;
+            if (u < -N / 2) u += N;
+            float xa = ((float)u - f) * dphi;
+            if (xa > pi_f) xa -= 2.0f * pi_f;
+            if (xa < -pi_f) xa += 2.0f * pi_f;
+            const float dp = xa * qs;
+            const float k = kern32(__builtin_amdgcn_sqrtf(dq2 + dp * dp), a.delta, kinv, sig3, a.kernel);
             if (k > 0.0f) X[rev[ai] * kPolarCols + c] += w * k;
+          }
+        } else {
+          // window [ac - hw, ac + hw] in unwrapped bins; fewer than N bins, so each
+          // bin of [lo, hi) is met by at most one of the three shifts
+          const int wlo = ac - hw, whi = ac + hw + 1;
+          for (int sh = -N; sh <= N; sh += N) {
+            const int u0 = max(wlo, lo + sh), u1 = min(whi, hi + sh);
+            for (int u = u0; u < u1; ++u) {
+              const float dp = ((float)(u - ac) - f) * dqs;
+              const float k = kern32(__builtin_amdgcn_sqrtf(dq2 + dp * dp), a.delta, kinv, sig3, a.kernel);
+              if (k > 0.0f) X[rev[u - sh] * kPolarCols + c] += w * k;
+            }
           }
         }
       }
@@ -204,7 +235,7 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
   }
   // block sums (fixed order): peak weights (FP16 scale) and sum of X^2 of this tile
   float xx = 0.0f;
-  for (int i = tid; i < a.N * kPolarCols; i += kThreads) xx += X[i] * X[i];
+  for (int i = tid; i < N * kPolarCols; i += kThreads) xx += X[i] * X[i];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     xx += __shfl_xor(xx, off, 64);
@@ -231,7 +262,7 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
   float sc = 1.0f;
   if (a.lowp == ACOM_FP16) {
     // |FFT{X}| <= sum_a X <= N * sum_m w_m; map that bound below 2^14.
-    const double bound = s_red64[0] * a.N;
+    const double bound = s_red64[0] * N;
     if (bound > 0.0) {
       int e = (int)floor(log2(16384.0 / bound));
       e = max(-60, min(60, e));
@@ -239,51 +270,57 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
     }
   }
   if (tid == 0) {
-    a.xnorm2[(size_t)p * gridDim.y + tile] = bad ? 0.0f : s_red[0];
+    a.xnorm2[(size_t)p * a.ntiles + tile] = bad ? 0.0f : s_red[0];
     if (tile == 0) {
       a.flags[p] = bad ? 1 : (empty ? 2 : 0);
       a.scale[p] = sc;
     }
   }
   if (a.Ximg) {
-    for (int i = tid; i < a.N * kPolarCols; i += kThreads) {
+    for (int i = tid; i < N * kPolarCols; i += kThreads) {
       const int ai = i / kPolarCols, cc = i % kPolarCols;
-      if (col0 + cc < a.R) a.Ximg[((size_t)p * a.N + ai) * a.R + col0 + cc] = bad ? 0.0f : X[rev[ai] * kPolarCols + cc];
+      if (col0 + cc < a.R) a.Ximg[((size_t)p * N + ai) * a.R + col0 + cc] = bad ? 0.0f : X[rev[ai] * kPolarCols + cc];
     }
   }
   if (!a.do_fft) return;
   __syncthreads();
-  block_fft_inplace(b0, tw, a.N, NS, a.rad, a.nrad, 1.0f);
+  if constexpr (NT > 0)
+    block_fft_inplace_ct<NT, NS>(b0, tw, 1.0f);
+  else
+    block_fft_inplace(b0, tw, N, NS, a.rad, a.nrad, 1.0f);
   const float2* F = b0;
   // unpack: column 2q = (Z_k + conj Z_{N-k}) / 2, column 2q+1 = -i (Z_k - conj Z_{N-k}) / 2
   const size_t pbase = (size_t)(p >> 6) * a.ld_tile + (size_t)(p & 63) * a.ldp;
   for (int it = tid; it < a.Nk * NS; it += kThreads) {
     const int k = it / NS, q = it % NS;
     const float2 Zk = F[k * NS + q];
-    const float2 Zn = F[(k == 0 ? 0 : a.N - k) * NS + q];
+    const float2 Zn = F[(k == 0 ? 0 : N - k) * NS + q];
     float2 E = make_float2(0.5f * (Zk.x + Zn.x), 0.5f * (Zk.y - Zn.y));
     float2 O = make_float2(0.5f * (Zk.y + Zn.y), -0.5f * (Zk.x - Zn.x));
     if (bad) E = O = make_float2(0.0f, 0.0f);
     const int s0 = col0 + 2 * q;
     const size_t o = pbase + (size_t)k * a.ldk + s0;
-    if (s0 < a.out_cols) {
-      a.xr[o] = E.x;
-      a.xi[o] = E.y;
-    }
-    if (s0 + 1 < a.out_cols) {
-      a.xr[o + 1] = O.x;
-      a.xi[o + 1] = O.y;
-    }
-    if (a.lowp == ACOM_BF16) {
-      a.lr[o] = to_bf16_bits(E.x);
-      a.li[o] = to_bf16_bits(E.y);
-      a.lr[o + 1] = to_bf16_bits(O.x);
-      a.li[o + 1] = to_bf16_bits(O.y);
-    } else if (a.lowp == ACOM_FP16) {
-      a.lr[o] = to_f16_bits(E.x * sc);
-      a.li[o] = to_f16_bits(E.y * sc);
-      a.lr[o + 1] = to_f16_bits(O.x * sc);
-      a.li[o + 1] = to_f16_bits(O.y * sc);
+    if (a.out_cols == a.Rp) {  // workspace layout: the column pair is one aligned 8-byte / 4-byte store
+      *reinterpret_cast<float2*>(a.xr + o) = make_float2(E.x, O.x);
+      *reinterpret_cast<float2*>(a.xi + o) = make_float2(E.y, O.y);
+      if (a.lowp == ACOM_BF16) {
+        *reinterpret_cast<uint32_t*>(a.lr + o) = (uint32_t)to_bf16_bits(E.x) | ((uint32_t)to_bf16_bits(O.x) << 16);
+        *reinterpret_cast<uint32_t*>(a.li + o) = (uint32_t)to_bf16_bits(E.y) | ((uint32_t)to_bf16_bits(O.y) << 16);
+      } else if (a.lowp == ACOM_FP16) {
+        *reinterpret_cast<uint32_t*>(a.lr + o) =
+            (uint32_t)to_f16_bits(E.x * sc) | ((uint32_t)to_f16_bits(O.x * sc) << 16);
+        *reinterpret_cast<uint32_t*>(a.li + o) =
+            (uint32_t)to_f16_bits(E.y * sc) | ((uint32_t)to_f16_bits(O.y * sc) << 16);
+      }
+    } else {  // caller's [p][k][s] layout with s < out_cols (verification entry point)
+      if (s0 < a.out_cols) {
+        a.xr[o] = E.x;
+        a.xi[o] = E.y;
+      }
+      if (s0 + 1 < a.out_cols) {
+        a.xr[o + 1] = O.x;
+        a.xi[o + 1] = O.y;
+      }
     }
   }
 }
@@ -492,6 +529,209 @@ __global__ void __launch_bounds__(kThreads) bound_kernel(BoundArgs a) {
     }
 }
 
+// Pipelined contraction: the operand tiles of step stp + 1 travel from global
+// memory straight into LDS (global_load_lds_dwordx4, no registers) while the
+// MFMAs of step stp run on the other of two LDS buffers, with one barrier per
+// step.  A staged row holds KCH radii (RB = 128 or 256 bytes) with no padding;
+// its 16-byte chunks are XOR-permuted by row so that the 16 rows one
+// quarter-wave reads for an MFMA operand fall in 16 distinct bank groups.
+// Tile shape, lane mapping, accumulators and epilogue are those of bound_kernel.
+template <int RB>
+__device__ __forceinline__ int chunk_swizzle(int row) {
+  return RB == 128 ? ((row >> 1) & 7) : (row & 15);
+}
+
+template <int KIND, int KCH>
+constexpr int pipe_stage_bytes() {
+  return 4 * 64 * KCH * (int)sizeof(typename BoundTraits<KIND>::T);
+}
+
+template <int KIND, int KCH>
+__global__ void __launch_bounds__(kThreads) bound_pipe_kernel(BoundArgs a) {
+  typedef typename BoundTraits<KIND>::T T;
+  constexpr int RB = KCH * (int)sizeof(T);  // bytes per staged row
+  static_assert(RB == 128 || RB == 256, "staged rows of 128 or 256 bytes");
+  static_assert(KIND != 0 || KCH == 32, "FP32 operands use 32-radius steps");
+  constexpr int VEC = 16 / (int)sizeof(T);  // elements per 16-byte chunk
+  constexpr int ARR = 64 * RB;              // bytes of one operand array per stage
+  constexpr int STAGE = 4 * ARR;
+  constexpr int NI = ARR / 1024 / (kThreads / 64);  // 1 KiB LDS-direct loads per wave per array
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+
+  int tp, tz;
+  if (a.order == 0) {
+    tp = blockIdx.x % a.nP;
+    tz = blockIdx.x / a.nP;
+  } else {
+    const int w = xcd_item(a.per);
+    if (w >= a.nP * a.nZ) return;
+    tp = w / a.nZ;
+    tz = w % a.nZ;
+  }
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = wave >> 1, wc = wave & 1;
+  const int li = lane & 15;
+  const int lg = lane >> 4;
+
+  float U[2][2][4], Um[2][2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) U[i][j][r] = Um[i][j][r] = 0.0f;
+
+  const size_t slab = (size_t)a.Nk * 64 * a.Rp;
+  const T* gsrc[4] = {reinterpret_cast<const T*>(a.xr) + (size_t)tp * slab,
+                      reinterpret_cast<const T*>(a.xi) + (size_t)tp * slab,
+                      reinterpret_cast<const T*>(a.pr) + (size_t)tz * slab,
+                      reinterpret_cast<const T*>(a.pi) + (size_t)tz * slab};
+  const int steps_per_k = a.Rp / KCH;
+  const int nsteps = a.Nk * steps_per_k;
+
+  // per-lane part of the LDS-direct copy: lane writes bytes [16 lane, 16 lane + 16)
+  // of its wave's KiB, i.e. row r, physical chunk c; it fetches logical chunk
+  // c ^ swizzle(r) of that row
+  size_t src_off[NI];
+#pragma unroll
+  for (int j = 0; j < NI; ++j) {
+    const int byte = (wave * NI + j) * 1024 + lane * 16;
+    const int row = byte / RB, phys = (byte % RB) / 16;
+    src_off[j] = (size_t)row * a.Rp + (size_t)((phys ^ chunk_swizzle<RB>(row)) * VEC);
+  }
+  auto issue = [&](int stp, int buf) {
+    const int k = stp / steps_per_k;
+    const size_t gbase = (size_t)k * 64 * a.Rp + (size_t)(stp - k * steps_per_k) * KCH;
+#pragma unroll
+    for (int arr = 0; arr < 4; ++arr)
+#pragma unroll
+      for (int j = 0; j < NI; ++j)
+        __builtin_amdgcn_global_load_lds(
+            (const void*)(gsrc[arr] + gbase + src_off[j]),
+            (__attribute__((address_space(3))) void*)(smem_raw + buf * STAGE + arr * ARR + (wave * NI + j) * 1024),
+            16, 0, 0);
+  };
+  // byte offset of (row, logical chunk) inside one operand array of a stage
+  auto at = [](int row, int chunk) { return row * RB + ((chunk ^ chunk_swizzle<RB>(row)) << 4); };
+
+  f32x4 acc[2][2][4];
+  issue(0, 0);
+  for (int stp = 0; stp < nsteps; ++stp) {
+    __builtin_amdgcn_s_waitcnt(0);  // this thread's copies of step stp have landed
+    __syncthreads();                // ... every thread's, and all reads of step stp - 1 are done
+    if (stp + 1 < nsteps) issue(stp + 1, (stp + 1) & 1);
+    const unsigned char* st = smem_raw + (stp & 1) * STAGE;
+    const unsigned char* sXr = st;
+    const unsigned char* sXi = st + ARR;
+    const unsigned char* sPr = st + 2 * ARR;
+    const unsigned char* sPi = st + 3 * ARR;
+    // the first step of a frequency starts its accumulators at 0 (compile-time operand)
+    auto mma = [&](auto zc) {
+      constexpr bool Z = decltype(zc)::value;
+      const f32x4 zero4 = {0.0f, 0.0f, 0.0f, 0.0f};
+      if constexpr (KIND == 0) {
+        float fxr[2][8], fxi[2][8], fpr[2][8], fpi[2][8];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const int rx = wr * 32 + i * 16 + li;
+          const int rp = wc * 32 + i * 16 + li;
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            // lane quarter lg holds radii 16 h + 4 lg .. + 3 (chunk 4 h + lg) of each operand
+            float4 t;
+            t = *reinterpret_cast<const float4*>(sXr + at(rx, h * 4 + lg));
+            fxr[i][4 * h] = t.x; fxr[i][4 * h + 1] = t.y; fxr[i][4 * h + 2] = t.z; fxr[i][4 * h + 3] = t.w;
+            t = *reinterpret_cast<const float4*>(sXi + at(rx, h * 4 + lg));
+            fxi[i][4 * h] = t.x; fxi[i][4 * h + 1] = t.y; fxi[i][4 * h + 2] = t.z; fxi[i][4 * h + 3] = t.w;
+            t = *reinterpret_cast<const float4*>(sPr + at(rp, h * 4 + lg));
+            fpr[i][4 * h] = t.x; fpr[i][4 * h + 1] = t.y; fpr[i][4 * h + 2] = t.z; fpr[i][4 * h + 3] = t.w;
+            t = *reinterpret_cast<const float4*>(sPi + at(rp, h * 4 + lg));
+            fpi[i][4 * h] = t.x; fpi[i][4 * h + 1] = t.y; fpi[i][4 * h + 2] = t.z; fpi[i][4 * h + 3] = t.w;
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+              acc[i][j][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxr[i][t], fpr[j][t], Z && t == 0 ? zero4 : acc[i][j][0], 0, 0, 0);
+              acc[i][j][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxi[i][t], fpi[j][t], Z && t == 0 ? zero4 : acc[i][j][1], 0, 0, 0);
+              acc[i][j][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxi[i][t], fpr[j][t], Z && t == 0 ? zero4 : acc[i][j][2], 0, 0, 0);
+              acc[i][j][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxr[i][t], fpi[j][t], Z && t == 0 ? zero4 : acc[i][j][3], 0, 0, 0);
+            }
+      } else {
+        typedef typename std::conditional<KIND == 1, bf16x8, f16x8>::type V8;
+#pragma unroll
+        for (int sub = 0; sub < KCH / 32; ++sub) {
+          V8 fxr[2], fxi[2], fpr[2], fpi[2];
+#pragma unroll
+          for (int i = 0; i < 2; ++i) {
+            const int rx = wr * 32 + i * 16 + li;
+            const int rp = wc * 32 + i * 16 + li;
+            fxr[i] = *reinterpret_cast<const V8*>(sXr + at(rx, sub * 4 + lg));
+            fxi[i] = *reinterpret_cast<const V8*>(sXi + at(rx, sub * 4 + lg));
+            fpr[i] = *reinterpret_cast<const V8*>(sPr + at(rp, sub * 4 + lg));
+            fpi[i] = *reinterpret_cast<const V8*>(sPi + at(rp, sub * 4 + lg));
+          }
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+              const bool z = Z && sub == 0;
+              if constexpr (KIND == 1) {
+                acc[i][j][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fxr[i], fpr[j], z ? zero4 : acc[i][j][0], 0, 0, 0);
+                acc[i][j][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fxi[i], fpi[j], z ? zero4 : acc[i][j][1], 0, 0, 0);
+                acc[i][j][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fxi[i], fpr[j], z ? zero4 : acc[i][j][2], 0, 0, 0);
+                acc[i][j][3] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fxr[i], fpi[j], z ? zero4 : acc[i][j][3], 0, 0, 0);
+              } else {
+                acc[i][j][0] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fxr[i], fpr[j], z ? zero4 : acc[i][j][0], 0, 0, 0);
+                acc[i][j][1] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fxi[i], fpi[j], z ? zero4 : acc[i][j][1], 0, 0, 0);
+                acc[i][j][2] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fxi[i], fpr[j], z ? zero4 : acc[i][j][2], 0, 0, 0);
+                acc[i][j][3] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fxr[i], fpi[j], z ? zero4 : acc[i][j][3], 0, 0, 0);
+              }
+            }
+        }
+      }
+    };
+    if (stp % steps_per_k == 0)
+      mma(std::true_type{});
+    else
+      mma(std::false_type{});
+    const int k = stp / steps_per_k;
+    if (stp - k * steps_per_k == steps_per_k - 1) {  // last radii of frequency k
+      const float wk = (k == 0 || 2 * k == a.N) ? 1.0f : 2.0f;
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const float A = acc[i][j][0][r], B = acc[i][j][1][r], C = acc[i][j][2][r], D = acc[i][j][3][r];
+            const float re = A + B, im = C - D, rm = A - B, imm = C + D;
+            U[i][j][r] += wk * __builtin_amdgcn_sqrtf(re * re + im * im);
+            Um[i][j][r] += wk * __builtin_amdgcn_sqrtf(rm * rm + imm * imm);
+          }
+    }
+  }
+  const float invN = 1.0f / (float)a.N;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int p = tp * kTileP + wr * 32 + i * 16 + lg * 4 + r;
+      if (p >= a.np) continue;
+      const float inv = invN / a.scale[p];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int z = tz * kTileZ + wc * 32 + j * 16 + li;
+        if (z < a.Zvalid) a.U[(size_t)p * a.ldU + z] = fmaxf(U[i][j][r], Um[i][j][r]) * inv;
+      }
+    }
+}
+
 // ------------------------------------------------------------ 3. exact ----
 
 struct ExactArgs {
@@ -541,7 +781,7 @@ __device__ void contract_exact(const ExactArgs& a, int p, const int* bz, int nb,
       const size_t po = ((size_t)bz[b] * a.Nk + k) * a.Rp + s0;
       const float* pr = a.pr + po;
       const float* pi = a.pi + po;
-#pragma unroll 8
+#pragma unroll 4
       for (int s = 0; s < rq; s += 4) {
         const float4 vr = *reinterpret_cast<const float4*>(xr + s);
         const float4 vi = *reinterpret_cast<const float4*>(xi + s);
@@ -834,6 +1074,8 @@ struct Tuning {
   int bound_order = 1;    // 0: pattern tiles fastest, 1: XCD-grouped zone tiles fastest
   int bound_kch16 = 128;  // radii per LDS step of the 16-bit contraction (32, 64 or 128)
   int exact_xcd = 1;      // exact pass: XCD-grouped pattern order
+  int polar_xcd = 1;      // polar pass: radial tiles of one pattern consecutive on one XCD
+  int bound_pipe = 1;     // contraction: 1 = double-buffered LDS-direct loads, 0 = staged through registers
 };
 Tuning g_tune;
 
@@ -894,8 +1136,7 @@ WsLayout layout(const PlanDev& d, bool lowp, int Pc) {
 }
 
 size_t polar_lds(const PlanDev& d) {
-  return (size_t)(d.N * (kPolarCols / 2) + d.N) * sizeof(float2) + (size_t)(d.N + (d.N & 1)) * 4 +
-         kPeakCache * (8 + 4 + 4);
+  return (size_t)(d.N * (kPolarCols / 2) + d.N) * sizeof(float2) + (size_t)d.N * 4 + kPeakCache * (4 + 4 + 4 + 4);
 }
 size_t exact_lds(const PlanDev& d) {
   return (size_t)(kBatch * d.N + d.N) * sizeof(float2) + (size_t)d.N * 4 + (size_t)d.Z * 4;
@@ -961,14 +1202,29 @@ void set_ws(PolarArgs& a, const WsLayout& L, unsigned char* ws, const PlanDev& d
   a.flags = reinterpret_cast<int*>(ws + L.flags);
 }
 
-acom_status_t launch_polar(const PlanDev& d, const PolarArgs& a, hipStream_t s) {
-  acom_status_t st = ensure_lds(polar_kernel, polar_lds(d));
+template <int NT>
+acom_status_t launch_polar_n(const PlanDev& d, const PolarArgs& a, hipStream_t s) {
+  acom_status_t st = ensure_lds(polar_kernel<NT>, polar_lds(d));
   if (st != ACOM_OK) return st;
-  dim3 grid(a.np, d.Rp / kPolarCols);
+  PolarArgs b = a;
+  b.ntiles = d.Rp / kPolarCols;
+  b.per = 0;
+  const int nblocks = g_tune.polar_xcd ? xcd_blocks(b.np * b.ntiles, &b.per) : b.np * b.ntiles;
   ProfScope prof(0, s);
-  polar_kernel<<<grid, kThreads, polar_lds(d), s>>>(a);
+  polar_kernel<NT><<<dim3(nblocks), kThreads, polar_lds(d), s>>>(b);
   ACOM_HIP(hipGetLastError());
   return ACOM_OK;
+}
+
+acom_status_t launch_polar(const PlanDev& d, const PolarArgs& a, hipStream_t s) {
+  switch (d.N) {  // FFT lengths with a compile-time schedule; any other length runs the generic one
+    case 90: return launch_polar_n<90>(d, a, s);
+    case 120: return launch_polar_n<120>(d, a, s);
+    case 180: return launch_polar_n<180>(d, a, s);
+    case 360: return launch_polar_n<360>(d, a, s);
+    case 720: return launch_polar_n<720>(d, a, s);
+    default: return launch_polar_n<0>(d, a, s);
+  }
 }
 
 acom_status_t launch_bound(const PlanDev& d, int precision, const WsLayout& L, unsigned char* ws, int np,
@@ -988,20 +1244,49 @@ acom_status_t launch_bound(const PlanDev& d, int precision, const WsLayout& L, u
   b.np = np;
   b.Zvalid = Zvalid;
   dim3 grid(nblocks);
-  ProfScope prof(1, s);
   if (precision == ACOM_FP32) {
     b.xr = ws + L.xr;
     b.xi = ws + L.xi;
     b.pr = d.d_PR;
     b.pi = d.d_PI;
-    bound_kernel<0, 32><<<grid, kThreads, 0, s>>>(b);
   } else {
     b.xr = ws + L.lr;
     b.xi = ws + L.li;
     b.pr = d.d_PR16[precision];
     b.pi = d.d_PI16[precision];
-    int kch = g_tune.bound_kch16;
-    while (d.Rp % kch) kch /= 2;
+  }
+  int kch = g_tune.bound_kch16;
+  while (d.Rp % kch) kch /= 2;
+  if (g_tune.bound_pipe) {
+    acom_status_t st = ACOM_OK;
+    if (precision == ACOM_FP32) {
+      if ((st = ensure_lds(bound_pipe_kernel<0, 32>, 2 * pipe_stage_bytes<0, 32>())) != ACOM_OK) return st;
+      ProfScope prof(1, s);
+      bound_pipe_kernel<0, 32><<<grid, kThreads, 2 * pipe_stage_bytes<0, 32>(), s>>>(b);
+    } else if (kch == 128) {
+      auto kern = precision == ACOM_BF16 ? bound_pipe_kernel<1, 128> : bound_pipe_kernel<2, 128>;
+      if ((st = ensure_lds(kern, 2 * pipe_stage_bytes<1, 128>())) != ACOM_OK) return st;
+      ProfScope prof(1, s);
+      kern<<<grid, kThreads, 2 * pipe_stage_bytes<1, 128>(), s>>>(b);
+    } else {  // Rp is a multiple of 32: 64-radius steps need Rp % 64 == 0, else the staged kernel runs
+      if (d.Rp % 64 == 0) {
+        auto kern = precision == ACOM_BF16 ? bound_pipe_kernel<1, 64> : bound_pipe_kernel<2, 64>;
+        if ((st = ensure_lds(kern, 2 * pipe_stage_bytes<1, 64>())) != ACOM_OK) return st;
+        ProfScope prof(1, s);
+        kern<<<grid, kThreads, 2 * pipe_stage_bytes<1, 64>(), s>>>(b);
+      } else {
+        ProfScope prof(1, s);
+        if (precision == ACOM_BF16) bound_kernel<1, 32><<<grid, kThreads, 0, s>>>(b);
+        else bound_kernel<2, 32><<<grid, kThreads, 0, s>>>(b);
+      }
+    }
+    ACOM_HIP(hipGetLastError());
+    return ACOM_OK;
+  }
+  ProfScope prof(1, s);
+  if (precision == ACOM_FP32) {
+    bound_kernel<0, 32><<<grid, kThreads, 0, s>>>(b);
+  } else {
     if (precision == ACOM_BF16) {
       if (kch == 128) bound_kernel<1, 128><<<grid, kThreads, 0, s>>>(b);
       else if (kch == 64) bound_kernel<1, 64><<<grid, kThreads, 0, s>>>(b);
@@ -1281,6 +1566,14 @@ extern "C" acom_status_t acom_set_tuning(int32_t key, int32_t value) {
     case 2:
       if (value != 0 && value != 1) return fail(ACOM_E_INVALID, "exact order must be 0 or 1");
       g_tune.exact_xcd = value;
+      return ACOM_OK;
+    case 3:
+      if (value != 0 && value != 1) return fail(ACOM_E_INVALID, "polar order must be 0 or 1");
+      g_tune.polar_xcd = value;
+      return ACOM_OK;
+    case 4:
+      if (value != 0 && value != 1) return fail(ACOM_E_INVALID, "contraction pipeline must be 0 or 1");
+      g_tune.bound_pipe = value;
       return ACOM_OK;
 
   }
