@@ -157,8 +157,9 @@ acom_status_t acom_match_workspace_size(acom_plan_t plan, int32_t precision, int
  * inverse FFT, and the maximum over zones, in-plane bins and the two branches.
  * The contraction runs in `precision`; every reported score is recomputed in
  * FP32 from the FP32 plan, and a zone is skipped only when the upper bound
- * (1/N) sum_k |G_k| of its correlogram (computed in `precision`, widened by a
- * precision-dependent margin) is below the current top_k-th exact score.
+ * (1/N) sum_k max(|G_k|, |G_m,k|) of its two correlograms (computed in
+ * `precision`, widened by a precision-dependent margin) is below the current
+ * top_k-th exact score.
  * Adds a 3-point parabolic sub-bin offset and the orientation matrix.
  * top_k in [1, 16]; `chunk` must equal the value given to the size query. */
 acom_status_t acom_match(acom_plan_t plan, const acom_peaks_t* peaks, int32_t top_k,
@@ -178,8 +179,9 @@ acom_status_t acom_polar_spectrum(acom_plan_t plan, const acom_peaks_t* peaks, f
                                   void* workspace, size_t workspace_bytes, void* stream);
 acom_status_t acom_correlate(acom_plan_t plan, const acom_peaks_t* peaks, float* C,
                              void* workspace, size_t workspace_bytes, void* stream);
-/* Upper bounds U[p][z] = (1/N) max(sum_k w_k |G_k|, sum_k w_k |G_m,k|) as computed by
- * the contraction pass in `precision` (n x Z, FP32), without margin. */
+/* Upper bounds U[p][z] = (1/N) sum_k w_k max(|G_k|, |G_m,k|) (k over the half
+ * spectrum, w_k = 1 at k = 0 and N/2, else 2) as computed by the contraction
+ * pass in `precision` (n x Z, FP32), without margin. */
 acom_status_t acom_bound(acom_plan_t plan, const acom_peaks_t* peaks, int32_t precision, float* U,
                          void* workspace, size_t workspace_bytes, void* stream);
 
@@ -234,7 +236,7 @@ acom_status_t acom_profile_end(void);
 /* Launch-shape tuning (process-wide; results do not depend on it):
  * key 0: contraction block order, 0 = pattern tiles fastest,
  *        1 = zone tiles fastest with the tiles of one pattern group on one XCD (default);
- * key 1: radii staged per LDS step by the BF16/FP16 contraction: 32, 64, 128 (default; the largest dividing Rp is used);
+ * key 1: radii staged per LDS step by the BF16/FP16 contraction: 32, 64 (default), 128 (the largest dividing Rp is used);
  * key 2: exact-pass pattern order, 1 = XCD-grouped (default), 0 = plain;
  * key 3: polar-pass order, 1 = the radial tiles of one pattern back to back on one XCD (default),
  *        0 = pattern index fastest;

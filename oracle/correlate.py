@@ -62,17 +62,18 @@ def correlate_fft(P, X):
 
 
 def spectral_bound(P, X):
-    """U[z] = max over the two branches of (1/N) sum_{k=0}^{N-1} |G_k| with
-    G_k = sum_s conj(Phat_ks) Xhat_ks (or Xhat^* for the mirror).
+    """U[z] = (1/N) sum_{k=0}^{N-1} max(|G_k|, |G'_k|) with
+    G_k = sum_s conj(Phat_ks) Xhat_ks and G'_k the same with Xhat^* (mirror).
 
-    Not a quantity of the paper: an upper bound on max_n C[z, n] (triangle
-    inequality on the inverse DFT), used to skip zones that cannot win."""
+    Not a quantity of the paper: an upper bound on max_n max(C, C_mirror)[z, n]
+    (triangle inequality on the inverse DFT of either branch, then the larger
+    modulus per frequency), used to skip zones that cannot win."""
     Ph = np.fft.fft(np.asarray(P, dtype=np.float64), axis=1)
     Xh = np.fft.fft(np.asarray(X, dtype=np.float64), axis=0)
     N = Ph.shape[1]
     G = np.sum(np.conj(Ph) * Xh[None], axis=2)
     Gm = np.sum(np.conj(Ph) * np.conj(Xh)[None], axis=2)
-    return np.maximum(np.abs(G).sum(axis=1), np.abs(Gm).sum(axis=1)) / N
+    return np.maximum(np.abs(G), np.abs(Gm)).sum(axis=1) / N
 
 
 def zone_best(C, Cm):

@@ -3,7 +3,7 @@
     python -m paper_2111_00171_amd.build
 
 Compiles every csrc/*.hip translation unit with hipcc (-O3, gfx950, packed
-FP32 instructions disabled) and links them into paper_2111_00171_amd/libacom.so.
+FP32 instructions disabled, MFMA accumulators in VGPRs) and links them into paper_2111_00171_amd/libacom.so.
 Objects go to paper_2111_00171_amd/_build/.
 """
 import os
@@ -19,6 +19,7 @@ ARCH = os.environ.get("ACOM_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-munsafe-fp-atomics",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-mllvm", "-amdgpu-mfma-vgpr-form",  # MFMA accumulators in VGPRs: no AGPR copies in the epilogue
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-but-set-variable"]
 
 

@@ -3,14 +3,16 @@
 // Per chunk of patterns, three launches on the caller's stream:
 //  1. polar_kernel   - sparse polar image X(phi_a, q_s) (Eq. image_polar) by a
 //                      deterministic per-column splat in LDS, then the FFT of X
-//                      along phi3 (block Stockham FFT, two real columns packed
-//                      in one complex sequence); writes FFT{X} in FP32 and, for
-//                      the low-precision contraction, BF16/FP16 copies.
-//  2. bound_kernel   - the per-frequency contraction G_k = sum_s FFT{P}^* FFT{X}
-//                      (and the mirror with FFT{X}^*) on MFMA for a 64x64
-//                      (pattern x zone) tile, streaming over k and accumulating
-//                      U = (1/N) sum_k w_k |G_k| (an upper bound of max_n C by the
-//                      triangle inequality on the inverse DFT) for both branches.
+//                      along phi3 (in-place mixed-radix FFT, two real columns
+//                      packed in one complex sequence); writes FFT{X} in FP32
+//                      and, for the low-precision contraction, BF16/FP16 copies.
+//  2. bound_pipe_kernel (or bound_kernel) - the per-frequency contraction
+//                      G_k = sum_s FFT{P}^* FFT{X} (and the mirror G'_k with
+//                      FFT{X}^*) on MFMA for a 64x64 (pattern x zone) tile,
+//                      streaming over k and accumulating
+//                      U = (1/N) sum_k w_k max(|G_k|, |G'_k|), an upper bound of
+//                      max_n max(C, C_mirror) by the triangle inequality on the
+//                      inverse DFT.
 //  3. exact_kernel   - per pattern, zones in decreasing U are evaluated exactly
 //                      in FP32 (contraction over s, inverse FFT along phi3 of
 //                      C + i C_mirror, argmax over (n, branch)) until no remaining
@@ -110,6 +112,7 @@ struct PolarArgs {
   int do_fft;
   int ntiles;              // radial tiles of kPolarCols columns
   int per;                 // > 0: XCD-grouped block order with this many items per XCD
+  uint32_t* cmask;         // np x ntiles: bit c set when column c of the tile holds a nonzero X (or null)
 };
 
 // Block (pattern, tile of kPolarCols radial columns).  Splat: thread
@@ -135,6 +138,7 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
   __shared__ int s_bad;
   __shared__ float s_red[kThreads / 64];
   __shared__ double s_red64[kThreads / 64];
+  __shared__ uint32_t s_cm[kThreads / 64];
 
   const int tid = threadIdx.x;
   int p, tile;
@@ -233,9 +237,19 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
     }
     __syncthreads();
   }
-  // block sums (fixed order): peak weights (FP16 scale) and sum of X^2 of this tile
+  // block sums (fixed order): peak weights (FP16 scale) and sum of X^2 of this
+  // tile; and which columns hold any nonzero X (a thread only visits column
+  // tid % kPolarCols, so lane l of a ballot speaks for column l % kPolarCols)
+  static_assert(64 % kPolarCols == 0 && kPolarCols == 16, "column mask folding assumes 16 columns");
   float xx = 0.0f;
-  for (int i = tid; i < N * kPolarCols; i += kThreads) xx += X[i] * X[i];
+  bool nz = false;
+  for (int i = tid; i < N * kPolarCols; i += kThreads) {
+    const float v = X[i];
+    xx += v * v;
+    nz = nz || v != 0.0f;
+  }
+  const unsigned long long bal = __ballot(nz);
+  const uint32_t cm = (uint32_t)((bal | (bal >> 16) | (bal >> 32) | (bal >> 48)) & 0xFFFFull);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     xx += __shfl_xor(xx, off, 64);
@@ -244,17 +258,21 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
   if ((tid & 63) == 0) {
     s_red[tid >> 6] = xx;
     s_red64[tid >> 6] = wsum;
+    s_cm[tid >> 6] = cm;
   }
   __syncthreads();
   if (tid == 0) {
     float t = 0.0f;
     double u = 0.0;
+    uint32_t m = 0;
     for (int w = 0; w < kThreads / 64; ++w) {
       t += s_red[w];
       u += s_red64[w];
+      m |= s_cm[w];
     }
     s_red[0] = t;
     s_red64[0] = u;
+    s_cm[0] = m;
   }
   __syncthreads();
   const bool bad = s_bad != 0;
@@ -271,6 +289,7 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
   }
   if (tid == 0) {
     a.xnorm2[(size_t)p * a.ntiles + tile] = bad ? 0.0f : s_red[0];
+    if (a.cmask) a.cmask[(size_t)p * a.ntiles + tile] = bad ? 0u : s_cm[0];
     if (tile == 0) {
       a.flags[p] = bad ? 1 : (empty ? 2 : 0);
       a.scale[p] = sc;
@@ -354,7 +373,9 @@ struct BoundTraits<0> {
 // of 16 x 16).  For each frequency k the K loop runs over s in steps of KCH
 // radii (KCH divides Rp) staged through LDS; four accumulators per block
 // give the real products A = Xr Pr, B = Xi Pi, C = Xi Pr, D = Xr Pi, so
-// G = (A + B) + i (C - D) and G_mirror = (A - B) - i (C + D).  Lanes of a
+// G = (A + B) + i (C - D) and G_mirror = (A - B) - i (C + D), whose larger
+// squared modulus is S + 2 |T| with S = A^2 + B^2 + C^2 + D^2, T = A B - C D
+// (one square root per element and frequency).  Lanes of a
 // quarter-wave (l / 16) take the contiguous s-range 8 (l / 16) .. +7 of every
 // 32 radii for both operands: the same permutation of the contraction index on
 // both sides.
@@ -388,13 +409,13 @@ __global__ void __launch_bounds__(kThreads) bound_kernel(BoundArgs a) {
   const int li = lane & 15;  // row within a 16-block
   const int lg = lane >> 4;  // quarter-wave
 
-  float U[2][2][4], Um[2][2][4];
+  float U[2][2][4];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) U[i][j][r] = Um[i][j][r] = 0.0f;
+      for (int r = 0; r < 4; ++r) U[i][j][r] = 0.0f;
 
   const size_t slab = (size_t)a.Nk * 64 * a.Rp;
   const T* gxr = reinterpret_cast<const T*>(a.xr) + (size_t)tp * slab;
@@ -504,10 +525,11 @@ __global__ void __launch_bounds__(kThreads) bound_kernel(BoundArgs a) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const float A = acc[i][j][0][r], B = acc[i][j][1][r], C = acc[i][j][2][r], D = acc[i][j][3][r];
-            const float re = A + B, im = C - D, rm = A - B, imm = C + D;
+            // max(|G|^2, |G_mirror|^2) = S + 2 |T|, S = A^2 + B^2 + C^2 + D^2, T = A B - C D
+            const float S = fmaf(A, A, fmaf(B, B, fmaf(C, C, D * D)));
+            const float T = fmaf(A, B, -(C * D));
             // hardware square root (<= 1 ulp): the certificate's relative slack covers it
-            U[i][j][r] += wk * __builtin_amdgcn_sqrtf(re * re + im * im);
-            Um[i][j][r] += wk * __builtin_amdgcn_sqrtf(rm * rm + imm * imm);
+            U[i][j][r] += wk * __builtin_amdgcn_sqrtf(fmaf(2.0f, fabsf(T), S));
           }
         }
     }
@@ -524,7 +546,7 @@ __global__ void __launch_bounds__(kThreads) bound_kernel(BoundArgs a) {
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const int z = tz * kTileZ + wc * 32 + j * 16 + li;
-        if (z < a.Zvalid) a.U[(size_t)p * a.ldU + z] = fmaxf(U[i][j][r], Um[i][j][r]) * inv;
+        if (z < a.Zvalid) a.U[(size_t)p * a.ldU + z] = U[i][j][r] * inv;
       }
     }
 }
@@ -575,13 +597,13 @@ __global__ void __launch_bounds__(kThreads) bound_pipe_kernel(BoundArgs a) {
   const int li = lane & 15;
   const int lg = lane >> 4;
 
-  float U[2][2][4], Um[2][2][4];
+  float U[2][2][4];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) U[i][j][r] = Um[i][j][r] = 0.0f;
+      for (int r = 0; r < 4; ++r) U[i][j][r] = 0.0f;
 
   const size_t slab = (size_t)a.Nk * 64 * a.Rp;
   const T* gsrc[4] = {reinterpret_cast<const T*>(a.xr) + (size_t)tp * slab,
@@ -710,9 +732,11 @@ __global__ void __launch_bounds__(kThreads) bound_pipe_kernel(BoundArgs a) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const float A = acc[i][j][0][r], B = acc[i][j][1][r], C = acc[i][j][2][r], D = acc[i][j][3][r];
-            const float re = A + B, im = C - D, rm = A - B, imm = C + D;
-            U[i][j][r] += wk * __builtin_amdgcn_sqrtf(re * re + im * im);
-            Um[i][j][r] += wk * __builtin_amdgcn_sqrtf(rm * rm + imm * imm);
+            // max(|G|^2, |G_mirror|^2) = S + 2 |T|, S = A^2 + B^2 + C^2 + D^2, T = A B - C D
+            const float S = fmaf(A, A, fmaf(B, B, fmaf(C, C, D * D)));
+            const float T = fmaf(A, B, -(C * D));
+            // hardware square root (<= 1 ulp): the certificate's relative slack covers it
+            U[i][j][r] += wk * __builtin_amdgcn_sqrtf(fmaf(2.0f, fabsf(T), S));
           }
     }
   }
@@ -727,7 +751,7 @@ __global__ void __launch_bounds__(kThreads) bound_pipe_kernel(BoundArgs a) {
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const int z = tz * kTileZ + wc * 32 + j * 16 + li;
-        if (z < a.Zvalid) a.U[(size_t)p * a.ldU + z] = fmaxf(U[i][j][r], Um[i][j][r]) * inv;
+        if (z < a.Zvalid) a.U[(size_t)p * a.ldU + z] = U[i][j][r] * inv;
       }
     }
 }
@@ -744,6 +768,7 @@ struct ExactArgs {
   const float* U;
   int ldU;
   const float* xnorm2;
+  const uint32_t* cmask;    // per pattern and radial tile: columns holding a nonzero X
   int ntiles;
   const int* flags;
   const float* M12;
@@ -757,52 +782,76 @@ struct ExactArgs {
   float* C;  // correlate mode: C[p][z][2][N] for every zone (no selection)
 };
 
+// The 4-radius groups of pattern p whose columns hold any nonzero X, in
+// increasing order (the others contribute exact zeros to every contraction).
+__device__ void active_groups(const ExactArgs& a, int p, int* groups, int* ng) {
+  if (threadIdx.x == 0) {
+    int n = 0;
+    for (int t = 0; t < a.ntiles; ++t) {
+      const uint32_t m = a.cmask ? a.cmask[(size_t)p * a.ntiles + t] : 0xFFFFu;
+      for (int j = 0; j < kPolarCols / 4; ++j)
+        if ((m >> (4 * j)) & 0xFu) groups[n++] = t * (kPolarCols / 4) + j;
+    }
+    *ng = n;
+  }
+  __syncthreads();
+}
+
 // H for nb zones of local pattern p: H_k = G_k + i G_mirror,k (k <= N/2) and
 // H_{N-k} = conj(G_k) + i conj(G_mirror,k), stored in digit-reversed order for
-// the in-place inverse FFT: H[rev(n) * nb + b].  Work items are (frequency k,
-// zone b) pairs.
-__device__ void contract_exact(const ExactArgs& a, int p, const int* bz, int nb, const int* rev, float2* H) {
-  // four consecutive lanes share an item, each summing a quarter of the radii
+// the in-place inverse FFT: H[rev(n) * nb + b].  Four consecutive lanes share a
+// frequency k and take every fourth active radius group; each group of X is
+// loaded once for all nb zones.
+__device__ void contract_exact(const ExactArgs& a, int p, const int* bz, int nb, const int* rev, float2* H,
+                               const int* groups, int ng) {
   const size_t xbase = tile_off(p, 0, 0, a.Nk, a.Rp);
   const size_t xk = (size_t)64 * a.Rp;
-  const float inv_nb = 1.0f / (float)nb;
   const int sub = threadIdx.x & 3;
-  const int rq = a.Rp >> 2;  // multiple of 8
-  const int nitems = a.Nk * nb;
-  for (int base = 0; base < nitems; base += (int)(blockDim.x >> 2)) {
-    const int it = base + (int)(threadIdx.x >> 2);
-    float A = 0.0f, B = 0.0f, C = 0.0f, D = 0.0f;
-    int k = 0, b = 0;
-    if (it < nitems) {
-      k = fdivmod(it, nb, inv_nb, &b);
-      const int s0 = sub * rq;
-      const float* xr = a.xr + xbase + (size_t)k * xk + s0;
-      const float* xi = a.xi + xbase + (size_t)k * xk + s0;
-      const size_t po = ((size_t)bz[b] * a.Nk + k) * a.Rp + s0;
-      const float* pr = a.pr + po;
-      const float* pi = a.pi + po;
-#pragma unroll 4
-      for (int s = 0; s < rq; s += 4) {
+  for (int base = 0; base < a.Nk; base += (int)(blockDim.x >> 2)) {
+    const int k = base + (int)(threadIdx.x >> 2);
+    float A[kBatch], B[kBatch], C[kBatch], D[kBatch];
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) A[b] = B[b] = C[b] = D[b] = 0.0f;
+    if (k < a.Nk) {
+      const float* xr = a.xr + xbase + (size_t)k * xk;
+      const float* xi = a.xi + xbase + (size_t)k * xk;
+      size_t po[kBatch];
+#pragma unroll
+      for (int b = 0; b < kBatch; ++b) po[b] = ((size_t)bz[b] * a.Nk + k) * a.Rp;
+#pragma unroll 2
+      for (int g = sub; g < ng; g += 4) {
+        const int s = groups[g] * 4;
         const float4 vr = *reinterpret_cast<const float4*>(xr + s);
         const float4 vi = *reinterpret_cast<const float4*>(xi + s);
-        const float4 wr = *reinterpret_cast<const float4*>(pr + s);
-        const float4 wi = *reinterpret_cast<const float4*>(pi + s);
-        A += vr.x * wr.x + vr.y * wr.y + vr.z * wr.z + vr.w * wr.w;
-        B += vi.x * wi.x + vi.y * wi.y + vi.z * wi.z + vi.w * wi.w;
-        C += vi.x * wr.x + vi.y * wr.y + vi.z * wr.z + vi.w * wr.w;
-        D += vr.x * wi.x + vr.y * wi.y + vr.z * wi.z + vr.w * wi.w;
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+          if (b < nb) {
+            const float4 wr = *reinterpret_cast<const float4*>(a.pr + po[b] + s);
+            const float4 wi = *reinterpret_cast<const float4*>(a.pi + po[b] + s);
+            A[b] += vr.x * wr.x + vr.y * wr.y + vr.z * wr.z + vr.w * wr.w;
+            B[b] += vi.x * wi.x + vi.y * wi.y + vi.z * wi.z + vi.w * wi.w;
+            C[b] += vi.x * wr.x + vi.y * wr.y + vi.z * wr.z + vi.w * wr.w;
+            D[b] += vr.x * wi.x + vr.y * wi.y + vr.z * wi.z + vr.w * wi.w;
+          }
+        }
       }
     }
 #pragma unroll
-    for (int off = 1; off <= 2; off <<= 1) {
-      A += __shfl_xor(A, off, 64);
-      B += __shfl_xor(B, off, 64);
-      C += __shfl_xor(C, off, 64);
-      D += __shfl_xor(D, off, 64);
-    }
-    if (it < nitems && sub == 0) {
-      H[rev[k] * nb + b] = make_float2((A + B) + (C + D), (C - D) + (A - B));
-      if (k > 0 && 2 * k < a.N) H[rev[a.N - k] * nb + b] = make_float2((A + B) - (C + D), (A - B) - (C - D));
+    for (int b = 0; b < kBatch; ++b) {
+      if (b < nb) {
+#pragma unroll
+        for (int off = 1; off <= 2; off <<= 1) {
+          A[b] += __shfl_xor(A[b], off, 64);
+          B[b] += __shfl_xor(B[b], off, 64);
+          C[b] += __shfl_xor(C[b], off, 64);
+          D[b] += __shfl_xor(D[b], off, 64);
+        }
+        if (k < a.Nk && sub == 0) {
+          H[rev[k] * nb + b] = make_float2((A[b] + B[b]) + (C[b] + D[b]), (C[b] - D[b]) + (A[b] - B[b]));
+          if (k > 0 && 2 * k < a.N)
+            H[rev[a.N - k] * nb + b] = make_float2((A[b] + B[b]) - (C[b] + D[b]), (A[b] - B[b]) - (C[b] - D[b]));
+        }
+      }
     }
   }
 }
@@ -857,6 +906,8 @@ __global__ void __launch_bounds__(kThreads) exact_kernel(ExactArgs a) {
   float2* tw = H0 + kBatch * a.N;
   int* rev = reinterpret_cast<int*>(tw + a.N);
   float* Ul = reinterpret_cast<float*>(rev + a.N);
+  int* groups = reinterpret_cast<int*>(Ul + a.Z);  // Rp / 4 entries
+  __shared__ int s_ng;
   __shared__ float sv[4];
   __shared__ int si[4];
   __shared__ float s_topv[kMaxTopK], s_tcm[kMaxTopK], s_tcp[kMaxTopK];
@@ -878,12 +929,12 @@ __global__ void __launch_bounds__(kThreads) exact_kernel(ExactArgs a) {
 
   if (a.C) {  // full correlogram of zones blockIdx.y * kBatch ..
     const int p = blockIdx.x;
-    __syncthreads();
+    active_groups(a, p, groups, &s_ng);
     int bz[kBatch];
     const int zb = blockIdx.y * kBatch;
     const int nb = min(kBatch, a.Z - zb);
     for (int b = 0; b < kBatch; ++b) bz[b] = zb + min(b, nb - 1);
-    contract_exact(a, p, bz, nb, rev, H0);
+    contract_exact(a, p, bz, nb, rev, H0, groups, s_ng);
     __syncthreads();
     block_fft_inplace(H0, tw, a.N, nb, a.rad, a.nrad, -1.0f);
     const float2* Fr = H0;
@@ -920,6 +971,7 @@ __global__ void __launch_bounds__(kThreads) exact_kernel(ExactArgs a) {
   for (int t = 0; t < a.ntiles; ++t) xn2 += a.xnorm2[(size_t)p * a.ntiles + t];
   const float margin_abs = a.eps_abs * sqrtf(xn2);
   for (int z = tid; z < a.Z; z += kThreads) Ul[z] = a.U[(size_t)p * a.ldU + z];
+  active_groups(a, p, groups, &s_ng);
   if (tid == 0) {
     s_cnt = 0;
     s_done = 0;
@@ -957,7 +1009,7 @@ __global__ void __launch_bounds__(kThreads) exact_kernel(ExactArgs a) {
     // ---- exact correlograms of the batch
     int bz[kBatch];
     for (int b = 0; b < kBatch; ++b) bz[b] = s_bz[min(b, nb - 1)];
-    contract_exact(a, p, bz, nb, rev, H0);
+    contract_exact(a, p, bz, nb, rev, H0, groups, s_ng);
     __syncthreads();
     block_fft_inplace(H0, tw, a.N, nb, a.rad, a.nrad, -1.0f);
     const float2* Fr = H0;
@@ -1072,7 +1124,7 @@ __global__ void __launch_bounds__(kThreads) exact_kernel(ExactArgs a) {
 
 struct Tuning {
   int bound_order = 1;    // 0: pattern tiles fastest, 1: XCD-grouped zone tiles fastest
-  int bound_kch16 = 128;  // radii per LDS step of the 16-bit contraction (32, 64 or 128)
+  int bound_kch16 = 64;   // radii per LDS step of the 16-bit contraction (32, 64 or 128)
   int exact_xcd = 1;      // exact pass: XCD-grouped pattern order
   int polar_xcd = 1;      // polar pass: radial tiles of one pattern consecutive on one XCD
   int bound_pipe = 1;     // contraction: 1 = double-buffered LDS-direct loads, 0 = staged through registers
@@ -1104,7 +1156,7 @@ struct ProfScope {
 };
 
 struct WsLayout {
-  size_t xr = 0, xi = 0, lr = 0, li = 0, scale = 0, xn2 = 0, flags = 0, U = 0, total = 0;
+  size_t xr = 0, xi = 0, lr = 0, li = 0, scale = 0, xn2 = 0, cmask = 0, flags = 0, U = 0, total = 0;
   int Pc = 0, ntiles = 0;
   bool lowp = false;
 };
@@ -1129,6 +1181,7 @@ WsLayout layout(const PlanDev& d, bool lowp, int Pc) {
   }
   L.scale = take((size_t)Pc * 4);
   L.xn2 = take((size_t)Pc * L.ntiles * 4);
+  L.cmask = take((size_t)Pc * L.ntiles * 4);
   L.flags = take((size_t)Pc * 4);
   L.U = take((size_t)Pc * d.Zp * 4);
   L.total = o;
@@ -1139,7 +1192,7 @@ size_t polar_lds(const PlanDev& d) {
   return (size_t)(d.N * (kPolarCols / 2) + d.N) * sizeof(float2) + (size_t)d.N * 4 + kPeakCache * (4 + 4 + 4 + 4);
 }
 size_t exact_lds(const PlanDev& d) {
-  return (size_t)(kBatch * d.N + d.N) * sizeof(float2) + (size_t)d.N * 4 + (size_t)d.Z * 4;
+  return (size_t)(kBatch * d.N + d.N) * sizeof(float2) + (size_t)d.N * 4 + (size_t)d.Z * 4 + (size_t)d.Rp;
 }
 
 template <class K>
@@ -1185,6 +1238,7 @@ PolarArgs polar_args(const PlanDev& d, const acom_peaks_t* pk, int64_t p_begin, 
   a.lowp = lowp;
   a.Ximg = nullptr;
   a.do_fft = 1;
+  a.cmask = nullptr;
   return a;
 }
 
@@ -1199,6 +1253,7 @@ void set_ws(PolarArgs& a, const WsLayout& L, unsigned char* ws, const PlanDev& d
   a.li = L.lowp ? reinterpret_cast<uint16_t*>(ws + L.li) : nullptr;
   a.scale = reinterpret_cast<float*>(ws + L.scale);
   a.xnorm2 = reinterpret_cast<float*>(ws + L.xn2);
+  a.cmask = reinterpret_cast<uint32_t*>(ws + L.cmask);
   a.flags = reinterpret_cast<int*>(ws + L.flags);
 }
 
@@ -1318,6 +1373,7 @@ ExactArgs exact_args(const PlanDev& d, const WsLayout& L, unsigned char* ws, int
   e.U = reinterpret_cast<const float*>(ws + L.U);
   e.ldU = d.Zp;
   e.xnorm2 = reinterpret_cast<const float*>(ws + L.xn2);
+  e.cmask = reinterpret_cast<const uint32_t*>(ws + L.cmask);
   e.ntiles = L.ntiles;
   e.flags = reinterpret_cast<const int*>(ws + L.flags);
   e.M12 = d.d_M12;
