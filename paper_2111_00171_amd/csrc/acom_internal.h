@@ -40,7 +40,7 @@ constexpr int kMaxAngular = 1024;
 constexpr int kMaxTopK = 16;
 constexpr int kMaxZonesExact = 16384;  // per-pattern bound row held in LDS by the exact pass
 
-// Mixed-radix factorisation of the angular length (radices 4, 2, 3, 5).
+// Mixed-radix factorisation of the angular length (radices 8, 9, 4, 2, 3, 5, greedily).
 struct Radices {
   int n = 0;
   int r[kMaxRadices] = {0};

@@ -21,6 +21,8 @@ acom_status_t hip_fail(hipError_t e, const char* what) {
 bool factor_angular(int N, Radices* out) {
   Radices r;
   int m = N;
+  while (m % 8 == 0 && r.n < kMaxRadices) { r.r[r.n++] = 8; m /= 8; }
+  while (m % 9 == 0 && r.n < kMaxRadices) { r.r[r.n++] = 9; m /= 9; }
   while (m % 4 == 0 && r.n < kMaxRadices) { r.r[r.n++] = 4; m /= 4; }
   while (m % 2 == 0 && r.n < kMaxRadices) { r.r[r.n++] = 2; m /= 2; }
   while (m % 3 == 0 && r.n < kMaxRadices) { r.r[r.n++] = 3; m /= 3; }

@@ -1,4 +1,4 @@
-// Block-cooperative mixed-radix FFTs in LDS (radices 2, 3, 4, 5).
+// Block-cooperative mixed-radix FFTs in LDS (radices 8, 9, 4, 2, 3, 5).
 //
 // The angular axis phi3 is transformed many sequences at a time: element a of
 // sequence q lives at buf[a * nseq + q], so consecutive threads touch
@@ -17,8 +17,6 @@
 // block_fft_inplace_ct<N, NSEQ> is the same transform with the length and the
 // (power-of-two) sequence count known at compile time, so every index
 // computation folds to shifts and constant divisions.
-//
-// block_fft (Stockham, two buffers) keeps natural order on both sides.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -35,9 +33,76 @@ __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(
 // multiply by -i*sg  (sg = +1: forward transform sign e^{-i...})
 __device__ __forceinline__ float2 rot_mi(float2 a, float sg) { return make_float2(sg * a.y, -sg * a.x); }
 
+__device__ __forceinline__ void dft3(float2& a, float2& b, float2& d, float sg) {
+  const float c = -0.5f, s = 0.866025403784438647f;
+  const float2 t = cadd(b, d);
+  const float2 m = make_float2(a.x + c * t.x, a.y + c * t.y);
+  const float2 u = rot_mi(csub(b, d), sg);  // -i sg (b - d)
+  a = cadd(a, t);
+  b = make_float2(m.x + s * u.x, m.y + s * u.y);
+  d = make_float2(m.x - s * u.x, m.y - s * u.y);
+}
+
+__device__ __forceinline__ void dft4(float2& a, float2& b, float2& c, float2& d, float sg) {
+  const float2 s0 = cadd(a, c), d0 = csub(a, c), s1 = cadd(b, d);
+  const float2 d1 = rot_mi(csub(b, d), sg);
+  a = cadd(s0, s1);
+  c = csub(s0, s1);
+  b = cadd(d0, d1);
+  d = csub(d0, d1);
+}
+
+// z * w with w = (cos t, -sg sin t): the forward transform's e^{-i t}
+__device__ __forceinline__ float2 twid(float2 z, float c, float s, float sg) {
+  const float sy = -sg * s;
+  return make_float2(z.x * c - z.y * sy, z.x * sy + z.y * c);
+}
+
 // In-register R-point DFT, sign sg = +1 for exp(-2 pi i r k / R), -1 for exp(+...).
 __device__ __forceinline__ void dft_small(float2* v, int R, float sg) {
-  if (R == 2) {
+  if (R == 8) {
+    // two 4-point DFTs over the even and odd inputs, joined by w8^k
+    float2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    float2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4(e0, e1, e2, e3, sg);
+    dft4(o0, o1, o2, o3, sg);
+    const float h = 0.707106781186547524f;
+    const float2 w1 = cadd(o1, rot_mi(o1, sg));                  // (1 - i sg) o1, times 1/sqrt2 below
+    const float2 t1 = make_float2(h * w1.x, h * w1.y);
+    const float2 t2 = rot_mi(o2, sg);                            // -i sg o2
+    const float2 w3 = rot_mi(cadd(o3, rot_mi(o3, sg)), sg);      // -i sg (1 - i sg) o3
+    const float2 t3 = make_float2(h * w3.x, h * w3.y);
+    v[0] = cadd(e0, o0);
+    v[4] = csub(e0, o0);
+    v[1] = cadd(e1, t1);
+    v[5] = csub(e1, t1);
+    v[2] = cadd(e2, t2);
+    v[6] = csub(e2, t2);
+    v[3] = cadd(e3, t3);
+    v[7] = csub(e3, t3);
+  } else if (R == 9) {
+    // n = 3 n1 + n2, k = k1 + 3 k2: 3-point DFTs over n1, twiddles w9^(n2 k1),
+    // 3-point DFTs over n2
+    float2 y00 = v[0], y01 = v[3], y02 = v[6];
+    float2 y10 = v[1], y11 = v[4], y12 = v[7];
+    float2 y20 = v[2], y21 = v[5], y22 = v[8];
+    dft3(y00, y01, y02, sg);
+    dft3(y10, y11, y12, sg);
+    dft3(y20, y21, y22, sg);
+    const float c1 = 0.766044443118978035f, s1 = 0.642787609686539326f;   // 2 pi / 9
+    const float c2 = 0.173648177666930349f, s2 = 0.984807753012208059f;   // 4 pi / 9
+    const float c4 = -0.939692620785908384f, s4 = 0.342020143325668734f;  // 8 pi / 9
+    y11 = twid(y11, c1, s1, sg);
+    y12 = twid(y12, c2, s2, sg);
+    y21 = twid(y21, c2, s2, sg);
+    y22 = twid(y22, c4, s4, sg);
+    dft3(y00, y10, y20, sg);
+    dft3(y01, y11, y21, sg);
+    dft3(y02, y12, y22, sg);
+    v[0] = y00; v[3] = y10; v[6] = y20;
+    v[1] = y01; v[4] = y11; v[7] = y21;
+    v[2] = y02; v[5] = y12; v[8] = y22;
+  } else if (R == 2) {
     float2 a = v[0], b = v[1];
     v[0] = cadd(a, b);
     v[1] = csub(a, b);
@@ -117,9 +182,9 @@ __device__ inline void block_fft_inplace(float2* buf, const float2* tw, int N, i
       int kk;
       const int b = fdivmod(t, S, inv_s, &kk);
       const int base = b * Li + kk;
-      float2 v[5];
+      float2 v[9];
 #pragma unroll
-      for (int r = 0; r < 5; ++r) {
+      for (int r = 0; r < 9; ++r) {
         if (r < R) {
           float2 x = buf[(base + S * r) * nseq + q];
           if (r > 0 && kk > 0) {
@@ -132,7 +197,7 @@ __device__ inline void block_fft_inplace(float2* buf, const float2* tw, int N, i
       }
       dft_small(v, R, sg);
 #pragma unroll
-      for (int r = 0; r < 5; ++r)
+      for (int r = 0; r < 9; ++r)
         if (r < R) buf[(base + S * r) * nseq + q] = v[r];
     }
     __syncthreads();
@@ -146,13 +211,14 @@ struct RadixPlan {
   int L[kMaxRadicesDev];
 };
 
-// Radices 4, 2, 3, 5 in that order (the same factorisation the host uses for
-// the digit-reversal table) and the level lengths L_0 = N, L_{i+1} = L_i / R_i.
+// Radices 8, 9, 4, 2, 3, 5 taken greedily in that order (the same
+// factorisation the host uses for the digit-reversal table) and the level
+// lengths L_0 = N, L_{i+1} = L_i / R_i.
 __host__ __device__ constexpr RadixPlan make_radix_plan(int N) {
   RadixPlan p{};
   int m = N;
-  const int fs[4] = {4, 2, 3, 5};
-  for (int f = 0; f < 4; ++f)
+  const int fs[6] = {8, 9, 4, 2, 3, 5};
+  for (int f = 0; f < 6; ++f)
     while (m % fs[f] == 0 && p.n < kMaxRadicesDev) {
       p.r[p.n++] = fs[f];
       m /= fs[f];
@@ -204,53 +270,6 @@ __device__ __forceinline__ void block_fft_inplace_ct(float2* buf, const float2* 
   constexpr RadixPlan P = make_radix_plan(N);
   static_assert(P.n > 0 && P.rest == 1, "length must factor into 2, 3, 5");
   fft_level_ct<N, NSEQ, P.n - 1>(buf, tw, sg);
-}
-
-// Transform `nseq` interleaved sequences of length N held in `a`; `b` is the
-// ping-pong buffer.  sg = +1 forward, -1 inverse (unnormalised).  Returns the
-// buffer holding the result.  All threads of the block must call it.
-// The twiddle exponent r * (j mod Ns) * N / (Ns R) is always below N.
-__device__ inline float2* block_fft(float2* a, float2* b, const float2* tw, int N, int nseq,
-                                   const int* radix, int nrad, float sg) {
-  int Ns = 1;
-  const float inv_nseq = 1.0f / (float)nseq;
-  for (int st = 0; st < nrad; ++st) {
-    const int R = radix[st];
-    const int NR = N / R;
-    const int step = N / (Ns * R);
-    const int items = NR * nseq;
-    const float inv_ns = 1.0f / (float)Ns;
-    for (int it = threadIdx.x; it < items; it += blockDim.x) {
-      int q;
-      const int j = fdivmod(it, nseq, inv_nseq, &q);
-      int jm;
-      const int jq = fdivmod(j, Ns, inv_ns, &jm);
-      float2 v[5];
-#pragma unroll
-      for (int r = 0; r < 5; ++r) {
-        if (r < R) {
-          float2 x = a[(j + r * NR) * nseq + q];
-          if (r > 0 && jm > 0) {
-            float2 w = tw[r * jm * step];
-            w.y *= -sg;  // forward uses conj(w)
-            x = cmul(x, w);
-          }
-          v[r] = x;
-        }
-      }
-      dft_small(v, R, sg);
-      const int d0 = jq * Ns * R + jm;
-#pragma unroll
-      for (int r = 0; r < 5; ++r)
-        if (r < R) b[(d0 + r * Ns) * nseq + q] = v[r];
-    }
-    __syncthreads();
-    float2* t = a;
-    a = b;
-    b = t;
-    Ns *= R;
-  }
-  return a;
 }
 
 }  // namespace acom

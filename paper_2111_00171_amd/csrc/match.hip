@@ -115,16 +115,23 @@ struct PolarArgs {
   uint32_t* cmask;         // np x ntiles: bit c set when column c of the tile holds a nonzero X (or null)
 };
 
-// Block (pattern, tile of kPolarCols radial columns).  Splat: thread
-// (column c, part t) owns the angular bins [t L, (t + 1) L) of column c and adds
-// every peak's kernel there in peak order (no atomics, deterministic).  A peak
-// at angle gamma sits at t = gamma / dphi = ac + f (ac the nearest bin); the
-// angle from bin ac + jj is then (jj - f) dphi, already wrapped while the window
-// is shorter than the circle, so cells need only FP32 arithmetic.  Then the
-// FFT along phi3 of the columns packed in pairs as complex sequences.
+// One workgroup per pattern, looping over its radial tiles of kPolarCols
+// columns.  The peaks are prepared once per pattern (bin of the nearest angle
+// ac, offset f, radius, weight) and, per tile, compacted to those whose radius
+// lies within the kernel reach of the tile's columns.  Splat: thread (column c,
+// part t) owns the angular bins a = t mod kPolarParts of column c (interleaved,
+// so that a peak's short window is shared by all parts) and adds the listed
+// peaks' kernel there in peak order (no atomics, deterministic).  A peak
+// at angle gamma sits at t = gamma / dphi = ac + f; the angle from bin ac + jj
+// is then (jj - f) dphi, already wrapped while the window is shorter than the
+// circle, so cells need only FP32 arithmetic.  Then the FFT along phi3 of the
+// columns packed in pairs as complex sequences (skipped for a tile with no
+// nonzero X, whose spectrum is exactly zero).
 // NT > 0: angular length known at compile time (FFT specialised); NT = 0: any.
 template <int NT>
 __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
+  static_assert(kPeakCache == kThreads, "one thread prepares one cached peak");
+  static_assert(64 % kPolarCols == 0 && kPolarCols == 16, "column mask folding assumes 16 columns");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int NS = kPolarCols / 2;
   const int N = NT > 0 ? NT : a.N;
@@ -135,35 +142,27 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
   float* pf = reinterpret_cast<float*>(pac + kPeakCache);
   float* pq = pf + kPeakCache;
   float* pw = pq + kPeakCache;
-  __shared__ int s_bad;
+  int* plist = reinterpret_cast<int*>(pw + kPeakCache);  // cached peaks reaching the current tile
+  float* sqs = reinterpret_cast<float*>(plist + kPeakCache);  // q_s of every column (-1 beyond R)
+  __shared__ int s_bad, s_nlist;
   __shared__ float s_red[kThreads / 64];
   __shared__ double s_red64[kThreads / 64];
   __shared__ uint32_t s_cm[kThreads / 64];
+  __shared__ float s_sc;
 
   const int tid = threadIdx.x;
-  int p, tile;
-  if (a.per > 0) {  // XCD-grouped: the radial tiles of one pattern run back to back on one XCD
-    const int w = xcd_item(a.per);
-    if (w >= a.np * a.ntiles) return;
-    p = w / a.ntiles;
-    tile = w - p * a.ntiles;
-  } else {
-    p = blockIdx.x % a.np;
-    tile = blockIdx.x / a.np;
-  }
-  const int col0 = tile * kPolarCols;
+  const int p = a.per > 0 ? xcd_item(a.per) : (int)blockIdx.x;
+  if (p >= a.np) return;
   const int64_t P = a.p_begin + p;
   int64_t m0 = a.offsets[P], m1 = a.offsets[P + 1];
   const bool bad_range = m0 < 0 || m1 < m0 || m1 > a.total_peaks;
   if (bad_range) m0 = m1 = 0;  // malformed CSR row: a data error, nothing is read
-  float* X = reinterpret_cast<float*>(b0);  // X(phi_a, column) at [rev(a)][kPolarCols]
-  for (int i = tid; i < N * kPolarCols; i += kThreads) X[i] = 0.0f;
   for (int i = tid; i < N; i += kThreads) {
     tw[i] = a.tw[i];
     rev[i] = a.rev[i];
   }
+  for (int i = tid; i < a.Rp; i += kThreads) sqs[i] = i < a.R ? a.qs[i] : -1.0f;
   if (tid == 0) s_bad = bad_range ? 1 : 0;
-  __syncthreads();
 
   const double inv_dphi = N / 6.283185307179586476925286766559;
   const float dphi = (float)(6.283185307179586476925286766559 / N);
@@ -171,20 +170,11 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
   const int c = tid % kPolarCols, part = tid / kPolarCols;
   const float kinv = a.kernel == ACOM_KERNEL_CONE ? 1.0f / a.delta : 1.0f / (2.0f * a.sigma * a.sigma);
   const float sig3 = 3.0f * a.sigma;
-  const int L = (N + kPolarParts - 1) / kPolarParts;
-  const int lo = part * L, hi = min(N, lo + L);
-  const int col = col0 + c;
-  const float qs = col < a.R ? a.qs[col] : -1.0f;
-  const float dqs = dphi * qs;
-  int hw = N;  // half-width of the angular window of this column
-  if (qs > 0.0f) {
-    const float h = a.rk / dqs + 1.0f;
-    hw = h > (float)N ? N : (int)ceilf(h);
-  }
-  const bool full = 2 * hw + 1 >= N;
-  double wsum = 0.0;
-  for (int64_t c0 = m0; c0 < m1; c0 += kPeakCache) {
-    const int cnt = (int)min((int64_t)kPeakCache, m1 - c0);
+  const bool single = (m1 - m0) <= kPeakCache;
+  double wsum = 0.0;  // this thread's share of sum_m w_m (first pass over the peaks only)
+
+  // cache peaks [c0, c0 + cnt): every thread calls; ends with a barrier
+  auto prep = [&](int64_t c0, int cnt, bool count) {
     if (tid < cnt) {
       const float x = a.qx[c0 + tid], y = a.qy[c0 + tid], in = a.I[c0 + tid];
       const bool bad = !isfinite(x) || !isfinite(y) || !isfinite(in) || in < 0.0f;
@@ -197,150 +187,201 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
       pq[tid] = (float)q;
       const float w = bad ? 0.0f : powe((float)q, a.gamma) * powe(in, 0.5f * a.omega);
       pw[tid] = w;
-      wsum += w;
+      if (count) wsum += w;
     }
     __syncthreads();
-    if (qs >= 0.0f && lo < hi) {
-      for (int j = 0; j < cnt; ++j) {
-        const float dq = pq[j] - qs;
-        const float w = pw[j];
-        if (fabsf(dq) >= a.rk || w == 0.0f) continue;
-        const int ac = pac[j];
-        const float f = pf[j];
-        const float dq2 = dq * dq;
-        if (full) {
-          for (int ai = lo; ai < hi; ++ai) {
-            int u = ai - ac;  // in (-3N/2, 3N/2): bring to [-N/2, N/2)
-            if (u >= N / 2) u -= N;
-            if (u < -N / 2) u += N;
-            float xa = ((float)u - f) * dphi;
-            if (xa > pi_f) xa -= 2.0f * pi_f;
-            if (xa < -pi_f) xa += 2.0f * pi_f;
-            const float dp = xa * qs;
-            const float k = kern32(__builtin_amdgcn_sqrtf(dq2 + dp * dp), a.delta, kinv, sig3, a.kernel);
-            if (k > 0.0f) X[rev[ai] * kPolarCols + c] += w * k;
-          }
-        } else {
-          // window [ac - hw, ac + hw] in unwrapped bins; fewer than N bins, so each
-          // bin of [lo, hi) is met by at most one of the three shifts
-          const int wlo = ac - hw, whi = ac + hw + 1;
-          for (int sh = -N; sh <= N; sh += N) {
-            const int u0 = max(wlo, lo + sh), u1 = min(whi, hi + sh);
-            for (int u = u0; u < u1; ++u) {
-              const float dp = ((float)(u - ac) - f) * dqs;
+  };
+  if (single) prep(m0, (int)(m1 - m0), true);
+  else __syncthreads();
+
+  float sc = 1.0f;
+  float* X = reinterpret_cast<float*>(b0);  // X(phi_a, column) at [rev(a)][kPolarCols]
+  const size_t pbase = (size_t)(p >> 6) * a.ld_tile + (size_t)(p & 63) * a.ldp;
+  for (int tile = 0; tile < a.ntiles; ++tile) {
+    const int col0 = tile * kPolarCols;
+    for (int i = tid; i < N * kPolarCols / 4; i += kThreads)
+      reinterpret_cast<float4*>(X)[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    // radii of the tile's real columns (padding columns carry q = -1: no peak reaches them)
+    const int cl = min(col0 + kPolarCols, a.R) - 1;
+    const float qlo = col0 < a.R ? sqs[col0] : -1.0f;
+    const float qhi = col0 < a.R ? sqs[cl] : -1.0f;
+    const float qs = sqs[col0 + c];
+    const float dqs = dphi * qs;
+    int hw = N;  // half-width of the angular window of this column
+    if (qs > 0.0f) {
+      const float h = a.rk / dqs + 1.0f;
+      hw = h > (float)N ? N : (int)ceilf(h);
+    }
+    const bool full = 2 * hw + 1 >= N;
+    __syncthreads();
+    for (int64_t c0 = m0; c0 < m1; c0 += kPeakCache) {
+      const int cnt = (int)min((int64_t)kPeakCache, m1 - c0);
+      if (!single) prep(c0, cnt, tile == 0);
+      // wave 0 lists, in peak order, the cached peaks within reach of [qlo, qhi]
+      // (the same float comparisons as the per-column test below, so no reached
+      // cell is dropped)
+      if (tid < 64) {
+        int base = 0;
+        for (int j0 = 0; j0 < cnt; j0 += 64) {
+          const int j = j0 + tid;
+          const bool hit = qlo >= 0.0f && j < cnt && pw[j] != 0.0f && (pq[j] - qhi < a.rk) && (qlo - pq[j] < a.rk);
+          const unsigned long long m = __ballot(hit);
+          if (hit) plist[base + __popcll(m & ((1ull << tid) - 1ull))] = j;
+          base += __popcll(m);
+        }
+        if (tid == 0) s_nlist = base;
+      }
+      __syncthreads();
+      const int nl = s_nlist;
+      if (qs >= 0.0f) {
+        for (int l = 0; l < nl; ++l) {
+          const int j = plist[l];
+          const float dq = pq[j] - qs;
+          const float w = pw[j];
+          if (fabsf(dq) >= a.rk) continue;
+          const int ac = pac[j];
+          const float f = pf[j];
+          const float dq2 = dq * dq;
+          if (full) {
+            for (int ai = part; ai < N; ai += kPolarParts) {
+              int u = ai - ac;  // in (-3N/2, 3N/2): bring to [-N/2, N/2)
+              if (u >= N / 2) u -= N;
+              if (u < -N / 2) u += N;
+              float xa = ((float)u - f) * dphi;
+              if (xa > pi_f) xa -= 2.0f * pi_f;
+              if (xa < -pi_f) xa += 2.0f * pi_f;
+              const float dp = xa * qs;
               const float k = kern32(__builtin_amdgcn_sqrtf(dq2 + dp * dp), a.delta, kinv, sig3, a.kernel);
-              if (k > 0.0f) X[rev[u - sh] * kPolarCols + c] += w * k;
+              if (k > 0.0f) X[rev[ai] * kPolarCols + c] += w * k;
+            }
+          } else {
+            // window [ac - hw, ac + hw] in unwrapped bins; fewer than N bins, so each
+            // bin is met by at most one of the three shifts; this thread takes the
+            // bins u - sh = part (mod kPolarParts)
+            const int wlo = ac - hw, whi = ac + hw + 1;
+            for (int sh = -N; sh <= N; sh += N) {
+              const int u0 = max(wlo, sh), u1 = min(whi, sh + N);
+              if (u0 >= u1) continue;
+              const int first = u0 + (part - (u0 - sh) % kPolarParts + kPolarParts) % kPolarParts;
+              for (int u = first; u < u1; u += kPolarParts) {
+                const float dp = ((float)(u - ac) - f) * dqs;
+                const float k = kern32(__builtin_amdgcn_sqrtf(dq2 + dp * dp), a.delta, kinv, sig3, a.kernel);
+                if (k > 0.0f) X[rev[u - sh] * kPolarCols + c] += w * k;
+              }
             }
           }
         }
       }
+      __syncthreads();
+    }
+    // block sums (fixed order): sum of X^2 of this tile, which of its columns
+    // hold any nonzero X (a thread only visits column tid % kPolarCols, so lane
+    // l of a ballot speaks for column l % kPolarCols), and on the first tile the
+    // peak weights (FP16 scale)
+    float xx = 0.0f;
+    bool nz = false;
+    for (int i = tid; i < N * kPolarCols; i += kThreads) {
+      const float v = X[i];
+      xx += v * v;
+      nz = nz || v != 0.0f;
+    }
+    const unsigned long long bal = __ballot(nz);
+    const uint32_t cm = (uint32_t)((bal | (bal >> 16) | (bal >> 32) | (bal >> 48)) & 0xFFFFull);
+    double ws = tile == 0 ? wsum : 0.0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      xx += __shfl_xor(xx, off, 64);
+      ws += __shfl_xor(ws, off, 64);
+    }
+    if ((tid & 63) == 0) {
+      s_red[tid >> 6] = xx;
+      s_red64[tid >> 6] = ws;
+      s_cm[tid >> 6] = cm;
     }
     __syncthreads();
-  }
-  // block sums (fixed order): peak weights (FP16 scale) and sum of X^2 of this
-  // tile; and which columns hold any nonzero X (a thread only visits column
-  // tid % kPolarCols, so lane l of a ballot speaks for column l % kPolarCols)
-  static_assert(64 % kPolarCols == 0 && kPolarCols == 16, "column mask folding assumes 16 columns");
-  float xx = 0.0f;
-  bool nz = false;
-  for (int i = tid; i < N * kPolarCols; i += kThreads) {
-    const float v = X[i];
-    xx += v * v;
-    nz = nz || v != 0.0f;
-  }
-  const unsigned long long bal = __ballot(nz);
-  const uint32_t cm = (uint32_t)((bal | (bal >> 16) | (bal >> 32) | (bal >> 48)) & 0xFFFFull);
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    xx += __shfl_xor(xx, off, 64);
-    wsum += __shfl_xor(wsum, off, 64);
-  }
-  if ((tid & 63) == 0) {
-    s_red[tid >> 6] = xx;
-    s_red64[tid >> 6] = wsum;
-    s_cm[tid >> 6] = cm;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    float t = 0.0f;
-    double u = 0.0;
-    uint32_t m = 0;
-    for (int w = 0; w < kThreads / 64; ++w) {
-      t += s_red[w];
-      u += s_red64[w];
-      m |= s_cm[w];
-    }
-    s_red[0] = t;
-    s_red64[0] = u;
-    s_cm[0] = m;
-  }
-  __syncthreads();
-  const bool bad = s_bad != 0;
-  const bool empty = (m1 <= m0);
-  float sc = 1.0f;
-  if (a.lowp == ACOM_FP16) {
-    // |FFT{X}| <= sum_a X <= N * sum_m w_m; map that bound below 2^14.
-    const double bound = s_red64[0] * N;
-    if (bound > 0.0) {
-      int e = (int)floor(log2(16384.0 / bound));
-      e = max(-60, min(60, e));
-      sc = ldexpf(1.0f, e);
-    }
-  }
-  if (tid == 0) {
-    a.xnorm2[(size_t)p * a.ntiles + tile] = bad ? 0.0f : s_red[0];
-    if (a.cmask) a.cmask[(size_t)p * a.ntiles + tile] = bad ? 0u : s_cm[0];
-    if (tile == 0) {
-      a.flags[p] = bad ? 1 : (empty ? 2 : 0);
-      a.scale[p] = sc;
-    }
-  }
-  if (a.Ximg) {
-    for (int i = tid; i < N * kPolarCols; i += kThreads) {
-      const int ai = i / kPolarCols, cc = i % kPolarCols;
-      if (col0 + cc < a.R) a.Ximg[((size_t)p * N + ai) * a.R + col0 + cc] = bad ? 0.0f : X[rev[ai] * kPolarCols + cc];
-    }
-  }
-  if (!a.do_fft) return;
-  __syncthreads();
-  if constexpr (NT > 0)
-    block_fft_inplace_ct<NT, NS>(b0, tw, 1.0f);
-  else
-    block_fft_inplace(b0, tw, N, NS, a.rad, a.nrad, 1.0f);
-  const float2* F = b0;
-  // unpack: column 2q = (Z_k + conj Z_{N-k}) / 2, column 2q+1 = -i (Z_k - conj Z_{N-k}) / 2
-  const size_t pbase = (size_t)(p >> 6) * a.ld_tile + (size_t)(p & 63) * a.ldp;
-  for (int it = tid; it < a.Nk * NS; it += kThreads) {
-    const int k = it / NS, q = it % NS;
-    const float2 Zk = F[k * NS + q];
-    const float2 Zn = F[(k == 0 ? 0 : N - k) * NS + q];
-    float2 E = make_float2(0.5f * (Zk.x + Zn.x), 0.5f * (Zk.y - Zn.y));
-    float2 O = make_float2(0.5f * (Zk.y + Zn.y), -0.5f * (Zk.x - Zn.x));
-    if (bad) E = O = make_float2(0.0f, 0.0f);
-    const int s0 = col0 + 2 * q;
-    const size_t o = pbase + (size_t)k * a.ldk + s0;
-    if (a.out_cols == a.Rp) {  // workspace layout: the column pair is one aligned 8-byte / 4-byte store
-      *reinterpret_cast<float2*>(a.xr + o) = make_float2(E.x, O.x);
-      *reinterpret_cast<float2*>(a.xi + o) = make_float2(E.y, O.y);
-      if (a.lowp == ACOM_BF16) {
-        *reinterpret_cast<uint32_t*>(a.lr + o) = (uint32_t)to_bf16_bits(E.x) | ((uint32_t)to_bf16_bits(O.x) << 16);
-        *reinterpret_cast<uint32_t*>(a.li + o) = (uint32_t)to_bf16_bits(E.y) | ((uint32_t)to_bf16_bits(O.y) << 16);
-      } else if (a.lowp == ACOM_FP16) {
-        *reinterpret_cast<uint32_t*>(a.lr + o) =
-            (uint32_t)to_f16_bits(E.x * sc) | ((uint32_t)to_f16_bits(O.x * sc) << 16);
-        *reinterpret_cast<uint32_t*>(a.li + o) =
-            (uint32_t)to_f16_bits(E.y * sc) | ((uint32_t)to_f16_bits(O.y * sc) << 16);
+    if (tid == 0) {
+      float t = 0.0f;
+      double u = 0.0;
+      uint32_t m = 0;
+      for (int w = 0; w < kThreads / 64; ++w) {
+        t += s_red[w];
+        u += s_red64[w];
+        m |= s_cm[w];
       }
-    } else {  // caller's [p][k][s] layout with s < out_cols (verification entry point)
-      if (s0 < a.out_cols) {
-        a.xr[o] = E.x;
-        a.xi[o] = E.y;
+      const bool bad = s_bad != 0;
+      if (tile == 0) {
+        float scl = 1.0f;
+        if (a.lowp == ACOM_FP16) {
+          // |FFT{X}| <= sum_a X <= N * sum_m w_m; map that bound below 2^14.
+          const double bound = u * N;
+          if (bound > 0.0) {
+            int e = (int)floor(log2(16384.0 / bound));
+            e = max(-60, min(60, e));
+            scl = ldexpf(1.0f, e);
+          }
+        }
+        s_sc = scl;
+        a.flags[p] = bad ? 1 : (m1 <= m0 ? 2 : 0);
+        a.scale[p] = scl;
       }
-      if (s0 + 1 < a.out_cols) {
-        a.xr[o + 1] = O.x;
-        a.xi[o + 1] = O.y;
+      a.xnorm2[(size_t)p * a.ntiles + tile] = bad ? 0.0f : t;
+      if (a.cmask) a.cmask[(size_t)p * a.ntiles + tile] = bad ? 0u : m;
+      s_cm[0] = m;
+    }
+    __syncthreads();
+    const bool bad = s_bad != 0;
+    sc = s_sc;
+    if (a.Ximg) {
+      for (int i = tid; i < N * kPolarCols; i += kThreads) {
+        const int ai = i / kPolarCols, cc = i % kPolarCols;
+        if (col0 + cc < a.R) a.Ximg[((size_t)p * N + ai) * a.R + col0 + cc] = bad ? 0.0f : X[rev[ai] * kPolarCols + cc];
       }
     }
+    if (!a.do_fft) {
+      __syncthreads();
+      continue;
+    }
+    if (s_cm[0] != 0u) {  // a tile of zeros has a zero spectrum: its LDS already holds it
+      if constexpr (NT > 0)
+        block_fft_inplace_ct<NT, NS>(b0, tw, 1.0f);
+      else
+        block_fft_inplace(b0, tw, N, NS, a.rad, a.nrad, 1.0f);
+    }
+    const float2* F = b0;
+    // unpack: column 2q = (Z_k + conj Z_{N-k}) / 2, column 2q+1 = -i (Z_k - conj Z_{N-k}) / 2
+    for (int it = tid; it < a.Nk * NS; it += kThreads) {
+      const int k = it / NS, q = it % NS;
+      const float2 Zk = F[k * NS + q];
+      const float2 Zn = F[(k == 0 ? 0 : N - k) * NS + q];
+      float2 E = make_float2(0.5f * (Zk.x + Zn.x), 0.5f * (Zk.y - Zn.y));
+      float2 O = make_float2(0.5f * (Zk.y + Zn.y), -0.5f * (Zk.x - Zn.x));
+      if (bad) E = O = make_float2(0.0f, 0.0f);
+      const int s0 = col0 + 2 * q;
+      const size_t o = pbase + (size_t)k * a.ldk + s0;
+      if (a.out_cols == a.Rp) {  // workspace layout: the column pair is one aligned 8-byte / 4-byte store
+        *reinterpret_cast<float2*>(a.xr + o) = make_float2(E.x, O.x);
+        *reinterpret_cast<float2*>(a.xi + o) = make_float2(E.y, O.y);
+        if (a.lowp == ACOM_BF16) {
+          *reinterpret_cast<uint32_t*>(a.lr + o) = (uint32_t)to_bf16_bits(E.x) | ((uint32_t)to_bf16_bits(O.x) << 16);
+          *reinterpret_cast<uint32_t*>(a.li + o) = (uint32_t)to_bf16_bits(E.y) | ((uint32_t)to_bf16_bits(O.y) << 16);
+        } else if (a.lowp == ACOM_FP16) {
+          *reinterpret_cast<uint32_t*>(a.lr + o) =
+              (uint32_t)to_f16_bits(E.x * sc) | ((uint32_t)to_f16_bits(O.x * sc) << 16);
+          *reinterpret_cast<uint32_t*>(a.li + o) =
+              (uint32_t)to_f16_bits(E.y * sc) | ((uint32_t)to_f16_bits(O.y * sc) << 16);
+        }
+      } else {  // caller's [p][k][s] layout with s < out_cols (verification entry point)
+        if (s0 < a.out_cols) {
+          a.xr[o] = E.x;
+          a.xi[o] = E.y;
+        }
+        if (s0 + 1 < a.out_cols) {
+          a.xr[o + 1] = O.x;
+          a.xi[o + 1] = O.y;
+        }
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -1189,7 +1230,8 @@ WsLayout layout(const PlanDev& d, bool lowp, int Pc) {
 }
 
 size_t polar_lds(const PlanDev& d) {
-  return (size_t)(d.N * (kPolarCols / 2) + d.N) * sizeof(float2) + (size_t)d.N * 4 + kPeakCache * (4 + 4 + 4 + 4);
+  return (size_t)(d.N * (kPolarCols / 2) + d.N) * sizeof(float2) + (size_t)d.N * 4 + kPeakCache * (4 + 4 + 4 + 4 + 4) +
+         (size_t)d.Rp * 4;
 }
 size_t exact_lds(const PlanDev& d) {
   return (size_t)(kBatch * d.N + d.N) * sizeof(float2) + (size_t)d.N * 4 + (size_t)d.Z * 4 + (size_t)d.Rp;
@@ -1264,7 +1306,7 @@ acom_status_t launch_polar_n(const PlanDev& d, const PolarArgs& a, hipStream_t s
   PolarArgs b = a;
   b.ntiles = d.Rp / kPolarCols;
   b.per = 0;
-  const int nblocks = g_tune.polar_xcd ? xcd_blocks(b.np * b.ntiles, &b.per) : b.np * b.ntiles;
+  const int nblocks = g_tune.polar_xcd ? xcd_blocks(b.np, &b.per) : b.np;
   ProfScope prof(0, s);
   polar_kernel<NT><<<dim3(nblocks), kThreads, polar_lds(d), s>>>(b);
   ACOM_HIP(hipGetLastError());

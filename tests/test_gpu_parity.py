@@ -259,9 +259,10 @@ def test_match_ragged_radial_padding(acom, n_radial, precision):
     _check_decisions(opl, d, res, range(40), top_k=2)
 
 
-@pytest.mark.parametrize("n_angular", [48, 150])
+@pytest.mark.parametrize("n_angular", [48, 72, 150])
 def test_match_generic_angular_length(acom, n_angular):
-    """Angular lengths without a compile-time FFT schedule (generic in-place FFT)."""
+    """Angular lengths without a compile-time FFT schedule (generic in-place FFT;
+    radices 8, 2, 3 for 48, 8, 9 for 72 and 2, 3, 5, 5 for 150)."""
     cfg = dict(k_max=1.2, n_radial=32, n_angular=n_angular, zone_step_deg=5.0)
     opl = helpers.oracle_plan(["fcc"], **cfg)
     gpl = helpers.gpu_plan(["fcc"], **cfg)
@@ -274,6 +275,7 @@ def test_match_generic_angular_length(acom, n_angular):
         assert np.abs(X[p] - Xo).max() <= 1e-5 * np.abs(Xo).max()
         F = np.fft.rfft(Xo, axis=0)
         assert np.abs(Xr[p].cpu().numpy() - F.real).max() <= 1e-5 * np.abs(F).max()
+        assert np.abs(Xi[p].cpu().numpy() - F.imag).max() <= 1e-5 * np.abs(F).max()
     res = gpl.match(pk, top_k=2, precision="bf16")
     torch.cuda.synchronize()
     res = {k: v.cpu().numpy() for k, v in res.items() if v is not None}
