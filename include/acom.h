@@ -238,10 +238,8 @@ acom_status_t acom_profile_end(void);
  *        1 = zone tiles fastest with the tiles of one pattern group on one XCD (default);
  * key 1: radii staged per LDS step by the BF16/FP16 contraction: 32, 64 (default), 128 (the largest dividing Rp is used);
  * key 2: exact-pass pattern order, 1 = XCD-grouped (default), 0 = plain;
- * key 3: polar-pass order, 1 = the radial tiles of one pattern back to back on one XCD (default),
- *        0 = pattern index fastest;
- * key 4: contraction pipeline, 1 = double-buffered LDS with direct global-to-LDS loads (default),
- *        0 = single buffer staged through registers. */
+ * key 3: polar-pass order, 1 = consecutive patterns grouped on one XCD (default),
+ *        0 = pattern index fastest. */
 acom_status_t acom_set_tuning(int32_t key, int32_t value);
 
 /* ------------------------------------------------------------- errors ---- */

@@ -6,7 +6,7 @@
 //                      along phi3 (in-place mixed-radix FFT, two real columns
 //                      packed in one complex sequence); writes FFT{X} in FP32
 //                      and, for the low-precision contraction, BF16/FP16 copies.
-//  2. bound_pipe_kernel (or bound_kernel) - the per-frequency contraction
+//  2. bound_kernel   - the per-frequency contraction
 //                      G_k = sum_s FFT{P}^* FFT{X} (and the mirror G'_k with
 //                      FFT{X}^*) on MFMA for a 64x64 (pattern x zone) tile,
 //                      streaming over k and accumulating
@@ -398,222 +398,46 @@ struct BoundArgs {
   int ldU, np, Zvalid;
 };
 
-// Operand element type per kind (0: FP32, 1: BF16, 2: FP16) and LDS row padding.
+// Operand element type per kind (0: FP32, 1: BF16, 2: FP16).
 template <int KIND>
 struct BoundTraits {
   typedef uint16_t T;
-  static constexpr int PAD = 8;
 };
 template <>
 struct BoundTraits<0> {
   typedef float T;
-  static constexpr int PAD = 4;
 };
 
-// One workgroup: 64 patterns x 64 zones, 4 waves of 32 x 32 (2 x 2 MFMA blocks
-// of 16 x 16).  For each frequency k the K loop runs over s in steps of KCH
-// radii (KCH divides Rp) staged through LDS; four accumulators per block
-// give the real products A = Xr Pr, B = Xi Pi, C = Xi Pr, D = Xr Pi, so
+// Contraction.  One workgroup: 64 patterns x 64 zones, 4 waves of 32 x 32 (2 x 2
+// MFMA blocks of 16 x 16).  For each frequency k the K loop runs over s in
+// steps of KCH radii (KCH divides Rp); four accumulators per block give the
+// real products A = Xr Pr, B = Xi Pi, C = Xi Pr, D = Xr Pi, so
 // G = (A + B) + i (C - D) and G_mirror = (A - B) - i (C + D), whose larger
 // squared modulus is S + 2 |T| with S = A^2 + B^2 + C^2 + D^2, T = A B - C D
-// (one square root per element and frequency).  Lanes of a
-// quarter-wave (l / 16) take the contiguous s-range 8 (l / 16) .. +7 of every
-// 32 radii for both operands: the same permutation of the contraction index on
-// both sides.
-template <int KIND, int KCH>
-__global__ void __launch_bounds__(kThreads) bound_kernel(BoundArgs a) {
-  static_assert(KIND != 0 || KCH == 32, "FP32 operands use 32-radius steps");
-  typedef typename BoundTraits<KIND>::T T;
-  constexpr int LD = KCH + BoundTraits<KIND>::PAD;
-  constexpr int VEC = 16 / sizeof(T);        // elements per 16-byte vector
-  constexpr int PER_ROW = KCH / VEC;         // vectors per row per step
-  constexpr int NV = kTileP * PER_ROW / kThreads;  // vectors per thread per array
-  __shared__ __align__(16) T sXr[kTileP * LD];
-  __shared__ __align__(16) T sXi[kTileP * LD];
-  __shared__ __align__(16) T sPr[kTileZ * LD];
-  __shared__ __align__(16) T sPi[kTileZ * LD];
-
-  int tp, tz;
-  if (a.order == 0) {  // pattern tiles fastest: concurrent blocks share one zone tile
-    tp = blockIdx.x % a.nP;
-    tz = blockIdx.x / a.nP;
-  } else {             // XCD-grouped, zone tiles fastest: concurrent blocks share pattern tiles
-    const int w = xcd_item(a.per);
-    if (w >= a.nP * a.nZ) return;
-    tp = w / a.nZ;
-    tz = w % a.nZ;
-  }
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
-  const int li = lane & 15;  // row within a 16-block
-  const int lg = lane >> 4;  // quarter-wave
-
-  float U[2][2][4];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) U[i][j][r] = 0.0f;
-
-  const size_t slab = (size_t)a.Nk * 64 * a.Rp;
-  const T* gxr = reinterpret_cast<const T*>(a.xr) + (size_t)tp * slab;
-  const T* gxi = reinterpret_cast<const T*>(a.xi) + (size_t)tp * slab;
-  const T* gpr = reinterpret_cast<const T*>(a.pr) + (size_t)tz * slab;
-  const T* gpi = reinterpret_cast<const T*>(a.pi) + (size_t)tz * slab;
-  const int steps_per_k = a.Rp / KCH;
-  const int nsteps = a.Nk * steps_per_k;
-
-  f32x4 acc[2][2][4];
-  for (int stp = 0; stp < nsteps; ++stp) {
-    {  // stage KCH radii of frequency k: 64 rows of each operand, 16-byte vectors
-      const int k = stp / steps_per_k;
-      const int s0 = (stp - k * steps_per_k) * KCH;
-      const size_t base = (size_t)k * 64 * a.Rp + s0;
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const int idx = tid + v * kThreads;
-        const int row = idx / PER_ROW, cv = idx % PER_ROW;
-        const size_t g = base + (size_t)row * a.Rp + cv * VEC;
-        const int l = row * LD + cv * VEC;
-        *reinterpret_cast<uint4*>(&sXr[l]) = *reinterpret_cast<const uint4*>(gxr + g);
-        *reinterpret_cast<uint4*>(&sXi[l]) = *reinterpret_cast<const uint4*>(gxi + g);
-        *reinterpret_cast<uint4*>(&sPr[l]) = *reinterpret_cast<const uint4*>(gpr + g);
-        *reinterpret_cast<uint4*>(&sPi[l]) = *reinterpret_cast<const uint4*>(gpi + g);
-      }
-    }
-    __syncthreads();
-    // MFMAs of this step; the first step of a frequency starts its accumulators at 0
-    auto step_mfma = [&](auto zc) {
-      constexpr bool Z = decltype(zc)::value;
-      const f32x4 zero4 = {0.0f, 0.0f, 0.0f, 0.0f};
-      if constexpr (KIND == 0) {
-        float fxr[2][8], fxi[2][8], fpr[2][8], fpi[2][8];
-  #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          const int rx = (wr * 32 + i * 16 + li) * LD + lg * 8;
-          const int rp = (wc * 32 + i * 16 + li) * LD + lg * 8;
-  #pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            float4 t;
-            t = *reinterpret_cast<const float4*>(&sXr[rx + 4 * h]);
-            fxr[i][4 * h] = t.x; fxr[i][4 * h + 1] = t.y; fxr[i][4 * h + 2] = t.z; fxr[i][4 * h + 3] = t.w;
-            t = *reinterpret_cast<const float4*>(&sXi[rx + 4 * h]);
-            fxi[i][4 * h] = t.x; fxi[i][4 * h + 1] = t.y; fxi[i][4 * h + 2] = t.z; fxi[i][4 * h + 3] = t.w;
-            t = *reinterpret_cast<const float4*>(&sPr[rp + 4 * h]);
-            fpr[i][4 * h] = t.x; fpr[i][4 * h + 1] = t.y; fpr[i][4 * h + 2] = t.z; fpr[i][4 * h + 3] = t.w;
-            t = *reinterpret_cast<const float4*>(&sPi[rp + 4 * h]);
-            fpi[i][4 * h] = t.x; fpi[i][4 * h + 1] = t.y; fpi[i][4 * h + 2] = t.z; fpi[i][4 * h + 3] = t.w;
-          }
-        }
-  #pragma unroll
-        for (int t = 0; t < 8; ++t)
-  #pragma unroll
-          for (int i = 0; i < 2; ++i)
-  #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-              acc[i][j][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxr[i][t], fpr[j][t], Z && t == 0 ? zero4 : acc[i][j][0], 0, 0, 0);
-              acc[i][j][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxi[i][t], fpi[j][t], Z && t == 0 ? zero4 : acc[i][j][1], 0, 0, 0);
-              acc[i][j][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxi[i][t], fpr[j][t], Z && t == 0 ? zero4 : acc[i][j][2], 0, 0, 0);
-              acc[i][j][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxr[i][t], fpi[j][t], Z && t == 0 ? zero4 : acc[i][j][3], 0, 0, 0);
-            }
-      } else {
-        typedef typename std::conditional<KIND == 1, bf16x8, f16x8>::type V8;
-  #pragma unroll
-        for (int sub = 0; sub < KCH / 32; ++sub) {
-          V8 fxr[2], fxi[2], fpr[2], fpi[2];
-  #pragma unroll
-          for (int i = 0; i < 2; ++i) {
-            const int rx = (wr * 32 + i * 16 + li) * LD + sub * 32 + lg * 8;
-            const int rp = (wc * 32 + i * 16 + li) * LD + sub * 32 + lg * 8;
-            fxr[i] = *reinterpret_cast<const V8*>(&sXr[rx]);
-            fxi[i] = *reinterpret_cast<const V8*>(&sXi[rx]);
-            fpr[i] = *reinterpret_cast<const V8*>(&sPr[rp]);
-            fpi[i] = *reinterpret_cast<const V8*>(&sPi[rp]);
-          }
-  #pragma unroll
-          for (int i = 0; i < 2; ++i)
-  #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-              if constexpr (KIND == 1) {
-                acc[i][j][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fxr[i], fpr[j], Z && sub == 0 ? zero4 : acc[i][j][0], 0, 0, 0);
-                acc[i][j][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fxi[i], fpi[j], Z && sub == 0 ? zero4 : acc[i][j][1], 0, 0, 0);
-                acc[i][j][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fxi[i], fpr[j], Z && sub == 0 ? zero4 : acc[i][j][2], 0, 0, 0);
-                acc[i][j][3] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fxr[i], fpi[j], Z && sub == 0 ? zero4 : acc[i][j][3], 0, 0, 0);
-              } else {
-                acc[i][j][0] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fxr[i], fpr[j], Z && sub == 0 ? zero4 : acc[i][j][0], 0, 0, 0);
-                acc[i][j][1] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fxi[i], fpi[j], Z && sub == 0 ? zero4 : acc[i][j][1], 0, 0, 0);
-                acc[i][j][2] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fxi[i], fpr[j], Z && sub == 0 ? zero4 : acc[i][j][2], 0, 0, 0);
-                acc[i][j][3] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fxr[i], fpi[j], Z && sub == 0 ? zero4 : acc[i][j][3], 0, 0, 0);
-              }
-            }
-        }
-      }
-    };
-    if (stp % steps_per_k == 0)
-      step_mfma(std::true_type{});
-    else
-      step_mfma(std::false_type{});
-    const int k = stp / steps_per_k;
-    if (stp - k * steps_per_k == steps_per_k - 1) {  // last radii of frequency k
-      const float wk = (k == 0 || 2 * k == a.N) ? 1.0f : 2.0f;
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const float A = acc[i][j][0][r], B = acc[i][j][1][r], C = acc[i][j][2][r], D = acc[i][j][3][r];
-            // max(|G|^2, |G_mirror|^2) = S + 2 |T|, S = A^2 + B^2 + C^2 + D^2, T = A B - C D
-            const float S = fmaf(A, A, fmaf(B, B, fmaf(C, C, D * D)));
-            const float T = fmaf(A, B, -(C * D));
-            // hardware square root (<= 1 ulp): the certificate's relative slack covers it
-            U[i][j][r] += wk * __builtin_amdgcn_sqrtf(fmaf(2.0f, fabsf(T), S));
-          }
-        }
-    }
-    __syncthreads();
-  }
-  const float invN = 1.0f / (float)a.N;
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int p = tp * kTileP + wr * 32 + i * 16 + lg * 4 + r;
-      if (p >= a.np) continue;
-      const float inv = invN / a.scale[p];
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int z = tz * kTileZ + wc * 32 + j * 16 + li;
-        if (z < a.Zvalid) a.U[(size_t)p * a.ldU + z] = U[i][j][r] * inv;
-      }
-    }
-}
-
-// Pipelined contraction: the operand tiles of step stp + 1 travel from global
-// memory straight into LDS (global_load_lds_dwordx4, no registers) while the
-// MFMAs of step stp run on the other of two LDS buffers, with one barrier per
-// step.  A staged row holds KCH radii (RB = 128 or 256 bytes) with no padding;
-// its 16-byte chunks are XOR-permuted by row so that the 16 rows one
-// quarter-wave reads for an MFMA operand fall in 16 distinct bank groups.
-// Tile shape, lane mapping, accumulators and epilogue are those of bound_kernel.
+// (one square root per element and frequency).  Both operands use the same
+// assignment of radii to lanes (a permutation of the contraction index).
+//
+// Pipeline: the operand tiles of step stp + 1 travel from global memory
+// straight into LDS (global_load_lds_dwordx4, no registers) while the MFMAs of
+// step stp run on the other of two LDS buffers, with one barrier per step.  A
+// staged row holds KCH radii (RB = 64, 128 or 256 bytes) with no padding; its
+// 16-byte chunks are XOR-permuted by row so that the 16 rows one quarter-wave
+// reads for an MFMA operand fall in 16 distinct bank groups.
 template <int RB>
 __device__ __forceinline__ int chunk_swizzle(int row) {
-  return RB == 128 ? ((row >> 1) & 7) : (row & 15);
+  return RB == 64 ? ((row >> 2) & 3) : RB == 128 ? ((row >> 1) & 7) : (row & 15);
 }
 
 template <int KIND, int KCH>
-constexpr int pipe_stage_bytes() {
+constexpr int bound_stage_bytes() {
   return 4 * 64 * KCH * (int)sizeof(typename BoundTraits<KIND>::T);
 }
 
 template <int KIND, int KCH>
-__global__ void __launch_bounds__(kThreads) bound_pipe_kernel(BoundArgs a) {
+__global__ void __launch_bounds__(kThreads) bound_kernel(BoundArgs a) {
   typedef typename BoundTraits<KIND>::T T;
   constexpr int RB = KCH * (int)sizeof(T);  // bytes per staged row
-  static_assert(RB == 128 || RB == 256, "staged rows of 128 or 256 bytes");
+  static_assert(RB == 64 || RB == 128 || RB == 256, "staged rows of 64, 128 or 256 bytes");
   static_assert(KIND != 0 || KCH == 32, "FP32 operands use 32-radius steps");
   constexpr int VEC = 16 / (int)sizeof(T);  // elements per 16-byte chunk
   constexpr int ARR = 64 * RB;              // bytes of one operand array per stage
@@ -1167,8 +991,7 @@ struct Tuning {
   int bound_order = 1;    // 0: pattern tiles fastest, 1: XCD-grouped zone tiles fastest
   int bound_kch16 = 64;   // radii per LDS step of the 16-bit contraction (32, 64 or 128)
   int exact_xcd = 1;      // exact pass: XCD-grouped pattern order
-  int polar_xcd = 1;      // polar pass: radial tiles of one pattern consecutive on one XCD
-  int bound_pipe = 1;     // contraction: 1 = double-buffered LDS-direct loads, 0 = staged through registers
+  int polar_xcd = 1;      // polar pass: consecutive patterns grouped on one XCD
 };
 Tuning g_tune;
 
@@ -1352,48 +1175,25 @@ acom_status_t launch_bound(const PlanDev& d, int precision, const WsLayout& L, u
     b.pr = d.d_PR16[precision];
     b.pi = d.d_PI16[precision];
   }
-  int kch = g_tune.bound_kch16;
+  int kch = g_tune.bound_kch16;  // 16-bit operands: the largest of 128, 64, 32 not above the setting dividing Rp
   while (d.Rp % kch) kch /= 2;
-  if (g_tune.bound_pipe) {
-    acom_status_t st = ACOM_OK;
-    if (precision == ACOM_FP32) {
-      if ((st = ensure_lds(bound_pipe_kernel<0, 32>, 2 * pipe_stage_bytes<0, 32>())) != ACOM_OK) return st;
-      ProfScope prof(1, s);
-      bound_pipe_kernel<0, 32><<<grid, kThreads, 2 * pipe_stage_bytes<0, 32>(), s>>>(b);
-    } else if (kch == 128) {
-      auto kern = precision == ACOM_BF16 ? bound_pipe_kernel<1, 128> : bound_pipe_kernel<2, 128>;
-      if ((st = ensure_lds(kern, 2 * pipe_stage_bytes<1, 128>())) != ACOM_OK) return st;
-      ProfScope prof(1, s);
-      kern<<<grid, kThreads, 2 * pipe_stage_bytes<1, 128>(), s>>>(b);
-    } else {  // Rp is a multiple of 32: 64-radius steps need Rp % 64 == 0, else the staged kernel runs
-      if (d.Rp % 64 == 0) {
-        auto kern = precision == ACOM_BF16 ? bound_pipe_kernel<1, 64> : bound_pipe_kernel<2, 64>;
-        if ((st = ensure_lds(kern, 2 * pipe_stage_bytes<1, 64>())) != ACOM_OK) return st;
-        ProfScope prof(1, s);
-        kern<<<grid, kThreads, 2 * pipe_stage_bytes<1, 64>(), s>>>(b);
-      } else {
-        ProfScope prof(1, s);
-        if (precision == ACOM_BF16) bound_kernel<1, 32><<<grid, kThreads, 0, s>>>(b);
-        else bound_kernel<2, 32><<<grid, kThreads, 0, s>>>(b);
-      }
-    }
-    ACOM_HIP(hipGetLastError());
+  acom_status_t st = ACOM_OK;
+  auto launch = [&](auto kern, size_t lds) -> acom_status_t {
+    acom_status_t e = ensure_lds(kern, lds);
+    if (e != ACOM_OK) return e;
+    ProfScope prof(1, s);
+    kern<<<grid, kThreads, lds, s>>>(b);
     return ACOM_OK;
-  }
-  ProfScope prof(1, s);
-  if (precision == ACOM_FP32) {
-    bound_kernel<0, 32><<<grid, kThreads, 0, s>>>(b);
-  } else {
-    if (precision == ACOM_BF16) {
-      if (kch == 128) bound_kernel<1, 128><<<grid, kThreads, 0, s>>>(b);
-      else if (kch == 64) bound_kernel<1, 64><<<grid, kThreads, 0, s>>>(b);
-      else bound_kernel<1, 32><<<grid, kThreads, 0, s>>>(b);
-    } else {
-      if (kch == 128) bound_kernel<2, 128><<<grid, kThreads, 0, s>>>(b);
-      else if (kch == 64) bound_kernel<2, 64><<<grid, kThreads, 0, s>>>(b);
-      else bound_kernel<2, 32><<<grid, kThreads, 0, s>>>(b);
-    }
-  }
+  };
+  if (precision == ACOM_FP32)
+    st = launch(bound_kernel<0, 32>, 2 * bound_stage_bytes<0, 32>());
+  else if (kch == 128)
+    st = launch(precision == ACOM_BF16 ? bound_kernel<1, 128> : bound_kernel<2, 128>, 2 * bound_stage_bytes<1, 128>());
+  else if (kch == 64)
+    st = launch(precision == ACOM_BF16 ? bound_kernel<1, 64> : bound_kernel<2, 64>, 2 * bound_stage_bytes<1, 64>());
+  else
+    st = launch(precision == ACOM_BF16 ? bound_kernel<1, 32> : bound_kernel<2, 32>, 2 * bound_stage_bytes<1, 32>());
+  if (st != ACOM_OK) return st;
   ACOM_HIP(hipGetLastError());
   return ACOM_OK;
 }
@@ -1668,10 +1468,6 @@ extern "C" acom_status_t acom_set_tuning(int32_t key, int32_t value) {
     case 3:
       if (value != 0 && value != 1) return fail(ACOM_E_INVALID, "polar order must be 0 or 1");
       g_tune.polar_xcd = value;
-      return ACOM_OK;
-    case 4:
-      if (value != 0 && value != 1) return fail(ACOM_E_INVALID, "contraction pipeline must be 0 or 1");
-      g_tune.bound_pipe = value;
       return ACOM_OK;
 
   }
