@@ -239,7 +239,10 @@ acom_status_t acom_profile_end(void);
  * key 1: radii staged per LDS step by the BF16/FP16 contraction: 32, 64 (default), 128 (the largest dividing Rp is used);
  * key 2: exact-pass pattern order, 1 = XCD-grouped (default), 0 = plain;
  * key 3: polar-pass order, 1 = consecutive patterns grouped on one XCD (default),
- *        0 = pattern index fastest. */
+ *        0 = pattern index fastest;
+ * key 4: contraction block tile, 0 = 64 x 64, 1 = large (128 x 128; 128 x 64 for FP32 operands),
+ *        2 = large for BF16/FP16 operands when it gives at least two tiles per compute unit,
+ *        else 64 x 64 (default). */
 acom_status_t acom_set_tuning(int32_t key, int32_t value);
 
 /* ------------------------------------------------------------- errors ---- */

@@ -389,7 +389,8 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
 
 struct BoundArgs {
   int Nk, Rp, N;
-  int nP, nZ, per;          // pattern tiles, zone tiles, XCD items per XCD
+  int nP, nZ, per;          // block tiles over patterns and zones, XCD items per XCD
+  int nX64, nP64;           // 64-row layout tiles of the pattern and zone operands
   int order;                // block order (see bound_kernel)
   const void *xr, *xi;      // tile-major over patterns (local to the chunk)
   const void *pr, *pi;      // tile-major over zones
@@ -428,21 +429,41 @@ __device__ __forceinline__ int chunk_swizzle(int row) {
   return RB == 64 ? ((row >> 2) & 3) : RB == 128 ? ((row >> 1) & 7) : (row & 15);
 }
 
-template <int KIND, int KCH>
+template <int KIND, int KCH, int WM, int WN, int IM, int JN>
 constexpr int bound_stage_bytes() {
-  return 4 * 64 * KCH * (int)sizeof(typename BoundTraits<KIND>::T);
+  return 2 * (WM * IM + WN * JN) * 16 * KCH * (int)sizeof(typename BoundTraits<KIND>::T);
 }
 
-template <int KIND, int KCH>
-__global__ void __launch_bounds__(kThreads) bound_kernel(BoundArgs a) {
+// Whether a step of KCH radii of both operands splits into whole KiB per wave,
+// the double-buffered stages fit the LDS, and (FP32) the fragments and
+// accumulators of a wave fit the registers of two waves per SIMD.
+template <int KIND, int KCH, int WM, int WN, int IM, int JN>
+constexpr bool bound_shape_ok() {
+  const int rb = KCH * (int)sizeof(typename BoundTraits<KIND>::T);
+  const int nw = WM * WN;
+  return (16 * WM * IM * rb) % (1024 * nw) == 0 && (16 * WN * JN * rb) % (1024 * nw) == 0 &&
+         2 * bound_stage_bytes<KIND, KCH, WM, WN, IM, JN>() <= 160 * 1024 && (KIND != 0 || IM * JN <= 4);
+}
+
+// Block tile: WM x WN waves, each computing IM x JN MFMA blocks of 16 x 16
+// (patterns x zones); TP = 16 WM IM patterns by TZ = 16 WN JN zones.  Operand
+// rows come from the 64-row tiles of the tile-major layout; rows past the end
+// of an operand array are read from its last tile (their results are never
+// stored), and a wave whose zones all lie past Zvalid skips its MFMAs.
+template <int KIND, int KCH, int WM, int WN, int IM, int JN>
+__global__ void __launch_bounds__(64 * WM * WN) bound_kernel(BoundArgs a) {
   typedef typename BoundTraits<KIND>::T T;
+  constexpr int NW = WM * WN;
+  constexpr int TP = 16 * WM * IM, TZ = 16 * WN * JN;
   constexpr int RB = KCH * (int)sizeof(T);  // bytes per staged row
   static_assert(RB == 64 || RB == 128 || RB == 256, "staged rows of 64, 128 or 256 bytes");
   static_assert(KIND != 0 || KCH == 32, "FP32 operands use 32-radius steps");
+  static_assert(TP % 64 == 0 && TZ % 64 == 0, "block tiles are whole layout tiles");
   constexpr int VEC = 16 / (int)sizeof(T);  // elements per 16-byte chunk
-  constexpr int ARR = 64 * RB;              // bytes of one operand array per stage
-  constexpr int STAGE = 4 * ARR;
-  constexpr int NI = ARR / 1024 / (kThreads / 64);  // 1 KiB LDS-direct loads per wave per array
+  constexpr int ARRX = TP * RB, ARRP = TZ * RB;  // bytes of one operand array per stage
+  constexpr int STAGE = 2 * ARRX + 2 * ARRP;
+  constexpr int NIX = ARRX / 1024 / NW, NIP = ARRP / 1024 / NW;  // 1 KiB LDS-direct loads per wave per array
+  static_assert(NIX * 1024 * NW == ARRX && NIP * 1024 * NW == ARRP, "whole KiB per wave");
   extern __shared__ __align__(16) unsigned char smem_raw[];
 
   int tp, tz;
@@ -458,115 +479,137 @@ __global__ void __launch_bounds__(kThreads) bound_kernel(BoundArgs a) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wr = wave >> 1, wc = wave & 1;
+  const int wr = wave / WN, wc = wave % WN;
   const int li = lane & 15;
   const int lg = lane >> 4;
+  // this wave's MFMAs matter only if some of its zones and patterns exist
+  const bool live = tz * TZ + wc * JN * 16 < a.Zvalid && tp * TP + wr * IM * 16 < a.np;
 
-  float U[2][2][4];
+  float U[IM][JN][4];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < IM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < JN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) U[i][j][r] = 0.0f;
 
   const size_t slab = (size_t)a.Nk * 64 * a.Rp;
-  const T* gsrc[4] = {reinterpret_cast<const T*>(a.xr) + (size_t)tp * slab,
-                      reinterpret_cast<const T*>(a.xi) + (size_t)tp * slab,
-                      reinterpret_cast<const T*>(a.pr) + (size_t)tz * slab,
-                      reinterpret_cast<const T*>(a.pi) + (size_t)tz * slab};
+  const T* gx[2] = {reinterpret_cast<const T*>(a.xr), reinterpret_cast<const T*>(a.xi)};
+  const T* gp[2] = {reinterpret_cast<const T*>(a.pr), reinterpret_cast<const T*>(a.pi)};
   const int steps_per_k = a.Rp / KCH;
   const int nsteps = a.Nk * steps_per_k;
 
-  // per-lane part of the LDS-direct copy: lane writes bytes [16 lane, 16 lane + 16)
-  // of its wave's KiB, i.e. row r, physical chunk c; it fetches logical chunk
-  // c ^ swizzle(r) of that row
-  size_t src_off[NI];
+  // per-lane part of the LDS-direct copies: lane writes bytes [16 lane, +16) of
+  // its wave's KiB, i.e. block row r, physical chunk c; it fetches logical chunk
+  // c ^ swizzle(r) of that row from layout tile (first tile + r / 64), clamped
+  size_t offx[NIX], offp[NIP];
 #pragma unroll
-  for (int j = 0; j < NI; ++j) {
-    const int byte = (wave * NI + j) * 1024 + lane * 16;
+  for (int j = 0; j < NIX; ++j) {
+    const int byte = (wave * NIX + j) * 1024 + lane * 16;
     const int row = byte / RB, phys = (byte % RB) / 16;
-    src_off[j] = (size_t)row * a.Rp + (size_t)((phys ^ chunk_swizzle<RB>(row)) * VEC);
+    const int t64 = min(tp * (TP / 64) + (row >> 6), a.nX64 - 1);
+    offx[j] = (size_t)t64 * slab + (size_t)(row & 63) * a.Rp + (size_t)((phys ^ chunk_swizzle<RB>(row)) * VEC);
+  }
+#pragma unroll
+  for (int j = 0; j < NIP; ++j) {
+    const int byte = (wave * NIP + j) * 1024 + lane * 16;
+    const int row = byte / RB, phys = (byte % RB) / 16;
+    const int t64 = min(tz * (TZ / 64) + (row >> 6), a.nP64 - 1);
+    offp[j] = (size_t)t64 * slab + (size_t)(row & 63) * a.Rp + (size_t)((phys ^ chunk_swizzle<RB>(row)) * VEC);
   }
   auto issue = [&](int stp, int buf) {
     const int k = stp / steps_per_k;
-    const size_t gbase = (size_t)k * 64 * a.Rp + (size_t)(stp - k * steps_per_k) * KCH;
+    const size_t kbase = (size_t)k * 64 * a.Rp + (size_t)(stp - k * steps_per_k) * KCH;
+    unsigned char* st = smem_raw + buf * STAGE;
 #pragma unroll
-    for (int arr = 0; arr < 4; ++arr)
+    for (int arr = 0; arr < 2; ++arr)
 #pragma unroll
-      for (int j = 0; j < NI; ++j)
+      for (int j = 0; j < NIX; ++j)
+        __builtin_amdgcn_global_load_lds((const void*)(gx[arr] + kbase + offx[j]),
+                                         (__attribute__((address_space(3))) void*)(st + arr * ARRX + (wave * NIX + j) * 1024),
+                                         16, 0, 0);
+#pragma unroll
+    for (int arr = 0; arr < 2; ++arr)
+#pragma unroll
+      for (int j = 0; j < NIP; ++j)
         __builtin_amdgcn_global_load_lds(
-            (const void*)(gsrc[arr] + gbase + src_off[j]),
-            (__attribute__((address_space(3))) void*)(smem_raw + buf * STAGE + arr * ARR + (wave * NI + j) * 1024),
-            16, 0, 0);
+            (const void*)(gp[arr] + kbase + offp[j]),
+            (__attribute__((address_space(3))) void*)(st + 2 * ARRX + arr * ARRP + (wave * NIP + j) * 1024), 16, 0, 0);
   };
   // byte offset of (row, logical chunk) inside one operand array of a stage
   auto at = [](int row, int chunk) { return row * RB + ((chunk ^ chunk_swizzle<RB>(row)) << 4); };
 
-  f32x4 acc[2][2][4];
+  f32x4 acc[IM][JN][4];
   issue(0, 0);
   for (int stp = 0; stp < nsteps; ++stp) {
     __builtin_amdgcn_s_waitcnt(0);  // this thread's copies of step stp have landed
     __syncthreads();                // ... every thread's, and all reads of step stp - 1 are done
     if (stp + 1 < nsteps) issue(stp + 1, (stp + 1) & 1);
+    if (!live) continue;
     const unsigned char* st = smem_raw + (stp & 1) * STAGE;
     const unsigned char* sXr = st;
-    const unsigned char* sXi = st + ARR;
-    const unsigned char* sPr = st + 2 * ARR;
-    const unsigned char* sPi = st + 3 * ARR;
+    const unsigned char* sXi = st + ARRX;
+    const unsigned char* sPr = st + 2 * ARRX;
+    const unsigned char* sPi = st + 2 * ARRX + ARRP;
     // the first step of a frequency starts its accumulators at 0 (compile-time operand)
     auto mma = [&](auto zc) {
       constexpr bool Z = decltype(zc)::value;
       const f32x4 zero4 = {0.0f, 0.0f, 0.0f, 0.0f};
       if constexpr (KIND == 0) {
-        float fxr[2][8], fxi[2][8], fpr[2][8], fpi[2][8];
+        // two halves of 16 radii; lane quarter lg holds radii 16 h + 4 lg .. + 3 (chunk 4 h + lg)
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          const int rx = wr * 32 + i * 16 + li;
-          const int rp = wc * 32 + i * 16 + li;
+        for (int h = 0; h < 2; ++h) {
+          float fxr[IM][4], fxi[IM][4], fpr[JN][4], fpi[JN][4];
 #pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            // lane quarter lg holds radii 16 h + 4 lg .. + 3 (chunk 4 h + lg) of each operand
-            float4 t;
-            t = *reinterpret_cast<const float4*>(sXr + at(rx, h * 4 + lg));
-            fxr[i][4 * h] = t.x; fxr[i][4 * h + 1] = t.y; fxr[i][4 * h + 2] = t.z; fxr[i][4 * h + 3] = t.w;
-            t = *reinterpret_cast<const float4*>(sXi + at(rx, h * 4 + lg));
-            fxi[i][4 * h] = t.x; fxi[i][4 * h + 1] = t.y; fxi[i][4 * h + 2] = t.z; fxi[i][4 * h + 3] = t.w;
-            t = *reinterpret_cast<const float4*>(sPr + at(rp, h * 4 + lg));
-            fpr[i][4 * h] = t.x; fpr[i][4 * h + 1] = t.y; fpr[i][4 * h + 2] = t.z; fpr[i][4 * h + 3] = t.w;
-            t = *reinterpret_cast<const float4*>(sPi + at(rp, h * 4 + lg));
-            fpi[i][4 * h] = t.x; fpi[i][4 * h + 1] = t.y; fpi[i][4 * h + 2] = t.z; fpi[i][4 * h + 3] = t.w;
+          for (int i = 0; i < IM; ++i) {
+            const int rx = wr * IM * 16 + i * 16 + li;
+            const float4 u = *reinterpret_cast<const float4*>(sXr + at(rx, h * 4 + lg));
+            const float4 v = *reinterpret_cast<const float4*>(sXi + at(rx, h * 4 + lg));
+            fxr[i][0] = u.x; fxr[i][1] = u.y; fxr[i][2] = u.z; fxr[i][3] = u.w;
+            fxi[i][0] = v.x; fxi[i][1] = v.y; fxi[i][2] = v.z; fxi[i][3] = v.w;
           }
+#pragma unroll
+          for (int j = 0; j < JN; ++j) {
+            const int rp = wc * JN * 16 + j * 16 + li;
+            const float4 u = *reinterpret_cast<const float4*>(sPr + at(rp, h * 4 + lg));
+            const float4 v = *reinterpret_cast<const float4*>(sPi + at(rp, h * 4 + lg));
+            fpr[j][0] = u.x; fpr[j][1] = u.y; fpr[j][2] = u.z; fpr[j][3] = u.w;
+            fpi[j][0] = v.x; fpi[j][1] = v.y; fpi[j][2] = v.z; fpi[j][3] = v.w;
+          }
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int i = 0; i < IM; ++i)
+#pragma unroll
+              for (int j = 0; j < JN; ++j) {
+                const bool z = Z && h == 0 && t == 0;
+                acc[i][j][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxr[i][t], fpr[j][t], z ? zero4 : acc[i][j][0], 0, 0, 0);
+                acc[i][j][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxi[i][t], fpi[j][t], z ? zero4 : acc[i][j][1], 0, 0, 0);
+                acc[i][j][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxi[i][t], fpr[j][t], z ? zero4 : acc[i][j][2], 0, 0, 0);
+                acc[i][j][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxr[i][t], fpi[j][t], z ? zero4 : acc[i][j][3], 0, 0, 0);
+              }
         }
-#pragma unroll
-        for (int t = 0; t < 8; ++t)
-#pragma unroll
-          for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-              acc[i][j][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxr[i][t], fpr[j][t], Z && t == 0 ? zero4 : acc[i][j][0], 0, 0, 0);
-              acc[i][j][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxi[i][t], fpi[j][t], Z && t == 0 ? zero4 : acc[i][j][1], 0, 0, 0);
-              acc[i][j][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxi[i][t], fpr[j][t], Z && t == 0 ? zero4 : acc[i][j][2], 0, 0, 0);
-              acc[i][j][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxr[i][t], fpi[j][t], Z && t == 0 ? zero4 : acc[i][j][3], 0, 0, 0);
-            }
       } else {
         typedef typename std::conditional<KIND == 1, bf16x8, f16x8>::type V8;
 #pragma unroll
         for (int sub = 0; sub < KCH / 32; ++sub) {
-          V8 fxr[2], fxi[2], fpr[2], fpi[2];
+          V8 fxr[IM], fxi[IM], fpr[JN], fpi[JN];
 #pragma unroll
-          for (int i = 0; i < 2; ++i) {
-            const int rx = wr * 32 + i * 16 + li;
-            const int rp = wc * 32 + i * 16 + li;
+          for (int i = 0; i < IM; ++i) {
+            const int rx = wr * IM * 16 + i * 16 + li;
             fxr[i] = *reinterpret_cast<const V8*>(sXr + at(rx, sub * 4 + lg));
             fxi[i] = *reinterpret_cast<const V8*>(sXi + at(rx, sub * 4 + lg));
-            fpr[i] = *reinterpret_cast<const V8*>(sPr + at(rp, sub * 4 + lg));
-            fpi[i] = *reinterpret_cast<const V8*>(sPi + at(rp, sub * 4 + lg));
           }
 #pragma unroll
-          for (int i = 0; i < 2; ++i)
+          for (int j = 0; j < JN; ++j) {
+            const int rp = wc * JN * 16 + j * 16 + li;
+            fpr[j] = *reinterpret_cast<const V8*>(sPr + at(rp, sub * 4 + lg));
+            fpi[j] = *reinterpret_cast<const V8*>(sPi + at(rp, sub * 4 + lg));
+          }
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
+          for (int i = 0; i < IM; ++i)
+#pragma unroll
+            for (int j = 0; j < JN; ++j) {
               const bool z = Z && sub == 0;
               if constexpr (KIND == 1) {
                 acc[i][j][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fxr[i], fpr[j], z ? zero4 : acc[i][j][0], 0, 0, 0);
@@ -591,31 +634,32 @@ __global__ void __launch_bounds__(kThreads) bound_kernel(BoundArgs a) {
     if (stp - k * steps_per_k == steps_per_k - 1) {  // last radii of frequency k
       const float wk = (k == 0 || 2 * k == a.N) ? 1.0f : 2.0f;
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < IM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < JN; ++j)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const float A = acc[i][j][0][r], B = acc[i][j][1][r], C = acc[i][j][2][r], D = acc[i][j][3][r];
             // max(|G|^2, |G_mirror|^2) = S + 2 |T|, S = A^2 + B^2 + C^2 + D^2, T = A B - C D
             const float S = fmaf(A, A, fmaf(B, B, fmaf(C, C, D * D)));
-            const float T = fmaf(A, B, -(C * D));
+            const float Tm = fmaf(A, B, -(C * D));
             // hardware square root (<= 1 ulp): the certificate's relative slack covers it
-            U[i][j][r] += wk * __builtin_amdgcn_sqrtf(fmaf(2.0f, fabsf(T), S));
+            U[i][j][r] += wk * __builtin_amdgcn_sqrtf(fmaf(2.0f, fabsf(Tm), S));
           }
     }
   }
+  if (!live) return;
   const float invN = 1.0f / (float)a.N;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < IM; ++i)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int p = tp * kTileP + wr * 32 + i * 16 + lg * 4 + r;
+      const int p = tp * TP + wr * IM * 16 + i * 16 + lg * 4 + r;
       if (p >= a.np) continue;
       const float inv = invN / a.scale[p];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int z = tz * kTileZ + wc * 32 + j * 16 + li;
+      for (int j = 0; j < JN; ++j) {
+        const int z = tz * TZ + wc * JN * 16 + j * 16 + li;
         if (z < a.Zvalid) a.U[(size_t)p * a.ldU + z] = U[i][j][r] * inv;
       }
     }
@@ -992,6 +1036,7 @@ struct Tuning {
   int bound_kch16 = 64;   // radii per LDS step of the 16-bit contraction (32, 64 or 128)
   int exact_xcd = 1;      // exact pass: XCD-grouped pattern order
   int polar_xcd = 1;      // polar pass: consecutive patterns grouped on one XCD
+  int bound_tile = 2;     // contraction block tile: 0 = 64 x 64, 1 = 128 x 128, 2 = by problem size
 };
 Tuning g_tune;
 
@@ -1147,23 +1192,61 @@ acom_status_t launch_polar(const PlanDev& d, const PolarArgs& a, hipStream_t s) 
   }
 }
 
+template <int WM, int WN, int IM, int JN>
+acom_status_t launch_bound_t(const PlanDev& d, int precision, BoundArgs b, hipStream_t s) {
+  constexpr int TP = 16 * WM * IM, TZ = 16 * WN * JN, NT = 64 * WM * WN;
+  b.nP = (b.np + TP - 1) / TP;
+  b.nZ = (b.Zvalid + TZ - 1) / TZ;
+  const int nblocks = b.order == 0 ? b.nP * b.nZ : xcd_blocks(b.nP * b.nZ, &b.per);
+  if (b.order == 0) b.per = 0;
+  // 16-bit operands: the largest of 128, 64, 32 not above the setting dividing Rp
+  // (at most 64 for the large tiles, whose two 128-radius stages would exceed the LDS)
+  int kch = (TP + TZ > 128) ? std::min(g_tune.bound_kch16, 64) : g_tune.bound_kch16;
+  while (d.Rp % kch) kch /= 2;
+  if (TP + TZ > 128 && kch == 32 && !bound_shape_ok<1, 32, WM, WN, IM, JN>()) kch = 64;
+  auto launch = [&](auto kern, size_t lds) -> acom_status_t {
+    acom_status_t e = ensure_lds(kern, lds);
+    if (e != ACOM_OK) return e;
+    ProfScope prof(1, s);
+    kern<<<dim3(nblocks), NT, lds, s>>>(b);
+    return ACOM_OK;
+  };
+  acom_status_t st = fail(ACOM_E_UNSUPPORTED, "no contraction kernel for this tile and step");
+  if (precision == ACOM_FP32) {
+    if constexpr (bound_shape_ok<0, 32, WM, WN, IM, JN>())
+      st = launch(bound_kernel<0, 32, WM, WN, IM, JN>, 2 * bound_stage_bytes<0, 32, WM, WN, IM, JN>());
+  } else if (kch == 128) {
+    if constexpr (bound_shape_ok<1, 128, WM, WN, IM, JN>())
+      st = launch(precision == ACOM_BF16 ? bound_kernel<1, 128, WM, WN, IM, JN> : bound_kernel<2, 128, WM, WN, IM, JN>,
+                  2 * bound_stage_bytes<1, 128, WM, WN, IM, JN>());
+  } else if (kch == 64) {
+    if constexpr (bound_shape_ok<1, 64, WM, WN, IM, JN>())
+      st = launch(precision == ACOM_BF16 ? bound_kernel<1, 64, WM, WN, IM, JN> : bound_kernel<2, 64, WM, WN, IM, JN>,
+                  2 * bound_stage_bytes<1, 64, WM, WN, IM, JN>());
+  } else {
+    if constexpr (bound_shape_ok<1, 32, WM, WN, IM, JN>())
+      st = launch(precision == ACOM_BF16 ? bound_kernel<1, 32, WM, WN, IM, JN> : bound_kernel<2, 32, WM, WN, IM, JN>,
+                  2 * bound_stage_bytes<1, 32, WM, WN, IM, JN>());
+  }
+  if (st != ACOM_OK) return st;
+  ACOM_HIP(hipGetLastError());
+  return ACOM_OK;
+}
+
 acom_status_t launch_bound(const PlanDev& d, int precision, const WsLayout& L, unsigned char* ws, int np,
                            float* U, int ldU, int Zvalid, hipStream_t s) {
   BoundArgs b;
   b.Nk = d.Nk;
   b.Rp = d.Rp;
   b.N = d.N;
-  b.nP = (np + kTileP - 1) / kTileP;
-  b.nZ = d.Zp / kTileZ;
   b.order = g_tune.bound_order;
-  const int nblocks = b.order == 0 ? b.nP * b.nZ : xcd_blocks(b.nP * b.nZ, &b.per);
-  if (b.order == 0) b.per = 0;
+  b.nX64 = (np + 63) / 64;
+  b.nP64 = d.Zp / 64;
   b.scale = reinterpret_cast<const float*>(ws + L.scale);
   b.U = U;
   b.ldU = ldU;
   b.np = np;
   b.Zvalid = Zvalid;
-  dim3 grid(nblocks);
   if (precision == ACOM_FP32) {
     b.xr = ws + L.xr;
     b.xi = ws + L.xi;
@@ -1175,27 +1258,18 @@ acom_status_t launch_bound(const PlanDev& d, int precision, const WsLayout& L, u
     b.pr = d.d_PR16[precision];
     b.pi = d.d_PI16[precision];
   }
-  int kch = g_tune.bound_kch16;  // 16-bit operands: the largest of 128, 64, 32 not above the setting dividing Rp
-  while (d.Rp % kch) kch /= 2;
-  acom_status_t st = ACOM_OK;
-  auto launch = [&](auto kern, size_t lds) -> acom_status_t {
-    acom_status_t e = ensure_lds(kern, lds);
-    if (e != ACOM_OK) return e;
-    ProfScope prof(1, s);
-    kern<<<grid, kThreads, lds, s>>>(b);
-    return ACOM_OK;
-  };
-  if (precision == ACOM_FP32)
-    st = launch(bound_kernel<0, 32>, 2 * bound_stage_bytes<0, 32>());
-  else if (kch == 128)
-    st = launch(precision == ACOM_BF16 ? bound_kernel<1, 128> : bound_kernel<2, 128>, 2 * bound_stage_bytes<1, 128>());
-  else if (kch == 64)
-    st = launch(precision == ACOM_BF16 ? bound_kernel<1, 64> : bound_kernel<2, 64>, 2 * bound_stage_bytes<1, 64>());
-  else
-    st = launch(precision == ACOM_BF16 ? bound_kernel<1, 32> : bound_kernel<2, 32>, 2 * bound_stage_bytes<1, 32>());
-  if (st != ACOM_OK) return st;
-  ACOM_HIP(hipGetLastError());
-  return ACOM_OK;
+  // Larger block tiles cut the operand traffic per flop (128 x 128 halves it);
+  // they need enough tiles to fill the chip.  FP32 keeps 32 x 32 per wave (a
+  // 64 x 32 wave tile of FP32 fragments would not fit the registers of two
+  // waves per SIMD), so its large tile is 128 x 64 with eight waves.
+  const int large = ((np + 127) / 128) * ((Zvalid + 127) / 128);
+  // (measured: the FP32 contraction, bound by the MFMA rate, runs faster with the
+  // 64 x 64 tile and two workgroups per compute unit; the 16-bit ones, bound by
+  // operand traffic, with 128 x 128)
+  const bool use_large = g_tune.bound_tile == 1 || (g_tune.bound_tile == 2 && precision != ACOM_FP32 && large >= 2 * 256);
+  if (use_large && precision == ACOM_FP32) return launch_bound_t<4, 2, 2, 2>(d, precision, b, s);
+  if (use_large) return launch_bound_t<2, 4, 4, 2>(d, precision, b, s);
+  return launch_bound_t<2, 2, 2, 2>(d, precision, b, s);
 }
 
 ExactArgs exact_args(const PlanDev& d, const WsLayout& L, unsigned char* ws, int64_t p_begin, int np) {
@@ -1468,6 +1542,10 @@ extern "C" acom_status_t acom_set_tuning(int32_t key, int32_t value) {
     case 3:
       if (value != 0 && value != 1) return fail(ACOM_E_INVALID, "polar order must be 0 or 1");
       g_tune.polar_xcd = value;
+      return ACOM_OK;
+    case 4:
+      if (value < 0 || value > 2) return fail(ACOM_E_INVALID, "contraction tile must be 0, 1 or 2");
+      g_tune.bound_tile = value;
       return ACOM_OK;
 
   }
