@@ -242,7 +242,9 @@ acom_status_t acom_profile_end(void);
  *        0 = pattern index fastest;
  * key 4: contraction block tile, 0 = 64 x 64, 1 = large (128 x 128; 128 x 64 for FP32 operands),
  *        2 = large for BF16/FP16 operands when it gives at least two tiles per compute unit,
- *        else 64 x 64 (default). */
+ *        else 64 x 64 (default);
+ * key 5: 1 = the contraction skips the leading radii where the plan is zero in every zone
+ *        (exact: those terms are zeros; default), 0 = it runs over all radii. */
 acom_status_t acom_set_tuning(int32_t key, int32_t value);
 
 /* ------------------------------------------------------------- errors ---- */

@@ -52,6 +52,7 @@ struct PlanDev {
   // sizes
   int Z = 0, Zp = 0;        // zones, zones padded to kTileZ
   int R = 0, Rp = 0;        // radial bins, padded to kSChunk
+  int r0 = 0;               // leading radial bins where FFT{P} is zero in every zone
   int N = 0, Nk = 0;        // angular bins, N/2 + 1
   int n_phases = 0;
   Radices rad;

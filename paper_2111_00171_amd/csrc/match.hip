@@ -391,6 +391,7 @@ struct BoundArgs {
   int Nk, Rp, N;
   int nP, nZ, per;          // block tiles over patterns and zones, XCD items per XCD
   int nX64, nP64;           // 64-row layout tiles of the pattern and zone operands
+  int r0;                   // leading radii where the plan is zero in every zone
   int order;                // block order (see bound_kernel)
   const void *xr, *xi;      // tile-major over patterns (local to the chunk)
   const void *pr, *pi;      // tile-major over zones
@@ -496,8 +497,12 @@ __global__ void __launch_bounds__(64 * WM * WN) bound_kernel(BoundArgs a) {
   const size_t slab = (size_t)a.Nk * 64 * a.Rp;
   const T* gx[2] = {reinterpret_cast<const T*>(a.xr), reinterpret_cast<const T*>(a.xi)};
   const T* gp[2] = {reinterpret_cast<const T*>(a.pr), reinterpret_cast<const T*>(a.pi)};
-  const int steps_per_k = a.Rp / KCH;
+  // radii below r0 are zero in every zone's plan: whole steps of them are
+  // skipped, and with FP32 operands also the first 16 radii of a step
+  const int s_begin = (a.r0 / KCH) * KCH;
+  const int steps_per_k = (a.Rp - s_begin) / KCH;
   const int nsteps = a.Nk * steps_per_k;
+  const bool skip_h0 = KIND == 0 && a.r0 - s_begin >= 16;
 
   // per-lane part of the LDS-direct copies: lane writes bytes [16 lane, +16) of
   // its wave's KiB, i.e. block row r, physical chunk c; it fetches logical chunk
@@ -519,7 +524,7 @@ __global__ void __launch_bounds__(64 * WM * WN) bound_kernel(BoundArgs a) {
   }
   auto issue = [&](int stp, int buf) {
     const int k = stp / steps_per_k;
-    const size_t kbase = (size_t)k * 64 * a.Rp + (size_t)(stp - k * steps_per_k) * KCH;
+    const size_t kbase = (size_t)k * 64 * a.Rp + s_begin + (size_t)(stp - k * steps_per_k) * KCH;
     unsigned char* st = smem_raw + buf * STAGE;
 #pragma unroll
     for (int arr = 0; arr < 2; ++arr)
@@ -540,7 +545,7 @@ __global__ void __launch_bounds__(64 * WM * WN) bound_kernel(BoundArgs a) {
   auto at = [](int row, int chunk) { return row * RB + ((chunk ^ chunk_swizzle<RB>(row)) << 4); };
 
   f32x4 acc[IM][JN][4];
-  issue(0, 0);
+  if (nsteps > 0) issue(0, 0);
   for (int stp = 0; stp < nsteps; ++stp) {
     __builtin_amdgcn_s_waitcnt(0);  // this thread's copies of step stp have landed
     __syncthreads();                // ... every thread's, and all reads of step stp - 1 are done
@@ -551,14 +556,16 @@ __global__ void __launch_bounds__(64 * WM * WN) bound_kernel(BoundArgs a) {
     const unsigned char* sXi = st + ARRX;
     const unsigned char* sPr = st + 2 * ARRX;
     const unsigned char* sPi = st + 2 * ARRX + ARRP;
-    // the first step of a frequency starts its accumulators at 0 (compile-time operand)
-    auto mma = [&](auto zc) {
+    // the first step of a frequency starts its accumulators at 0 (compile-time
+    // operand); H0 = 1 skips the first half of an FP32 step (zero plan radii)
+    auto mma = [&](auto zc, auto hc) {
       constexpr bool Z = decltype(zc)::value;
+      constexpr int H0 = decltype(hc)::value;
       const f32x4 zero4 = {0.0f, 0.0f, 0.0f, 0.0f};
       if constexpr (KIND == 0) {
         // two halves of 16 radii; lane quarter lg holds radii 16 h + 4 lg .. + 3 (chunk 4 h + lg)
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = H0; h < 2; ++h) {
           float fxr[IM][4], fxi[IM][4], fpr[JN][4], fpi[JN][4];
 #pragma unroll
           for (int i = 0; i < IM; ++i) {
@@ -582,7 +589,7 @@ __global__ void __launch_bounds__(64 * WM * WN) bound_kernel(BoundArgs a) {
             for (int i = 0; i < IM; ++i)
 #pragma unroll
               for (int j = 0; j < JN; ++j) {
-                const bool z = Z && h == 0 && t == 0;
+                const bool z = Z && h == H0 && t == 0;
                 acc[i][j][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxr[i][t], fpr[j][t], z ? zero4 : acc[i][j][0], 0, 0, 0);
                 acc[i][j][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxi[i][t], fpi[j][t], z ? zero4 : acc[i][j][1], 0, 0, 0);
                 acc[i][j][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxi[i][t], fpr[j][t], z ? zero4 : acc[i][j][2], 0, 0, 0);
@@ -626,10 +633,12 @@ __global__ void __launch_bounds__(64 * WM * WN) bound_kernel(BoundArgs a) {
         }
       }
     };
-    if (stp % steps_per_k == 0)
-      mma(std::true_type{});
+    if (stp % steps_per_k != 0)
+      mma(std::false_type{}, std::integral_constant<int, 0>{});
+    else if (skip_h0)
+      mma(std::true_type{}, std::integral_constant<int, 1>{});
     else
-      mma(std::false_type{});
+      mma(std::true_type{}, std::integral_constant<int, 0>{});
     const int k = stp / steps_per_k;
     if (stp - k * steps_per_k == steps_per_k - 1) {  // last radii of frequency k
       const float wk = (k == 0 || 2 * k == a.N) ? 1.0f : 2.0f;
@@ -1037,6 +1046,7 @@ struct Tuning {
   int exact_xcd = 1;      // exact pass: XCD-grouped pattern order
   int polar_xcd = 1;      // polar pass: consecutive patterns grouped on one XCD
   int bound_tile = 2;     // contraction block tile: 0 = 64 x 64, 1 = 128 x 128, 2 = by problem size
+  int skip_zero_radii = 1;  // contraction: skip the leading radii where the plan is zero in every zone
 };
 Tuning g_tune;
 
@@ -1242,6 +1252,7 @@ acom_status_t launch_bound(const PlanDev& d, int precision, const WsLayout& L, u
   b.order = g_tune.bound_order;
   b.nX64 = (np + 63) / 64;
   b.nP64 = d.Zp / 64;
+  b.r0 = g_tune.skip_zero_radii ? d.r0 : 0;
   b.scale = reinterpret_cast<const float*>(ws + L.scale);
   b.U = U;
   b.ldU = ldU;
@@ -1546,6 +1557,10 @@ extern "C" acom_status_t acom_set_tuning(int32_t key, int32_t value) {
     case 4:
       if (value < 0 || value > 2) return fail(ACOM_E_INVALID, "contraction tile must be 0, 1 or 2");
       g_tune.bound_tile = value;
+      return ACOM_OK;
+    case 5:
+      if (value != 0 && value != 1) return fail(ACOM_E_INVALID, "zero-radius skipping must be 0 or 1");
+      g_tune.skip_zero_radii = value;
       return ACOM_OK;
 
   }

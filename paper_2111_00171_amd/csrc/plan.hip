@@ -288,6 +288,28 @@ __global__ void plan_dft_kernel(int Z, int N, int Nk, int R, int Rp, const doubl
   }
 }
 
+// Radial columns that carry a nonzero FFT{P} value in some zone: block z,
+// threads over s, one byte per (z, s); then one thread per s ORs over zones.
+__global__ void plan_colnz_kernel(int Z, int Nk, int Rp, const float* PRz, const float* PIz, uint8_t* nz) {
+  const int z = blockIdx.x;
+  for (int s = threadIdx.x; s < Rp; s += blockDim.x) {
+    bool any = false;
+    for (int k = 0; k < Nk && !any; ++k) {
+      const size_t o = ((size_t)z * Nk + k) * Rp + s;
+      any = PRz[o] != 0.0f || PIz[o] != 0.0f;
+    }
+    nz[(size_t)z * Rp + s] = any ? 1 : 0;
+  }
+}
+
+__global__ void plan_colany_kernel(int Z, int Rp, const uint8_t* nz, int32_t* colany) {
+  for (int s = threadIdx.x; s < Rp; s += blockDim.x) {
+    int any = 0;
+    for (int z = 0; z < Z && !any; ++z) any = nz[(size_t)z * Rp + s];
+    colany[s] = any;
+  }
+}
+
 template <class T>
 acom_status_t dalloc(T** p, size_t n) {
   *p = nullptr;
@@ -615,6 +637,26 @@ extern "C" acom_status_t acom_build_plan(const acom_phase_t* phases, int32_t n_p
                                             d.d_PIz, d.d_PR16[ACOM_BF16], d.d_PI16[ACOM_BF16], d.d_PR16[ACOM_FP16],
                                             d.d_PI16[ACOM_FP16]);
   if (hipGetLastError() != hipSuccess) return bail(fail(ACOM_E_HIP, "plan_dft_kernel launch"));
+  // leading radii where every zone's FFT{P} is exactly zero: the contraction
+  // may skip them (their terms are exact zeros)
+  {
+    uint8_t* d_nz = nullptr;
+    int32_t* d_colany = nullptr;
+    if ((st = dalloc(&d_nz, (size_t)d.Z * d.Rp)) || (st = dalloc(&d_colany, d.Rp))) {
+      (void)hipFree(d_nz);
+      return bail(st);
+    }
+    plan_colnz_kernel<<<d.Z, 128, 0, stream>>>(d.Z, d.Nk, d.Rp, d.d_PRz, d.d_PIz, d_nz);
+    plan_colany_kernel<<<1, 256, 0, stream>>>(d.Z, d.Rp, d_nz, d_colany);
+    std::vector<int32_t> colany(d.Rp, 1);
+    const bool ok = hipGetLastError() == hipSuccess && hipStreamSynchronize(stream) == hipSuccess &&
+                    hipMemcpy(colany.data(), d_colany, sizeof(int32_t) * d.Rp, hipMemcpyDeviceToHost) == hipSuccess;
+    (void)hipFree(d_nz);
+    (void)hipFree(d_colany);
+    if (!ok) return bail(fail(ACOM_E_HIP, "plan column scan"));
+    d.r0 = 0;
+    while (d.r0 < d.R && !colany[d.r0]) ++d.r0;
+  }
 
   // small tables
   std::vector<double> M12(9 * (size_t)d.Z);

@@ -245,6 +245,34 @@ def test_full_scan_sampled_against_oracle(acom, scan, precision):
     assert np.median(mis) < 1.0
 
 
+@pytest.mark.parametrize("n_radial,k_max", [(128, 2.0), (512, 2.0)])
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_zero_plan_radii_skipped_exactly(acom, n_radial, k_max, precision):
+    """The contraction skips the leading radii where every zone's plan is zero
+    (a half step with FP32 operands at 128 bins, whole steps at 512): the bound
+    equals the full-range one up to FP32 summation order, and the decisions
+    match the oracle."""
+    cfg = dict(k_max=k_max, n_radial=n_radial, n_angular=90, zone_step_deg=5.0)
+    opl = helpers.oracle_plan(["fcc"], **cfg)
+    gpl = helpers.gpu_plan(["fcc"], **cfg)
+    r0 = int(np.argmax((np.abs(opl["P"]) > 0).any(axis=(0, 1))))
+    assert r0 >= 16
+    d = synth.subset(synth.make("small"), np.arange(64))
+    pk = acom.Peaks.from_host(d)
+    try:
+        acom.set_tuning(skip_zero_radii=0)
+        U_full = gpl.bound(pk, precision).cpu().numpy()
+        acom.set_tuning(skip_zero_radii=1)
+        U = gpl.bound(pk, precision).cpu().numpy()
+        res = gpl.match(pk, top_k=2, precision=precision)
+        torch.cuda.synchronize()
+    finally:
+        acom.set_tuning(skip_zero_radii=1)
+    assert np.abs(U - U_full).max() <= 1e-5 * U_full.max()
+    res = {k: v.cpu().numpy() for k, v in res.items() if v is not None}
+    _check_decisions(opl, d, res, range(64), top_k=2)
+
+
 @pytest.mark.parametrize("n_radial", [20, 48])
 @pytest.mark.parametrize("precision", ["fp32", "bf16", "fp16"])
 def test_match_ragged_radial_padding(acom, n_radial, precision):
