@@ -106,7 +106,7 @@ struct PolarArgs {
   uint16_t *lr, *li;       // low-precision copies (same layout) or null
   int lowp;                // 0 none, ACOM_BF16, ACOM_FP16
   float* scale;            // np: factor applied before the FP16 cast (else 1)
-  float* xnorm2;           // np x ntiles: sum of X^2 of each radial tile
+  float* xnorm2;           // np: sum of X^2 of the pattern's polar image
   int* flags;              // np: 0 ok, 1 invalid data, 2 no peaks
   float* Ximg;             // optional X[p][a][s] (np x N x R)
   int do_fft;
@@ -144,10 +144,10 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
   float* pw = pq + kPeakCache;
   int* plist = reinterpret_cast<int*>(pw + kPeakCache);  // cached peaks reaching the current tile
   float* sqs = reinterpret_cast<float*>(plist + kPeakCache);  // q_s of every column (-1 beyond R)
+  uint32_t* scmw = reinterpret_cast<uint32_t*>(sqs + a.Rp);  // [tile][wave] column masks
   __shared__ int s_bad, s_nlist;
   __shared__ float s_red[kThreads / 64];
   __shared__ double s_red64[kThreads / 64];
-  __shared__ uint32_t s_cm[kThreads / 64];
   __shared__ float s_sc;
 
   const int tid = threadIdx.x;
@@ -195,6 +195,7 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
   else __syncthreads();
 
   float sc = 1.0f;
+  float xx = 0.0f;  // this thread's share of sum X^2 over all tiles (fixed order)
   float* X = reinterpret_cast<float*>(b0);  // X(phi_a, column) at [rev(a)][kPolarCols]
   const size_t pbase = (size_t)(p >> 6) * a.ld_tile + (size_t)(p & 63) * a.ldp;
   for (int tile = 0; tile < a.ntiles; ++tile) {
@@ -213,6 +214,7 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
       hw = h > (float)N ? N : (int)ceilf(h);
     }
     const bool full = 2 * hw + 1 >= N;
+    bool listed = false;  // some peak reaches the tile (else its X is exactly zero)
     __syncthreads();
     for (int64_t c0 = m0; c0 < m1; c0 += kPeakCache) {
       const int cnt = (int)min((int64_t)kPeakCache, m1 - c0);
@@ -233,6 +235,7 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
       }
       __syncthreads();
       const int nl = s_nlist;
+      listed = listed || nl > 0;
       if (qs >= 0.0f) {
         for (int l = 0; l < nl; ++l) {
           const int j = plist[l];
@@ -274,42 +277,16 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
       }
       __syncthreads();
     }
-    // block sums (fixed order): sum of X^2 of this tile, which of its columns
-    // hold any nonzero X (a thread only visits column tid % kPolarCols, so lane
-    // l of a ballot speaks for column l % kPolarCols), and on the first tile the
-    // peak weights (FP16 scale)
-    float xx = 0.0f;
-    bool nz = false;
-    for (int i = tid; i < N * kPolarCols; i += kThreads) {
-      const float v = X[i];
-      xx += v * v;
-      nz = nz || v != 0.0f;
-    }
-    const unsigned long long bal = __ballot(nz);
-    const uint32_t cm = (uint32_t)((bal | (bal >> 16) | (bal >> 32) | (bal >> 48)) & 0xFFFFull);
-    double ws = tile == 0 ? wsum : 0.0;
+    if (tile == 0) {
+      // the peak weights (FP16 scale) and the flags, before the first unpack
+      double ws = wsum;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      xx += __shfl_xor(xx, off, 64);
-      ws += __shfl_xor(ws, off, 64);
-    }
-    if ((tid & 63) == 0) {
-      s_red[tid >> 6] = xx;
-      s_red64[tid >> 6] = ws;
-      s_cm[tid >> 6] = cm;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      float t = 0.0f;
-      double u = 0.0;
-      uint32_t m = 0;
-      for (int w = 0; w < kThreads / 64; ++w) {
-        t += s_red[w];
-        u += s_red64[w];
-        m |= s_cm[w];
-      }
-      const bool bad = s_bad != 0;
-      if (tile == 0) {
+      for (int off = 32; off > 0; off >>= 1) ws += __shfl_xor(ws, off, 64);
+      if ((tid & 63) == 0) s_red64[tid >> 6] = ws;
+      __syncthreads();
+      if (tid == 0) {
+        double u = 0.0;
+        for (int w = 0; w < kThreads / 64; ++w) u += s_red64[w];
         float scl = 1.0f;
         if (a.lowp == ACOM_FP16) {
           // |FFT{X}| <= sum_a X <= N * sum_m w_m; map that bound below 2^14.
@@ -321,16 +298,13 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
           }
         }
         s_sc = scl;
-        a.flags[p] = bad ? 1 : (m1 <= m0 ? 2 : 0);
+        a.flags[p] = s_bad ? 1 : (m1 <= m0 ? 2 : 0);
         a.scale[p] = scl;
       }
-      a.xnorm2[(size_t)p * a.ntiles + tile] = bad ? 0.0f : t;
-      if (a.cmask) a.cmask[(size_t)p * a.ntiles + tile] = bad ? 0u : m;
-      s_cm[0] = m;
+      __syncthreads();
+      sc = s_sc;
     }
-    __syncthreads();
     const bool bad = s_bad != 0;
-    sc = s_sc;
     if (a.Ximg) {
       for (int i = tid; i < N * kPolarCols; i += kThreads) {
         const int ai = i / kPolarCols, cc = i % kPolarCols;
@@ -341,14 +315,18 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
       __syncthreads();
       continue;
     }
-    if (s_cm[0] != 0u) {  // a tile of zeros has a zero spectrum: its LDS already holds it
+    if (listed) {  // a tile of zeros has a zero spectrum: its LDS already holds it
       if constexpr (NT > 0)
         block_fft_inplace_ct<NT, NS>(b0, tw, 1.0f);
       else
         block_fft_inplace(b0, tw, N, NS, a.rad, a.nrad, 1.0f);
     }
     const float2* F = b0;
-    // unpack: column 2q = (Z_k + conj Z_{N-k}) / 2, column 2q+1 = -i (Z_k - conj Z_{N-k}) / 2
+    // unpack: column 2q = (Z_k + conj Z_{N-k}) / 2, column 2q+1 = -i (Z_k - conj Z_{N-k}) / 2.
+    // On the way: sum X^2 by Parseval (sum_a X_a^2 = (1/N) sum_k |Xhat_k|^2, the
+    // half spectrum counted twice except k = 0 and N/2), and which columns have
+    // a nonzero spectrum (a thread always holds pair q = tid % NS)
+    bool nzE = false, nzO = false;
     for (int it = tid; it < a.Nk * NS; it += kThreads) {
       const int k = it / NS, q = it % NS;
       const float2 Zk = F[k * NS + q];
@@ -356,6 +334,10 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
       float2 E = make_float2(0.5f * (Zk.x + Zn.x), 0.5f * (Zk.y - Zn.y));
       float2 O = make_float2(0.5f * (Zk.y + Zn.y), -0.5f * (Zk.x - Zn.x));
       if (bad) E = O = make_float2(0.0f, 0.0f);
+      const float wk = (k == 0 || 2 * k == N) ? 1.0f : 2.0f;
+      xx += wk * ((E.x * E.x + E.y * E.y) + (O.x * O.x + O.y * O.y));
+      nzE = nzE || E.x != 0.0f || E.y != 0.0f;
+      nzO = nzO || O.x != 0.0f || O.y != 0.0f;
       const int s0 = col0 + 2 * q;
       const size_t o = pbase + (size_t)k * a.ldk + s0;
       if (a.out_cols == a.Rp) {  // workspace layout: the column pair is one aligned 8-byte / 4-byte store
@@ -381,8 +363,41 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
         }
       }
     }
+    {
+      static_assert(kThreads % NS == 0 && 64 % NS == 0, "a thread keeps its column pair across the unpack");
+      const unsigned long long be = __ballot(nzE), bo = __ballot(nzO);
+      uint32_t m = 0;
+#pragma unroll
+      for (int l = 0; l < NS; ++l) {  // lane l + NS j holds pair l
+        bool e = false, o = false;
+#pragma unroll
+        for (int j = 0; j < 64 / NS; ++j) {
+          e = e || ((be >> (l + NS * j)) & 1ull);
+          o = o || ((bo >> (l + NS * j)) & 1ull);
+        }
+        m |= (e ? 1u : 0u) << (2 * l) | (o ? 1u : 0u) << (2 * l + 1);
+      }
+      if ((tid & 63) == 0) scmw[tile * (kThreads / 64) + (tid >> 6)] = m;
+    }
     __syncthreads();
   }
+  // per pattern: sum of X^2 (fixed order) and the column masks of every tile
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) xx += __shfl_xor(xx, off, 64);
+  if ((tid & 63) == 0) s_red[tid >> 6] = xx;
+  __syncthreads();
+  const bool bad = s_bad != 0;
+  if (tid == 0) {
+    float t = 0.0f;
+    for (int w = 0; w < kThreads / 64; ++w) t += s_red[w];
+    a.xnorm2[p] = bad ? 0.0f : t / (float)N;
+  }
+  if (a.cmask)
+    for (int t = tid; t < a.ntiles; t += kThreads) {
+      uint32_t m = 0;
+      for (int w = 0; w < kThreads / 64; ++w) m |= scmw[t * (kThreads / 64) + w];
+      a.cmask[(size_t)p * a.ntiles + t] = bad ? 0u : m;
+    }
 }
 
 // ------------------------------------------------------------ 2. bound ----
@@ -885,9 +900,7 @@ __global__ void __launch_bounds__(kThreads) exact_kernel(ExactArgs a) {
     if (a.n_eval && tid == 0) a.n_eval[P] = 0;
     return;
   }
-  float xn2 = 0.0f;
-  for (int t = 0; t < a.ntiles; ++t) xn2 += a.xnorm2[(size_t)p * a.ntiles + t];
-  const float margin_abs = a.eps_abs * sqrtf(xn2);
+  const float margin_abs = a.eps_abs * sqrtf(a.xnorm2[p]);
   for (int z = tid; z < a.Z; z += kThreads) Ul[z] = a.U[(size_t)p * a.ldU + z];
   active_groups(a, p, groups, &s_ng);
   if (tid == 0) {
@@ -1099,7 +1112,7 @@ WsLayout layout(const PlanDev& d, bool lowp, int Pc) {
     L.li = take(nx * 2);
   }
   L.scale = take((size_t)Pc * 4);
-  L.xn2 = take((size_t)Pc * L.ntiles * 4);
+  L.xn2 = take((size_t)Pc * 4);
   L.cmask = take((size_t)Pc * L.ntiles * 4);
   L.flags = take((size_t)Pc * 4);
   L.U = take((size_t)Pc * d.Zp * 4);
@@ -1109,7 +1122,7 @@ WsLayout layout(const PlanDev& d, bool lowp, int Pc) {
 
 size_t polar_lds(const PlanDev& d) {
   return (size_t)(d.N * (kPolarCols / 2) + d.N) * sizeof(float2) + (size_t)d.N * 4 + kPeakCache * (4 + 4 + 4 + 4 + 4) +
-         (size_t)d.Rp * 4;
+         (size_t)d.Rp * 4 + (size_t)(d.Rp / kPolarCols) * (kThreads / 64) * 4;
 }
 size_t exact_lds(const PlanDev& d) {
   return (size_t)(kBatch * d.N + d.N) * sizeof(float2) + (size_t)d.N * 4 + (size_t)d.Z * 4 + (size_t)d.Rp;
