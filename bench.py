@@ -1,11 +1,11 @@
 #!/usr/bin/env python3
 """Diffraction patterns indexed per second on one MI355X.
 
-Workload ("scan"): a seeded synthetic 256 x 256 FCC (a = 4.08 A) scan of 65,536
-patterns with 10-60 Bragg peaks each (50 Voronoi grains, position jitter,
-intensity noise, 0-2 spurious peaks), matched against the 1-degree orientation
-plan of the cubic fundamental zone (1081 zone axes), 128 radial bins to
-k_max = 2.0 1/A and 360 angular bins, top-1 match per pattern.
+Default workload ("scan"): a seeded synthetic 256 x 256 FCC (a = 4.08 A) scan
+of 65,536 patterns with 10-60 Bragg peaks each (50 Voronoi grains, position
+jitter, intensity noise, 0-2 spurious peaks), matched against the 1-degree
+orientation plan of the cubic fundamental zone (1081 zone axes), 128 radial
+bins to k_max = 2.0 1/A and 360 angular bins, top-1 match per pattern.
 
 One step = one acom_match over the whole scan (peaks already resident in HBM):
 polar image + FFT, MFMA bound contraction, exact FP32 pass, orientation.
@@ -13,6 +13,17 @@ polar image + FFT, MFMA bound contraction, exact FP32 pass, orientation.
 contraction with FP32 rescoring is timed on the same inputs and reported
 beside it.  The dominant kernel's roofline uses its average duration from HIP
 events recorded on its launch stream during the timed steps.
+
+Other workloads (--workload), each printing one JSON line of the same form:
+  hcp     256 x 256 HCP (a = 2.95, c = 4.68) scan against the 6/m wedge at 1
+          degree (8281 zones); BF16 / FP16 / FP32 contraction, top-8 FP32
+          rescoring.
+  multi   512 x 512 three-phase scan (FCC + BCC + HCP plans concatenated,
+          10,443 zones), ragged peak counts 3-150; BF16; the whole acom_match
+          captured once in a HIP graph and timed by graph replays.
+  refine  65,536 FCC patterns at random (off-grid) orientations: top-4 grid
+          candidates (FP32 contraction) refined by gradient ascent on the
+          continuous score (acom_refine, FP32).
 """
 import argparse
 import hashlib
@@ -28,6 +39,29 @@ METRIC = "diffraction patterns indexed/sec at 1 GPU, BF16 vs FP32 at ≥99.9% or
 PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0}   # dense MFMA
 HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "bound_kernel_scan_traffic.json")
+DATA = "synthetic (seeded generator; the paper's datasets are not available)"
+
+PLAN_CFG = {  # phases and plan parameters of each workload
+    "scan": (["fcc"], dict(k_max=2.0, n_radial=128, n_angular=360, zone_step_deg=1.0)),
+    "hcp": (["hcp"], dict(k_max=2.0, n_radial=128, n_angular=360, zone_step_deg=1.0)),
+    "multi": (["fcc", "bcc", "hcp"], dict(k_max=2.0, n_radial=128, n_angular=360, zone_step_deg=1.0)),
+    "refine": (["fcc"], dict(k_max=2.0, n_radial=128, n_angular=360, zone_step_deg=1.0)),
+}
+DESCR = {
+    "scan": "scan: 256x256 FCC scan, 65,536 patterns x 10-60 peaks, 1-degree plan (1081 zones), "
+            "128 radial x 360 angular bins, top-1, FP32 contraction",
+    "hcp": "hcp: 256x256 HCP scan, 65,536 patterns, 6/m wedge at 1 degree (8281 zones), 128 x 360 bins, "
+           "top-8 FP32 rescoring",
+    "multi": "multi: 512x512 three-phase scan (FCC 4.08 + BCC 2.87 + HCP), 262,144 patterns x 3-150 peaks, "
+             "10,443 zones, 128 x 360 bins, top-1, BF16 contraction, one HIP-graph replay per step",
+    "refine": "refine: 65,536 FCC patterns at random orientations, top-4 grid candidates (FP32 contraction) "
+              "refined by gradient ascent on the continuous score (<= 64 trials each)",
+}
+
+
+def log(msg):
+    """Progress of the run on stderr (the JSON line stays alone on stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
 def kernel_source_hash():
@@ -39,8 +73,9 @@ def kernel_source_hash():
 
 
 def measured_traffic(precision, launches_patterns):
-    """HBM bytes per launch of the bound kernel from rocprofv3 FETCH_SIZE/WRITE_SIZE
-    counters (profiles/), or None if they were taken on a different kernel source."""
+    """HBM bytes per launch of the bound kernel on the scan workload from
+    rocprofv3 FETCH_SIZE/WRITE_SIZE counters (profiles/), or None if they were
+    taken on a different kernel source."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as f:
@@ -53,30 +88,43 @@ def measured_traffic(precision, launches_patterns):
     return e["bytes_per_launch"]
 
 
-def cpu_baseline(d, res_by_prec, sample_target_s=15.0, max_patterns=512):
-    """The oracle (plain-C FP64 direct sum, OpenMP) on a bounded seeded sample."""
+def _oracle_plan(workload):
+    from tests import helpers
+    phases, cfg = PLAN_CFG[workload]
+    return helpers.oracle_plan(phases, **cfg)
+
+
+def cpu_baseline_match(workload, d, res_by_prec, sample_target_s=15.0, max_patterns=512):
+    """The oracle (plain-C FP64 direct sum, OpenMP) on a bounded seeded sample;
+    also the argmax agreement of each precision on that sample."""
     import numpy as np
     import synth
     from oracle import directsum
-    from tests import helpers
 
-    opl = helpers.oracle_plan(["fcc"], **helpers.SCAN)
+    t0 = time.perf_counter()
+    opl = _oracle_plan(workload)
+    log(f"{workload}: oracle plan built ({time.perf_counter() - t0:.1f} s)")
     rng = np.random.default_rng(2024)
     n = len(d["offsets"]) - 1
     idx_all = rng.permutation(n)
-    # calibrate on 16 patterns, then size the sample to ~sample_target_s
-    t0 = time.perf_counter()
-    first = np.sort(idx_all[:16])
-    sub = synth.subset(d, first)
-    zs0 = directsum.zone_scores(opl, sub["offsets"], sub["qx"], sub["qy"], sub["I"])
-    t_cal = time.perf_counter() - t0
-    m = int(min(max_patterns, max(16, 16 * sample_target_s / max(t_cal, 1e-3))))
-    idx = np.sort(idx_all[:m])
-    sub = synth.subset(d, idx)
-    t0 = time.perf_counter()
-    zs = directsum.zone_scores(opl, sub["offsets"], sub["qx"], sub["qy"], sub["I"])
-    el = time.perf_counter() - t0
+    # the oracle runs one pattern per thread: time batches of `cores` patterns
+    # until about sample_target_s of work is done
     cores = directsum.num_threads()
+    batches, el = [], 0.0
+    while True:
+        b = len(batches)
+        idx = np.sort(idx_all[b * cores:(b + 1) * cores])
+        sub = synth.subset(d, idx)
+        t0 = time.perf_counter()
+        batches.append((idx, directsum.zone_scores(opl, sub["offsets"], sub["qx"], sub["qy"], sub["I"])))
+        el += time.perf_counter() - t0
+        log(f"{workload}: oracle batch {b + 1} of {cores} patterns ({el:.1f} s)")
+        per = el / len(batches)
+        if el + per > sample_target_s * 1.25 or len(batches) * cores >= max_patterns:
+            break
+    idx = np.concatenate([i for i, _ in batches])
+    zs = {k: np.concatenate([z[k] for _, z in batches]) for k in ("score", "n", "mirror")}
+    m = len(idx)
     agree = {}
     for prec, res in res_by_prec.items():
         zone = res["zone"][idx, 0]
@@ -92,10 +140,281 @@ def cpu_baseline(d, res_by_prec, sample_target_s=15.0, max_patterns=512):
             ok_strict += strict
             ok_tie += (z >= 0 and sc[z] >= mx - 1e-5 * mx)
         agree[prec] = {"tie_aware": ok_tie / m, "strict": ok_strict / m, "patterns": m}
+    Z = opl["P"].shape[0]
     return ({"value": m / el, "unit": "patterns/s", "cores": cores, "kind": "oracle",
-             "sample": f"{m} seeded patterns of the same scan; plain-C FP64 direct-sum correlation "
-                       f"over all 1081 zones x 360 bins x 2 branches (OpenMP, {cores} threads); "
+             "sample": f"{m} seeded patterns of the same workload; plain-C FP64 direct-sum correlation "
+                       f"over all {Z} zones x 360 bins x 2 branches (OpenMP, {cores} threads); "
                        f"plan build excluded as on the GPU"}, agree)
+
+
+def cpu_baseline_refine(d, init, res, sample_target_s=15.0, max_patterns=256):
+    """The oracle refinement (FP64 score and gradient, the same ascent) on a
+    bounded seeded sample from the GPU's top-4 grid candidates; also the
+    misorientation between the GPU and oracle refinements on that sample."""
+    import numpy as np
+    from oracle import crystal, metrics, score
+    from oracle import plan as oplan
+    from tests import helpers
+
+    refl = crystal.reflections(np.eye(3) * helpers.A_FCC, helpers.FCC_FRAC, 2.0)
+    prm = oplan.Params(k_max=2.0)
+    o = d["offsets"]
+    G = metrics.cubic_rotations()
+    rng = np.random.default_rng(2025)
+    order = rng.permutation(len(o) - 1)
+    done, mis, t_used = 0, [], 0.0
+    while done < max_patterns and t_used < sample_target_s:
+        p = int(order[done])
+        t0 = time.perf_counter()
+        mo, _ = score.refine(refl, d["qx"][o[p]:o[p + 1]].astype(np.float64), d["qy"][o[p]:o[p + 1]].astype(np.float64),
+                             d["I"][o[p]:o[p + 1]].astype(np.float64), list(init[p]), prm, max_iter=64)
+        t_used += time.perf_counter() - t0
+        mis.append(metrics.misorientation_deg(res[p], mo, G))
+        done += 1
+        if done % 8 == 0:
+            log(f"refine: oracle refined {done} patterns ({t_used:.1f} s)")
+    return ({"value": done / t_used, "unit": "patterns/s", "cores": 1, "kind": "oracle",
+             "sample": f"{done} seeded patterns; FP64 continuous-score refinement of the same 4 candidates "
+                       f"(numpy, single thread); candidate search excluded"},
+            {"gpu_vs_oracle_misorientation_deg": {"median": float(np.median(mis)), "max": float(np.max(mis)),
+                                                  "patterns": done}})
+
+
+def time_match(gpl, pk, prec, top_k, chunk, steps, warmup, n, flop_per_pattern):
+    import torch
+    from paper_2111_00171_amd import acom
+    ws = torch.empty(gpl.match_workspace_bytes(prec, chunk), dtype=torch.uint8, device="cuda")
+    out = gpl.empty_matches(n, top_k, True, "cuda")
+    for _ in range(warmup):
+        gpl.match(pk, top_k, prec, chunk, ws, out=out)
+    torch.cuda.synchronize()
+    acom.profile_begin(8192)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        gpl.match(pk, top_k, prec, chunk, ws, out=out)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = acom.profile_read()
+    acom.profile_end()
+    kern = {k: {"avg_ms": (t / c if c else None), "launches": c} for k, (t, c) in prof.items()}
+    b = prof["bound"]
+    per_launch = min(chunk, n)
+    achieved = flop_per_pattern * per_launch / (b[0] / b[1] * 1e-3) / 1e12
+    nev = out["n_evaluated"].float()
+    run = {"value": n * steps / el, "ms_per_step": el * 1e3 / steps, "kernels": kern,
+           "bound_tflops": achieved, "bound_frac": achieved / PEAK_TFLOPS[prec],
+           "zones_evaluated_mean": float(nev.mean()), "zones_evaluated_max": int(nev.max())}
+    host = {k: out[k].cpu().numpy() for k in ("zone", "phase", "bin", "mirror", "score")}
+    host["orient"] = out["orient"].cpu().numpy()
+    del ws
+    return run, host
+
+
+def by_precision(runs):
+    return {p: {"patterns_per_s": round(v["value"], 1), "ms_per_step": round(v["ms_per_step"], 3),
+                "bound_tflops": round(v["bound_tflops"], 3), "bound_frac_of_peak": round(v["bound_frac"], 4),
+                "kernel_avg_ms": {k: (None if kk["avg_ms"] is None else round(kk["avg_ms"], 4))
+                                  for k, kk in v["kernels"].items()},
+                "zones_evaluated_mean": round(v["zones_evaluated_mean"], 3),
+                "zones_evaluated_max": v["zones_evaluated_max"]} for p, v in runs.items()}
+
+
+def roofline(runs, prec, per_launch, flop_per_pattern, traffic):
+    r = runs[prec]
+    kern = r["kernels"]
+    dominant = max(kern, key=lambda k: (kern[k]["avg_ms"] or 0) * kern[k]["launches"])
+    return {"kernel": "bound_kernel (MFMA contraction, %s operands)" % prec, "bound": "mfma",
+            "achieved": round(r["bound_tflops"], 3), "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+            "frac": round(r["bound_frac"], 4), "traffic": traffic,
+            "algorithmic_flop_per_launch": flop_per_pattern * per_launch, "dominant_kernel_of_step": dominant}
+
+
+def line(workload, value, ms, steps, warmup, dtype, cfg, roof, cpu, extra):
+    out = {"metric": METRIC, "value": round(value, 1), "unit": "patterns/s", "n_gpus": 1, "steps": steps,
+           "warmup": warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": dtype, "data": DATA, "config": {"workload": DESCR[workload], **cfg},
+           "roofline": roof, "cpu_baseline": cpu}
+    out.update(extra)
+    return out
+
+
+def run_match_workload(args, workload):
+    import numpy as np
+    import torch
+    import synth
+    from paper_2111_00171_amd import acom
+
+    precs = [p for p in args.precisions.split(",") if p]
+    top_k = 8 if workload == "hcp" else 1
+    t0 = time.perf_counter()
+    d = synth.make(workload)
+    t_gen = time.perf_counter() - t0
+    log(f"{workload}: inputs generated ({len(d['offsets']) - 1} patterns, {t_gen:.1f} s)")
+    phases, cfg = PLAN_CFG[workload]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gpl = acom.Plan([{"fcc": acom.fcc, "bcc": acom.bcc, "hcp": acom.hcp}[k]() for k in phases],
+                    acom.PlanParams(precisions=precs, **cfg))
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    n = len(d["offsets"]) - 1
+    pk = acom.Peaks.from_host(d)
+    Z, R, N = gpl.n_zones, gpl.n_radial, gpl.n_angular
+    flop_per_pattern = 8.0 * Z * (N // 2 + 1) * R
+    runs, host = {}, {}
+    log(f"{workload}: plan built ({Z} zones, {t_plan:.1f} s)")
+    for prec in precs:
+        runs[prec], host[prec] = time_match(gpl, pk, prec, top_k, args.chunk, args.steps, args.warmup, n,
+                                            flop_per_pattern)
+        log(f"{workload}: {prec} timed, {runs[prec]['value']:.0f} patterns/s")
+    cpu = agree = None
+    if not args.no_cpu_baseline:
+        cpu, agree = cpu_baseline_match(workload, d, host)
+        log(f"{workload}: oracle sample timed")
+    main_prec = precs[0]
+    per_launch = min(args.chunk, n)
+    traffic = measured_traffic(main_prec, per_launch) if workload == "scan" else None
+    extra = {"argmax_match_vs_oracle": agree, "by_precision": by_precision(runs),
+             "plan_build_s": round(t_plan, 3), "input_generation_s": round(t_gen, 3)}
+    if workload != "scan":
+        # the generator's ground truth: misorientation of the top match within the 1-degree grid
+        from oracle import metrics
+        G = metrics.hexagonal_rotations() if workload == "hcp" else metrics.cubic_rotations()
+        idx = np.random.default_rng(7).choice(n, 256, replace=False)
+        mis = [metrics.misorientation_deg(host[main_prec]["orient"][p, 0], d["truth"][p], G) for p in idx]
+        extra["misorientation_vs_truth_deg"] = {"median": float(np.median(mis)), "p90": float(np.percentile(mis, 90)),
+                                                "patterns": 256, "precision": main_prec}
+    ccfg = {"patterns": n, "peaks": int(d["offsets"][-1]), "zones": Z, "n_radial": R, "n_angular": N,
+            "chunk": args.chunk, "top_k": top_k}
+    r = runs[main_prec]
+    return line(workload, r["value"], r["ms_per_step"], args.steps, args.warmup,
+                {"fp32": "f32", "bf16": "bf16", "fp16": "f16"}[main_prec], ccfg,
+                roofline(runs, main_prec, per_launch, flop_per_pattern, traffic), cpu, extra)
+
+
+def run_multi(args):
+    """Batching: one acom_match over the whole ragged 3-phase scan captured in a
+    HIP graph; a step is one graph replay."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2111_00171_amd import acom
+
+    prec = "bf16"
+    t0 = time.perf_counter()
+    d = synth.make("multi")
+    t_gen = time.perf_counter() - t0
+    log(f"multi: inputs generated ({len(d['offsets']) - 1} patterns, {t_gen:.1f} s)")
+    phases, cfg = PLAN_CFG["multi"]
+    t0 = time.perf_counter()
+    gpl = acom.Plan([{"fcc": acom.fcc, "bcc": acom.bcc, "hcp": acom.hcp}[k]() for k in phases],
+                    acom.PlanParams(precisions=[prec], **cfg))
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    n = len(d["offsets"]) - 1
+    pk = acom.Peaks.from_host(d)
+    Z, R, N = gpl.n_zones, gpl.n_radial, gpl.n_angular
+    flop_per_pattern = 8.0 * Z * (N // 2 + 1) * R
+    # kernel averages and the contraction roofline from an eager profiled run
+    log(f"multi: plan built ({Z} zones, {t_plan:.1f} s)")
+    run, host = time_match(gpl, pk, prec, 1, args.chunk, 2, 1, n, flop_per_pattern)
+    log(f"multi: eager profiled run, {run['value']:.0f} patterns/s")
+    # the graph: captured once, replayed
+    ws = torch.empty(gpl.match_workspace_bytes(prec, args.chunk), dtype=torch.uint8, device="cuda")
+    out = gpl.empty_matches(n, 1, True, "cuda")
+    gpl.match(pk, 1, prec, args.chunk, ws, out=out)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        gpl.match(pk, 1, prec, args.chunk, ws, out=out)
+    for _ in range(args.warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.replay()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    same = bool(np.array_equal(out["zone"].cpu().numpy(), host["zone"]))
+    log(f"multi: graph replays timed, {n * args.steps / el:.0f} patterns/s")
+    cpu = agree = None
+    if not args.no_cpu_baseline:
+        cpu, agree = cpu_baseline_match("multi", d, {prec: host})
+    cnt = np.diff(d["offsets"])
+    sel = np.flatnonzero(cnt >= 8)
+    phase_ok = float(np.mean((host["zone"][sel, 0] >= 0) & (host["phase"][sel, 0] == d["phase"][sel])))
+    per_launch = min(args.chunk, n)
+    extra = {"argmax_match_vs_oracle": agree, "by_precision": by_precision({prec: run}),
+             "graph_replay_matches_eager": same, "phase_identified_fraction_ge8_peaks": phase_ok,
+             "plan_build_s": round(t_plan, 3), "input_generation_s": round(t_gen, 3)}
+    ccfg = {"patterns": n, "peaks": int(d["offsets"][-1]), "zones": Z, "n_radial": R, "n_angular": N,
+            "chunk": args.chunk, "top_k": 1, "graph": True}
+    return line("multi", n * args.steps / el, el * 1e3 / args.steps, args.steps, args.warmup, "bf16", ccfg,
+                roofline({prec: run}, prec, per_launch, flop_per_pattern, None), cpu, extra)
+
+
+def run_refine(args):
+    """Differentiation: top-4 grid candidates (FP32 contraction) refined on the
+    continuous score; a step is acom_match + acom_refine over all patterns."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2111_00171_amd import acom
+    from oracle import metrics
+
+    t0 = time.perf_counter()
+    d = synth.make("refine")
+    t_gen = time.perf_counter() - t0
+    log(f"refine: inputs generated ({len(d['offsets']) - 1} patterns, {t_gen:.1f} s)")
+    phases, cfg = PLAN_CFG["refine"]
+    gpl = acom.Plan([acom.fcc()], acom.PlanParams(precisions=["fp32"], **cfg))
+    n = len(d["offsets"]) - 1
+    pk = acom.Peaks.from_host(d)
+    ws = torch.empty(gpl.match_workspace_bytes("fp32", args.chunk), dtype=torch.uint8, device="cuda")
+    out = gpl.empty_matches(n, 4, True, "cuda")
+
+    def step():
+        gpl.match(pk, 4, "fp32", args.chunk, ws, out=out)
+        return gpl.refine(pk, out["orient"].reshape(n, 4, 9), max_iter=64)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t_match = t_ref = 0.0
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        gpl.match(pk, 4, "fp32", args.chunk, ws, out=out)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        m, S, c = gpl.refine(pk, out["orient"].reshape(n, 4, 9), max_iter=64)
+        torch.cuda.synchronize()
+        t_ref += time.perf_counter() - t1
+        t_match += t1 - t0
+    el = t_match + t_ref
+    log(f"refine: timed, {n * args.steps / el:.0f} patterns/s")
+    m = m.cpu().numpy()
+    init = out["orient"].reshape(n, 4, 3, 3).cpu().numpy()
+    G = metrics.cubic_rotations()
+    idx = np.random.default_rng(9).choice(n, 512, replace=False)
+    mis_grid = [metrics.misorientation_deg(init[p, 0], d["truth"][p], G) for p in idx]
+    mis_ref = [metrics.misorientation_deg(m[p], d["truth"][p], G) for p in idx]
+    cpu = ext = None
+    if not args.no_cpu_baseline:
+        cpu, ext = cpu_baseline_refine(d, init, m)
+    extra = {"refinement_vs_truth_deg": {"grid_top1_median": float(np.median(mis_grid)),
+                                         "refined_median": float(np.median(mis_ref)),
+                                         "refined_p90": float(np.percentile(mis_ref, 90)),
+                                         "refined_p99": float(np.percentile(mis_ref, 99)), "patterns": 512},
+             "ms_per_step_match": round(t_match * 1e3 / args.steps, 3),
+             "ms_per_step_refine": round(t_ref * 1e3 / args.steps, 3),
+             "oracle_comparison": ext, "input_generation_s": round(t_gen, 3)}
+    ccfg = {"patterns": n, "peaks": int(d["offsets"][-1]), "zones": gpl.n_zones, "n_radial": gpl.n_radial,
+            "n_angular": gpl.n_angular, "candidates": 4, "max_trials": 64}
+    roof = {"kernel": "refine_kernel (continuous score and gradient, FP32 VALU)", "bound": "alu", "achieved": None,
+            "peak": None, "unit": None, "frac": None, "traffic": None,
+            "note": "latency-bound gradient ascent; see DESIGN.md"}
+    return line("refine", n * args.steps / el, el * 1e3 / args.steps, args.steps, args.warmup, "f32", ccfg, roof,
+                cpu, extra)
 
 
 def main():
@@ -103,7 +422,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precisions", default="fp32,bf16,fp16")
+    ap.add_argument("--workload", default="scan", choices=["scan", "hcp", "multi", "refine"])
+    ap.add_argument("--precisions", default=None,
+                    help="comma list; the first is `value` (scan: fp32,bf16,fp16; hcp: bf16,fp16,fp32)")
     ap.add_argument("--chunk", type=int, default=16384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
@@ -114,14 +435,10 @@ def main():
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); patterns are independent, so a "
               f"multi-GPU run shards the scan with no exchange (see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+    if args.precisions is None:
+        args.precisions = "bf16,fp16,fp32" if args.workload == "hcp" else "fp32,bf16,fp16"
 
-    import numpy as np
     import torch
-
-    import synth
-    from paper_2111_00171_amd import acom
-
-    precs = [p for p in args.precisions.split(",") if p]
     if args.calibrate_copy_gib > 0:
         nb = int(args.calibrate_copy_gib * (1 << 30))
         src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
@@ -129,87 +446,13 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    t0 = time.perf_counter()
-    d = synth.make("scan")
-    t_gen = time.perf_counter() - t0
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    gpl = acom.Plan([acom.fcc()], acom.PlanParams(k_max=2.0, n_radial=128, n_angular=360, zone_step_deg=1.0,
-                                                  precisions=precs))
-    torch.cuda.synchronize()
-    t_plan = time.perf_counter() - t0
-    n = len(d["offsets"]) - 1
-    pk = acom.Peaks.from_host(d)
-    Z, R, N = gpl.n_zones, gpl.n_radial, gpl.n_angular
-    Nk = N // 2 + 1
-    flop_per_pattern = 8.0 * Z * Nk * R
-
-    runs = {}
-    host = {}
-    for prec in precs:
-        ws = torch.empty(gpl.match_workspace_bytes(prec, args.chunk), dtype=torch.uint8, device="cuda")
-        out = gpl.empty_matches(n, 1, True, "cuda")
-        for _ in range(args.warmup):
-            gpl.match(pk, 1, prec, args.chunk, ws, out=out)
-        torch.cuda.synchronize()
-        acom.profile_begin(4096)
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            gpl.match(pk, 1, prec, args.chunk, ws, out=out)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        prof = acom.profile_read()
-        acom.profile_end()
-        ms = el * 1e3 / args.steps
-        kern = {k: {"avg_ms": (t / c if c else None), "launches": c} for k, (t, c) in prof.items()}
-        b = prof["bound"]
-        per_launch_patterns = min(args.chunk, n)
-        bound_avg_ms = b[0] / b[1]
-        achieved = flop_per_pattern * per_launch_patterns / (bound_avg_ms * 1e-3) / 1e12
-        nev = out["n_evaluated"].float()
-        runs[prec] = {"value": n * args.steps / el, "ms_per_step": ms, "kernels": kern,
-                      "bound_tflops": achieved, "bound_frac": achieved / PEAK_TFLOPS[prec],
-                      "zones_evaluated_mean": float(nev.mean()), "zones_evaluated_max": int(nev.max())}
-        host[prec] = {k: out[k].cpu().numpy() for k in ("zone", "bin", "mirror", "score")}
-        del ws
-
-    cpu = None
-    agree = None
-    if not args.no_cpu_baseline:
-        cpu, agree = cpu_baseline(d, host)
-
-    main_prec = "fp32" if "fp32" in runs else precs[0]
-    r = runs[main_prec]
-    kern = r["kernels"]
-    dominant = max(kern, key=lambda k: (kern[k]["avg_ms"] or 0) * kern[k]["launches"])
-    per_launch_patterns = min(args.chunk, n)
-    traffic = measured_traffic(main_prec, per_launch_patterns)
-    roof = {"kernel": "bound_kernel (MFMA contraction, %s operands)" % main_prec, "bound": "mfma",
-            "achieved": round(r["bound_tflops"], 3), "peak": PEAK_TFLOPS[main_prec], "unit": "TFLOP/s",
-            "frac": round(r["bound_frac"], 4), "traffic": traffic,
-            "algorithmic_flop_per_launch": flop_per_pattern * per_launch_patterns,
-            "dominant_kernel_of_step": dominant}
-    line = {
-        "metric": METRIC, "value": round(r["value"], 1), "unit": "patterns/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(r["ms_per_step"], 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic (seeded scan generator; the paper's datasets are not available)",
-        "config": {"workload": "scan: 256x256 FCC scan, 65,536 patterns x 10-60 peaks, 1-degree plan "
-                               "(1081 zones), 128 radial x 360 angular bins, top-1, FP32 contraction",
-                   "patterns": n, "peaks": int(d["offsets"][-1]), "zones": Z, "n_radial": R, "n_angular": N,
-                   "chunk": args.chunk},
-        "roofline": roof,
-        "cpu_baseline": cpu,
-        "argmax_match_vs_oracle": agree,
-        "by_precision": {p: {"patterns_per_s": round(v["value"], 1), "ms_per_step": round(v["ms_per_step"], 3),
-                             "bound_tflops": round(v["bound_tflops"], 3), "bound_frac_of_peak": round(v["bound_frac"], 4),
-                             "kernel_avg_ms": {k: (None if kk["avg_ms"] is None else round(kk["avg_ms"], 4))
-                                               for k, kk in v["kernels"].items()},
-                             "zones_evaluated_mean": round(v["zones_evaluated_mean"], 3),
-                             "zones_evaluated_max": v["zones_evaluated_max"]} for p, v in runs.items()},
-        "plan_build_s": round(t_plan, 3), "input_generation_s": round(t_gen, 3),
-    }
-    print(json.dumps(line))
+    if args.workload in ("scan", "hcp"):
+        out = run_match_workload(args, args.workload)
+    elif args.workload == "multi":
+        out = run_multi(args)
+    else:
+        out = run_refine(args)
+    print(json.dumps(out))
 
 
 if __name__ == "__main__":
