@@ -107,21 +107,22 @@ def cpu_baseline_match(workload, d, res_by_prec, sample_target_s=15.0, max_patte
     rng = np.random.default_rng(2024)
     n = len(d["offsets"]) - 1
     idx_all = rng.permutation(n)
-    # the oracle runs one pattern per thread: time batches of `cores` patterns
-    # until about sample_target_s of work is done
+    # the oracle runs one pattern per thread: a first batch of `cores` patterns
+    # calibrates, then one call takes the rest of about sample_target_s of work
+    # (dynamic scheduling over more patterns than threads keeps them busy)
     cores = directsum.num_threads()
     batches, el = [], 0.0
-    while True:
-        b = len(batches)
-        idx = np.sort(idx_all[b * cores:(b + 1) * cores])
+    for b in range(2):
+        lo = 0 if b == 0 else cores
+        hi = cores if b == 0 else min(max_patterns, cores + int(cores * (sample_target_s - el) / el) // cores * cores)
+        if hi <= lo:
+            break
+        idx = np.sort(idx_all[lo:hi])
         sub = synth.subset(d, idx)
         t0 = time.perf_counter()
         batches.append((idx, directsum.zone_scores(opl, sub["offsets"], sub["qx"], sub["qy"], sub["I"])))
         el += time.perf_counter() - t0
-        log(f"{workload}: oracle batch {b + 1} of {cores} patterns ({el:.1f} s)")
-        per = el / len(batches)
-        if el + per > sample_target_s * 1.25 or len(batches) * cores >= max_patterns:
-            break
+        log(f"{workload}: oracle on {hi - lo} patterns ({el:.1f} s in total)")
     idx = np.concatenate([i for i, _ in batches])
     zs = {k: np.concatenate([z[k] for _, z in batches]) for k in ("score", "n", "mirror")}
     m = len(idx)
@@ -180,11 +181,12 @@ def cpu_baseline_refine(d, init, res, sample_target_s=15.0, max_patterns=256):
                                                   "patterns": done}})
 
 
-def time_match(gpl, pk, prec, top_k, chunk, steps, warmup, n, flop_per_pattern):
+def time_match(gpl, pk, prec, top_k, chunk, steps, warmup, n, flop_per_pattern, autotune=True):
     import torch
     from paper_2111_00171_amd import acom
     ws = torch.empty(gpl.match_workspace_bytes(prec, chunk), dtype=torch.uint8, device="cuda")
     out = gpl.empty_matches(n, top_k, True, "cuda")
+    shape = gpl.autotune(pk, prec, chunk, ws) if autotune else None
     for _ in range(warmup):
         gpl.match(pk, top_k, prec, chunk, ws, out=out)
     torch.cuda.synchronize()
@@ -201,7 +203,7 @@ def time_match(gpl, pk, prec, top_k, chunk, steps, warmup, n, flop_per_pattern):
     per_launch = min(chunk, n)
     achieved = flop_per_pattern * per_launch / (b[0] / b[1] * 1e-3) / 1e12
     nev = out["n_evaluated"].float()
-    run = {"value": n * steps / el, "ms_per_step": el * 1e3 / steps, "kernels": kern,
+    run = {"value": n * steps / el, "ms_per_step": el * 1e3 / steps, "kernels": kern, "contraction_shape": shape,
            "bound_tflops": achieved, "bound_frac": achieved / PEAK_TFLOPS[prec],
            "zones_evaluated_mean": float(nev.mean()), "zones_evaluated_max": int(nev.max())}
     host = {k: out[k].cpu().numpy() for k in ("zone", "phase", "bin", "mirror", "score")}
@@ -216,7 +218,8 @@ def by_precision(runs):
                 "kernel_avg_ms": {k: (None if kk["avg_ms"] is None else round(kk["avg_ms"], 4))
                                   for k, kk in v["kernels"].items()},
                 "zones_evaluated_mean": round(v["zones_evaluated_mean"], 3),
-                "zones_evaluated_max": v["zones_evaluated_max"]} for p, v in runs.items()}
+                "zones_evaluated_max": v["zones_evaluated_max"],
+                "contraction_shape": v["contraction_shape"]} for p, v in runs.items()}
 
 
 def roofline(runs, prec, per_launch, flop_per_pattern, traffic):
@@ -373,6 +376,8 @@ def run_refine(args):
     ws = torch.empty(gpl.match_workspace_bytes("fp32", args.chunk), dtype=torch.uint8, device="cuda")
     out = gpl.empty_matches(n, 4, True, "cuda")
 
+    shape = gpl.autotune(pk, "fp32", args.chunk, ws)
+
     def step():
         gpl.match(pk, 4, "fp32", args.chunk, ws, out=out)
         return gpl.refine(pk, out["orient"].reshape(n, 4, 9), max_iter=64)
@@ -405,7 +410,7 @@ def run_refine(args):
                                          "refined_median": float(np.median(mis_ref)),
                                          "refined_p90": float(np.percentile(mis_ref, 90)),
                                          "refined_p99": float(np.percentile(mis_ref, 99)), "patterns": 512},
-             "ms_per_step_match": round(t_match * 1e3 / args.steps, 3),
+             "contraction_shape": shape, "ms_per_step_match": round(t_match * 1e3 / args.steps, 3),
              "ms_per_step_refine": round(t_ref * 1e3 / args.steps, 3),
              "oracle_comparison": ext, "input_generation_s": round(t_gen, 3)}
     ccfg = {"patterns": n, "peaks": int(d["offsets"][-1]), "zones": gpl.n_zones, "n_radial": gpl.n_radial,

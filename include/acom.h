@@ -166,6 +166,19 @@ acom_status_t acom_match(acom_plan_t plan, const acom_peaks_t* peaks, int32_t to
                          int32_t precision, int32_t chunk, void* workspace, size_t workspace_bytes,
                          const acom_matches_t* out, void* stream);
 
+/* Autotuner of the contraction launch shape (block tile 64 x 64 or large,
+ * radii per LDS step for BF16/FP16 operands, block order) for `precision` on
+ * this plan: runs the polar pass on the first chunk of `peaks`, times every
+ * candidate shape of the contraction on it with HIP events (one warm-up and two
+ * timed launches each), and stores the fastest in the plan, where acom_match
+ * then uses it.  Results of acom_match do not depend on the shape.  Synchronous;
+ * must not run while another call uses the plan.  `workspace` as for
+ * acom_match with the same `chunk`.  shape [host, 3] (tile: 0 = 64 x 64,
+ * 1 = large; radii per step; order) and ms [host] (one launch of the fastest
+ * shape) may be NULL. */
+acom_status_t acom_autotune(acom_plan_t plan, const acom_peaks_t* peaks, int32_t precision, int32_t chunk,
+                            void* workspace, size_t workspace_bytes, void* stream, int32_t* shape, float* ms);
+
 /* Intermediate outputs, for verification (same arithmetic as acom_match).
  * acom_polar_image: X[p][a][s] (n x N_phi x N_r, FP32), Eq. image_polar.
  * acom_polar_spectrum: FFT of X along phi3, Xr/Xi[p][k][s] (n x (N_phi/2+1) x N_r).

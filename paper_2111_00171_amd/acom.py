@@ -67,6 +67,8 @@ def lib():
             "acom_plan_destroy": [c_void_p],
             "acom_match_workspace_size": [c_void_p, c_int32, c_int32, P(c_size_t)],
             "acom_match": [c_void_p, P(_Peaks), c_int32, c_int32, c_int32, c_void_p, c_size_t, P(_Matches), c_void_p],
+            "acom_autotune": [c_void_p, P(_Peaks), c_int32, c_int32, c_void_p, c_size_t, c_void_p, P(c_int32),
+                              P(ctypes.c_float)],
             "acom_debug_workspace_size": [c_void_p, c_int64, P(c_size_t)],
             "acom_polar_image": [c_void_p, P(_Peaks), c_void_p, c_void_p, c_size_t, c_void_p],
             "acom_polar_spectrum": [c_void_p, P(_Peaks), c_void_p, c_void_p, c_void_p, c_size_t, c_void_p],
@@ -332,6 +334,21 @@ class Plan:
                                 c_void_p(workspace.data_ptr()), workspace.numel(), ctypes.byref(m), _stream(stream)),
                "acom_match")
         return out
+
+    def autotune(self, peaks: Peaks, precision="fp32", chunk=0, workspace=None, stream=None):
+        """Time every contraction launch shape on the first chunk of `peaks` and
+        keep the fastest for `precision` in this plan (acom_autotune)."""
+        dev = peaks.offsets.device
+        if workspace is None:
+            workspace = torch.empty(self.match_workspace_bytes(precision, chunk), dtype=torch.uint8, device=dev)
+        shape = (c_int32 * 3)()
+        ms = ctypes.c_float()
+        pk = peaks.c()
+        _check(lib().acom_autotune(self._h, ctypes.byref(pk), PRECISIONS[precision], int(chunk),
+                                   c_void_p(workspace.data_ptr()), workspace.numel(), _stream(stream), shape,
+                                   ctypes.byref(ms)), "acom_autotune")
+        return {"tile": "large" if shape[0] else "64x64", "radii_per_step": shape[1], "order": shape[2],
+                "ms": ms.value}
 
     @staticmethod
     def empty_matches(n, top_k, orient=True, device="cuda"):

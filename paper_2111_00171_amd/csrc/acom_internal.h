@@ -77,6 +77,13 @@ struct PlanDev {
   uint16_t* d_PR16[3] = {nullptr, nullptr, nullptr};  // tile-major 16-bit copies (index = acom_precision_t)
   uint16_t* d_PI16[3] = {nullptr, nullptr, nullptr};
   double* d_Pang = nullptr;     // optional FP64 angular plan Z x N x R
+  // contraction launch shape per operand precision (index = acom_precision_t),
+  // set by acom_autotune; unset -> the library's rules
+  struct BoundShape {
+    int set = 0, tile = 0, kch = 64, order = 1;
+    float ms = 0.0f;
+  };
+  BoundShape tuned[3];
   // reflections for the continuous score (all phases concatenated)
   int G = 0;
   float4* d_refl = nullptr;     // (gx, gy, gz, |g|)

@@ -1216,7 +1216,7 @@ acom_status_t launch_polar(const PlanDev& d, const PolarArgs& a, hipStream_t s) 
 }
 
 template <int WM, int WN, int IM, int JN>
-acom_status_t launch_bound_t(const PlanDev& d, int precision, BoundArgs b, hipStream_t s) {
+acom_status_t launch_bound_t(const PlanDev& d, int precision, BoundArgs b, int kch_setting, hipStream_t s) {
   constexpr int TP = 16 * WM * IM, TZ = 16 * WN * JN, NT = 64 * WM * WN;
   b.nP = (b.np + TP - 1) / TP;
   b.nZ = (b.Zvalid + TZ - 1) / TZ;
@@ -1224,7 +1224,7 @@ acom_status_t launch_bound_t(const PlanDev& d, int precision, BoundArgs b, hipSt
   if (b.order == 0) b.per = 0;
   // 16-bit operands: the largest of 128, 64, 32 not above the setting dividing Rp
   // (at most 64 for the large tiles, whose two 128-radius stages would exceed the LDS)
-  int kch = (TP + TZ > 128) ? std::min(g_tune.bound_kch16, 64) : g_tune.bound_kch16;
+  int kch = (TP + TZ > 128) ? std::min(kch_setting, 64) : kch_setting;
   while (d.Rp % kch) kch /= 2;
   if (TP + TZ > 128 && kch == 32 && !bound_shape_ok<1, 32, WM, WN, IM, JN>()) kch = 64;
   auto launch = [&](auto kern, size_t lds) -> acom_status_t {
@@ -1259,10 +1259,11 @@ acom_status_t launch_bound_t(const PlanDev& d, int precision, BoundArgs b, hipSt
 acom_status_t launch_bound(const PlanDev& d, int precision, const WsLayout& L, unsigned char* ws, int np,
                            float* U, int ldU, int Zvalid, hipStream_t s) {
   BoundArgs b;
+  const PlanDev::BoundShape* t = d.tuned[precision].set ? &d.tuned[precision] : nullptr;
   b.Nk = d.Nk;
   b.Rp = d.Rp;
   b.N = d.N;
-  b.order = g_tune.bound_order;
+  b.order = t ? t->order : g_tune.bound_order;
   b.nX64 = (np + 63) / 64;
   b.nP64 = d.Zp / 64;
   b.r0 = g_tune.skip_zero_radii ? d.r0 : 0;
@@ -1290,10 +1291,13 @@ acom_status_t launch_bound(const PlanDev& d, int precision, const WsLayout& L, u
   // (measured: the FP32 contraction, bound by the MFMA rate, runs faster with the
   // 64 x 64 tile and two workgroups per compute unit; the 16-bit ones, bound by
   // operand traffic, with 128 x 128)
-  const bool use_large = g_tune.bound_tile == 1 || (g_tune.bound_tile == 2 && precision != ACOM_FP32 && large >= 2 * 256);
-  if (use_large && precision == ACOM_FP32) return launch_bound_t<4, 2, 2, 2>(d, precision, b, s);
-  if (use_large) return launch_bound_t<2, 4, 4, 2>(d, precision, b, s);
-  return launch_bound_t<2, 2, 2, 2>(d, precision, b, s);
+  // A shape chosen by acom_autotune for this plan and precision takes precedence.
+  const int tile = t ? t->tile : g_tune.bound_tile;
+  const int kch = t ? t->kch : g_tune.bound_kch16;
+  const bool use_large = tile == 1 || (tile == 2 && precision != ACOM_FP32 && large >= 2 * 256);
+  if (use_large && precision == ACOM_FP32) return launch_bound_t<4, 2, 2, 2>(d, precision, b, kch, s);
+  if (use_large) return launch_bound_t<2, 4, 4, 2>(d, precision, b, kch, s);
+  return launch_bound_t<2, 2, 2, 2>(d, precision, b, kch, s);
 }
 
 ExactArgs exact_args(const PlanDev& d, const WsLayout& L, unsigned char* ws, int64_t p_begin, int np) {
@@ -1412,6 +1416,80 @@ extern "C" acom_status_t acom_match(acom_plan_t plan, const acom_peaks_t* peaks,
     }
     ACOM_HIP(hipGetLastError());
   }
+  return ACOM_OK;
+}
+
+extern "C" acom_status_t acom_autotune(acom_plan_t plan, const acom_peaks_t* peaks, int32_t precision, int32_t chunk,
+                                       void* workspace, size_t workspace_bytes, void* stream_v, int32_t* shape,
+                                       float* ms) {
+  acom_status_t st = check_plan_precision(plan, precision);
+  if (st != ACOM_OK) return st;
+  if ((st = check_peaks(peaks)) != ACOM_OK) return st;
+  if (peaks->n_patterns == 0) return fail(ACOM_E_INVALID, "autotune needs at least one pattern");
+  PlanDev& d = plan->d;
+  const int Pc = chunk_of(chunk);
+  const WsLayout L = layout(d, precision != ACOM_FP32, Pc);
+  if (!workspace || workspace_bytes < L.total)
+    return fail(ACOM_E_WORKSPACE, "workspace smaller than acom_match_workspace_size");
+  hipStream_t s = (hipStream_t)stream_v;
+  unsigned char* ws = reinterpret_cast<unsigned char*>(workspace);
+  const int np = (int)std::min<int64_t>(Pc, peaks->n_patterns);
+  PolarArgs pa = polar_args(d, peaks, 0, np, precision);
+  set_ws(pa, L, ws, d);
+  if ((st = launch_polar(d, pa, s)) != ACOM_OK) return st;
+  // candidate shapes: block tile x radius step (16-bit operands) x block order
+  std::vector<PlanDev::BoundShape> cand;
+  for (int tile = 0; tile <= 1; ++tile)
+    for (int order = 0; order <= 1; ++order)
+      for (int kch = 32; kch <= (precision == ACOM_FP32 ? 32 : (tile ? 64 : 128)); kch *= 2) {
+        if (d.Rp % kch) continue;
+        PlanDev::BoundShape c;
+        c.set = 1;
+        c.tile = tile;
+        c.kch = kch;
+        c.order = order;
+        cand.push_back(c);
+      }
+  hipEvent_t e0, e1;
+  ACOM_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(ACOM_E_HIP, "hipEventCreate");
+  }
+  const PlanDev::BoundShape saved = d.tuned[precision];
+  int best = -1;
+  float best_ms = 0.0f;
+  float* U = reinterpret_cast<float*>(ws + L.U);
+  for (size_t i = 0; i < cand.size() && st == ACOM_OK; ++i) {
+    d.tuned[precision] = cand[i];
+    constexpr int kReps = 2;
+    st = launch_bound(d, precision, L, ws, np, U, d.Zp, d.Zp, s);  // warm-up
+    if (st == ACOM_OK && hipEventRecord(e0, s) != hipSuccess) st = fail(ACOM_E_HIP, "hipEventRecord");
+    for (int r = 0; r < kReps && st == ACOM_OK; ++r) st = launch_bound(d, precision, L, ws, np, U, d.Zp, d.Zp, s);
+    float t = 0.0f;
+    if (st == ACOM_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                          hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+      st = fail(ACOM_E_HIP, "timing a contraction shape");
+    t /= kReps;
+    if (st == ACOM_OK && (best < 0 || t < best_ms)) {
+      best = (int)i;
+      best_ms = t;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != ACOM_OK || best < 0) {
+    d.tuned[precision] = saved;
+    return st != ACOM_OK ? st : fail(ACOM_E_UNSUPPORTED, "no contraction shape ran");
+  }
+  d.tuned[precision] = cand[best];
+  d.tuned[precision].ms = best_ms;
+  if (shape) {
+    shape[0] = cand[best].tile;
+    shape[1] = cand[best].kch;
+    shape[2] = cand[best].order;
+  }
+  if (ms) *ms = best_ms;
   return ACOM_OK;
 }
 

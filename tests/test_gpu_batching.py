@@ -93,3 +93,21 @@ def test_match_in_hip_graph(acom, multi):
         torch.cuda.synchronize()
         for k in ("zone", "bin", "mirror", "score", "phi3", "orient", "n_evaluated"):
             assert torch.equal(got[k], ref[k]), (rep, k)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_autotune_keeps_results(acom, multi, precision):
+    """The autotuner picks a contraction shape by timing; matching with it gives
+    the same decisions and exact scores as the library's default shape."""
+    d, opl, gpl = multi
+    pk = acom.Peaks.from_host(d)
+    ref = gpl.match(pk, top_k=2, precision=precision, chunk=128)
+    torch.cuda.synchronize()
+    ref = {k: v.cpu().numpy() for k, v in ref.items() if v is not None}
+    shape = gpl.autotune(pk, precision, chunk=128)
+    assert shape["tile"] in ("64x64", "large") and shape["order"] in (0, 1) and shape["ms"] > 0.0
+    assert shape["radii_per_step"] in ((32,) if precision == "fp32" else (32, 64, 128))
+    res = gpl.match(pk, top_k=2, precision=precision, chunk=128)
+    torch.cuda.synchronize()
+    for k in ("zone", "bin", "mirror", "score"):
+        assert np.array_equal(res[k].cpu().numpy(), ref[k]), k
