@@ -480,7 +480,10 @@ __global__ void __launch_bounds__(64 * WM * WN) bound_kernel(BoundArgs a) {
   constexpr int STAGE = 2 * ARRX + 2 * ARRP;
   constexpr int NIX = ARRX / 1024 / NW, NIP = ARRP / 1024 / NW;  // 1 KiB LDS-direct loads per wave per array
   static_assert(NIX * 1024 * NW == ARRX && NIP * 1024 * NW == ARRP, "whole KiB per wave");
-  extern __shared__ __align__(16) unsigned char smem_raw[];
+  // two stage buffers as distinct LDS objects: the compiler can then see that
+  // the direct-to-LDS copies of one step never alias the reads of the other
+  __shared__ __align__(16) unsigned char sbuf0[STAGE];
+  __shared__ __align__(16) unsigned char sbuf1[STAGE];
 
   int tp, tz;
   if (a.order == 0) {
@@ -537,10 +540,9 @@ __global__ void __launch_bounds__(64 * WM * WN) bound_kernel(BoundArgs a) {
     const int t64 = min(tz * (TZ / 64) + (row >> 6), a.nP64 - 1);
     offp[j] = (size_t)t64 * slab + (size_t)(row & 63) * a.Rp + (size_t)((phys ^ chunk_swizzle<RB>(row)) * VEC);
   }
-  auto issue = [&](int stp, int buf) {
+  auto issue = [&](int stp, unsigned char* st) {
     const int k = stp / steps_per_k;
     const size_t kbase = (size_t)k * 64 * a.Rp + s_begin + (size_t)(stp - k * steps_per_k) * KCH;
-    unsigned char* st = smem_raw + buf * STAGE;
 #pragma unroll
     for (int arr = 0; arr < 2; ++arr)
 #pragma unroll
@@ -560,13 +562,8 @@ __global__ void __launch_bounds__(64 * WM * WN) bound_kernel(BoundArgs a) {
   auto at = [](int row, int chunk) { return row * RB + ((chunk ^ chunk_swizzle<RB>(row)) << 4); };
 
   f32x4 acc[IM][JN][4];
-  if (nsteps > 0) issue(0, 0);
-  for (int stp = 0; stp < nsteps; ++stp) {
-    __builtin_amdgcn_s_waitcnt(0);  // this thread's copies of step stp have landed
-    __syncthreads();                // ... every thread's, and all reads of step stp - 1 are done
-    if (stp + 1 < nsteps) issue(stp + 1, (stp + 1) & 1);
-    if (!live) continue;
-    const unsigned char* st = smem_raw + (stp & 1) * STAGE;
+  // MFMAs and, after the last step of a frequency, the epilogue of step stp on stage st
+  auto compute = [&](int stp, const unsigned char* st) {
     const unsigned char* sXr = st;
     const unsigned char* sXi = st + ARRX;
     const unsigned char* sPr = st + 2 * ARRX;
@@ -671,6 +668,18 @@ __global__ void __launch_bounds__(64 * WM * WN) bound_kernel(BoundArgs a) {
             U[i][j][r] += wk * __builtin_amdgcn_sqrtf(fmaf(2.0f, fabsf(Tm), S));
           }
     }
+  };
+  if (nsteps > 0) issue(0, sbuf0);
+  for (int stp = 0; stp < nsteps; stp += 2) {  // two steps per trip, one per stage buffer
+    __builtin_amdgcn_s_waitcnt(0);  // this thread's copies of step stp have landed
+    __syncthreads();                // ... every thread's, and all reads of step stp - 1 are done
+    if (stp + 1 < nsteps) issue(stp + 1, sbuf1);
+    if (live) compute(stp, sbuf0);
+    if (stp + 1 >= nsteps) break;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (stp + 2 < nsteps) issue(stp + 2, sbuf0);
+    if (live) compute(stp + 1, sbuf1);
   }
   if (!live) return;
   const float invN = 1.0f / (float)a.N;
@@ -1227,11 +1236,10 @@ acom_status_t launch_bound_t(const PlanDev& d, int precision, BoundArgs b, int k
   int kch = (TP + TZ > 128) ? std::min(kch_setting, 64) : kch_setting;
   while (d.Rp % kch) kch /= 2;
   if (TP + TZ > 128 && kch == 32 && !bound_shape_ok<1, 32, WM, WN, IM, JN>()) kch = 64;
-  auto launch = [&](auto kern, size_t lds) -> acom_status_t {
-    acom_status_t e = ensure_lds(kern, lds);
-    if (e != ACOM_OK) return e;
+  auto launch = [&](auto kern, size_t lds) -> acom_status_t {  // lds: static, checked against the CU's 160 KiB
+    if (lds > 160 * 1024) return fail(ACOM_E_UNSUPPORTED, "contraction stages exceed the LDS");
     ProfScope prof(1, s);
-    kern<<<dim3(nblocks), NT, lds, s>>>(b);
+    kern<<<dim3(nblocks), NT, 0, s>>>(b);
     return ACOM_OK;
   };
   acom_status_t st = fail(ACOM_E_UNSUPPORTED, "no contraction kernel for this tile and step");
