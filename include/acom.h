@@ -174,8 +174,9 @@ acom_status_t acom_match(acom_plan_t plan, const acom_peaks_t* peaks, int32_t to
  * then uses it.  Results of acom_match do not depend on the shape.  Synchronous;
  * must not run while another call uses the plan.  `workspace` as for
  * acom_match with the same `chunk`.  shape [host, 3] (tile: 0 = 64 x 64,
- * 1 = large; radii per step; order) and ms [host] (one launch of the fastest
- * shape) may be NULL. */
+ * 1 = large; radii per LDS step, 16 or 32 for FP32 operands and 32, 64 or 128
+ * for 16-bit ones; order) and ms [host] (one launch of the fastest shape) may
+ * be NULL. */
 acom_status_t acom_autotune(acom_plan_t plan, const acom_peaks_t* peaks, int32_t precision, int32_t chunk,
                             void* workspace, size_t workspace_bytes, void* stream, int32_t* shape, float* ms);
 
@@ -257,7 +258,9 @@ acom_status_t acom_profile_end(void);
  *        2 = large for BF16/FP16 operands when it gives at least two tiles per compute unit,
  *        else 64 x 64 (default);
  * key 5: 1 = the contraction skips the leading radii where the plan is zero in every zone
- *        (exact: those terms are zeros; default), 0 = it runs over all radii. */
+ *        (exact: those terms are zeros; default), 0 = it runs over all radii;
+ * key 6: radii staged per LDS step by the FP32 contraction: 16 (default) or 32.
+ * A shape stored in the plan by acom_autotune takes precedence over keys 0, 1, 4 and 6. */
 acom_status_t acom_set_tuning(int32_t key, int32_t value);
 
 /* ------------------------------------------------------------- errors ---- */

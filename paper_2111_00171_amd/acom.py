@@ -448,13 +448,14 @@ class Plan:
 
 
 KERNEL_KINDS = {"polar": 0, "bound": 1, "exact": 2}
-TUNING_KEYS = {"bound_order": 0, "bound_kch16": 1, "exact_xcd": 2, "polar_xcd": 3, "bound_tile": 4, "skip_zero_radii": 5}
+TUNING_KEYS = {"bound_order": 0, "bound_kch16": 1, "exact_xcd": 2, "polar_xcd": 3, "bound_tile": 4, "skip_zero_radii": 5,
+               "bound_kch32": 6}
 
 
 def set_tuning(**kw):
     """Launch-shape knobs (results do not depend on them): bound_order (0/1),
     bound_kch16 (32/64/128), exact_xcd (0/1), polar_xcd (0/1), bound_tile (0/1/2),
-    skip_zero_radii (0/1)."""
+    skip_zero_radii (0/1), bound_kch32 (16/32)."""
     for k, v in kw.items():
         _check(lib().acom_set_tuning(TUNING_KEYS[k], int(v)), "acom_set_tuning")
 

@@ -473,7 +473,7 @@ __global__ void __launch_bounds__(64 * WM * WN) bound_kernel(BoundArgs a) {
   constexpr int TP = 16 * WM * IM, TZ = 16 * WN * JN;
   constexpr int RB = KCH * (int)sizeof(T);  // bytes per staged row
   static_assert(RB == 64 || RB == 128 || RB == 256, "staged rows of 64, 128 or 256 bytes");
-  static_assert(KIND != 0 || KCH == 32, "FP32 operands use 32-radius steps");
+  static_assert(KIND != 0 || KCH == 16 || KCH == 32, "FP32 operands use 16- or 32-radius steps");
   static_assert(TP % 64 == 0 && TZ % 64 == 0, "block tiles are whole layout tiles");
   constexpr int VEC = 16 / (int)sizeof(T);  // elements per 16-byte chunk
   constexpr int ARRX = TP * RB, ARRP = TZ * RB;  // bytes of one operand array per stage
@@ -520,7 +520,7 @@ __global__ void __launch_bounds__(64 * WM * WN) bound_kernel(BoundArgs a) {
   const int s_begin = (a.r0 / KCH) * KCH;
   const int steps_per_k = (a.Rp - s_begin) / KCH;
   const int nsteps = a.Nk * steps_per_k;
-  const bool skip_h0 = KIND == 0 && a.r0 - s_begin >= 16;
+  const bool skip_h0 = KIND == 0 && KCH == 32 && a.r0 - s_begin >= 16;
 
   // per-lane part of the LDS-direct copies: lane writes bytes [16 lane, +16) of
   // its wave's KiB, i.e. block row r, physical chunk c; it fetches logical chunk
@@ -577,7 +577,7 @@ __global__ void __launch_bounds__(64 * WM * WN) bound_kernel(BoundArgs a) {
       if constexpr (KIND == 0) {
         // two halves of 16 radii; lane quarter lg holds radii 16 h + 4 lg .. + 3 (chunk 4 h + lg)
 #pragma unroll
-        for (int h = H0; h < 2; ++h) {
+        for (int h = H0; h < KCH / 16; ++h) {
           float fxr[IM][4], fxi[IM][4], fpr[JN][4], fpi[JN][4];
 #pragma unroll
           for (int i = 0; i < IM; ++i) {
@@ -1069,6 +1069,7 @@ struct Tuning {
   int polar_xcd = 1;      // polar pass: consecutive patterns grouped on one XCD
   int bound_tile = 2;     // contraction block tile: 0 = 64 x 64, 1 = 128 x 128, 2 = by problem size
   int skip_zero_radii = 1;  // contraction: skip the leading radii where the plan is zero in every zone
+  int bound_kch32 = 16;   // radii per LDS step of the FP32 contraction (16 or 32)
 };
 Tuning g_tune;
 
@@ -1244,8 +1245,12 @@ acom_status_t launch_bound_t(const PlanDev& d, int precision, BoundArgs b, int k
   };
   acom_status_t st = fail(ACOM_E_UNSUPPORTED, "no contraction kernel for this tile and step");
   if (precision == ACOM_FP32) {
-    if constexpr (bound_shape_ok<0, 32, WM, WN, IM, JN>())
+    if (kch_setting == 16) {  // FP32 with 16-radius steps
+      if constexpr (bound_shape_ok<0, 16, WM, WN, IM, JN>())
+        st = launch(bound_kernel<0, 16, WM, WN, IM, JN>, 2 * bound_stage_bytes<0, 16, WM, WN, IM, JN>());
+    } else if constexpr (bound_shape_ok<0, 32, WM, WN, IM, JN>()) {
       st = launch(bound_kernel<0, 32, WM, WN, IM, JN>, 2 * bound_stage_bytes<0, 32, WM, WN, IM, JN>());
+    }
   } else if (kch == 128) {
     if constexpr (bound_shape_ok<1, 128, WM, WN, IM, JN>())
       st = launch(precision == ACOM_BF16 ? bound_kernel<1, 128, WM, WN, IM, JN> : bound_kernel<2, 128, WM, WN, IM, JN>,
@@ -1301,7 +1306,7 @@ acom_status_t launch_bound(const PlanDev& d, int precision, const WsLayout& L, u
   // operand traffic, with 128 x 128)
   // A shape chosen by acom_autotune for this plan and precision takes precedence.
   const int tile = t ? t->tile : g_tune.bound_tile;
-  const int kch = t ? t->kch : g_tune.bound_kch16;
+  const int kch = t ? t->kch : (precision == ACOM_FP32 ? g_tune.bound_kch32 : g_tune.bound_kch16);
   const bool use_large = tile == 1 || (tile == 2 && precision != ACOM_FP32 && large >= 2 * 256);
   if (use_large && precision == ACOM_FP32) return launch_bound_t<4, 2, 2, 2>(d, precision, b, kch, s);
   if (use_large) return launch_bound_t<2, 4, 4, 2>(d, precision, b, kch, s);
@@ -1449,7 +1454,7 @@ extern "C" acom_status_t acom_autotune(acom_plan_t plan, const acom_peaks_t* pea
   std::vector<PlanDev::BoundShape> cand;
   for (int tile = 0; tile <= 1; ++tile)
     for (int order = 0; order <= 1; ++order)
-      for (int kch = 32; kch <= (precision == ACOM_FP32 ? 32 : (tile ? 64 : 128)); kch *= 2) {
+      for (int kch = (precision == ACOM_FP32 ? 16 : 32); kch <= (precision == ACOM_FP32 ? 32 : (tile ? 64 : 128)); kch *= 2) {
         if (d.Rp % kch) continue;
         PlanDev::BoundShape c;
         c.set = 1;
@@ -1472,6 +1477,10 @@ extern "C" acom_status_t acom_autotune(acom_plan_t plan, const acom_peaks_t* pea
     d.tuned[precision] = cand[i];
     constexpr int kReps = 2;
     st = launch_bound(d, precision, L, ws, np, U, d.Zp, d.Zp, s);  // warm-up
+    if (st == ACOM_E_UNSUPPORTED) {  // a shape this plan cannot use
+      st = ACOM_OK;
+      continue;
+    }
     if (st == ACOM_OK && hipEventRecord(e0, s) != hipSuccess) st = fail(ACOM_E_HIP, "hipEventRecord");
     for (int r = 0; r < kReps && st == ACOM_OK; ++r) st = launch_bound(d, precision, L, ws, np, U, d.Zp, d.Zp, s);
     float t = 0.0f;
@@ -1660,6 +1669,10 @@ extern "C" acom_status_t acom_set_tuning(int32_t key, int32_t value) {
     case 5:
       if (value != 0 && value != 1) return fail(ACOM_E_INVALID, "zero-radius skipping must be 0 or 1");
       g_tune.skip_zero_radii = value;
+      return ACOM_OK;
+    case 6:
+      if (value != 16 && value != 32) return fail(ACOM_E_INVALID, "FP32 step must be 16 or 32");
+      g_tune.bound_kch32 = value;
       return ACOM_OK;
 
   }

@@ -246,12 +246,12 @@ def test_full_scan_sampled_against_oracle(acom, scan, precision):
 
 
 @pytest.mark.parametrize("n_radial,k_max", [(128, 2.0), (512, 2.0)])
-@pytest.mark.parametrize("precision", ["fp32", "bf16"])
-def test_zero_plan_radii_skipped_exactly(acom, n_radial, k_max, precision):
+@pytest.mark.parametrize("precision,kch32", [("fp32", 16), ("fp32", 32), ("bf16", 16)])
+def test_zero_plan_radii_skipped_exactly(acom, n_radial, k_max, precision, kch32):
     """The contraction skips the leading radii where every zone's plan is zero
-    (a half step with FP32 operands at 128 bins, whole steps at 512): the bound
-    equals the full-range one up to FP32 summation order, and the decisions
-    match the oracle."""
+    (whole steps; with 32-radius FP32 steps at 128 bins also the first half of
+    a step): the bound equals the full-range one up to FP32 summation order,
+    and the decisions match the oracle."""
     cfg = dict(k_max=k_max, n_radial=n_radial, n_angular=90, zone_step_deg=5.0)
     opl = helpers.oracle_plan(["fcc"], **cfg)
     gpl = helpers.gpu_plan(["fcc"], **cfg)
@@ -260,14 +260,14 @@ def test_zero_plan_radii_skipped_exactly(acom, n_radial, k_max, precision):
     d = synth.subset(synth.make("small"), np.arange(64))
     pk = acom.Peaks.from_host(d)
     try:
-        acom.set_tuning(skip_zero_radii=0)
+        acom.set_tuning(skip_zero_radii=0, bound_kch32=kch32)
         U_full = gpl.bound(pk, precision).cpu().numpy()
         acom.set_tuning(skip_zero_radii=1)
         U = gpl.bound(pk, precision).cpu().numpy()
         res = gpl.match(pk, top_k=2, precision=precision)
         torch.cuda.synchronize()
     finally:
-        acom.set_tuning(skip_zero_radii=1)
+        acom.set_tuning(skip_zero_radii=1, bound_kch32=16)
     assert np.abs(U - U_full).max() <= 1e-5 * U_full.max()
     res = {k: v.cpu().numpy() for k, v in res.items() if v is not None}
     _check_decisions(opl, d, res, range(64), top_k=2)
