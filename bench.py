@@ -430,7 +430,8 @@ def main():
     ap.add_argument("--workload", default="scan", choices=["scan", "hcp", "multi", "refine"])
     ap.add_argument("--precisions", default=None,
                     help="comma list; the first is `value` (scan: fp32,bf16,fp16; hcp: bf16,fp16,fp32)")
-    ap.add_argument("--chunk", type=int, default=16384)
+    ap.add_argument("--chunk", type=int, default=65536,
+                    help="patterns per internal launch (65,536: one launch per step on the scan; ~19 GB of workspace)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
                     help="first copy this many GiB device-to-device (a plain copy kernel of known size, "

@@ -174,7 +174,7 @@ acom_status_t acom_match(acom_plan_t plan, const acom_peaks_t* peaks, int32_t to
  * then uses it.  Results of acom_match do not depend on the shape.  Synchronous;
  * must not run while another call uses the plan.  `workspace` as for
  * acom_match with the same `chunk`.  shape [host, 3] (tile: 0 = 64 x 64,
- * 1 = large; radii per LDS step, 16 or 32 for FP32 operands and 32, 64 or 128
+ * 1 = large, 3 = 128 x 128 two-group schedule (16-bit operands); radii per LDS step, 16 or 32 for FP32 operands and 32, 64 or 128
  * for 16-bit ones; order) and ms [host] (one launch of the fastest shape) may
  * be NULL. */
 acom_status_t acom_autotune(acom_plan_t plan, const acom_peaks_t* peaks, int32_t precision, int32_t chunk,
@@ -256,10 +256,13 @@ acom_status_t acom_profile_end(void);
  *        0 = pattern index fastest;
  * key 4: contraction block tile, 0 = 64 x 64, 1 = large (128 x 128; 128 x 64 for FP32 operands),
  *        2 = large for BF16/FP16 operands when it gives at least two tiles per compute unit,
- *        else 64 x 64 (default);
+ *        else 64 x 64 (default),
+ *        3 = 128 x 128 on the two-group schedule (BF16/FP16 operands only; 32-radius steps);
  * key 5: 1 = the contraction skips the leading radii where the plan is zero in every zone
  *        (exact: those terms are zeros; default), 0 = it runs over all radii;
- * key 6: radii staged per LDS step by the FP32 contraction: 16 (default) or 32.
+ * key 6: radii staged per LDS step by the FP32 contraction: 16 (default) or 32;
+ * key 7: radial columns per pass of the polar (splat + FFT) kernel: 16 or 32 (default; 16 when
+ *        Rp is not a multiple of 32).  The image and spectrum are bit-identical either way.
  * A shape stored in the plan by acom_autotune takes precedence over keys 0, 1, 4 and 6. */
 acom_status_t acom_set_tuning(int32_t key, int32_t value);
 

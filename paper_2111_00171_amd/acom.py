@@ -347,8 +347,8 @@ class Plan:
         _check(lib().acom_autotune(self._h, ctypes.byref(pk), PRECISIONS[precision], int(chunk),
                                    c_void_p(workspace.data_ptr()), workspace.numel(), _stream(stream), shape,
                                    ctypes.byref(ms)), "acom_autotune")
-        return {"tile": "large" if shape[0] else "64x64", "radii_per_step": shape[1], "order": shape[2],
-                "ms": ms.value}
+        tile = {0: "64x64", 1: "large", 3: "128x128 two-group"}.get(shape[0], str(shape[0]))
+        return {"tile": tile, "radii_per_step": shape[1], "order": shape[2], "ms": ms.value}
 
     @staticmethod
     def empty_matches(n, top_k, orient=True, device="cuda"):
@@ -449,13 +449,13 @@ class Plan:
 
 KERNEL_KINDS = {"polar": 0, "bound": 1, "exact": 2}
 TUNING_KEYS = {"bound_order": 0, "bound_kch16": 1, "exact_xcd": 2, "polar_xcd": 3, "bound_tile": 4, "skip_zero_radii": 5,
-               "bound_kch32": 6}
+               "bound_kch32": 6, "polar_cols": 7}
 
 
 def set_tuning(**kw):
     """Launch-shape knobs (results do not depend on them): bound_order (0/1),
-    bound_kch16 (32/64/128), exact_xcd (0/1), polar_xcd (0/1), bound_tile (0/1/2),
-    skip_zero_radii (0/1), bound_kch32 (16/32)."""
+    bound_kch16 (32/64/128), exact_xcd (0/1), polar_xcd (0/1), bound_tile (0/1/2/3),
+    skip_zero_radii (0/1), bound_kch32 (16/32), polar_cols (16/32)."""
     for k, v in kw.items():
         _check(lib().acom_set_tuning(TUNING_KEYS[k], int(v)), "acom_set_tuning")
 

@@ -33,8 +33,8 @@ namespace acom {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kPolarCols = 16;   // radial columns per polar block (8 complex sequences)
-constexpr int kPeakCache = 256;
+constexpr int kPolarCols = 16;   // radial columns per column-mask word (and per pass of the narrow polar variant)
+constexpr int kPeakCache = 256;  // peaks prepared at once by the 16-column polar pass (128 by the 32-column one)
 constexpr int kBatch = 4;        // zones evaluated together by the exact pass
 constexpr int kDefaultChunk = 16384;
 
@@ -83,8 +83,6 @@ inline int xcd_blocks(int total, int* per) {
 
 // ------------------------------------------------------------ 1. polar ----
 
-constexpr int kPolarParts = kThreads / kPolarCols;  // angular partitions of the splat
-
 struct PolarArgs {
   int N, R, Rp, Nk, nrad;
   int rad[kMaxRadices];
@@ -110,41 +108,51 @@ struct PolarArgs {
   int* flags;              // np: 0 ok, 1 invalid data, 2 no peaks
   float* Ximg;             // optional X[p][a][s] (np x N x R)
   int do_fft;
-  int ntiles;              // radial tiles of kPolarCols columns
+  int ntiles;              // radial tiles of kPolarCols columns (column-mask words per pattern)
   int per;                 // > 0: XCD-grouped block order with this many items per XCD
   uint32_t* cmask;         // np x ntiles: bit c set when column c of the tile holds a nonzero X (or null)
 };
 
-// One workgroup per pattern, looping over its radial tiles of kPolarCols
-// columns.  The peaks are prepared once per pattern (bin of the nearest angle
+// One workgroup per pattern, looping over its radial tiles of NC columns (16 or
+// 32).  The peaks are prepared once per pattern (bin of the nearest angle
 // ac, offset f, radius, weight) and, per tile, compacted to those whose radius
 // lies within the kernel reach of the tile's columns.  Splat: thread (column c,
-// part t) owns the angular bins a = t mod kPolarParts of column c (interleaved,
+// part t) owns the angular bins a = t mod (256 / NC) of column c (interleaved,
 // so that a peak's short window is shared by all parts) and adds the listed
 // peaks' kernel there in peak order (no atomics, deterministic).  A peak
 // at angle gamma sits at t = gamma / dphi = ac + f; the angle from bin ac + jj
 // is then (jj - f) dphi, already wrapped while the window is shorter than the
 // circle, so cells need only FP32 arithmetic.  Then the FFT along phi3 of the
 // columns packed in pairs as complex sequences (skipped for a tile with no
-// nonzero X, whose spectrum is exactly zero).
+// nonzero X, whose spectrum is exactly zero).  With NC = 32 the column pairs of
+// a tile are 16 complex sequences, the FFT's butterflies fill the workgroup
+// better, a (pattern, frequency) row segment of FP32 output is one 128-byte
+// line, and there are half as many passes and barriers; the LDS (53 KiB at
+// N = 360, peak cache of 128) still admits three workgroups per compute unit.
 // NT > 0: angular length known at compile time (FFT specialised); NT = 0: any.
-template <int NT>
+template <int NC>
+constexpr int polar_peak_cache() {
+  return NC == 32 ? 128 : kPeakCache;
+}
+template <int NT, int NC>
 __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
-  static_assert(kPeakCache == kThreads, "one thread prepares one cached peak");
-  static_assert(64 % kPolarCols == 0 && kPolarCols == 16, "column mask folding assumes 16 columns");
+  static_assert(NC == 16 || NC == 32, "16 or 32 columns per pass");
+  constexpr int PC = polar_peak_cache<NC>();
+  constexpr int kParts = kThreads / NC;  // angular partitions of the splat
+  static_assert(PC <= kThreads, "one thread prepares one cached peak");
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  constexpr int NS = kPolarCols / 2;
+  constexpr int NS = NC / 2;
   const int N = NT > 0 ? NT : a.N;
   float2* b0 = reinterpret_cast<float2*>(smem_raw);   // [rev(a)][NS] complex: columns packed in pairs
   float2* tw = b0 + N * NS;
   int* rev = reinterpret_cast<int*>(tw + N);
   int* pac = rev + N;
-  float* pf = reinterpret_cast<float*>(pac + kPeakCache);
-  float* pq = pf + kPeakCache;
-  float* pw = pq + kPeakCache;
-  int* plist = reinterpret_cast<int*>(pw + kPeakCache);  // cached peaks reaching the current tile
-  float* sqs = reinterpret_cast<float*>(plist + kPeakCache);  // q_s of every column (-1 beyond R)
-  uint32_t* scmw = reinterpret_cast<uint32_t*>(sqs + a.Rp);  // [tile][wave] column masks
+  float* pf = reinterpret_cast<float*>(pac + PC);
+  float* pq = pf + PC;
+  float* pw = pq + PC;
+  int* plist = reinterpret_cast<int*>(pw + PC);  // cached peaks reaching the current tile
+  float* sqs = reinterpret_cast<float*>(plist + PC);  // q_s of every column (-1 beyond R)
+  uint32_t* scmw = reinterpret_cast<uint32_t*>(sqs + a.Rp);  // [16-column tile][wave] column masks
   __shared__ int s_bad, s_nlist;
   __shared__ float s_red[kThreads / 64];
   __shared__ double s_red64[kThreads / 64];
@@ -167,10 +175,10 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
   const double inv_dphi = N / 6.283185307179586476925286766559;
   const float dphi = (float)(6.283185307179586476925286766559 / N);
   const float pi_f = 3.14159265358979323846f;
-  const int c = tid % kPolarCols, part = tid / kPolarCols;
+  const int c = tid % NC, part = tid / NC;
   const float kinv = a.kernel == ACOM_KERNEL_CONE ? 1.0f / a.delta : 1.0f / (2.0f * a.sigma * a.sigma);
   const float sig3 = 3.0f * a.sigma;
-  const bool single = (m1 - m0) <= kPeakCache;
+  const bool single = (m1 - m0) <= PC;
   double wsum = 0.0;  // this thread's share of sum_m w_m (first pass over the peaks only)
 
   // cache peaks [c0, c0 + cnt): every thread calls; ends with a barrier
@@ -196,14 +204,15 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
 
   float sc = 1.0f;
   float xx = 0.0f;  // this thread's share of sum X^2 over all tiles (fixed order)
-  float* X = reinterpret_cast<float*>(b0);  // X(phi_a, column) at [rev(a)][kPolarCols]
+  float* X = reinterpret_cast<float*>(b0);  // X(phi_a, column) at [rev(a)][NC]
   const size_t pbase = (size_t)(p >> 6) * a.ld_tile + (size_t)(p & 63) * a.ldp;
-  for (int tile = 0; tile < a.ntiles; ++tile) {
-    const int col0 = tile * kPolarCols;
-    for (int i = tid; i < N * kPolarCols / 4; i += kThreads)
+  const int npass = a.Rp / NC;
+  for (int tile = 0; tile < npass; ++tile) {
+    const int col0 = tile * NC;
+    for (int i = tid; i < N * NC / 4; i += kThreads)
       reinterpret_cast<float4*>(X)[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     // radii of the tile's real columns (padding columns carry q = -1: no peak reaches them)
-    const int cl = min(col0 + kPolarCols, a.R) - 1;
+    const int cl = min(col0 + NC, a.R) - 1;
     const float qlo = col0 < a.R ? sqs[col0] : -1.0f;
     const float qhi = col0 < a.R ? sqs[cl] : -1.0f;
     const float qs = sqs[col0 + c];
@@ -216,8 +225,8 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
     const bool full = 2 * hw + 1 >= N;
     bool listed = false;  // some peak reaches the tile (else its X is exactly zero)
     __syncthreads();
-    for (int64_t c0 = m0; c0 < m1; c0 += kPeakCache) {
-      const int cnt = (int)min((int64_t)kPeakCache, m1 - c0);
+    for (int64_t c0 = m0; c0 < m1; c0 += PC) {
+      const int cnt = (int)min((int64_t)PC, m1 - c0);
       if (!single) prep(c0, cnt, tile == 0);
       // wave 0 lists, in peak order, the cached peaks within reach of [qlo, qhi]
       // (the same float comparisons as the per-column test below, so no reached
@@ -246,7 +255,7 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
           const float f = pf[j];
           const float dq2 = dq * dq;
           if (full) {
-            for (int ai = part; ai < N; ai += kPolarParts) {
+            for (int ai = part; ai < N; ai += kParts) {
               int u = ai - ac;  // in (-3N/2, 3N/2): bring to [-N/2, N/2)
               if (u >= N / 2) u -= N;
               if (u < -N / 2) u += N;
@@ -255,21 +264,21 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
               if (xa < -pi_f) xa += 2.0f * pi_f;
               const float dp = xa * qs;
               const float k = kern32(__builtin_amdgcn_sqrtf(dq2 + dp * dp), a.delta, kinv, sig3, a.kernel);
-              if (k > 0.0f) X[rev[ai] * kPolarCols + c] += w * k;
+              if (k > 0.0f) X[rev[ai] * NC + c] += w * k;
             }
           } else {
             // window [ac - hw, ac + hw] in unwrapped bins; fewer than N bins, so each
             // bin is met by at most one of the three shifts; this thread takes the
-            // bins u - sh = part (mod kPolarParts)
+            // bins u - sh = part (mod kParts)
             const int wlo = ac - hw, whi = ac + hw + 1;
             for (int sh = -N; sh <= N; sh += N) {
               const int u0 = max(wlo, sh), u1 = min(whi, sh + N);
               if (u0 >= u1) continue;
-              const int first = u0 + (part - (u0 - sh) % kPolarParts + kPolarParts) % kPolarParts;
-              for (int u = first; u < u1; u += kPolarParts) {
+              const int first = u0 + (part - (u0 - sh) % kParts + kParts) % kParts;
+              for (int u = first; u < u1; u += kParts) {
                 const float dp = ((float)(u - ac) - f) * dqs;
                 const float k = kern32(__builtin_amdgcn_sqrtf(dq2 + dp * dp), a.delta, kinv, sig3, a.kernel);
-                if (k > 0.0f) X[rev[u - sh] * kPolarCols + c] += w * k;
+                if (k > 0.0f) X[rev[u - sh] * NC + c] += w * k;
               }
             }
           }
@@ -306,9 +315,9 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
     }
     const bool bad = s_bad != 0;
     if (a.Ximg) {
-      for (int i = tid; i < N * kPolarCols; i += kThreads) {
-        const int ai = i / kPolarCols, cc = i % kPolarCols;
-        if (col0 + cc < a.R) a.Ximg[((size_t)p * N + ai) * a.R + col0 + cc] = bad ? 0.0f : X[rev[ai] * kPolarCols + cc];
+      for (int i = tid; i < N * NC; i += kThreads) {
+        const int ai = i / NC, cc = i % NC;
+        if (col0 + cc < a.R) a.Ximg[((size_t)p * N + ai) * a.R + col0 + cc] = bad ? 0.0f : X[rev[ai] * NC + cc];
       }
     }
     if (!a.do_fft) {
@@ -366,7 +375,7 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
     {
       static_assert(kThreads % NS == 0 && 64 % NS == 0, "a thread keeps its column pair across the unpack");
       const unsigned long long be = __ballot(nzE), bo = __ballot(nzO);
-      uint32_t m = 0;
+      uint32_t m = 0;  // bit c: column col0 + c has a nonzero spectrum in this wave's share
 #pragma unroll
       for (int l = 0; l < NS; ++l) {  // lane l + NS j holds pair l
         bool e = false, o = false;
@@ -377,7 +386,12 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
         }
         m |= (e ? 1u : 0u) << (2 * l) | (o ? 1u : 0u) << (2 * l + 1);
       }
-      if ((tid & 63) == 0) scmw[tile * (kThreads / 64) + (tid >> 6)] = m;
+      if ((tid & 63) == 0) {
+        constexpr int T16 = NC / kPolarCols;  // mask words per pass
+#pragma unroll
+        for (int h = 0; h < T16; ++h)
+          scmw[(tile * T16 + h) * (kThreads / 64) + (tid >> 6)] = (m >> (kPolarCols * h)) & 0xFFFFu;
+      }
     }
     __syncthreads();
   }
@@ -693,6 +707,221 @@ __global__ void __launch_bounds__(64 * WM * WN) bound_kernel(BoundArgs a) {
 #pragma unroll
       for (int j = 0; j < JN; ++j) {
         const int z = tz * TZ + wc * JN * 16 + j * 16 + li;
+        if (z < a.Zvalid) a.U[(size_t)p * a.ldU + z] = U[i][j][r] * inv;
+      }
+    }
+}
+
+// Contraction with 16-bit operands on a two-group ("ping-pong") schedule.
+// Block tile 128 x 128 (patterns x zones), eight waves in two groups of four:
+// the hardware places wave w on SIMD w % 4, so every SIMD holds one wave of
+// each group.  Group g computes patterns 64 g .. 64 g + 63 and wave q of a group
+// zones 32 q .. 32 q + 31 (4 x 2 MFMA blocks of 16 x 16, the same products and
+// epilogue as bound_kernel).  The contraction advances in subs of 32 radii, one
+// LDS stage each, in a ring of four stages.  Every wave alternates
+//   read section:  LDS-direct copies of sub j + 3, fragment reads of sub j and,
+//                  on the first sub of a frequency, the previous frequency's
+//                  epilogue (square roots into U);
+//   MFMA section:  the 32 MFMAs of sub j,
+// with a workgroup barrier after each section.  Group 1 passes one extra barrier
+// first, so it runs one section behind group 0: while one wave of a SIMD issues
+// MFMAs, the other reads LDS or runs its epilogue, and the matrix unit is not
+// left idle during either.
+//
+// Stage hazards: sub j is read by group 0 in section 2j and by group 1 in
+// section 2j + 1; its copies land before either (every wave waits for its own
+// copies of sub j + 1 at the end of its read section of sub j, before a
+// barrier), and the stage of sub j - 1 is refilled (with sub j + 3) only from
+// section 2j on, after both groups have finished reading it.
+namespace pp {
+constexpr int kStages = 4;
+constexpr int kRB = 64;                 // 32 radii of 16-bit operands per staged row
+constexpr int kArr = 128 * kRB;         // one operand array of one stage: 8 KiB
+constexpr int kStage = 4 * kArr;        // Xr, Xi, Pr, Pi
+constexpr int kCopies = 4;              // 1 KiB LDS-direct copies per wave per stage
+// s_waitcnt immediates (gfx9 encoding: vmcnt[3:0] | expcnt << 4 | lgkmcnt << 8 | vmcnt[5:4] << 14)
+constexpr int kWaitLgkmVm0 = 0x0070;                    // lgkmcnt(0) vmcnt(0)
+constexpr int kWaitLgkmVmRing = 0x0070 | ((kStages - 2) * kCopies);  // lgkmcnt(0), the later subs' copies may be in flight
+constexpr int kWaitVm = 0x0F70;                          // | n: vmcnt(n) only
+}  // namespace pp
+
+// A workgroup barrier that orders nothing but itself: the waits it needs are
+// explicit s_waitcnt before it, and no instruction is scheduled across it.
+__device__ __forceinline__ void pp_barrier() {
+  __builtin_amdgcn_sched_barrier(0);
+  asm volatile("s_barrier" ::: "memory");
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(512) bound_pp_kernel(BoundArgs a) {
+  using namespace pp;
+  static_assert(KIND == 1 || KIND == 2, "16-bit operands");
+  typedef typename std::conditional<KIND == 1, bf16x8, f16x8>::type V8;
+  constexpr int TP = 128, TZ = 128, IM = 4, JN = 2;
+  // one LDS object per stage, so that the compiler sees that the copies into
+  // one stage never alias the fragment reads of another
+  static_assert(kStages >= 3 && kStages <= 5 && (kStages - 2) * kCopies < 16, "ring of 3 to 5 stages");
+  __shared__ __align__(16) unsigned char sb0[kStage];
+  __shared__ __align__(16) unsigned char sb1[kStage];
+  __shared__ __align__(16) unsigned char sb2[kStage];
+  __shared__ __align__(16) unsigned char sb3[kStages > 3 ? kStage : 16];
+  __shared__ __align__(16) unsigned char sb4[kStages > 4 ? kStage : 16];
+  unsigned char* const ring[5] = {sb0, sb1, sb2, sb3, sb4};
+
+  int tp, tz;
+  if (a.order == 0) {
+    tp = blockIdx.x % a.nP;
+    tz = blockIdx.x / a.nP;
+  } else {
+    const int w = xcd_item(a.per);
+    if (w >= a.nP * a.nZ) return;
+    tp = w / a.nZ;
+    tz = w % a.nZ;
+  }
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int grp = wave >> 2, q = wave & 3;
+  const int li = lane & 15, lg = lane >> 4;
+  const bool live = tz * TZ + q * 32 < a.Zvalid && tp * TP + grp * 64 < a.np;
+
+  float U[IM][JN][4];
+#pragma unroll
+  for (int i = 0; i < IM; ++i)
+#pragma unroll
+    for (int j = 0; j < JN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) U[i][j][r] = 0.0f;
+
+  const uint16_t* gx0 = reinterpret_cast<const uint16_t*>(a.xr);
+  const uint16_t* gx1 = reinterpret_cast<const uint16_t*>(a.xi);
+  const uint16_t* gp0 = reinterpret_cast<const uint16_t*>(a.pr);
+  const uint16_t* gp1 = reinterpret_cast<const uint16_t*>(a.pi);
+  const size_t slab = (size_t)a.Nk * 64 * a.Rp;
+  const int s_begin = (a.r0 / 32) * 32;  // whole subs of radii that are zero in every zone
+  const int spk = (a.Rp - s_begin) / 32;
+  const int nsub = a.Nk * spk;
+
+  // this lane's 16 bytes of the wave's KiB of each operand array: block row
+  // 16 wave + lane / 4, physical chunk lane % 4, holding logical chunk
+  // phys ^ swizzle(row) of that row
+  size_t offx, offp;
+  {
+    const int row = wave * 16 + (lane >> 2), phys = lane & 3;
+    const int ch = (phys ^ chunk_swizzle<kRB>(row)) * 8;
+    offx = (size_t)min(tp * 2 + (row >> 6), a.nX64 - 1) * slab + (size_t)(row & 63) * a.Rp + ch;
+    offp = (size_t)min(tz * 2 + (row >> 6), a.nP64 - 1) * slab + (size_t)(row & 63) * a.Rp + ch;
+  }
+  auto issue = [&](int g, unsigned char* st) __attribute__((always_inline)) {
+    const int k = g / spk;
+    const size_t kb = (size_t)k * 64 * a.Rp + s_begin + (size_t)(g - k * spk) * 32;
+    typedef __attribute__((address_space(3))) void* lds_t;
+    __builtin_amdgcn_global_load_lds((const void*)(gx0 + kb + offx), (lds_t)(st + 0 * kArr + wave * 1024), 16, 0, 0);
+    __builtin_amdgcn_global_load_lds((const void*)(gx1 + kb + offx), (lds_t)(st + 1 * kArr + wave * 1024), 16, 0, 0);
+    __builtin_amdgcn_global_load_lds((const void*)(gp0 + kb + offp), (lds_t)(st + 2 * kArr + wave * 1024), 16, 0, 0);
+    __builtin_amdgcn_global_load_lds((const void*)(gp1 + kb + offp), (lds_t)(st + 3 * kArr + wave * 1024), 16, 0, 0);
+  };
+  auto at = [](int row, int chunk) { return row * kRB + ((chunk ^ chunk_swizzle<kRB>(row)) << 4); };
+
+  V8 fxr[IM], fxi[IM], fpr[JN], fpi[JN];
+  f32x4 acc[IM][JN][4];
+  auto read = [&](const unsigned char* st) __attribute__((always_inline)) {
+#pragma unroll
+    for (int i = 0; i < IM; ++i) {
+      const int rx = grp * 64 + i * 16 + li;
+      fxr[i] = *reinterpret_cast<const V8*>(st + 0 * kArr + at(rx, lg));
+      fxi[i] = *reinterpret_cast<const V8*>(st + 1 * kArr + at(rx, lg));
+    }
+#pragma unroll
+    for (int j = 0; j < JN; ++j) {
+      const int rp = q * 32 + j * 16 + li;
+      fpr[j] = *reinterpret_cast<const V8*>(st + 2 * kArr + at(rp, lg));
+      fpi[j] = *reinterpret_cast<const V8*>(st + 3 * kArr + at(rp, lg));
+    }
+  };
+  auto mma = [&](auto zc) __attribute__((always_inline)) {
+    constexpr bool Z = decltype(zc)::value;
+    const f32x4 zero4 = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int i = 0; i < IM; ++i)
+#pragma unroll
+      for (int j = 0; j < JN; ++j) {
+        if constexpr (KIND == 1) {
+          acc[i][j][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fxr[i], fpr[j], Z ? zero4 : acc[i][j][0], 0, 0, 0);
+          acc[i][j][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fxi[i], fpi[j], Z ? zero4 : acc[i][j][1], 0, 0, 0);
+          acc[i][j][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fxi[i], fpr[j], Z ? zero4 : acc[i][j][2], 0, 0, 0);
+          acc[i][j][3] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fxr[i], fpi[j], Z ? zero4 : acc[i][j][3], 0, 0, 0);
+        } else {
+          acc[i][j][0] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fxr[i], fpr[j], Z ? zero4 : acc[i][j][0], 0, 0, 0);
+          acc[i][j][1] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fxi[i], fpi[j], Z ? zero4 : acc[i][j][1], 0, 0, 0);
+          acc[i][j][2] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fxi[i], fpr[j], Z ? zero4 : acc[i][j][2], 0, 0, 0);
+          acc[i][j][3] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fxr[i], fpi[j], Z ? zero4 : acc[i][j][3], 0, 0, 0);
+        }
+      }
+  };
+  auto epilogue = [&](int k) __attribute__((always_inline)) {
+    const float wk = (k == 0 || 2 * k == a.N) ? 1.0f : 2.0f;
+#pragma unroll
+    for (int i = 0; i < IM; ++i)
+#pragma unroll
+      for (int j = 0; j < JN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float A = acc[i][j][0][r], B = acc[i][j][1][r], C = acc[i][j][2][r], D = acc[i][j][3][r];
+          const float S = fmaf(A, A, fmaf(B, B, fmaf(C, C, D * D)));
+          const float Tm = fmaf(A, B, -(C * D));
+          U[i][j][r] += wk * __builtin_amdgcn_sqrtf(fmaf(2.0f, fabsf(Tm), S));
+        }
+  };
+  // one sub: read section, barrier, MFMA section, barrier.  Sub g lives in stage
+  // g % kStages, and the copies of sub g + kStages - 1 go to the stage of sub g - 1.
+  auto body = [&](int g, unsigned char* st, unsigned char* st_ahead) __attribute__((always_inline)) {
+    const bool ahead = g + kStages - 1 < nsub;
+    if (ahead) issue(g + kStages - 1, st_ahead);
+    const int k = g / spk;
+    const bool first = g == k * spk;
+    if (live) {
+      read(st);
+      if (first && g > 0) epilogue(k - 1);
+    }
+    if (ahead) __builtin_amdgcn_s_waitcnt(kWaitLgkmVmRing);
+    else __builtin_amdgcn_s_waitcnt(kWaitLgkmVm0);
+    pp_barrier();
+    if (live) {
+      if (first) mma(std::true_type{});
+      else mma(std::false_type{});
+    }
+    pp_barrier();
+  };
+
+  // prologue: subs 0 .. kStages - 2 in flight, then every wave's copies of sub 0 landed
+#pragma unroll
+  for (int j = 0; j < kStages - 1; ++j)
+    if (j < nsub) issue(j, ring[j]);
+  if (nsub >= kStages - 1) __builtin_amdgcn_s_waitcnt(kWaitVm | ((kStages - 2) * kCopies));
+  else __builtin_amdgcn_s_waitcnt(kWaitVm | 0);
+  pp_barrier();
+  if (grp == 1) pp_barrier();
+  for (int g = 0; g < nsub; g += kStages) {
+#pragma unroll
+    for (int j = 0; j < kStages; ++j)
+      if (g + j < nsub) body(g + j, ring[j], ring[(j + kStages - 1) % kStages]);
+  }
+  if (grp == 0) pp_barrier();
+  if (!live) return;
+  if (nsub > 0) epilogue(a.Nk - 1);
+  const float invN = 1.0f / (float)a.N;
+#pragma unroll
+  for (int i = 0; i < IM; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int p = tp * TP + grp * 64 + i * 16 + lg * 4 + r;
+      if (p >= a.np) continue;
+      const float inv = invN / a.scale[p];
+#pragma unroll
+      for (int j = 0; j < JN; ++j) {
+        const int z = tz * TZ + q * 32 + j * 16 + li;
         if (z < a.Zvalid) a.U[(size_t)p * a.ldU + z] = U[i][j][r] * inv;
       }
     }
@@ -1070,6 +1299,7 @@ struct Tuning {
   int bound_tile = 2;     // contraction block tile: 0 = 64 x 64, 1 = 128 x 128, 2 = by problem size
   int skip_zero_radii = 1;  // contraction: skip the leading radii where the plan is zero in every zone
   int bound_kch32 = 16;   // radii per LDS step of the FP32 contraction (16 or 32)
+  int polar_cols = 32;    // radial columns per pass of the polar kernel (16 or 32)
 };
 Tuning g_tune;
 
@@ -1130,8 +1360,9 @@ WsLayout layout(const PlanDev& d, bool lowp, int Pc) {
   return L;
 }
 
+template <int NC>
 size_t polar_lds(const PlanDev& d) {
-  return (size_t)(d.N * (kPolarCols / 2) + d.N) * sizeof(float2) + (size_t)d.N * 4 + kPeakCache * (4 + 4 + 4 + 4 + 4) +
+  return (size_t)(d.N * (NC / 2) + d.N) * sizeof(float2) + (size_t)d.N * 4 + polar_peak_cache<NC>() * (4 + 4 + 4 + 4 + 4) +
          (size_t)d.Rp * 4 + (size_t)(d.Rp / kPolarCols) * (kThreads / 64) * 4;
 }
 size_t exact_lds(const PlanDev& d) {
@@ -1200,18 +1431,24 @@ void set_ws(PolarArgs& a, const WsLayout& L, unsigned char* ws, const PlanDev& d
   a.flags = reinterpret_cast<int*>(ws + L.flags);
 }
 
-template <int NT>
-acom_status_t launch_polar_n(const PlanDev& d, const PolarArgs& a, hipStream_t s) {
-  acom_status_t st = ensure_lds(polar_kernel<NT>, polar_lds(d));
+template <int NT, int NC>
+acom_status_t launch_polar_nc(const PlanDev& d, const PolarArgs& a, hipStream_t s) {
+  acom_status_t st = ensure_lds(polar_kernel<NT, NC>, polar_lds<NC>(d));
   if (st != ACOM_OK) return st;
   PolarArgs b = a;
   b.ntiles = d.Rp / kPolarCols;
   b.per = 0;
   const int nblocks = g_tune.polar_xcd ? xcd_blocks(b.np, &b.per) : b.np;
   ProfScope prof(0, s);
-  polar_kernel<NT><<<dim3(nblocks), kThreads, polar_lds(d), s>>>(b);
+  polar_kernel<NT, NC><<<dim3(nblocks), kThreads, polar_lds<NC>(d), s>>>(b);
   ACOM_HIP(hipGetLastError());
   return ACOM_OK;
+}
+template <int NT>
+acom_status_t launch_polar_n(const PlanDev& d, const PolarArgs& a, hipStream_t s) {
+  // 32 columns per pass when Rp allows it (Rp is a multiple of 32) and the tuning asks
+  if (g_tune.polar_cols == 32 && d.Rp % 32 == 0) return launch_polar_nc<NT, 32>(d, a, s);
+  return launch_polar_nc<NT, 16>(d, a, s);
 }
 
 acom_status_t launch_polar(const PlanDev& d, const PolarArgs& a, hipStream_t s) {
@@ -1307,6 +1544,20 @@ acom_status_t launch_bound(const PlanDev& d, int precision, const WsLayout& L, u
   // A shape chosen by acom_autotune for this plan and precision takes precedence.
   const int tile = t ? t->tile : g_tune.bound_tile;
   const int kch = t ? t->kch : (precision == ACOM_FP32 ? g_tune.bound_kch32 : g_tune.bound_kch16);
+  if (tile == 3) {  // two-group schedule, 16-bit operands only
+    if (precision == ACOM_FP32) return fail(ACOM_E_UNSUPPORTED, "the two-group contraction takes 16-bit operands");
+    b.nP = (b.np + 127) / 128;
+    b.nZ = (b.Zvalid + 127) / 128;
+    const int nblocks = b.order == 0 ? b.nP * b.nZ : xcd_blocks(b.nP * b.nZ, &b.per);
+    if (b.order == 0) b.per = 0;
+    ProfScope prof(1, s);
+    if (precision == ACOM_BF16)
+      bound_pp_kernel<1><<<dim3(nblocks), 512, 0, s>>>(b);
+    else
+      bound_pp_kernel<2><<<dim3(nblocks), 512, 0, s>>>(b);
+    ACOM_HIP(hipGetLastError());
+    return ACOM_OK;
+  }
   const bool use_large = tile == 1 || (tile == 2 && precision != ACOM_FP32 && large >= 2 * 256);
   if (use_large && precision == ACOM_FP32) return launch_bound_t<4, 2, 2, 2>(d, precision, b, kch, s);
   if (use_large) return launch_bound_t<2, 4, 4, 2>(d, precision, b, kch, s);
@@ -1452,9 +1703,12 @@ extern "C" acom_status_t acom_autotune(acom_plan_t plan, const acom_peaks_t* pea
   if ((st = launch_polar(d, pa, s)) != ACOM_OK) return st;
   // candidate shapes: block tile x radius step (16-bit operands) x block order
   std::vector<PlanDev::BoundShape> cand;
-  for (int tile = 0; tile <= 1; ++tile)
+  for (int tile = 0; tile <= 3; ++tile) {
+    if (tile == 2 || (tile == 3 && precision == ACOM_FP32)) continue;
+    const int kmin = precision == ACOM_FP32 ? 16 : 32;
+    const int kmax = precision == ACOM_FP32 ? 32 : (tile == 0 ? 128 : tile == 1 ? 64 : 32);
     for (int order = 0; order <= 1; ++order)
-      for (int kch = (precision == ACOM_FP32 ? 16 : 32); kch <= (precision == ACOM_FP32 ? 32 : (tile ? 64 : 128)); kch *= 2) {
+      for (int kch = kmin; kch <= kmax; kch *= 2) {
         if (d.Rp % kch) continue;
         PlanDev::BoundShape c;
         c.set = 1;
@@ -1463,6 +1717,7 @@ extern "C" acom_status_t acom_autotune(acom_plan_t plan, const acom_peaks_t* pea
         c.order = order;
         cand.push_back(c);
       }
+  }
   hipEvent_t e0, e1;
   ACOM_HIP(hipEventCreate(&e0));
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -1663,7 +1918,7 @@ extern "C" acom_status_t acom_set_tuning(int32_t key, int32_t value) {
       g_tune.polar_xcd = value;
       return ACOM_OK;
     case 4:
-      if (value < 0 || value > 2) return fail(ACOM_E_INVALID, "contraction tile must be 0, 1 or 2");
+      if (value < 0 || value > 3) return fail(ACOM_E_INVALID, "contraction tile must be 0, 1, 2 or 3");
       g_tune.bound_tile = value;
       return ACOM_OK;
     case 5:
@@ -1673,6 +1928,10 @@ extern "C" acom_status_t acom_set_tuning(int32_t key, int32_t value) {
     case 6:
       if (value != 16 && value != 32) return fail(ACOM_E_INVALID, "FP32 step must be 16 or 32");
       g_tune.bound_kch32 = value;
+      return ACOM_OK;
+    case 7:
+      if (value != 16 && value != 32) return fail(ACOM_E_INVALID, "polar columns per pass must be 16 or 32");
+      g_tune.polar_cols = value;
       return ACOM_OK;
 
   }

@@ -75,6 +75,51 @@ def test_polar_image_and_spectrum(acom, small):
         assert np.abs(Xi[p] - F.imag).max() <= 1e-5 * scf
 
 
+@pytest.mark.parametrize("cfg", ["small", "ragged48", "scan"])
+def test_polar_pass_widths_agree(acom, cfg):
+    """The polar kernel's 32-column passes compute every cell and every
+    spectrum value with the same operations in the same order as its 16-column
+    passes (cell sums in peak order, the same butterflies per sequence), so the
+    image and the spectrum are bit-identical; both match the oracle, and so do
+    the decisions of a match run on top of either."""
+    if cfg == "small":
+        pcfg, d = helpers.SMALL, synth.make("small")
+    elif cfg == "ragged48":
+        pcfg = dict(k_max=1.2, n_radial=48, n_angular=90, zone_step_deg=5.0)
+        d = synth.make("small")
+    else:
+        pcfg = helpers.SCAN
+        d = synth.subset(synth.make("scan"), np.arange(0, 65536, 97))
+    opl = helpers.oracle_plan(["fcc"], **pcfg)
+    gpl = helpers.gpu_plan(["fcc"], **pcfg)
+    pk = acom.Peaks.from_host(d)
+    out = {}
+    try:
+        for nc in (16, 32):
+            acom.set_tuning(polar_cols=nc)
+            X = gpl.polar_image(pk).cpu().numpy()
+            Xr, Xi = gpl.polar_spectrum(pk)
+            res = gpl.match(pk, top_k=2, precision="bf16")
+            torch.cuda.synchronize()
+            out[nc] = (X, Xr.cpu().numpy(), Xi.cpu().numpy(), {k: v.cpu().numpy() for k, v in res.items() if v is not None})
+    finally:
+        acom.set_tuning(polar_cols=32)
+    for i in range(3):
+        assert np.array_equal(out[16][i], out[32][i]), i
+    for k in ("zone", "bin", "mirror", "score"):
+        assert np.array_equal(out[16][3][k], out[32][3][k]), k
+    X, Xr, Xi, _ = out[32]
+    for p in range(0, len(d["offsets"]) - 1, 37):
+        Xo = helpers.oracle_image(opl, d, p)
+        sc = max(np.abs(Xo).max(), 1e-30)
+        assert np.abs(X[p] - Xo).max() <= 1e-5 * sc
+        F = np.fft.rfft(Xo, axis=0)
+        scf = max(np.abs(F).max(), 1e-30)
+        assert np.abs(Xr[p] - F.real).max() <= 1e-5 * scf
+        assert np.abs(Xi[p] - F.imag).max() <= 1e-5 * scf
+    _check_decisions(opl, d, out[32][3], range(0, len(d["offsets"]) - 1, 37), top_k=2)
+
+
 def test_correlogram_and_bound(acom, small):
     d, opl, gpl = small
     pk = acom.Peaks.from_host(d)
@@ -243,6 +288,34 @@ def test_full_scan_sampled_against_oracle(acom, scan, precision):
     G = metrics.cubic_rotations()
     mis = [metrics.misorientation_deg(res["orient"][p, 0], d["truth"][p], G) for p in idx[:16]]
     assert np.median(mis) < 1.0
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp16"])
+def test_contraction_shapes_agree_on_scan(acom, scan, precision):
+    """Every launch shape of the 16-bit contraction (64 x 64, 128 x 128, and
+    128 x 128 on the two-group schedule with 32-radius stages) issues the same
+    MFMA sequence for each (pattern, zone) and the same epilogue, so the bound
+    is bit-identical across shapes.  Checked on 16,684 scan patterns against
+    the 1081-zone plan (ragged tails in both tile dimensions), and against the
+    oracle's bound within the rigorous operand-rounding margin on samples."""
+    d, opl, gpl = scan
+    sub = synth.subset(d, np.arange(16384 + 300))
+    pk = acom.Peaks.from_host(sub)
+    U = {}
+    try:
+        for tile, kch in ((0, 64), (1, 64), (3, 64)):
+            acom.set_tuning(bound_tile=tile, bound_kch16=kch)
+            U[tile] = gpl.bound(pk, precision).cpu().numpy()
+    finally:
+        acom.set_tuning(bound_tile=2, bound_kch16=64)
+    assert np.array_equal(U[0], U[1])
+    assert np.array_equal(U[0], U[3])
+    eps = 2 * 2 ** -8 if precision == "bf16" else 2 * 2 ** -11
+    for p in (0, 127, 128, 16383, 16384 + 299):
+        Xo = helpers.oracle_image(opl, sub, p)
+        Uo = correlate.spectral_bound(opl["P"], Xo)
+        xn = np.sqrt(np.sum(Xo ** 2))
+        assert np.all(np.abs(U[3][p] - Uo) <= eps * xn + 1e-5 * Uo.max()), p
 
 
 @pytest.mark.parametrize("n_radial,k_max", [(128, 2.0), (512, 2.0)])
