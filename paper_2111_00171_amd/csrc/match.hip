@@ -118,7 +118,8 @@ struct PolarArgs {
 // ac, offset f, radius, weight) and, per tile, compacted to those whose radius
 // lies within the kernel reach of the tile's columns.  Splat: thread (column c,
 // part t) owns the angular bins a = t mod (256 / NC) of column c (interleaved,
-// so that a peak's short window is shared by all parts) and adds the listed
+// so that a peak's short window is shared by all parts; the parts of a column
+// are consecutive threads) and adds the listed
 // peaks' kernel there in peak order (no atomics, deterministic).  A peak
 // at angle gamma sits at t = gamma / dphi = ac + f; the angle from bin ac + jj
 // is then (jj - f) dphi, already wrapped while the window is shorter than the
@@ -175,7 +176,10 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
   const double inv_dphi = N / 6.283185307179586476925286766559;
   const float dphi = (float)(6.283185307179586476925286766559 / N);
   const float pi_f = 3.14159265358979323846f;
-  const int c = tid % NC, part = tid / NC;
+  // the parts of one column are consecutive lanes: a wave covers 64 / kParts
+  // whole columns, so the waves whose columns no listed peak reaches skip the
+  // splat loop as a whole instead of idling lanes in every wave
+  const int c = tid / kParts, part = tid % kParts;
   const float kinv = a.kernel == ACOM_KERNEL_CONE ? 1.0f / a.delta : 1.0f / (2.0f * a.sigma * a.sigma);
   const float sig3 = 3.0f * a.sigma;
   const bool single = (m1 - m0) <= PC;
@@ -453,10 +457,13 @@ struct BoundTraits<0> {
 // step stp run on the other of two LDS buffers, with one barrier per step.  A
 // staged row holds KCH radii (RB = 64, 128 or 256 bytes) with no padding; its
 // 16-byte chunks are XOR-permuted by row so that the 16 rows one quarter-wave
-// reads for an MFMA operand fall in 16 distinct bank groups.
+// reads for an MFMA operand (one 16-byte chunk each) meet no LDS bank conflict.
+// The permutations were chosen by measurement on gfx950 (ds_read_b128 rate of
+// each pattern): for 64-byte rows (row >> 1) & 3 is conflict-free while
+// (row >> 2) & 3 runs at two thirds of the rate.
 template <int RB>
 __device__ __forceinline__ int chunk_swizzle(int row) {
-  return RB == 64 ? ((row >> 2) & 3) : RB == 128 ? ((row >> 1) & 7) : (row & 15);
+  return RB == 64 ? ((row >> 1) & 3) : RB == 128 ? ((row >> 1) & 7) : (row & 15);
 }
 
 template <int KIND, int KCH, int WM, int WN, int IM, int JN>
@@ -718,21 +725,24 @@ __global__ void __launch_bounds__(64 * WM * WN) bound_kernel(BoundArgs a) {
 // each group.  Group g computes patterns 64 g .. 64 g + 63 and wave q of a group
 // zones 32 q .. 32 q + 31 (4 x 2 MFMA blocks of 16 x 16, the same products and
 // epilogue as bound_kernel).  The contraction advances in subs of 32 radii, one
-// LDS stage each, in a ring of four stages.  Every wave alternates
-//   read section:  LDS-direct copies of sub j + 3, fragment reads of sub j and,
-//                  on the first sub of a frequency, the previous frequency's
-//                  epilogue (square roots into U);
-//   MFMA section:  the 32 MFMAs of sub j,
+// LDS stage each, in a ring of kStages stages.  Every wave alternates
+//   read section:  fragment reads of sub j and, on the first sub of a
+//                  frequency, the previous frequency's epilogue (square roots
+//                  into U);
+//   MFMA section:  LDS-direct copies of sub j + kStages - 1 and the 32 MFMAs
+//                  of sub j,
 // with a workgroup barrier after each section.  Group 1 passes one extra barrier
 // first, so it runs one section behind group 0: while one wave of a SIMD issues
-// MFMAs, the other reads LDS or runs its epilogue, and the matrix unit is not
-// left idle during either.
+// MFMAs, the other reads LDS or runs its epilogue.
 //
-// Stage hazards: sub j is read by group 0 in section 2j and by group 1 in
-// section 2j + 1; its copies land before either (every wave waits for its own
-// copies of sub j + 1 at the end of its read section of sub j, before a
-// barrier), and the stage of sub j - 1 is refilled (with sub j + 3) only from
-// section 2j on, after both groups have finished reading it.
+// Sections are numbered from the prologue's barrier: group 0 reads sub j in
+// section 2j + 1 and multiplies in 2j + 2, group 1 one section later.  Stage
+// hazards: the stage of sub j - 1 was last read in section 2j (group 1), so the
+// copies of sub j + kStages - 1 into it start in the MFMA section of sub j
+// (section 2j + 2 or 2j + 3); every wave's copies of sub j + 1 have landed by
+// the end of section 2j + 2 (group 0 waits at the end of its MFMA section of
+// sub j, group 1 at the end of its read section of sub j), before group 0
+// reads sub j + 1 in section 2j + 3.
 namespace pp {
 constexpr int kStages = 4;
 constexpr int kRB = 64;                 // 32 radii of 16-bit operands per staged row
@@ -741,7 +751,8 @@ constexpr int kStage = 4 * kArr;        // Xr, Xi, Pr, Pi
 constexpr int kCopies = 4;              // 1 KiB LDS-direct copies per wave per stage
 // s_waitcnt immediates (gfx9 encoding: vmcnt[3:0] | expcnt << 4 | lgkmcnt << 8 | vmcnt[5:4] << 14)
 constexpr int kWaitLgkmVm0 = 0x0070;                    // lgkmcnt(0) vmcnt(0)
-constexpr int kWaitLgkmVmRing = 0x0070 | ((kStages - 2) * kCopies);  // lgkmcnt(0), the later subs' copies may be in flight
+constexpr int kWaitLgkmVmOne = 0x0070 | ((kStages - 3) * kCopies);  // lgkmcnt(0), later subs' copies may be in flight
+constexpr int kWaitLgkm = 0xC07F;                        // lgkmcnt(0) only
 constexpr int kWaitVm = 0x0F70;                          // | n: vmcnt(n) only
 }  // namespace pp
 
@@ -878,20 +889,27 @@ __global__ void __launch_bounds__(512) bound_pp_kernel(BoundArgs a) {
   // g % kStages, and the copies of sub g + kStages - 1 go to the stage of sub g - 1.
   auto body = [&](int g, unsigned char* st, unsigned char* st_ahead) __attribute__((always_inline)) {
     const bool ahead = g + kStages - 1 < nsub;
-    if (ahead) issue(g + kStages - 1, st_ahead);
     const int k = g / spk;
     const bool first = g == k * spk;
     if (live) {
       read(st);
       if (first && g > 0) epilogue(k - 1);
     }
-    if (ahead) __builtin_amdgcn_s_waitcnt(kWaitLgkmVmRing);
-    else __builtin_amdgcn_s_waitcnt(kWaitLgkmVm0);
+    // group 1 ends section 2g + 2 here: its copies of sub g + 1 (issued two
+    // MFMA sections ago; only those of sub g + 2 may still be in flight)
+    if (grp == 1 && g + kStages - 2 < nsub) __builtin_amdgcn_s_waitcnt(kWaitLgkmVmOne);
+    else if (grp == 1) __builtin_amdgcn_s_waitcnt(kWaitLgkmVm0);
+    else __builtin_amdgcn_s_waitcnt(kWaitLgkm);
     pp_barrier();
+    // the stage of sub g - 1 has been read by both groups: refill it while the MFMAs run
+    if (ahead) issue(g + kStages - 1, st_ahead);
     if (live) {
       if (first) mma(std::true_type{});
       else mma(std::false_type{});
     }
+    // group 0 ends section 2g + 2 here: its copies of sub g + 1 landed
+    if (grp == 0 && ahead) __builtin_amdgcn_s_waitcnt(kWaitVm | ((kStages - 2) * kCopies));
+    else if (grp == 0) __builtin_amdgcn_s_waitcnt(kWaitVm | 0);
     pp_barrier();
   };
 
@@ -1071,6 +1089,28 @@ __device__ __forceinline__ float parabolic(float cm1, float c0, float cp1) {
   return fminf(0.5f, fmaxf(-0.5f, 0.5f * (cm1 - cp1) / den));
 }
 
+// Inverse FFT of the batch's sequences (stride nbp in H): with the angular
+// length known at compile time, the specialised schedule for 1, 2 or 4
+// sequences (a batch of 3 is padded to 4 by its caller).
+template <int NT>
+__device__ __forceinline__ void exact_ifft(float2* H, const float2* tw, const ExactArgs& a, int nbp) {
+  if constexpr (NT > 0) {
+    if (nbp == 1)
+      block_fft_inplace_ct<NT, 1>(H, tw, -1.0f);
+    else if (nbp == 2)
+      block_fft_inplace_ct<NT, 2>(H, tw, -1.0f);
+    else
+      block_fft_inplace_ct<NT, 4>(H, tw, -1.0f);
+  } else {
+    block_fft_inplace(H, tw, a.N, nbp, a.rad, a.nrad, -1.0f);
+  }
+}
+template <int NT>
+__device__ __forceinline__ int exact_stride(int nb) {
+  return (NT > 0 && nb == 3) ? 4 : nb;
+}
+
+template <int NT>
 __global__ void __launch_bounds__(kThreads) exact_kernel(ExactArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   float2* H0 = reinterpret_cast<float2*>(smem_raw);
@@ -1104,14 +1144,15 @@ __global__ void __launch_bounds__(kThreads) exact_kernel(ExactArgs a) {
     int bz[kBatch];
     const int zb = blockIdx.y * kBatch;
     const int nb = min(kBatch, a.Z - zb);
+    const int nbp = exact_stride<NT>(nb);
     for (int b = 0; b < kBatch; ++b) bz[b] = zb + min(b, nb - 1);
-    contract_exact(a, p, bz, nb, rev, H0, groups, s_ng);
+    contract_exact(a, p, bz, nbp, rev, H0, groups, s_ng);
     __syncthreads();
-    block_fft_inplace(H0, tw, a.N, nb, a.rad, a.nrad, -1.0f);
+    exact_ifft<NT>(H0, tw, a, nbp);
     const float2* Fr = H0;
     for (int it = tid; it < nb * a.N; it += kThreads) {
       const int b = it / a.N, n = it % a.N;
-      const float2 v = Fr[n * nb + b];
+      const float2 v = Fr[n * nbp + b];
       float* out = a.C + (((size_t)p * a.Z + zb + b) * 2) * a.N;
       out[n] = v.x * invN;
       out[a.N + n] = v.y * invN;
@@ -1178,15 +1219,16 @@ __global__ void __launch_bounds__(kThreads) exact_kernel(ExactArgs a) {
     // ---- exact correlograms of the batch
     int bz[kBatch];
     for (int b = 0; b < kBatch; ++b) bz[b] = s_bz[min(b, nb - 1)];
-    contract_exact(a, p, bz, nb, rev, H0, groups, s_ng);
+    const int nbp = exact_stride<NT>(nb);  // a padded batch repeats its last zone
+    contract_exact(a, p, bz, nbp, rev, H0, groups, s_ng);
     __syncthreads();
-    block_fft_inplace(H0, tw, a.N, nb, a.rad, a.nrad, -1.0f);
+    exact_ifft<NT>(H0, tw, a, nbp);
     const float2* Fr = H0;
     for (int b = wave; b < nb; b += kThreads / 64) {
       float bv = -INFINITY;
       int bi = INT_MAX;
       for (int t = lane; t < 2 * a.N; t += 64) {
-        const float2 v = Fr[(t >> 1) * nb + b];
+        const float2 v = Fr[(t >> 1) * nbp + b];
         const float x = ((t & 1) ? v.y : v.x) * invN;
         if (x > bv || (x == bv && t < bi)) {
           bv = x;
@@ -1204,8 +1246,8 @@ __global__ void __launch_bounds__(kThreads) exact_kernel(ExactArgs a) {
       }
       if (lane == 0) {
         const int n = bi >> 1, m = bi & 1;
-        const float2 vm = Fr[(n == 0 ? a.N - 1 : n - 1) * nb + b];
-        const float2 vp = Fr[(n == a.N - 1 ? 0 : n + 1) * nb + b];
+        const float2 vm = Fr[(n == 0 ? a.N - 1 : n - 1) * nbp + b];
+        const float2 vp = Fr[(n == a.N - 1 ? 0 : n + 1) * nbp + b];
         s_rv[b] = bv;
         s_rn[b] = n;
         s_rm[b] = m;
@@ -1451,6 +1493,25 @@ acom_status_t launch_polar_n(const PlanDev& d, const PolarArgs& a, hipStream_t s
   return launch_polar_nc<NT, 16>(d, a, s);
 }
 
+template <int NT>
+acom_status_t launch_exact_n(const PlanDev& d, const ExactArgs& e, dim3 grid, hipStream_t s) {
+  acom_status_t st = ensure_lds(exact_kernel<NT>, exact_lds(d));
+  if (st != ACOM_OK) return st;
+  exact_kernel<NT><<<grid, kThreads, exact_lds(d), s>>>(e);
+  ACOM_HIP(hipGetLastError());
+  return ACOM_OK;
+}
+acom_status_t launch_exact(const PlanDev& d, const ExactArgs& e, dim3 grid, hipStream_t s) {
+  switch (d.N) {  // the same compile-time FFT lengths as the polar pass
+    case 90: return launch_exact_n<90>(d, e, grid, s);
+    case 120: return launch_exact_n<120>(d, e, grid, s);
+    case 180: return launch_exact_n<180>(d, e, grid, s);
+    case 360: return launch_exact_n<360>(d, e, grid, s);
+    case 720: return launch_exact_n<720>(d, e, grid, s);
+    default: return launch_exact_n<0>(d, e, grid, s);
+  }
+}
+
 acom_status_t launch_polar(const PlanDev& d, const PolarArgs& a, hipStream_t s) {
   switch (d.N) {  // FFT lengths with a compile-time schedule; any other length runs the generic one
     case 90: return launch_polar_n<90>(d, a, s);
@@ -1650,7 +1711,6 @@ extern "C" acom_status_t acom_match(acom_plan_t plan, const acom_peaks_t* peaks,
     return fail(ACOM_E_WORKSPACE, "workspace smaller than acom_match_workspace_size");
   hipStream_t s = (hipStream_t)stream_v;
   unsigned char* ws = reinterpret_cast<unsigned char*>(workspace);
-  if ((st = ensure_lds(exact_kernel, exact_lds(d))) != ACOM_OK) return st;
   for (int64_t c0 = 0; c0 < peaks->n_patterns; c0 += Pc) {
     const int np = (int)std::min<int64_t>(Pc, peaks->n_patterns - c0);
     PolarArgs pa = polar_args(d, peaks, c0, np, precision);
@@ -1676,9 +1736,8 @@ extern "C" acom_status_t acom_match(acom_plan_t plan, const acom_peaks_t* peaks,
       e.per = -1;
     {
       ProfScope prof(2, s);
-      exact_kernel<<<nblk, kThreads, exact_lds(d), s>>>(e);
+      if ((st = launch_exact(d, e, dim3(nblk), s)) != ACOM_OK) return st;
     }
-    ACOM_HIP(hipGetLastError());
   }
   return ACOM_OK;
 }
@@ -1836,11 +1895,7 @@ extern "C" acom_status_t acom_correlate(acom_plan_t plan, const acom_peaks_t* pe
   if ((st = launch_polar(d, pa, s)) != ACOM_OK) return st;
   ExactArgs e = exact_args(d, L, ws, 0, np);
   e.C = C;
-  if ((st = ensure_lds(exact_kernel, exact_lds(d))) != ACOM_OK) return st;
-  dim3 grid(np, (d.Z + kBatch - 1) / kBatch);
-  exact_kernel<<<grid, kThreads, exact_lds(d), s>>>(e);
-  ACOM_HIP(hipGetLastError());
-  return ACOM_OK;
+  return launch_exact(d, e, dim3(np, (d.Z + kBatch - 1) / kBatch), s);
 }
 
 extern "C" acom_status_t acom_bound(acom_plan_t plan, const acom_peaks_t* peaks, int32_t precision, float* U,
