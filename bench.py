@@ -403,13 +403,22 @@ def run_refine(args):
     idx = np.random.default_rng(9).choice(n, 512, replace=False)
     mis_grid = [metrics.misorientation_deg(init[p, 0], d["truth"][p], G) for p in idx]
     mis_ref = [metrics.misorientation_deg(m[p], d["truth"][p], G) for p in idx]
+    # the far tail: is the refined orientation a higher maximum of the score than
+    # the truth (the score itself prefers it), or did the search stop short?
+    truth = torch.tensor(np.ascontiguousarray(d["truth"].reshape(n, 9)), dtype=torch.float32, device="cuda")
+    S_truth = gpl.score(pk, truth, torch.zeros(n, 3, dtype=torch.float32, device="cuda")).cpu().numpy()
+    S_ref = S.cpu().numpy()
+    far = [p for p, mr in zip(idx, mis_ref) if mr > 5.0]
+    tail = {"patterns_over_5deg": len(far),
+            "refined_score_at_least_truth_score": int(sum(S_ref[p] >= S_truth[p] * (1.0 - 1e-5) for p in far))}
     cpu = ext = None
     if not args.no_cpu_baseline:
         cpu, ext = cpu_baseline_refine(d, init, m)
     extra = {"refinement_vs_truth_deg": {"grid_top1_median": float(np.median(mis_grid)),
                                          "refined_median": float(np.median(mis_ref)),
                                          "refined_p90": float(np.percentile(mis_ref, 90)),
-                                         "refined_p99": float(np.percentile(mis_ref, 99)), "patterns": 512},
+                                         "refined_p99": float(np.percentile(mis_ref, 99)), "patterns": 512,
+                                         "tail_over_5deg": tail},
              "contraction_shape": shape, "ms_per_step_match": round(t_match * 1e3 / args.steps, 3),
              "ms_per_step_refine": round(t_ref * 1e3 / args.steps, 3),
              "oracle_comparison": ext, "input_generation_s": round(t_gen, 3)}

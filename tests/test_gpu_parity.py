@@ -291,6 +291,28 @@ def test_full_scan_sampled_against_oracle(acom, scan, precision):
 
 
 @pytest.mark.parametrize("precision", ["bf16", "fp16"])
+def test_workspace_cells_never_read_before_written(acom, scan, precision):
+    """Every workspace cell a kernel of acom_match reads is written earlier in
+    the same call (rows past a chunk's last pattern are read only into results
+    that are never stored).  A workspace filled with NaN bytes (0xFF) beforehand
+    gives the same decisions and scores as a zeroed one, over two chunks (so the
+    second, ragged chunk also runs on the first one's leftovers)."""
+    d, opl, gpl = scan
+    sub = synth.subset(d, np.arange(4096 + 1000))
+    pk = acom.Peaks.from_host(sub)
+    nb = gpl.match_workspace_bytes(precision, 4096)
+    res = {}
+    for fill in (0, 0xFF):
+        ws = torch.full((nb,), fill, dtype=torch.uint8, device="cuda")
+        r = gpl.match(pk, top_k=2, precision=precision, chunk=4096, workspace=ws)
+        torch.cuda.synchronize()
+        res[fill] = {k: v.cpu().numpy() for k, v in r.items() if v is not None}
+    for k in ("zone", "bin", "mirror", "score"):
+        assert np.array_equal(res[0][k], res[0xFF][k]), k
+    assert np.all(np.isfinite(res[0xFF]["score"]))
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp16"])
 def test_contraction_shapes_agree_on_scan(acom, scan, precision):
     """Every launch shape of the 16-bit contraction (64 x 64, 128 x 128, and
     128 x 128 on the two-group schedule with 32-radius stages) issues the same
