@@ -46,6 +46,7 @@ PLAN_CFG = {  # phases and plan parameters of each workload
     "hcp": (["hcp"], dict(k_max=2.0, n_radial=128, n_angular=360, zone_step_deg=1.0)),
     "multi": (["fcc", "bcc", "hcp"], dict(k_max=2.0, n_radial=128, n_angular=360, zone_step_deg=1.0)),
     "refine": (["fcc"], dict(k_max=2.0, n_radial=128, n_angular=360, zone_step_deg=1.0)),
+    "overlap": (["fcc"], dict(k_max=2.0, n_radial=128, n_angular=360, zone_step_deg=1.0)),
 }
 DESCR = {
     "scan": "scan: 256x256 FCC scan, 65,536 patterns x 10-60 peaks, 1-degree plan (1081 zones), "
@@ -56,6 +57,9 @@ DESCR = {
              "10,443 zones, 128 x 360 bins, top-1, BF16 contraction, one HIP-graph replay per step",
     "refine": "refine: 65,536 FCC patterns at random orientations, top-4 grid candidates (FP32 contraction) "
               "refined by gradient ascent on the continuous score (<= 64 trials each)",
+    "overlap": "overlap: 65,536 FCC patterns, each two overlapping grains (second at 0.4-0.9 intensity), "
+               "up to 3 orientations per pattern by iterative match + forward pattern + peak deletion "
+               "(deletion radius 0.04 1/A), BF16 contraction, 1-degree plan, 128 x 360 bins",
 }
 
 
@@ -431,12 +435,122 @@ def run_refine(args):
                 cpu, extra)
 
 
+def cpu_baseline_overlap(d, res, r_del, n_orient, budget_s=15.0):
+    """The oracle (oracle/multi.match_multi_c: the plain-C direct sum for each
+    round's maximum) on seeded patterns of the workload until ~budget_s of CPU
+    time; also how often its decisions equal the GPU's."""
+    import numpy as np
+    from oracle import directsum, multi
+    from tests import helpers
+    phases, cfg = PLAN_CFG["overlap"]
+    opl = helpers.oracle_plan(phases, **cfg)
+    log("overlap: oracle plan built")
+    cores = directsum.num_threads()
+    o = d["offsets"]
+    idx = np.random.default_rng(11).permutation(len(o) - 1)
+    t0 = time.perf_counter()
+    done = same = 0
+    for p in idx:
+        p = int(p)
+        out = multi.match_multi_c(opl, d["qx"][o[p]:o[p + 1]], d["qy"][o[p]:o[p + 1]],
+                                  d["I"][o[p]:o[p + 1]].astype(np.float64), n_orient, r_del, nthreads=cores)
+        done += 1
+        same += all((r is None and res["zone"][p, k] < 0) or
+                    (r is not None and (r["zone"], r["n"], r["mirror"]) ==
+                     (int(res["zone"][p, k]), int(res["bin"][p, k]), int(res["mirror"][p, k])))
+                    for k, r in enumerate(out))
+        if time.perf_counter() - t0 > budget_s:
+            break
+    el = time.perf_counter() - t0
+    log(f"overlap: oracle on {done} patterns ({el:.1f} s)")
+    return ({"value": done / el, "unit": "patterns/s", "cores": cores, "kind": "oracle",
+             "sample": f"{done} seeded patterns of the same workload; the oracle's iterative procedure with the "
+                       f"plain-C FP64 direct sum over all zones for each of the {n_orient} rounds (OpenMP, "
+                       f"{cores} threads); plan build excluded as on the GPU"},
+            {"patterns": done, "all_rounds_identical_to_gpu": same})
+
+
+def run_overlap(args):
+    """Matching of overlapping patterns: a step is one acom_match_multi call over
+    all patterns (up to 3 rounds of polar + contraction + exact, the original
+    pattern's rescoring and the peak edit)."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2111_00171_amd import acom
+    from oracle import metrics
+
+    prec, n_orient, r_del = "bf16", 3, 0.04
+    t0 = time.perf_counter()
+    d = synth.make("overlap", n=65536, k_max=2.0)
+    t_gen = time.perf_counter() - t0
+    log(f"overlap: inputs generated ({len(d['offsets']) - 1} patterns, {t_gen:.1f} s)")
+    phases, cfg = PLAN_CFG["overlap"]
+    gpl = acom.Plan([acom.fcc()], acom.PlanParams(precisions=[prec], **cfg))
+    n = len(d["offsets"]) - 1
+    pk = acom.Peaks.from_host(d)
+    Z, R, N = gpl.n_zones, gpl.n_radial, gpl.n_angular
+    flop_per_pattern = 8.0 * Z * (N // 2 + 1) * R
+    ws = torch.empty(gpl.match_multi_workspace_bytes(pk.total_peaks, prec, args.chunk), dtype=torch.uint8,
+                     device="cuda")
+    shape = gpl.autotune(pk, prec, args.chunk, ws)
+    out = gpl.empty_matches(n, n_orient, True, "cuda")
+    out["n_evaluated"] = None
+
+    def step():
+        gpl.match_multi(pk, n_orient, r_del, 0.01, 0.0, prec, args.chunk, ws, out=out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    acom.profile_begin(8192)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = acom.profile_read()
+    acom.profile_end()
+    log(f"overlap: timed, {n * args.steps / el:.0f} patterns/s")
+    kern = {k: {"avg_ms": (t / c if c else None), "launches": c} for k, (t, c) in prof.items()}
+    b = prof["bound"]
+    achieved = flop_per_pattern * min(args.chunk, n) / (b[0] / b[1] * 1e-3) / 1e12
+    res = {k: v.cpu().numpy() for k, v in out.items() if v is not None}
+    found = (res["zone"] >= 0).sum(axis=1)
+    # the generator's two grains: each within 2 degrees of some found orientation
+    G = metrics.cubic_rotations()
+    idx = np.random.default_rng(7).choice(n, 1024, replace=False)
+    both = one = 0
+    for p in idx:
+        orients = [res["orient"][p, k] for k in range(n_orient) if res["zone"][p, k] >= 0]
+        hit = [any(metrics.misorientation_deg(m, d["truth"][p, j], G) < 2.0 for m in orients) for j in range(2)]
+        both += all(hit)
+        one += any(hit)
+    cpu = check = None
+    if not args.no_cpu_baseline:
+        cpu, check = cpu_baseline_overlap(d, res, r_del, n_orient)
+    roof = {"kernel": "bound_kernel (MFMA contraction, bf16 operands)", "bound": "mfma",
+            "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_TFLOPS[prec], 4), "traffic": None,
+            "algorithmic_flop_per_launch": flop_per_pattern * min(args.chunk, n),
+            "dominant_kernel_of_step": "bound"}
+    extra = {"kernel_avg_ms": {k: (None if v["avg_ms"] is None else round(v["avg_ms"], 4)) for k, v in kern.items()},
+             "kernel_launches_per_step": {k: v["launches"] / args.steps for k, v in kern.items()},
+             "orientations_found_per_pattern": {str(k): int((found == k).sum()) for k in range(n_orient + 1)},
+             "grains_recovered_within_2deg": {"both": both / 1024, "at_least_one": one / 1024, "patterns": 1024},
+             "oracle_check": check, "contraction_shape": shape, "input_generation_s": round(t_gen, 3)}
+    ccfg = {"patterns": n, "peaks": int(d["offsets"][-1]), "zones": Z, "n_radial": R, "n_angular": N,
+            "chunk": args.chunk, "rounds": n_orient, "deletion_radius": r_del}
+    return line("overlap", n * args.steps / el, el * 1e3 / args.steps, args.steps, args.warmup, "bf16", ccfg, roof,
+                cpu, extra)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="scan", choices=["scan", "hcp", "multi", "refine"])
+    ap.add_argument("--workload", default="scan", choices=["scan", "hcp", "multi", "refine", "overlap"])
     ap.add_argument("--precisions", default=None,
                     help="comma list; the first is `value` (scan: fp32,bf16,fp16; hcp: bf16,fp16,fp32)")
     ap.add_argument("--chunk", type=int, default=65536,
@@ -465,6 +579,8 @@ def main():
         out = run_match_workload(args, args.workload)
     elif args.workload == "multi":
         out = run_multi(args)
+    elif args.workload == "overlap":
+        out = run_overlap(args)
     else:
         out = run_refine(args)
     print(json.dumps(out))

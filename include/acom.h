@@ -166,6 +166,31 @@ acom_status_t acom_match(acom_plan_t plan, const acom_peaks_t* peaks, int32_t to
                          int32_t precision, int32_t chunk, void* workspace, size_t workspace_bytes,
                          const acom_matches_t* out, void* stream);
 
+/* Matching of overlapping diffraction patterns (Methods > Matching of
+ * Overlapping Diffraction Patterns): n_orient rounds per pattern.  Round 0 is
+ * the top-1 match of acom_match.  After each round the forward kinematical
+ * pattern of the matched orientation (Methods > Calculation of Kinematical
+ * Diffraction Patterns: reflection g at the (x, y) of orient^T g, intensity
+ * |F_g|^2 exp(-s_g^2 / 2 sigma_exc^2), kept when above rel_cut times the phase's
+ * largest |F|^2) is compared with the peaks: a peak within deletion_radius of
+ * the nearest simulated peak gets intensity 0, one at a distance d below the
+ * correlation kernel's reach r_k (delta for the cone kernel, 3 sigma for the
+ * Gaussian) has its intensity multiplied by (d - deletion_radius) /
+ * (r_k - deletion_radius); the edits accumulate and the next round matches the
+ * edited peaks.  The score reported for every round is the correlogram value of
+ * the ORIGINAL peaks at that round's (zone, bin, branch).  A round whose match
+ * is empty or whose score is <= 0 or below min_score reports zone -1 and ends
+ * the search for that pattern (later rounds report -1 too).
+ * out arrays are n x n_orient (orient n x n_orient x 9, may be NULL; n_evaluated
+ * is not written).  deletion_radius in [0, r_k), rel_cut in (0, 1], n_orient in
+ * [1, 16].  `chunk` must equal the value given to the size query. */
+acom_status_t acom_match_multi_workspace_size(acom_plan_t plan, int32_t precision, int32_t chunk,
+                                              int64_t total_peaks, size_t* bytes);
+acom_status_t acom_match_multi(acom_plan_t plan, const acom_peaks_t* peaks, int32_t n_orient,
+                               float deletion_radius, float rel_cut, float min_score, int32_t precision,
+                               int32_t chunk, void* workspace, size_t workspace_bytes,
+                               const acom_matches_t* out, void* stream);
+
 /* Autotuner of the contraction launch shape (block tile 64 x 64 or large,
  * radii per LDS step for BF16/FP16 operands, block order) for `precision` on
  * this plan: runs the polar pass on the first chunk of `peaks`, times every

@@ -67,6 +67,9 @@ def lib():
             "acom_plan_destroy": [c_void_p],
             "acom_match_workspace_size": [c_void_p, c_int32, c_int32, P(c_size_t)],
             "acom_match": [c_void_p, P(_Peaks), c_int32, c_int32, c_int32, c_void_p, c_size_t, P(_Matches), c_void_p],
+            "acom_match_multi_workspace_size": [c_void_p, c_int32, c_int32, c_int64, P(c_size_t)],
+            "acom_match_multi": [c_void_p, P(_Peaks), c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float, c_int32,
+                                 c_int32, c_void_p, c_size_t, P(_Matches), c_void_p],
             "acom_autotune": [c_void_p, P(_Peaks), c_int32, c_int32, c_void_p, c_size_t, c_void_p, P(c_int32),
                               P(ctypes.c_float)],
             "acom_debug_workspace_size": [c_void_p, c_int64, P(c_size_t)],
@@ -333,6 +336,34 @@ class Plan:
         _check(lib().acom_match(self._h, ctypes.byref(pk), int(top_k), PRECISIONS[precision], int(chunk),
                                 c_void_p(workspace.data_ptr()), workspace.numel(), ctypes.byref(m), _stream(stream)),
                "acom_match")
+        return out
+
+    def match_multi_workspace_bytes(self, total_peaks, precision="fp32", chunk=0):
+        n = c_size_t()
+        _check(lib().acom_match_multi_workspace_size(self._h, PRECISIONS[precision], int(chunk), int(total_peaks),
+                                                     ctypes.byref(n)), "acom_match_multi_workspace_size")
+        return n.value
+
+    def match_multi(self, peaks: Peaks, n_orient=3, deletion_radius=0.04, rel_cut=0.01, min_score=0.0,
+                    precision="fp32", chunk=0, workspace=None, stream=None, out=None):
+        """Up to n_orient orientations per pattern from overlapping patterns
+        (acom_match_multi): dict of device tensors of shape (n, n_orient)
+        (orient (n, n_orient, 3, 3)); zone -1 where a round found nothing."""
+        n = peaks.n_patterns
+        dev = peaks.offsets.device
+        if workspace is None:
+            workspace = torch.empty(self.match_multi_workspace_bytes(peaks.total_peaks, precision, chunk),
+                                    dtype=torch.uint8, device=dev)
+        if out is None:
+            out = self.empty_matches(n, n_orient, True, dev)
+            out["n_evaluated"] = None
+        m = _Matches(*(None if out.get(k) is None else out[k].data_ptr()
+                       for k in ("zone", "phase", "bin", "mirror", "score", "phi3", "orient", "n_evaluated")))
+        pk = peaks.c()
+        _check(lib().acom_match_multi(self._h, ctypes.byref(pk), int(n_orient), float(deletion_radius),
+                                      float(rel_cut), float(min_score), PRECISIONS[precision], int(chunk),
+                                      c_void_p(workspace.data_ptr()), workspace.numel(), ctypes.byref(m),
+                                      _stream(stream)), "acom_match_multi")
         return out
 
     def autotune(self, peaks: Peaks, precision="fp32", chunk=0, workspace=None, stream=None):

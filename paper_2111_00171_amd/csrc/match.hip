@@ -969,6 +969,11 @@ struct ExactArgs {
   int *zone, *phase, *bin, *mirror, *n_eval;
   float *score, *phi3, *orient;
   float* C;  // correlate mode: C[p][z][2][N] for every zone (no selection)
+  int64_t out_p0;           // outputs are indexed by global pattern P - out_p0
+  // forced mode: per global pattern P, the correlogram value of zone
+  // force_zone[P] at bin force_bin[P], branch force_mirror[P] (no selection)
+  const int *force_zone, *force_bin, *force_mirror;
+  float* force_score;
 };
 
 // The 4-radius groups of pattern p whose columns hold any nonzero X, in
@@ -1160,13 +1165,36 @@ __global__ void __launch_bounds__(kThreads) exact_kernel(ExactArgs a) {
     return;
   }
 
+  if (a.force_zone) {  // one given (zone, bin, branch) per pattern
+    const int p = a.per < 0 ? (int)blockIdx.x : xcd_item(a.per);
+    if (p >= a.np) return;
+    const int64_t P = a.p_begin + p;
+    const int z = a.force_zone[P - a.out_p0];
+    if (z < 0 || z >= a.Z || a.flags[p] != 0) {
+      if (tid == 0) a.force_score[P - a.out_p0] = 0.0f;
+      return;
+    }
+    active_groups(a, p, groups, &s_ng);
+    int bz[kBatch];
+    for (int b = 0; b < kBatch; ++b) bz[b] = z;
+    contract_exact(a, p, bz, 1, rev, H0, groups, s_ng);
+    __syncthreads();
+    exact_ifft<NT>(H0, tw, a, 1);
+    if (tid == 0) {
+      const int n = min(max(a.force_bin[P - a.out_p0], 0), a.N - 1);
+      const float2 v = H0[n];
+      a.force_score[P - a.out_p0] = (a.force_mirror[P - a.out_p0] ? v.y : v.x) * invN;
+    }
+    return;
+  }
+
   const int p = a.per < 0 ? (int)blockIdx.x : xcd_item(a.per);
   if (p >= a.np) return;
   const int64_t P = a.p_begin + p;
   const int fl = a.flags[p];
   if (fl != 0) {
     for (int t = tid; t < a.top_k; t += kThreads) {
-      const size_t o = (size_t)P * a.top_k + t;
+      const size_t o = (size_t)(P - a.out_p0) * a.top_k + t;
       a.zone[o] = -1;
       if (a.phase) a.phase[o] = -1;
       if (a.bin) a.bin[o] = 0;
@@ -1176,7 +1204,7 @@ __global__ void __launch_bounds__(kThreads) exact_kernel(ExactArgs a) {
       if (a.orient)
         for (int i = 0; i < 9; ++i) a.orient[o * 9 + i] = 0.0f;
     }
-    if (a.n_eval && tid == 0) a.n_eval[P] = 0;
+    if (a.n_eval && tid == 0) a.n_eval[P - a.out_p0] = 0;
     return;
   }
   const float margin_abs = a.eps_abs * sqrtf(a.xnorm2[p]);
@@ -1289,7 +1317,7 @@ __global__ void __launch_bounds__(kThreads) exact_kernel(ExactArgs a) {
   // ---- outputs
   const float two_pi = 6.283185307179586f;
   for (int t = tid; t < a.top_k; t += kThreads) {
-    const size_t o = (size_t)P * a.top_k + t;
+    const size_t o = (size_t)(P - a.out_p0) * a.top_k + t;
     if (t < s_cnt) {
       const int z = s_topz[t], n = s_topn[t], m = s_topm[t];
       const float off = parabolic(s_tcm[t], s_topv[t], s_tcp[t]);
@@ -1328,7 +1356,134 @@ __global__ void __launch_bounds__(kThreads) exact_kernel(ExactArgs a) {
         for (int i = 0; i < 9; ++i) a.orient[o * 9 + i] = 0.0f;
     }
   }
-  if (a.n_eval && tid == 0) a.n_eval[P] = s_eval;
+  if (a.n_eval && tid == 0) a.n_eval[P - a.out_p0] = s_eval;
+}
+
+// --------------------------------------------- 4. overlapping patterns ----
+//
+// Matching of Overlapping Diffraction Patterns: after each round's match, the
+// forward kinematical pattern of the matched orientation (Methods >
+// Calculation of Kinematical Diffraction Patterns: a reflection g sits at
+// (x, y) of m^T g with intensity |F_g|^2 exp(-s_g^2 / 2 sigma^2), kept above
+// rel_cut of the phase's largest |F|^2) is laid over the experimental peaks:
+// a peak closer than the deletion radius r_del to a simulated peak is removed
+// (intensity 0), one between r_del and the correlation kernel's reach r_k has
+// its intensity scaled by (d - r_del) / (r_k - r_del), d the distance to the
+// nearest simulated peak, and the next round matches the edited peaks.
+
+struct EditArgs {
+  const int64_t* offsets;
+  const float *qx, *qy;
+  int64_t total_peaks;
+  const float* I_src;       // intensities before this round's edit
+  float* I_dst;             // after it (may alias I_src)
+  int64_t p_begin;
+  int np;
+  // this round's match of the chunk (local pattern index) and the score of the
+  // same (zone, bin, branch) on the original peaks
+  const int *zone, *phase, *bin, *mirror;
+  const float *score_orig, *phi3, *orient;
+  const int* flags;
+  // reflections
+  const float4* refl;
+  const float* F2;
+  const int* refl_off;
+  float k0, sigma_e, rel_cut, r_del, r_k, min_score;
+  // outputs for round `round` of n_orient (global pattern index)
+  int round, n_orient;
+  int *o_zone, *o_phase, *o_bin, *o_mirror;
+  float *o_score, *o_phi3, *o_orient;
+};
+
+constexpr int kSimBatch = 256;  // reflections examined per pass (one per thread)
+
+__device__ __forceinline__ float excitation_error_f(float x, float y, float z, float k0) {
+  // s_g of a sample-frame reciprocal vector for a beam along +z (Eq. excitation error)
+  return -(2.0f * k0 * z + (x * x + y * y + z * z)) / (2.0f * sqrtf(x * x + y * y + (k0 + z) * (k0 + z)));
+}
+
+__global__ void __launch_bounds__(kThreads) multi_edit_kernel(EditArgs a) {
+  __shared__ float sx[kSimBatch], sy[kSimBatch];
+  __shared__ int s_ns;
+  __shared__ float s_red[kThreads / 64];
+  const int tid = threadIdx.x;
+  const int p = blockIdx.x;
+  if (p >= a.np) return;
+  const int64_t P = a.p_begin + p;
+  int64_t m0 = a.offsets[P], m1 = a.offsets[P + 1];
+  if (m0 < 0 || m1 < m0 || m1 > a.total_peaks) m0 = m1 = 0;  // malformed row: nothing to edit
+  const int z = a.zone[p];
+  const bool valid = z >= 0 && a.flags[p] == 0 && a.score_orig[p] > 0.0f && a.score_orig[p] >= a.min_score;
+  // this round's outputs
+  if (tid == 0) {
+    const size_t o = (size_t)P * a.n_orient + a.round;
+    a.o_zone[o] = valid ? z : -1;
+    if (a.o_phase) a.o_phase[o] = valid ? a.phase[p] : -1;
+    if (a.o_bin) a.o_bin[o] = valid ? a.bin[p] : 0;
+    if (a.o_mirror) a.o_mirror[o] = valid ? a.mirror[p] : 0;
+    a.o_score[o] = valid ? a.score_orig[p] : 0.0f;
+    if (a.o_phi3) a.o_phi3[o] = valid ? a.phi3[p] : 0.0f;
+    if (a.o_orient)
+      for (int i = 0; i < 9; ++i) a.o_orient[o * 9 + i] = valid ? a.orient[(size_t)p * 9 + i] : 0.0f;
+  }
+  if (!valid) {  // no further orientation: every later round finds nothing
+    for (int64_t m = m0 + tid; m < m1; m += kThreads) a.I_dst[m] = 0.0f;
+    return;
+  }
+  float M[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) M[i] = a.orient[(size_t)p * 9 + i];
+  const int ph = a.phase[p];
+  const int g0 = a.refl_off[ph], g1 = a.refl_off[ph + 1];
+  // the phase's largest |F|^2
+  float fm = 0.0f;
+  for (int g = g0 + tid; g < g1; g += kThreads) fm = fmaxf(fm, a.F2[g]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) fm = fmaxf(fm, __shfl_xor(fm, off, 64));
+  if ((tid & 63) == 0) s_red[tid >> 6] = fm;
+  __syncthreads();
+  fm = fmaxf(fmaxf(s_red[0], s_red[1]), fmaxf(s_red[2], s_red[3]));
+  const float cut = a.rel_cut * fm;
+  const float inv2s2 = 1.0f / (2.0f * a.sigma_e * a.sigma_e);
+  for (int64_t mb = m0; mb < m1; mb += kThreads) {
+    const int64_t m = mb + tid;
+    const bool has = m < m1;
+    const float px = has ? a.qx[m] : 0.0f, py = has ? a.qy[m] : 0.0f;
+    float d2 = INFINITY;  // squared distance to the nearest simulated peak
+    for (int gb = g0; gb < g1; gb += kSimBatch) {
+      if (tid == 0) s_ns = 0;
+      __syncthreads();
+      const int g = gb + tid;
+      if (tid < kSimBatch && g < g1) {
+        const float4 r = a.refl[g];
+        // sample frame: (x, y, z) = m^T g
+        const float x = M[0] * r.x + M[3] * r.y + M[6] * r.z;
+        const float y = M[1] * r.x + M[4] * r.y + M[7] * r.z;
+        const float zz = M[2] * r.x + M[5] * r.y + M[8] * r.z;
+        const float sg = excitation_error_f(x, y, zz, a.k0);
+        if (a.F2[g] * expf(-sg * sg * inv2s2) > cut) {
+          const int slot = atomicAdd(&s_ns, 1);  // any order: only the minimum distance is used
+          sx[slot] = x;
+          sy[slot] = y;
+        }
+      }
+      __syncthreads();
+      const int ns = s_ns;
+      if (has)
+        for (int t = 0; t < ns; ++t) {
+          const float dx = px - sx[t], dy = py - sy[t];
+          d2 = fminf(d2, dx * dx + dy * dy);
+        }
+      __syncthreads();
+    }
+    if (has) {
+      const float d = sqrtf(d2);
+      float f = 1.0f;
+      if (d < a.r_del) f = 0.0f;
+      else if (d < a.r_k) f = (d - a.r_del) / (a.r_k - a.r_del);
+      a.I_dst[m] = a.I_src[m] * f;
+    }
+  }
 }
 
 // ------------------------------------------------------------- tuning ----
@@ -1655,6 +1810,9 @@ ExactArgs exact_args(const PlanDev& d, const WsLayout& L, unsigned char* ws, int
   e.zone = e.phase = e.bin = e.mirror = e.n_eval = nullptr;
   e.score = e.phi3 = e.orient = nullptr;
   e.C = nullptr;
+  e.out_p0 = 0;
+  e.force_zone = e.force_bin = e.force_mirror = nullptr;
+  e.force_score = nullptr;
   return e;
 }
 
@@ -1673,6 +1831,38 @@ acom_status_t check_plan_precision(acom_plan_t plan, int precision) {
     return fail(ACOM_E_INVALID, "plan was built without this precision (acom_plan_params_t.precisions)");
   if (plan->d.Z > kMaxZonesExact) return fail(ACOM_E_UNSUPPORTED, "more than 16384 zones");
   return ACOM_OK;
+}
+
+// One chunk of acom_match: polar pass, contraction, exact pass.  Outputs are
+// indexed by global pattern minus out_p0.
+acom_status_t match_chunk(const PlanDev& d, const acom_peaks_t* peaks, int64_t c0, int np, int top_k, int precision,
+                          const WsLayout& L, unsigned char* ws, const acom_matches_t& out, int64_t out_p0,
+                          hipStream_t s) {
+  acom_status_t st;
+  PolarArgs pa = polar_args(d, peaks, c0, np, precision);
+  set_ws(pa, L, ws, d);
+  if ((st = launch_polar(d, pa, s)) != ACOM_OK) return st;
+  if ((st = launch_bound(d, precision, L, ws, np, reinterpret_cast<float*>(ws + L.U), d.Zp, d.Zp, s)) != ACOM_OK)
+    return st;
+  ExactArgs e = exact_args(d, L, ws, c0, np);
+  e.eps_abs = eps_abs_for(precision);
+  e.top_k = top_k;
+  e.out_p0 = out_p0;
+  e.zone = out.zone;
+  e.phase = out.phase;
+  e.bin = out.bin;
+  e.mirror = out.mirror;
+  e.score = out.score;
+  e.phi3 = out.phi3;
+  e.orient = out.orient;
+  e.n_eval = out.n_evaluated;
+  int nblk = np;
+  if (g_tune.exact_xcd)
+    nblk = xcd_blocks(np, &e.per);
+  else
+    e.per = -1;
+  ProfScope prof(2, s);
+  return launch_exact(d, e, dim3(nblk), s);
 }
 
 int chunk_of(int chunk) {
@@ -1713,30 +1903,144 @@ extern "C" acom_status_t acom_match(acom_plan_t plan, const acom_peaks_t* peaks,
   unsigned char* ws = reinterpret_cast<unsigned char*>(workspace);
   for (int64_t c0 = 0; c0 < peaks->n_patterns; c0 += Pc) {
     const int np = (int)std::min<int64_t>(Pc, peaks->n_patterns - c0);
-    PolarArgs pa = polar_args(d, peaks, c0, np, precision);
-    set_ws(pa, L, ws, d);
-    if ((st = launch_polar(d, pa, s)) != ACOM_OK) return st;
-    if ((st = launch_bound(d, precision, L, ws, np, reinterpret_cast<float*>(ws + L.U), d.Zp, d.Zp, s)) != ACOM_OK)
-      return st;
-    ExactArgs e = exact_args(d, L, ws, c0, np);
-    e.eps_abs = eps_abs_for(precision);
-    e.top_k = top_k;
-    e.zone = out->zone;
-    e.phase = out->phase;
-    e.bin = out->bin;
-    e.mirror = out->mirror;
-    e.score = out->score;
-    e.phi3 = out->phi3;
-    e.orient = out->orient;
-    e.n_eval = out->n_evaluated;
-    int nblk = np;
-    if (g_tune.exact_xcd)
-      nblk = xcd_blocks(np, &e.per);
-    else
-      e.per = -1;
-    {
-      ProfScope prof(2, s);
-      if ((st = launch_exact(d, e, dim3(nblk), s)) != ACOM_OK) return st;
+    if ((st = match_chunk(d, peaks, c0, np, top_k, precision, L, ws, *out, 0, s)) != ACOM_OK) return st;
+  }
+  return ACOM_OK;
+}
+
+namespace {
+// Workspace of acom_match_multi: the match workspace, the edited intensities
+// (one per peak) and one round's per-pattern results of a chunk.
+struct MultiLayout {
+  WsLayout L;
+  size_t I = 0, zone = 0, phase = 0, bin = 0, mirror = 0, score = 0, phi3 = 0, score_orig = 0, orient = 0, total = 0;
+};
+MultiLayout multi_layout(const PlanDev& d, int precision, int Pc, int64_t total_peaks) {
+  MultiLayout M;
+  M.L = layout(d, precision != ACOM_FP32, Pc);
+  size_t o = M.L.total;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes, 256);
+    return at;
+  };
+  M.I = take((size_t)std::max<int64_t>(total_peaks, 1) * 4);
+  M.zone = take((size_t)Pc * 4);
+  M.phase = take((size_t)Pc * 4);
+  M.bin = take((size_t)Pc * 4);
+  M.mirror = take((size_t)Pc * 4);
+  M.score = take((size_t)Pc * 4);
+  M.phi3 = take((size_t)Pc * 4);
+  M.score_orig = take((size_t)Pc * 4);
+  M.orient = take((size_t)Pc * 9 * 4);
+  M.total = o;
+  return M;
+}
+}  // namespace
+
+extern "C" acom_status_t acom_match_multi_workspace_size(acom_plan_t plan, int32_t precision, int32_t chunk,
+                                                         int64_t total_peaks, size_t* bytes) {
+  acom_status_t st = check_plan_precision(plan, precision);
+  if (st != ACOM_OK) return st;
+  if (!bytes) return fail(ACOM_E_INVALID, "bytes is null");
+  if (total_peaks < 0) return fail(ACOM_E_INVALID, "negative peak count");
+  *bytes = multi_layout(plan->d, precision, chunk_of(chunk), total_peaks).total;
+  return ACOM_OK;
+}
+
+extern "C" acom_status_t acom_match_multi(acom_plan_t plan, const acom_peaks_t* peaks, int32_t n_orient,
+                                          float deletion_radius, float rel_cut, float min_score, int32_t precision,
+                                          int32_t chunk, void* workspace, size_t workspace_bytes,
+                                          const acom_matches_t* out, void* stream_v) {
+  acom_status_t st = check_plan_precision(plan, precision);
+  if (st != ACOM_OK) return st;
+  if ((st = check_peaks(peaks)) != ACOM_OK) return st;
+  if (n_orient < 1 || n_orient > kMaxTopK) return fail(ACOM_E_INVALID, "n_orient must be in [1, 16]");
+  const PlanDev& d = plan->d;
+  const float r_k = d.kernel == ACOM_KERNEL_CONE ? (float)d.delta : (float)(3.0 * d.gauss_sigma);
+  if (!(deletion_radius >= 0.0f) || !(deletion_radius < r_k))
+    return fail(ACOM_E_INVALID, "deletion_radius must be in [0, kernel reach)");
+  if (!(rel_cut > 0.0f) || !(rel_cut <= 1.0f)) return fail(ACOM_E_INVALID, "rel_cut must be in (0, 1]");
+  if (!std::isfinite(min_score)) return fail(ACOM_E_INVALID, "min_score must be finite");
+  if (!out) return fail(ACOM_E_INVALID, "matches is null");
+  if (peaks->n_patterns == 0) return ACOM_OK;
+  if (!out->zone || !out->score) return fail(ACOM_E_INVALID, "matches: zone and score outputs are required");
+  const int Pc = chunk_of(chunk);
+  const MultiLayout M = multi_layout(d, precision, Pc, peaks->total_peaks);
+  if (!workspace || workspace_bytes < M.total)
+    return fail(ACOM_E_WORKSPACE, "workspace smaller than acom_match_multi_workspace_size");
+  hipStream_t s = (hipStream_t)stream_v;
+  unsigned char* ws = reinterpret_cast<unsigned char*>(workspace);
+  float* I_cur = reinterpret_cast<float*>(ws + M.I);
+  acom_matches_t tmp{};
+  tmp.zone = reinterpret_cast<int32_t*>(ws + M.zone);
+  tmp.phase = reinterpret_cast<int32_t*>(ws + M.phase);
+  tmp.bin = reinterpret_cast<int32_t*>(ws + M.bin);
+  tmp.mirror = reinterpret_cast<int32_t*>(ws + M.mirror);
+  tmp.score = reinterpret_cast<float*>(ws + M.score);
+  tmp.phi3 = reinterpret_cast<float*>(ws + M.phi3);
+  tmp.orient = reinterpret_cast<float*>(ws + M.orient);
+  tmp.n_evaluated = nullptr;
+  float* score_orig = reinterpret_cast<float*>(ws + M.score_orig);
+  acom_peaks_t edited = *peaks;
+  edited.intensity = I_cur;
+  for (int64_t c0 = 0; c0 < peaks->n_patterns; c0 += Pc) {
+    const int np = (int)std::min<int64_t>(Pc, peaks->n_patterns - c0);
+    for (int r = 0; r < n_orient; ++r) {
+      // round r: the best orientation of the (edited) peaks
+      if ((st = match_chunk(d, r == 0 ? peaks : &edited, c0, np, 1, precision, M.L, ws, tmp, c0, s)) != ACOM_OK)
+        return st;
+      if (r > 0) {
+        // its correlogram value on the original peaks (the reported score)
+        PolarArgs pa = polar_args(d, peaks, c0, np, 0);
+        set_ws(pa, M.L, ws, d);
+        if ((st = launch_polar(d, pa, s)) != ACOM_OK) return st;
+        ExactArgs e = exact_args(d, M.L, ws, c0, np);
+        e.out_p0 = c0;
+        e.force_zone = tmp.zone;
+        e.force_bin = tmp.bin;
+        e.force_mirror = tmp.mirror;
+        e.force_score = score_orig;
+        e.per = -1;
+        if ((st = launch_exact(d, e, dim3(np), s)) != ACOM_OK) return st;
+      }
+      EditArgs ea;
+      ea.offsets = peaks->offsets;
+      ea.qx = peaks->qx;
+      ea.qy = peaks->qy;
+      ea.total_peaks = peaks->total_peaks;
+      ea.I_src = r == 0 ? peaks->intensity : I_cur;
+      ea.I_dst = I_cur;
+      ea.p_begin = c0;
+      ea.np = np;
+      ea.zone = tmp.zone;
+      ea.phase = tmp.phase;
+      ea.bin = tmp.bin;
+      ea.mirror = tmp.mirror;
+      ea.score_orig = r == 0 ? tmp.score : score_orig;
+      ea.phi3 = tmp.phi3;
+      ea.orient = tmp.orient;
+      ea.flags = reinterpret_cast<const int*>(ws + M.L.flags);
+      ea.refl = d.d_refl;
+      ea.F2 = d.d_reflF2;
+      ea.refl_off = d.d_refl_off;
+      ea.k0 = (float)d.k0;
+      ea.sigma_e = (float)d.sigma_exc;
+      ea.rel_cut = rel_cut;
+      ea.r_del = deletion_radius;
+      ea.r_k = r_k;
+      ea.min_score = min_score;
+      ea.round = r;
+      ea.n_orient = n_orient;
+      ea.o_zone = out->zone;
+      ea.o_phase = out->phase;
+      ea.o_bin = out->bin;
+      ea.o_mirror = out->mirror;
+      ea.o_score = out->score;
+      ea.o_phi3 = out->phi3;
+      ea.o_orient = out->orient;
+      multi_edit_kernel<<<dim3(np), kThreads, 0, s>>>(ea);
+      ACOM_HIP(hipGetLastError());
     }
   }
   return ACOM_OK;

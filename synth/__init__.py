@@ -24,6 +24,9 @@ Configurations (name -> recipe):
   multi   512x512 scan, 200 grains, phase per grain uniform in {FCC, BCC, HCP},
           n ~ round(exp(U(ln 3, ln 150))) strongest reflections, noise (seed 1004)
   refine  65,536 Haar-random FCC orientations, noise as 'scan'       (seed 1005)
+  overlap patterns that each sum the peaks of two Haar-random FCC grains (the
+          second's intensities scaled by U(0.4, 0.9)), per grain the reflections
+          above 1% of max |F|^2 (at most its 40 strongest), noise as 'scan' (seed 1006)
 """
 import json
 import math
@@ -205,6 +208,27 @@ def refine(seed=1005, n=65536, k_max=2.0):
     return _pack(lists, R, np.zeros(n), {"name": "refine", "k_max": k_max, "phases": ["fcc_a4.08"]})
 
 
+def overlap(seed=1006, n=4096, k_max=2.0, second=(0.4, 0.9), per_grain=40):
+    rng = np.random.default_rng(seed)
+    t = load_table("fcc_a4.08")
+    R = haar_rotations(rng, 2 * n).reshape(n, 2, 3, 3)
+    lists = []
+    for i in range(n):
+        parts = []
+        for j in range(2):
+            qx, qy, I = recorded_peaks(t, R[i, j], k_max)
+            keep = I > 0.01 * t["F2"].max()
+            qx, qy, I = qx[keep][:per_grain], qy[keep][:per_grain], I[keep][:per_grain]
+            if j == 1:
+                I = I * rng.uniform(*second)
+            parts.append((qx, qy, I))
+        qx = np.concatenate([parts[0][0], parts[1][0]])
+        qy = np.concatenate([parts[0][1], parts[1][1]])
+        I = np.concatenate([parts[0][2], parts[1][2]])
+        lists.append(_noisy(rng, qx, qy, I))
+    return _pack(lists, R, np.zeros(n), {"name": "overlap", "k_max": k_max, "phases": ["fcc_a4.08"]})
+
+
 def subset(d, idx):
     """Patterns idx of a generated scan, re-packed (for bounded oracle samples)."""
     idx = np.asarray(idx, dtype=np.int64)
@@ -214,7 +238,7 @@ def subset(d, idx):
                                                             "phases": d["phases"]})
 
 
-CONFIGS = {"small": small, "scan": scan, "hcp": hcp, "multi": multi, "refine": refine}
+CONFIGS = {"small": small, "scan": scan, "hcp": hcp, "multi": multi, "refine": refine, "overlap": overlap}
 
 
 def make(name, **kw):
