@@ -58,7 +58,7 @@ DESCR = {
     "refine": "refine: 65,536 FCC patterns at random orientations, top-4 grid candidates (FP32 contraction) "
               "refined by gradient ascent on the continuous score (<= 64 trials each)",
     "overlap": "overlap: 65,536 FCC patterns, each two overlapping grains (second at 0.4-0.9 intensity), "
-               "up to 3 orientations per pattern by iterative match + forward pattern + peak deletion "
+               "up to 2 orientations per pattern by iterative match + forward pattern + peak deletion "
                "(deletion radius 0.04 1/A), BF16 contraction, 1-degree plan, 128 x 360 bins",
 }
 
@@ -435,13 +435,14 @@ def run_refine(args):
                 cpu, extra)
 
 
-def cpu_baseline_overlap(d, res, r_del, n_orient, budget_s=15.0):
+def cpu_baseline_overlap(d, res, r_del, n_orient, budget_s=25.0):
     """The oracle (oracle/multi.match_multi_c: the plain-C direct sum for each
     round's maximum) on seeded patterns of the workload until ~budget_s of CPU
     time; also how often its decisions equal the GPU's."""
     import numpy as np
-    from oracle import directsum, multi
+    from oracle import directsum, metrics, multi
     from tests import helpers
+    G = metrics.cubic_rotations()
     phases, cfg = PLAN_CFG["overlap"]
     opl = helpers.oracle_plan(phases, **cfg)
     log("overlap: oracle plan built")
@@ -449,7 +450,7 @@ def cpu_baseline_overlap(d, res, r_del, n_orient, budget_s=15.0):
     o = d["offsets"]
     idx = np.random.default_rng(11).permutation(len(o) - 1)
     t0 = time.perf_counter()
-    done = same = 0
+    done = same = close = 0
     for p in idx:
         p = int(p)
         out = multi.match_multi_c(opl, d["qx"][o[p]:o[p + 1]], d["qy"][o[p]:o[p + 1]],
@@ -459,6 +460,11 @@ def cpu_baseline_overlap(d, res, r_del, n_orient, budget_s=15.0):
                     (r is not None and (r["zone"], r["n"], r["mirror"]) ==
                      (int(res["zone"][p, k]), int(res["bin"][p, k]), int(res["mirror"][p, k])))
                     for k, r in enumerate(out))
+        # the same orientations up to the crystal's symmetry (a strict mismatch may be an exact tie)
+        close += all((r is None and res["zone"][p, k] < 0) or
+                     (r is not None and res["zone"][p, k] >= 0 and
+                      metrics.misorientation_deg(r["orient"], res["orient"][p, k], G) < 0.5)
+                     for k, r in enumerate(out))
         if time.perf_counter() - t0 > budget_s:
             break
     el = time.perf_counter() - t0
@@ -467,7 +473,8 @@ def cpu_baseline_overlap(d, res, r_del, n_orient, budget_s=15.0):
              "sample": f"{done} seeded patterns of the same workload; the oracle's iterative procedure with the "
                        f"plain-C FP64 direct sum over all zones for each of the {n_orient} rounds (OpenMP, "
                        f"{cores} threads); plan build excluded as on the GPU"},
-            {"patterns": done, "all_rounds_identical_to_gpu": same})
+            {"patterns": done, "all_rounds_identical_to_gpu": same,
+             "all_rounds_within_0.5deg_of_gpu": close})
 
 
 def run_overlap(args):
@@ -480,7 +487,7 @@ def run_overlap(args):
     from paper_2111_00171_amd import acom
     from oracle import metrics
 
-    prec, n_orient, r_del = "bf16", 3, 0.04
+    prec, n_orient, r_del = "bf16", args.rounds, 0.04
     t0 = time.perf_counter()
     d = synth.make("overlap", n=65536, k_max=2.0)
     t_gen = time.perf_counter() - t0
@@ -556,6 +563,8 @@ def main():
     ap.add_argument("--chunk", type=int, default=65536,
                     help="patterns per internal launch (65,536: one launch per step on the scan; ~19 GB of workspace)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--rounds", type=int, default=2,
+                    help="overlap workload: orientations sought per pattern (the generator draws two grains)")
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
                     help="first copy this many GiB device-to-device (a plain copy kernel of known size, "
                          "for scaling HBM counters)")
