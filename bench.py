@@ -47,6 +47,7 @@ PLAN_CFG = {  # phases and plan parameters of each workload
     "multi": (["fcc", "bcc", "hcp"], dict(k_max=2.0, n_radial=128, n_angular=360, zone_step_deg=1.0)),
     "refine": (["fcc"], dict(k_max=2.0, n_radial=128, n_angular=360, zone_step_deg=1.0)),
     "overlap": (["fcc"], dict(k_max=2.0, n_radial=128, n_angular=360, zone_step_deg=1.0)),
+    "simulate": (["fcc"], dict(k_max=2.0, n_radial=128, n_angular=360, zone_step_deg=1.0)),
 }
 DESCR = {
     "scan": "scan: 256x256 FCC scan, 65,536 patterns x 10-60 peaks, 1-degree plan (1081 zones), "
@@ -60,6 +61,8 @@ DESCR = {
     "overlap": "overlap: 65,536 FCC patterns, each two overlapping grains (second at 0.4-0.9 intensity), "
                "up to 2 orientations per pattern by iterative match + forward pattern + peak deletion "
                "(deletion radius 0.04 1/A), BF16 contraction, 1-degree plan, 128 x 360 bins",
+    "simulate": "simulate: forward kinematical patterns of 65,536 random FCC orientations (reflections with "
+                "|g| < 2.0 1/A, kept above 1% of max |F|^2 after the excitation-error shape factor), CSR output",
 }
 
 
@@ -552,12 +555,57 @@ def run_overlap(args):
                 cpu, extra)
 
 
+def run_simulate(args):
+    """Forward kinematical patterns: a step is acom_simulate_count, the read of
+    the total, and acom_simulate_fill for all orientations."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2111_00171_amd import acom
+
+    n = 65536
+    R = synth.haar_rotations(np.random.default_rng(31), n)
+    phases, cfg = PLAN_CFG["simulate"]
+    gpl = acom.Plan([acom.fcc()], acom.PlanParams(precisions=["fp32"], **cfg))
+    orient = torch.tensor(R.reshape(n, 9), dtype=torch.float32, device="cuda")
+    for _ in range(args.warmup):
+        gpl.simulate(orient)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        off, qx, qy, I = gpl.simulate(orient)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    total = int(off[-1].item())
+    log(f"simulate: timed, {n * args.steps / el:.0f} patterns/s, {total / n:.1f} peaks per pattern")
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import kinematics
+        from tests import helpers
+        opl = helpers.oracle_plan(phases, **cfg)
+        refl = opl["refl"][0]
+        t0 = time.perf_counter()
+        k = 0
+        while time.perf_counter() - t0 < 10.0 and k < n:
+            kinematics.pattern(refl, R[k], opl["params"].k0, sigma=0.02, rel_cut=0.01)
+            k += 1
+        cel = time.perf_counter() - t0
+        cpu = {"value": k / cel, "unit": "patterns/s", "cores": 1, "kind": "oracle",
+               "sample": f"{k} of the same orientations; oracle/kinematics.pattern (numpy FP64, one thread)"}
+    roof = {"kernel": "simulate_kernel (per pattern: rotate, excitation error, shape factor, compaction)",
+            "bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None, "traffic": None,
+            "note": "latency-bound (one block per pattern, barriers per 256 reflections)"}
+    ccfg = {"patterns": n, "peaks_per_pattern": round(total / n, 2), "k_max": cfg["k_max"]}
+    return line("simulate", n * args.steps / el, el * 1e3 / args.steps, args.steps, args.warmup, "f32", ccfg, roof,
+                cpu, {"metric": "forward kinematical patterns simulated/sec at 1 GPU"})
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="scan", choices=["scan", "hcp", "multi", "refine", "overlap"])
+    ap.add_argument("--workload", default="scan", choices=["scan", "hcp", "multi", "refine", "overlap", "simulate"])
     ap.add_argument("--precisions", default=None,
                     help="comma list; the first is `value` (scan: fp32,bf16,fp16; hcp: bf16,fp16,fp32)")
     ap.add_argument("--chunk", type=int, default=65536,
@@ -590,6 +638,8 @@ def main():
         out = run_multi(args)
     elif args.workload == "overlap":
         out = run_overlap(args)
+    elif args.workload == "simulate":
+        out = run_simulate(args)
     else:
         out = run_refine(args)
     print(json.dumps(out))

@@ -291,6 +291,39 @@ acom_status_t acom_profile_end(void);
  * A shape stored in the plan by acom_autotune takes precedence over keys 0, 1, 4 and 6. */
 acom_status_t acom_set_tuning(int32_t key, int32_t value);
 
+/* Fiber-texture zone sets (the paper's alternative orientation plans: zone
+ * axes within theta_max of a fiber axis, optionally an azimuthal wedge about it)
+ * for acom_phase_t.zones_explicit.  Rings of polar angle i*step about the axis
+ * (i = 0 .. floor(theta_max / step)); ring i holds ceil(360 sin(theta_i) / step)
+ * points evenly around a full circle (phi1 - phi0 = 360), or
+ * ceil((phi1 - phi0) sin(theta_i) / step) intervals of the wedge [phi0, phi1]
+ * with both ends; the axis itself comes first.  Azimuth 0 is unit(f x e) with e
+ * the coordinate axis least aligned with f.  Host call, no GPU work: writes up
+ * to `capacity` directions (n x 3, unit) into `zones` (may be NULL to query the
+ * count) and the number needed into *count; ACOM_E_INVALID when capacity is
+ * too small. */
+acom_status_t acom_fiber_zones(const double* axis, double theta_max_deg, double phi0_deg, double phi1_deg,
+                               double step_deg, double* zones, int32_t capacity, int32_t* count);
+
+/* ---------------------------------------------------- forward patterns ---- */
+/* Forward kinematical diffraction patterns (Methods > Calculation of
+ * Kinematical Diffraction Patterns) for n orientations: a reflection g of the
+ * phase (the plan's reflections, 0 < |g| < k_max) appears at the (x, y) of
+ * orient^T g with intensity |F_g|^2 exp(-s_g^2 / 2 sigma_exc^2) (Eq. excitation
+ * error, Gaussian shape factor) when that exceeds rel_cut (0, 1] times the
+ * phase's largest |F|^2.  orient n x 9 (sample -> crystal, row-major), phase n
+ * (int32) or NULL for phase 0; n in [0, 2^24].  Device pointers, asynchronous.
+ * acom_simulate_count writes counts (n, int32) and the CSR offsets (n + 1,
+ * int64, offsets[0] = 0); after reading offsets[n] the caller sizes the peak
+ * arrays, and acom_simulate_fill writes qx, qy, intensity (offsets[n] each) in
+ * the plan's reflection order within each pattern.  A phase index outside the
+ * plan gives an empty pattern. */
+acom_status_t acom_simulate_count(acom_plan_t plan, int64_t n, const float* orient, const int32_t* phase,
+                                  float rel_cut, int32_t* counts, int64_t* offsets, void* stream);
+acom_status_t acom_simulate_fill(acom_plan_t plan, int64_t n, const float* orient, const int32_t* phase,
+                                 float rel_cut, const int64_t* offsets, float* qx, float* qy, float* intensity,
+                                 void* stream);
+
 /* ------------------------------------------------------------- errors ---- */
 const char* acom_status_string(acom_status_t s);
 const char* acom_last_error(void);

@@ -117,3 +117,38 @@ def hex_wedge_triangles():
     e30 = np.array([math.cos(math.radians(30)), math.sin(math.radians(30)), 0.0])
     e60 = np.array([math.cos(math.radians(60)), math.sin(math.radians(60)), 0.0])
     return [[z, e0, e30], [z, e60, e30]]
+
+
+def fiber_grid(axis, theta_max_deg, step_deg, phi0_deg=0.0, phi1_deg=360.0):
+    """Zone axes of a fiber-texture plan (Orientation plans of other types:
+    fiber texture): directions within theta_max of the fiber axis f.
+
+    Reading (the paper gives the idea, not the grid): rings of polar angle
+    theta_i = i * step about f, i = 0 .. floor(theta_max / step); ring 0 is f;
+    ring i has points spaced at most `step` of arc along it: over a full circle
+    n_i = ceil(360 sin(theta_i) / step) points at phi0 + j 360 / n_i, over a
+    wedge [phi0, phi1] n_i = ceil((phi1 - phi0) sin(theta_i) / step) equal
+    intervals with both ends.  Azimuth 0 is unit(f x e), e the coordinate axis
+    least aligned with f (ties to the lower index); 90 degrees is f x u.
+    """
+    f = np.asarray(axis, dtype=np.float64)
+    f = f / np.linalg.norm(f)
+    e = np.zeros(3)
+    e[int(np.argmin(np.abs(f)))] = 1.0
+    u = np.cross(f, e)
+    u /= np.linalg.norm(u)
+    v = np.cross(f, u)
+    full = phi1_deg - phi0_deg >= 360.0 - 1e-9
+    out = [f]
+    for i in range(1, int(math.floor(theta_max_deg / step_deg + 1e-9)) + 1):
+        th = math.radians(i * step_deg)
+        if full:
+            m = max(1, math.ceil(360.0 * math.sin(th) / step_deg - 1e-9))
+            phis = [phi0_deg + j * 360.0 / m for j in range(m)]
+        else:
+            m = max(1, math.ceil((phi1_deg - phi0_deg) * math.sin(th) / step_deg - 1e-9))
+            phis = [phi0_deg + j * (phi1_deg - phi0_deg) / m for j in range(m + 1)]
+        for ph in phis:
+            p = math.radians(ph)
+            out.append(math.cos(th) * f + math.sin(th) * (math.cos(p) * u + math.sin(p) * v))
+    return np.array(out)

@@ -68,6 +68,11 @@ def lib():
             "acom_match_workspace_size": [c_void_p, c_int32, c_int32, P(c_size_t)],
             "acom_match": [c_void_p, P(_Peaks), c_int32, c_int32, c_int32, c_void_p, c_size_t, P(_Matches), c_void_p],
             "acom_match_multi_workspace_size": [c_void_p, c_int32, c_int32, c_int64, P(c_size_t)],
+            "acom_fiber_zones": [P(c_double), c_double, c_double, c_double, c_double, c_void_p, c_int32, P(c_int32)],
+            "acom_simulate_count": [c_void_p, c_int64, c_void_p, c_void_p, ctypes.c_float, c_void_p, c_void_p,
+                                    c_void_p],
+            "acom_simulate_fill": [c_void_p, c_int64, c_void_p, c_void_p, ctypes.c_float, c_void_p, c_void_p,
+                                   c_void_p, c_void_p, c_void_p],
             "acom_match_multi": [c_void_p, P(_Peaks), c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float, c_int32,
                                  c_int32, c_void_p, c_size_t, P(_Matches), c_void_p],
             "acom_autotune": [c_void_p, P(_Peaks), c_int32, c_int32, c_void_p, c_size_t, c_void_p, P(c_int32),
@@ -154,6 +159,22 @@ class Phase:
     species: Optional[Sequence[int]] = None
     f_q: Optional[Sequence[float]] = None
     f_tab: Optional[Sequence[Sequence[float]]] = None
+
+
+def fiber_zones(axis, theta_max_deg, step_deg, phi_range_deg=(0.0, 360.0)):
+    """Zone axes of a fiber-texture plan (acom_fiber_zones): within theta_max of
+    `axis`, optionally in an azimuthal wedge; (n, 3) numpy array for the
+    `zones` argument of fcc / bcc / hcp."""
+    import numpy as np
+    ax = (c_double * 3)(*[float(v) for v in axis])
+    cnt = c_int32()
+    _check(lib().acom_fiber_zones(ax, float(theta_max_deg), float(phi_range_deg[0]), float(phi_range_deg[1]),
+                                  float(step_deg), None, 0, ctypes.byref(cnt)), "acom_fiber_zones")
+    buf = (c_double * (3 * cnt.value))()
+    _check(lib().acom_fiber_zones(ax, float(theta_max_deg), float(phi_range_deg[0]), float(phi_range_deg[1]),
+                                  float(step_deg), ctypes.cast(buf, c_void_p), cnt.value, ctypes.byref(cnt)),
+           "acom_fiber_zones")
+    return np.array(buf[:]).reshape(-1, 3)
 
 
 def fcc(a=4.08, triangles=None, zones=None):
@@ -365,6 +386,27 @@ class Plan:
                                       c_void_p(workspace.data_ptr()), workspace.numel(), ctypes.byref(m),
                                       _stream(stream)), "acom_match_multi")
         return out
+
+    def simulate(self, orient, phase=None, rel_cut=0.01, stream=None):
+        """Forward kinematical patterns of orientations orient (n, 3, 3) on the
+        plan's device (acom_simulate_count / _fill): (offsets, qx, qy, intensity)
+        device tensors, peaks in the plan's reflection order."""
+        orient = orient.reshape(-1, 9)
+        n = orient.shape[0]
+        dev = orient.device
+        counts = torch.empty(n, dtype=torch.int32, device=dev)
+        offsets = torch.empty(n + 1, dtype=torch.int64, device=dev)
+        ph = _ptr(phase, torch.int32, "phase")
+        _check(lib().acom_simulate_count(self._h, n, _ptr(orient, torch.float32, "orient"), ph, float(rel_cut),
+                                         c_void_p(counts.data_ptr()), c_void_p(offsets.data_ptr()), _stream(stream)),
+               "acom_simulate_count")
+        total = int(offsets[-1].item())  # synchronises
+        f32 = dict(dtype=torch.float32, device=dev)
+        qx, qy, I = torch.empty(total, **f32), torch.empty(total, **f32), torch.empty(total, **f32)
+        _check(lib().acom_simulate_fill(self._h, n, _ptr(orient, torch.float32, "orient"), ph, float(rel_cut),
+                                        c_void_p(offsets.data_ptr()), c_void_p(qx.data_ptr()), c_void_p(qy.data_ptr()),
+                                        c_void_p(I.data_ptr()), _stream(stream)), "acom_simulate_fill")
+        return offsets, qx, qy, I
 
     def autotune(self, peaks: Peaks, precision="fp32", chunk=0, workspace=None, stream=None):
         """Time every contraction launch shape on the first chunk of `peaks` and

@@ -729,3 +729,65 @@ extern "C" acom_status_t acom_plan_destroy(acom_plan_t plan) {
   delete plan;
   return ACOM_OK;
 }
+
+// Fiber-texture zone sets (Orientation plans of other types: fiber texture).
+// The zone axes w within theta_max of the fiber axis f, on rings of polar angle
+// theta_i = i step about f (i = 0 .. floor(theta_max / step)), each ring with
+// azimuths spaced at most `step` of arc: for a full circle n_i =
+// ceil(360 sin theta_i / step) points phi0 + j 360 / n_i; for a wedge
+// [phi0, phi1] n_i = ceil((phi1 - phi0) sin theta_i / step) intervals with both
+// ends included.  Azimuth 0 is the direction u = unit(f x e), e the coordinate
+// axis least aligned with f (ties to the lower index), and 90 degrees is f x u;
+// w = cos theta f + sin theta (cos phi u + sin phi v).  Host memory only.
+extern "C" acom_status_t acom_fiber_zones(const double* axis, double theta_max_deg, double phi0_deg,
+                                          double phi1_deg, double step_deg, double* zones, int32_t capacity,
+                                          int32_t* count) {
+  if (!axis || !count) return fail(ACOM_E_INVALID, "acom_fiber_zones: axis and count are required");
+  if (!(step_deg > 0.0) || !(theta_max_deg >= 0.0) || !(theta_max_deg <= 180.0))
+    return fail(ACOM_E_INVALID, "acom_fiber_zones: step > 0 and theta_max in [0, 180] degrees");
+  if (!(phi1_deg > phi0_deg) || phi1_deg - phi0_deg > 360.0 + 1e-9)
+    return fail(ACOM_E_INVALID, "acom_fiber_zones: need phi0 < phi1 <= phi0 + 360");
+  const double nf = std::sqrt(axis[0] * axis[0] + axis[1] * axis[1] + axis[2] * axis[2]);
+  if (!(nf > 0.0) || !std::isfinite(nf)) return fail(ACOM_E_INVALID, "acom_fiber_zones: zero or invalid axis");
+  const V3 f = v3(axis[0] / nf, axis[1] / nf, axis[2] / nf);
+  const double af[3] = {std::fabs(f.x), std::fabs(f.y), std::fabs(f.z)};
+  int ie = 0;
+  for (int i = 1; i < 3; ++i)
+    if (af[i] < af[ie]) ie = i;
+  const V3 e = v3(ie == 0 ? 1.0 : 0.0, ie == 1 ? 1.0 : 0.0, ie == 2 ? 1.0 : 0.0);
+  const V3 u = unit(cross(f, e));
+  const V3 v = cross(f, u);
+  const double d2r = 3.14159265358979323846 / 180.0;
+  const bool full = phi1_deg - phi0_deg >= 360.0 - 1e-9;
+  const int rings = (int)std::floor(theta_max_deg / step_deg + 1e-9);
+  int n = 0;
+  auto put = [&](V3 w) {
+    if (zones && n < capacity) {
+      zones[3 * n] = w.x;
+      zones[3 * n + 1] = w.y;
+      zones[3 * n + 2] = w.z;
+    }
+    ++n;
+  };
+  put(f);
+  for (int i = 1; i <= rings; ++i) {
+    const double th = i * step_deg * d2r;
+    const double st = std::sin(th), ct = std::cos(th);
+    if (full) {
+      const int m = std::max(1, (int)std::ceil(360.0 * st / step_deg - 1e-9));
+      for (int j = 0; j < m; ++j) {
+        const double ph = (phi0_deg + j * 360.0 / m) * d2r;
+        put(add(scale(f, ct), scale(add(scale(u, std::cos(ph)), scale(v, std::sin(ph))), st)));
+      }
+    } else {
+      const int m = std::max(1, (int)std::ceil((phi1_deg - phi0_deg) * st / step_deg - 1e-9));
+      for (int j = 0; j <= m; ++j) {
+        const double ph = (phi0_deg + j * (phi1_deg - phi0_deg) / m) * d2r;
+        put(add(scale(f, ct), scale(add(scale(u, std::cos(ph)), scale(v, std::sin(ph))), st)));
+      }
+    }
+  }
+  *count = n;
+  if (zones && n > capacity) return fail(ACOM_E_INVALID, "acom_fiber_zones: capacity too small (count holds the need)");
+  return ACOM_OK;
+}

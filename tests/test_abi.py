@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -74,3 +75,16 @@ def test_invalid_arguments_return_status_codes():
     assert L.acom_score(None, None, None, None, None, None, None) == 1
     assert L.acom_plan_destroy(None) == 0
     assert L.acom_status_string(5) == b"workspace too small"
+
+
+@pytest.mark.parametrize("axis,tmax,step,phis", [([0, 0, 1], 10.0, 2.0, (0, 360)), ([1, 1, 1], 15.0, 1.0, (0, 60)),
+                                                  ([0.3, -1, 2], 5.0, 0.5, (10, 370))])
+def test_fiber_zones_host_call_matches_oracle(axis, tmax, step, phis):
+    """acom_fiber_zones is a host-only call (no GPU): its zone list equals the
+    oracle's fiber grid direction by direction (the same reading, written twice)."""
+    from paper_2111_00171_amd import acom
+    from oracle import zones
+    w = acom.fiber_zones(axis, tmax, step, phis)
+    o = zones.fiber_grid(axis, tmax, step, *phis)
+    assert w.shape == o.shape
+    np.testing.assert_allclose(w, o, atol=1e-12)

@@ -430,3 +430,33 @@ def test_multi_c_variant_equals_plain_procedure():
                 continue
             assert (ra["zone"], ra["n"], ra["mirror"]) == (rb["zone"], rb["n"], rb["mirror"])
             assert abs(ra["score"] - rb["score"]) <= 1e-9 * abs(ra["score"])
+
+
+# ------------------------------------------------------- fiber texture ----
+
+@pytest.mark.parametrize("axis", [[0, 0, 1], [1, 1, 1], [1, 2, 0.3]])
+def test_fiber_grid_geometry(axis):
+    """Fiber-texture zone sets: the axis comes first; every direction is a unit
+    vector within theta_max of the axis, on rings of polar angle i*step; a full
+    ring of polar angle theta has ceil(360 sin(theta) / step) points whose
+    neighbours are at most `step` of arc apart; a wedge keeps its two ends."""
+    step, tmax = 2.0, 10.0
+    w = zones.fiber_grid(axis, tmax, step)
+    f = np.asarray(axis, float) / np.linalg.norm(axis)
+    np.testing.assert_allclose(w[0], f, atol=1e-15)
+    np.testing.assert_allclose(np.linalg.norm(w, axis=1), 1.0, atol=1e-14)
+    th = np.degrees(np.arccos(np.clip(w @ f, -1, 1)))
+    assert th.max() <= tmax + 1e-9
+    rings = np.round(th / step).astype(int)
+    np.testing.assert_allclose(th, rings * step, atol=1e-9)
+    for i in range(1, int(tmax / step) + 1):
+        ring = w[rings == i]
+        assert len(ring) == math.ceil(360.0 * math.sin(math.radians(i * step)) / step - 1e-9)
+        # neighbours around the ring: arc length along the ring circle <= step
+        c = ring - np.outer(ring @ f, f)
+        ang = np.sort(np.degrees(np.arctan2(c @ np.cross(f, c[0] / np.linalg.norm(c[0])), c @ (c[0] / np.linalg.norm(c[0])))) % 360.0)
+        gaps = np.diff(np.concatenate([ang, [ang[0] + 360.0]]))
+        assert gaps.max() * math.sin(math.radians(i * step)) <= step + 1e-9
+    wedge = zones.fiber_grid(axis, tmax, step, 0.0, 90.0)
+    assert len(wedge) == 1 + sum(math.ceil(90.0 * math.sin(math.radians(i * step)) / step - 1e-9) + 1
+                                 for i in range(1, 6))
