@@ -92,9 +92,11 @@ def test_simulate_feeds_match(acom):
 def test_fiber_texture_plan(acom):
     """A fiber-texture plan (zone axes within 8 degrees of [111], 1-degree step,
     from acom_fiber_zones): the GPU's FP64 plan equals the oracle's for the same
-    zone list (1e-12 relative), and noise-free patterns simulated on the GPU at
-    grid orientations of this plan are matched back (the generating zone and
-    bin reach the best score)."""
+    zone list (1e-12 relative); for noise-free patterns simulated on the GPU at
+    grid orientations of this plan, the GPU's score is the oracle's maximum over
+    the plan (1e-5) and its orientation lies within 2 degrees of the generating
+    one (neighbouring zones 1 degree apart can score within 1e-4 of each other
+    at 2-degree angular bins, so the generating zone itself need not win)."""
     from oracle import correlate, image
     from oracle import plan as oplan
     zl = acom.fiber_zones([1.0, 1.0, 1.0], 8.0, 1.0)
@@ -111,11 +113,16 @@ def test_fiber_texture_plan(acom):
     off, qx, qy, I = gpl.simulate(orient, rel_cut=0.01)
     res = gpl.match(acom.Peaks(off, qx, qy, I), top_k=1, precision="bf16")
     torch.cuda.synchronize()
+    from oracle import metrics
     score = res["score"][:, 0].cpu().numpy()
+    gor = res["orient"][:, 0].cpu().numpy()
     assert np.all(res["zone"][:, 0].cpu().numpy() >= 0)
+    G = metrics.cubic_rotations()
     o, hx, hy, hI = off.cpu().numpy(), qx.cpu().numpy(), qy.cpu().numpy(), I.cpu().numpy()
-    for i, (z, n) in enumerate(zip(zs, bins)):
+    for i in range(len(zs)):
         X = image.polar_image(hx[o[i]:o[i + 1]], hy[o[i]:o[i + 1]], hI[o[i]:o[i + 1]], opl["q_s"], 180,
                               opl["params"])
-        C, _ = correlate.correlate_direct(opl["P"][z:z + 1], X)
-        assert C[0, n] >= score[i] * (1 - 1e-5), (i, z, n, C[0, n], score[i])
+        C, Cm = correlate.correlate_direct(opl["P"], X)
+        mx = max(C.max(), Cm.max())
+        assert abs(score[i] - mx) <= 1e-5 * mx, (i, score[i], mx)
+        assert metrics.misorientation_deg(gor[i], R[i], G) < 2.0, i
