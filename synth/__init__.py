@@ -27,6 +27,13 @@ Configurations (name -> recipe):
   overlap patterns that each sum the peaks of two Haar-random FCC grains (the
           second's intensities scaled by U(0.4, 0.9)), per grain the reflections
           above 1% of max |F|^2 (at most its 40 strongest), noise as 'scan' (seed 1006)
+  frames  raw size x size detector frames (float32 counts) of Haar-random FCC grains: each
+          recorded peak (at most the 40 strongest above 1% of max |F|^2, jitter as 'scan')
+          drawn as a probe disk (radius 3.5 px, 1 px linear edge) of amplitude 1000 I/max|F|^2
+          centred at its sub-pixel position, an unscattered beam of amplitude 3000 on the
+          optical axis (size/2, size/2), background 2 + N(0, 3^2) + shot noise N(0, signal);
+          |q| = k_max falls (size/2 - 4) px from the axis; plus the vacuum probe image
+          (the same disk on the axis, noise-free)                    (seed 1007)
 """
 import json
 import math
@@ -229,6 +236,50 @@ def overlap(seed=1006, n=4096, k_max=2.0, second=(0.4, 0.9), per_grain=40):
     return _pack(lists, R, np.zeros(n), {"name": "overlap", "k_max": k_max, "phases": ["fcc_a4.08"]})
 
 
+def probe_disk(size, cy, cx, radius=3.5):
+    """A probe disk of the given radius with a 1 px linear edge, centred at (cy, cx)."""
+    y, x = np.meshgrid(np.arange(size), np.arange(size), indexing="ij")
+    rho = np.sqrt((y - cy) ** 2 + (x - cx) ** 2)
+    return np.clip(radius + 0.5 - rho, 0.0, 1.0)
+
+
+def frames(seed=1007, n=256, size=128, k_max=2.0, per_grain=40, radius=3.5):
+    rng = np.random.default_rng(seed)
+    t = load_table("fcc_a4.08")
+    R = haar_rotations(rng, n)
+    c = size // 2
+    pix = k_max / (size / 2 - 4)
+    w = int(math.ceil(radius + 1.5))
+    oy, ox = np.meshgrid(np.arange(-w, w + 1), np.arange(-w, w + 1), indexing="ij")
+    out = np.empty((n, size, size), np.float32)
+    peaks_y, peaks_x, amps = [], [], []
+    Fmax = t["F2"].max()
+    for i in range(n):
+        qx, qy, I = recorded_peaks(t, R[i], k_max)
+        keep = I > 0.01 * Fmax
+        qx, qy, I = _noisy(rng, qx[keep][:per_grain], qy[keep][:per_grain], I[keep][:per_grain])
+        py = np.concatenate([[float(c)], c + qy / pix])
+        px = np.concatenate([[float(c)], c + qx / pix])
+        a = np.concatenate([[3000.0], 1000.0 * np.maximum(I, 0.0) / Fmax])
+        sig = np.zeros((size, size))
+        iy = np.rint(py).astype(np.int64)
+        ix = np.rint(px).astype(np.int64)
+        yy = iy[:, None, None] + oy[None]
+        xx = ix[:, None, None] + ox[None]
+        rho = np.sqrt((yy - py[:, None, None]) ** 2 + (xx - px[:, None, None]) ** 2)
+        val = a[:, None, None] * np.clip(radius + 0.5 - rho, 0.0, 1.0)
+        ok = (yy >= 0) & (yy < size) & (xx >= 0) & (xx < size) & (val > 0)
+        np.add.at(sig, (yy[ok], xx[ok]), val[ok])
+        f = 2.0 + sig + rng.normal(0.0, 3.0, sig.shape) + rng.normal(size=sig.shape) * np.sqrt(sig)
+        out[i] = f
+        peaks_y.append(py[1:])
+        peaks_x.append(px[1:])
+        amps.append(a[1:])
+    return {"name": "frames", "frames": out, "probe": probe_disk(size, c, c, radius).astype(np.float32),
+            "center": (float(c), float(c)), "pixel_size": pix, "k_max": k_max, "truth": R,
+            "peaks_y": peaks_y, "peaks_x": peaks_x, "amplitude": amps, "phases": ["fcc_a4.08"]}
+
+
 def subset(d, idx):
     """Patterns idx of a generated scan, re-packed (for bounded oracle samples)."""
     idx = np.asarray(idx, dtype=np.int64)
@@ -238,7 +289,8 @@ def subset(d, idx):
                                                             "phases": d["phases"]})
 
 
-CONFIGS = {"small": small, "scan": scan, "hcp": hcp, "multi": multi, "refine": refine, "overlap": overlap}
+CONFIGS = {"small": small, "scan": scan, "hcp": hcp, "multi": multi, "refine": refine, "overlap": overlap,
+           "frames": frames}
 
 
 def make(name, **kw):
