@@ -324,6 +324,61 @@ acom_status_t acom_simulate_fill(acom_plan_t plan, int64_t n, const float* orien
                                  float rel_cut, const int64_t* offsets, float* qx, float* qy, float* intensity,
                                  void* stream);
 
+/* ------------------------------------------------- Bragg disk detection ---- */
+/* The peak list of each pattern comes from correlating its raw detector frame
+ * with the image of the probe over vacuum (Methods > Correlation Pattern
+ * Matching; Methods > Software Implementation): disk positions are the
+ * correlation maxima, and a peak's intensity is the correlation value there.
+ * The paper cites this step without defining it; the library computes:
+ *   C[y][x] = sum_{u,v} f[(y+u) mod N][(x+v) mod N] t[u][v]   (circular, FP32 FFTs)
+ * with t the probe image shifted so that its centre pixel is at the origin;
+ * candidates are interior pixels (at least `edge` from every border, not
+ * within `exclusion_radius` of the optical axis) whose C is strictly above all
+ * 8 neighbours; kept are those with C > max(min_abs, min_rel * largest
+ * candidate C), taken in order of decreasing C (ties: lower raster index
+ * y*N+x first) when no kept peak is closer than `min_spacing` pixels, at most
+ * `max_peaks`; each is placed at the vertex of the parabola through C at the
+ * peak and its two neighbours, per axis, and reported as
+ * qx = (x + dx - center_x) * pixel_size, qy = (y + dy - center_y) * pixel_size,
+ * intensity = C[y][x], strongest first. */
+typedef struct {
+  int32_t size;            /* N: frames are N x N float32, row-major (y, x); 64 or 128 */
+  int32_t edge;            /* in [1, N/2) */
+  float min_rel, min_abs;  /* threshold relative to the largest candidate (>= 0), and absolute */
+  int32_t min_spacing;     /* pixels, in [0, 2N]; 0 or 1 = no spacing rule */
+  int32_t max_peaks;       /* in [1, 256]: slots per frame */
+  float center_y, center_x;   /* optical axis, pixels */
+  float exclusion_radius;     /* pixels (>= 0; 0 = none), compared as radius^2 in FP32 */
+  float pixel_size;           /* 1/A per pixel (> 0) */
+} acom_disk_params_t;
+
+/* Conjugate spectrum of the probe template, scaled by 1/N^2: spectrum is
+ * N x (N/2 + 1) complex (interleaved float pairs, device), computed from the
+ * device probe image (N x N float32) with its centre pixel (cy0, cx0) moved to
+ * the origin.  Asynchronous on stream; INVALID for other sizes or a centre
+ * outside the frame. */
+acom_status_t acom_disk_template(const float* probe, int32_t size, int32_t cy0, int32_t cx0, float* spectrum,
+                                 void* stream);
+
+/* Detection on n frames (device, n x N x N float32, 16-byte aligned): writes
+ * counts[n] (peaks found per frame), offsets[n + 1] (exclusive prefix sum of
+ * counts, int64) and per frame max_peaks slots of slot_qx, slot_qy, slot_I
+ * (and slot_pixel = y*N + x when not null; all n x max_peaks, slot t of frame p
+ * at p*max_peaks + t, slots beyond the count untouched).  flags (n, nullable):
+ * 1 when more than 1024 candidates passed the threshold, in which case the
+ * first 1024 in raster order were ranked.  One workgroup per frame (about
+ * 76 KiB of LDS at N = 128), no workspace.  Asynchronous on stream; host
+ * checks return INVALID (sizes, ranges, nulls, alignment, n beyond 2^26). */
+acom_status_t acom_detect_disks(const float* frames, int64_t n, const float* spectrum, const acom_disk_params_t* p,
+                                int32_t* counts, int64_t* offsets, float* slot_qx, float* slot_qy, float* slot_I,
+                                int32_t* slot_pixel, int32_t* flags, void* stream);
+
+/* Compacts the slots of acom_detect_disks into CSR peak arrays (qx, qy,
+ * intensity, offsets[n] entries each, device) usable as acom_peaks_t. */
+acom_status_t acom_gather_peaks(int64_t n, int32_t max_peaks, const int32_t* counts, const int64_t* offsets,
+                                const float* slot_qx, const float* slot_qy, const float* slot_I, float* qx, float* qy,
+                                float* intensity, void* stream);
+
 /* ------------------------------------------------------------- errors ---- */
 const char* acom_status_string(acom_status_t s);
 const char* acom_last_error(void);

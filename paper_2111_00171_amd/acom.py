@@ -48,6 +48,12 @@ class _Matches(ctypes.Structure):
                 ("score", c_void_p), ("phi3", c_void_p), ("orient", c_void_p), ("n_evaluated", c_void_p)]
 
 
+class _DiskParams(ctypes.Structure):
+    _fields_ = [("size", c_int32), ("edge", c_int32), ("min_rel", ctypes.c_float), ("min_abs", ctypes.c_float),
+                ("min_spacing", c_int32), ("max_peaks", c_int32), ("center_y", ctypes.c_float),
+                ("center_x", ctypes.c_float), ("exclusion_radius", ctypes.c_float), ("pixel_size", ctypes.c_float)]
+
+
 _lib = None
 
 
@@ -87,6 +93,11 @@ def lib():
                                 c_void_p, c_void_p],
             "acom_refine": [c_void_p, P(_Peaks), c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
                             c_void_p],
+            "acom_disk_template": [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p],
+            "acom_detect_disks": [c_void_p, c_int64, c_void_p, P(_DiskParams), c_void_p, c_void_p, c_void_p, c_void_p,
+                                  c_void_p, c_void_p, c_void_p, c_void_p],
+            "acom_gather_peaks": [c_int64, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                  c_void_p, c_void_p, c_void_p],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -232,6 +243,65 @@ class Peaks:
         return _Peaks(self.n_patterns, self.total_peaks, _ptr(self.offsets, torch.int64, "offsets").value,
                       _ptr(self.qx, torch.float32, "qx").value, _ptr(self.qy, torch.float32, "qy").value,
                       _ptr(self.intensity, torch.float32, "intensity").value)
+
+
+class DiskDetector:
+    """Bragg disk detection on raw N x N frames (N = 64 or 128) by correlation
+    with the vacuum probe image (acom_disk_template / acom_detect_disks /
+    acom_gather_peaks).  probe: (N, N) float32 device tensor; probe_center:
+    its centre pixel (row, column); center: the optical axis of the frames in
+    pixels; pixel_size: 1/A per pixel."""
+
+    def __init__(self, probe, probe_center, center, pixel_size, edge=4, min_rel=0.005, min_abs=0.0,
+                 min_spacing=5, max_peaks=64, exclusion_radius=0.0, stream=None):
+        N = int(probe.shape[-1])
+        if probe.shape != (N, N):
+            raise ValueError("probe must be square")
+        self.size = N
+        self.max_peaks = int(max_peaks)
+        self.params = _DiskParams(N, int(edge), float(min_rel), float(min_abs), int(min_spacing), int(max_peaks),
+                                  float(center[0]), float(center[1]), float(exclusion_radius), float(pixel_size))
+        self.spectrum = torch.empty((N, N // 2 + 1, 2), dtype=torch.float32, device=probe.device)
+        _check(lib().acom_disk_template(_ptr(probe, torch.float32, "probe"), N, int(probe_center[0]),
+                                        int(probe_center[1]), c_void_p(self.spectrum.data_ptr()), _stream(stream)),
+               "acom_disk_template")
+
+    def detect(self, frames, with_pixels=False, stream=None):
+        """Per-frame slots: dict(counts, offsets, qx, qy, I (n, max_peaks), pixel, flags)."""
+        n = int(frames.shape[0])
+        dev = frames.device
+        out = {"counts": torch.empty(n, dtype=torch.int32, device=dev),
+               "offsets": torch.empty(n + 1, dtype=torch.int64, device=dev),
+               "flags": torch.empty(n, dtype=torch.int32, device=dev)}
+        for k in ("qx", "qy", "I"):
+            out[k] = torch.zeros((n, self.max_peaks), dtype=torch.float32, device=dev)
+        out["pixel"] = (torch.full((n, self.max_peaks), -1, dtype=torch.int32, device=dev) if with_pixels
+                        else None)
+        _check(lib().acom_detect_disks(_ptr(frames, torch.float32, "frames"), n,
+                                       c_void_p(self.spectrum.data_ptr()), ctypes.byref(self.params),
+                                       c_void_p(out["counts"].data_ptr()), c_void_p(out["offsets"].data_ptr()),
+                                       c_void_p(out["qx"].data_ptr()), c_void_p(out["qy"].data_ptr()),
+                                       c_void_p(out["I"].data_ptr()), _ptr(out["pixel"], torch.int32, "pixel"),
+                                       c_void_p(out["flags"].data_ptr()), _stream(stream)), "acom_detect_disks")
+        return out
+
+    def gather(self, det, out=None, stream=None):
+        """CSR Peaks from the slots of detect() (reads the total: synchronises)."""
+        n = int(det["counts"].numel())
+        total = int(det["offsets"][-1].item())
+        dev = det["counts"].device
+        if out is None:
+            out = tuple(torch.empty(total, dtype=torch.float32, device=dev) for _ in range(3))
+        qx, qy, I = out
+        _check(lib().acom_gather_peaks(n, self.max_peaks, c_void_p(det["counts"].data_ptr()),
+                                       c_void_p(det["offsets"].data_ptr()), c_void_p(det["qx"].data_ptr()),
+                                       c_void_p(det["qy"].data_ptr()), c_void_p(det["I"].data_ptr()),
+                                       c_void_p(qx.data_ptr()), c_void_p(qy.data_ptr()), c_void_p(I.data_ptr()),
+                                       _stream(stream)), "acom_gather_peaks")
+        return Peaks(det["offsets"], qx[:total], qy[:total], I[:total], device=dev)
+
+    def peaks(self, frames, stream=None):
+        return self.gather(self.detect(frames, stream=stream), stream=stream)
 
 
 class Plan:

@@ -159,6 +159,14 @@ acom_status_t sim_args(acom_plan_t plan, int64_t n, const float* orient, const i
 }
 
 }  // namespace
+
+// Exclusive prefix sum of n int32 counts into n + 1 int64 offsets (one block);
+// also used by the disk detector.
+hipError_t launch_scan_counts(const int32_t* counts, int n, int64_t* offsets, hipStream_t s) {
+  scan_counts_kernel<<<1, kScanThreads, 0, s>>>(counts, n, offsets);
+  return hipGetLastError();
+}
+
 }  // namespace acom
 
 using namespace acom;
@@ -175,8 +183,7 @@ extern "C" acom_status_t acom_simulate_count(acom_plan_t plan, int64_t n, const 
     simulate_kernel<false><<<dim3((unsigned)n), kSimThreads, 0, s>>>(a);
     ACOM_HIP(hipGetLastError());
   }
-  scan_counts_kernel<<<1, kScanThreads, 0, s>>>(counts, (int)n, offsets);
-  ACOM_HIP(hipGetLastError());
+  ACOM_HIP(launch_scan_counts(counts, (int)n, offsets, s));
   return ACOM_OK;
 }
 
