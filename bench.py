@@ -24,6 +24,11 @@ Other workloads (--workload), each printing one JSON line of the same form:
   refine  65,536 FCC patterns at random (off-grid) orientations: top-4 grid
           candidates (FP32 contraction) refined by gradient ascent on the
           continuous score (acom_refine, FP32).
+  overlap 65,536 patterns of two overlapping FCC grains: up to two
+          orientations each (acom_match_multi, BF16).
+  simulate forward kinematical patterns of 65,536 orientations (CSR).
+  detect  Bragg disk detection on 65,536 raw 128 x 128 frames (acom_detect_disks
+          and acom_gather_peaks); frames/s, HBM roofline of the detection kernel.
 """
 import argparse
 import hashlib
@@ -63,7 +68,12 @@ DESCR = {
                "(deletion radius 0.04 1/A), BF16 contraction, 1-degree plan, 128 x 360 bins",
     "simulate": "simulate: forward kinematical patterns of 65,536 random FCC orientations (reflections with "
                 "|g| < 2.0 1/A, kept above 1% of max |F|^2 after the excitation-error shape factor), CSR output",
+    "detect": "detect: Bragg disk detection on 65,536 raw 128x128 float32 frames of FCC grains (4,096 distinct "
+              "frames tiled 16 times; probe disk radius 3.5 px), correlation with the probe image, at most 64 "
+              "peaks per frame (spacing 5 px, threshold 0.5% of the strongest, 4 px edge, 4 px beam exclusion), "
+              "CSR output",
 }
+DISK_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "disk_detect_kernel_traffic.json")
 
 
 def log(msg):
@@ -77,6 +87,26 @@ def kernel_source_hash():
         with open(os.path.join(ROOT, "paper_2111_00171_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def disk_source_hash():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2111_00171_amd", "csrc", "disks.hip"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_disk_traffic(frames_per_launch):
+    """HBM bytes per launch of the disk detection kernel from rocprofv3
+    FETCH_SIZE/WRITE_SIZE counters (profiles/), or None if they were taken on a
+    different kernel source or launch size."""
+    if not os.path.exists(DISK_TRAFFIC_FILE):
+        return None
+    with open(DISK_TRAFFIC_FILE) as f:
+        t = json.load(f)
+    if t.get("source_hash") != disk_source_hash() or t.get("frames_per_launch") != frames_per_launch:
+        return None
+    return t["bytes_per_launch"]
 
 
 def measured_traffic(precision, launches_patterns):
@@ -600,12 +630,78 @@ def run_simulate(args):
                 cpu, {"metric": "forward kinematical patterns simulated/sec at 1 GPU"})
 
 
+def run_detect(args):
+    """Bragg disk detection: a step is acom_detect_disks (detection kernel and
+    the counts scan) on all frames, the read of the total, and
+    acom_gather_peaks into CSR arrays."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2111_00171_amd import acom
+
+    n, U, N = 65536, 4096, 128
+    t0 = time.perf_counter()
+    d = synth.frames(seed=1007, n=U, size=N)
+    log(f"detect: {U} distinct frames generated ({time.perf_counter() - t0:.1f} s)")
+    fr = torch.tensor(d["frames"], device="cuda").repeat(n // U, 1, 1).contiguous()
+    c = int(d["center"][0])
+    prm = dict(edge=4, min_rel=0.005, min_abs=0.0, min_spacing=5, max_peaks=64, exclusion_radius=4.0)
+    det = acom.DiskDetector(torch.tensor(d["probe"], device="cuda"), (c, c), d["center"], d["pixel_size"], **prm)
+    cap = tuple(torch.empty(n * prm["max_peaks"], dtype=torch.float32, device="cuda") for _ in range(3))
+    for _ in range(args.warmup):
+        det.gather(det.detect(fr), out=cap)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record()
+        res = det.detect(fr)
+        ev[i][1].record()
+        pk = det.gather(res, out=cap)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    t_det = sum(a.elapsed_time(b) for a, b in ev) / args.steps
+    total = int(pk.total_peaks)
+    log(f"detect: timed, {n * args.steps / el:.0f} frames/s, detection call {t_det:.3f} ms, "
+        f"{total / n:.1f} peaks per frame")
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import disks
+        t = disks.probe_template(d["probe"], c, c)
+        kw = dict(edge=4, min_rel=0.005, min_abs=0.0, min_spacing=5, max_peaks=64, cy=d["center"][0],
+                  cx=d["center"][1], r_excl=4.0, pixel_size=d["pixel_size"])
+        t0 = time.perf_counter()
+        k = 0
+        while time.perf_counter() - t0 < 15.0 and k < U:
+            disks.detect(d["frames"][k], t, **kw)
+            k += 1
+        cel = time.perf_counter() - t0
+        cpu = {"value": k / cel, "unit": "frames/s", "cores": 1, "kind": "oracle",
+               "sample": f"the first {k} distinct frames; oracle/disks.detect (numpy FP64 direct correlation over "
+                         f"the probe's nonzero taps, one thread)"}
+    per_frame = N * N * 4 + 16                      # frame read; count, offset, flag
+    alg = n * per_frame + total * 12                # + the kept peaks' slots
+    gbs = alg / (t_det * 1e-3) / 1e9
+    traffic = measured_disk_traffic(n)
+    roof = {"kernel": "disk_detect_kernel<128> (+ the one-block counts scan in the same call)", "bound": "hbm",
+            "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s", "frac": round(gbs / 8000.0, 4),
+            "traffic": traffic, "algorithmic_bytes_per_launch": alg,
+            "detect_call_ms": round(t_det, 4)}
+    ccfg = {"frames": n, "frame": [N, N], "distinct_frames": U, "peaks_per_frame": round(total / n, 2),
+            "max_peaks": prm["max_peaks"]}
+    out = line("detect", n * args.steps / el, el * 1e3 / args.steps, args.steps, args.warmup, "f32", ccfg, roof,
+               cpu, {"metric": "raw diffraction frames reduced to Bragg peak lists/sec at 1 GPU"})
+    out["unit"] = "frames/s"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="scan", choices=["scan", "hcp", "multi", "refine", "overlap", "simulate"])
+    ap.add_argument("--workload", default="scan", choices=["scan", "hcp", "multi", "refine", "overlap", "simulate",
+                                                             "detect"])
     ap.add_argument("--precisions", default=None,
                     help="comma list; the first is `value` (scan: fp32,bf16,fp16; hcp: bf16,fp16,fp32)")
     ap.add_argument("--chunk", type=int, default=65536,
@@ -640,6 +736,8 @@ def main():
         out = run_overlap(args)
     elif args.workload == "simulate":
         out = run_simulate(args)
+    elif args.workload == "detect":
+        out = run_detect(args)
     else:
         out = run_refine(args)
     print(json.dumps(out))

@@ -82,9 +82,15 @@ struct SmallDft {
     SmallDft<R / 2, INV>::run(o);
 #pragma unroll
     for (int k = 0; k < R / 2; ++k) {
-      const float c = kCos16[k * (16 / R)], sn = kSin16[k * (16 / R)];
-      const float2 w = make_float2(c, INV ? sn : -sn);
-      const float2 t = cmul(w, o[k]);
+      float2 t;
+      if (k == 0) {
+        t = o[k];
+      } else if (4 * k == R) {
+        t = rot_i<INV>(o[k]);
+      } else {
+        const float c = kCos16[k * (16 / R)], sn = kSin16[k * (16 / R)];
+        t = cmul(make_float2(c, INV ? sn : -sn), o[k]);
+      }
       v[k] = cadd(e[k], t);
       v[k + R / 2] = csub(e[k], t);
     }
@@ -150,7 +156,8 @@ __device__ __forceinline__ void make_twiddles(float2* tw) {
 }
 
 // Row spectra (Z-view, pos = kx, seq = row pair j) -> column layout (S-view,
-// pos = y, seq = kx), kx = 0 and N/2 packed as one complex column.
+// pos = y, seq = kx), kx = 0 and N/2 packed as one complex column.  Lanes run
+// over kx: the reads step by one LDS row, the writes are consecutive.
 template <int N>
 __device__ __forceinline__ void split_rows(float2* buf) {
   using S = DiskShape<N>;
@@ -159,7 +166,7 @@ __device__ __forceinline__ void split_rows(float2* buf) {
   float2 lo[PER], hi[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
-    const int idx = tid + q * S::NT, j = idx % H, k = idx / H;
+    const int idx = tid + q * S::NT, k = idx % H, j = idx / H;
     const float2 a = buf[k * P + j];
     const float2 b = buf[(k == 0 ? H : N - k) * P + j];
     if (k == 0) {
@@ -174,7 +181,7 @@ __device__ __forceinline__ void split_rows(float2* buf) {
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
-    const int idx = tid + q * S::NT, j = idx % H, k = idx / H;
+    const int idx = tid + q * S::NT, k = idx % H, j = idx / H;
     buf[(2 * j) * P + k] = lo[q];
     buf[(2 * j + 1) * P + k] = hi[q];
   }
@@ -182,7 +189,7 @@ __device__ __forceinline__ void split_rows(float2* buf) {
 }
 
 // Inverse of split_rows: half spectra of rows 2j, 2j+1 -> Z_k = A_k + i B_k
-// over the full kx range (A_{N-k} = conj A_k).
+// over the full kx range (A_{N-k} = conj A_k); lanes over kx.
 template <int N>
 __device__ __forceinline__ void join_rows(float2* buf) {
   using S = DiskShape<N>;
@@ -191,7 +198,7 @@ __device__ __forceinline__ void join_rows(float2* buf) {
   float2 u[PER], w[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
-    const int idx = tid + q * S::NT, j = idx % H, k = idx / H;
+    const int idx = tid + q * S::NT, k = idx % H, j = idx / H;
     const float2 A = buf[(2 * j) * P + k];
     const float2 B = buf[(2 * j + 1) * P + k];
     if (k == 0) {
@@ -205,7 +212,7 @@ __device__ __forceinline__ void join_rows(float2* buf) {
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
-    const int idx = tid + q * S::NT, j = idx % H, k = idx / H;
+    const int idx = tid + q * S::NT, k = idx % H, j = idx / H;
     buf[k * P + j] = u[q];
     buf[(k == 0 ? H : N - k) * P + j] = w[q];
   }
@@ -287,15 +294,12 @@ __global__ void __launch_bounds__(DiskShape<N>::NT) disk_detect_kernel(DiskArgs 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   make_twiddles<N>(L.tw);
   const float* f = a.frames + (size_t)p * (N * N);
-  // ---- load: packed rows, Z-view (pos = x, seq = j)
-  for (int idx = tid; idx < H * (N / 4); idx += NT) {
-    const int x4 = idx % (N / 4), j = idx / (N / 4);
-    const float4 r0 = *reinterpret_cast<const float4*>(f + (2 * j) * N + 4 * x4);
-    const float4 r1 = *reinterpret_cast<const float4*>(f + (2 * j + 1) * N + 4 * x4);
-    L.buf[(4 * x4 + 0) * P + j] = make_float2(r0.x, r1.x);
-    L.buf[(4 * x4 + 1) * P + j] = make_float2(r0.y, r1.y);
-    L.buf[(4 * x4 + 2) * P + j] = make_float2(r0.z, r1.z);
-    L.buf[(4 * x4 + 3) * P + j] = make_float2(r0.w, r1.w);
+  // ---- load: packed rows, Z-view (pos = x, seq = j); lanes over x, so each
+  // wave reads 256 contiguous bytes of a row and writes one LDS column
+#pragma unroll 4
+  for (int idx = tid; idx < H * N; idx += NT) {
+    const int x = idx % N, j = idx / N;
+    L.buf[x * P + j] = make_float2(f[(2 * j) * N + x], f[(2 * j + 1) * N + x]);
   }
   __syncthreads();
   fft_all<N, false>(L.buf, L.tw);
@@ -327,25 +331,30 @@ __global__ void __launch_bounds__(DiskShape<N>::NT) disk_detect_kernel(DiskArgs 
   const float* cf = reinterpret_cast<const float*>(L.buf);
   auto C = [&](int y, int x) { return cf[2 * (x * P + (y >> 1)) + (y & 1)]; };
 
-  // ---- strict 3x3 maxima in the interior (thread: PIX consecutive raster pixels of row y)
-  const int y = (tid * PIX) / N, x0 = (tid * PIX) % N;
+  // ---- strict 3x3 maxima in the interior.  Thread: PIX consecutive pixels of
+  // row y starting at x0; lanes run over y so that each read is 64 consecutive
+  // words.  Its raster slot (y * N / PIX + run) orders the compaction.
+  constexpr int RUNS = N / PIX;
+  const int y = tid % N, run = tid / N, x0 = run * PIX;
+  const int slot = y * RUNS + run;
   const int xa = max(x0, a.edge), xb = min(x0 + PIX, N - a.edge);
   unsigned mask = 0u;
   float vmax = -INFINITY;
   if (y >= a.edge && y < N - a.edge && xa < xb) {
-    float u0 = C(y - 1, xa - 1), m0 = C(y, xa - 1), d0 = C(y + 1, xa - 1);
-    float u1 = C(y - 1, xa), m1 = C(y, xa), d1 = C(y + 1, xa);
+    // column maxima of the rows above and below, slid along x
+    float v0 = fmaxf(C(y - 1, xa - 1), C(y + 1, xa - 1)), m0 = C(y, xa - 1);
+    float v1 = fmaxf(C(y - 1, xa), C(y + 1, xa)), m1 = C(y, xa);
     const float dy = (float)y - a.cy;
     for (int x = xa; x < xb; ++x) {
-      const float u2 = C(y - 1, x + 1), m2 = C(y, x + 1), d2 = C(y + 1, x + 1);
-      const float nb = fmaxf(fmaxf(fmaxf(u0, u1), fmaxf(u2, m0)), fmaxf(fmaxf(m2, d0), fmaxf(d1, d2)));
+      const float v2 = fmaxf(C(y - 1, x + 1), C(y + 1, x + 1)), m2 = C(y, x + 1);
+      const float nb = fmaxf(fmaxf(v0, v1), fmaxf(fmaxf(v2, m0), m2));
       const float dx = (float)x - a.cx;
       if (m1 > nb && dy * dy + dx * dx >= a.r2_excl) {
         mask |= 1u << (x - x0);
         vmax = fmaxf(vmax, m1);
       }
-      u0 = u1; m0 = m1; d0 = d1;
-      u1 = u2; m1 = m2; d1 = d2;
+      v0 = v1; m0 = m1;
+      v1 = v2; m1 = m2;
     }
   }
 #pragma unroll
@@ -356,10 +365,14 @@ __global__ void __launch_bounds__(DiskShape<N>::NT) disk_detect_kernel(DiskArgs 
 #pragma unroll
   for (int w = 1; w < NW; ++w) cmax = fmaxf(cmax, L.red[w]);
   const float thr = fmaxf(a.min_abs, a.min_rel * cmax);
-  // ---- candidates above the threshold, compacted in raster order
+  // ---- candidates above the threshold, compacted in raster order: counts by
+  // raster slot, an exclusive scan over the slots, then each run writes its own
   int cnt = 0;
   for (unsigned m = mask; m; m &= m - 1u) cnt += C(y, x0 + __builtin_ctz(m)) > thr;
-  int incl = cnt;
+  L.order[slot] = (int16_t)cnt;
+  __syncthreads();
+  const int mine = L.order[tid];
+  int incl = mine;
 #pragma unroll
   for (int off = 1; off < 64; off <<= 1) {
     const int t = __shfl_up(incl, off, 64);
@@ -373,7 +386,9 @@ __global__ void __launch_bounds__(DiskShape<N>::NT) disk_detect_kernel(DiskArgs 
     before += w < wave ? L.wsum[w] : 0;
     total += L.wsum[w];
   }
-  int pos = before + incl - cnt;
+  L.order[tid] = (int16_t)min(before + incl - mine, kDiskMaxCand);
+  __syncthreads();
+  int pos = L.order[slot];
   for (unsigned m = mask; m; m &= m - 1u) {
     const int x = x0 + __builtin_ctz(m);
     const float v = C(y, x);

@@ -101,7 +101,10 @@ __global__ void __launch_bounds__(kSimThreads) simulate_kernel(SimArgs a) {
 }
 
 // offsets[0] = 0, offsets[i + 1] = offsets[i] + counts[i]: one block walks the
-// counts in slices of 1024 with a block-wide scan per slice.
+// counts in slices of 1024 x kScanPer; each thread sums kScanPer consecutive
+// counts, a block-wide scan of those sums gives each thread its base, and the
+// thread writes its kScanPer offsets.
+constexpr int kScanPer = 16;
 __global__ void __launch_bounds__(kScanThreads) scan_counts_kernel(const int* counts, int n, int64_t* offsets) {
   __shared__ int64_t s_wsum[kScanThreads / 64];
   __shared__ int64_t s_carry;
@@ -111,10 +114,16 @@ __global__ void __launch_bounds__(kScanThreads) scan_counts_kernel(const int* co
     offsets[0] = 0;
   }
   __syncthreads();
-  for (int b = 0; b < n; b += kScanThreads) {
-    const int i = b + tid;
-    int64_t v = i < n ? counts[i] : 0;
-    // inclusive scan within the wave
+  for (int b = 0; b < n; b += kScanThreads * kScanPer) {
+    const int i0 = b + tid * kScanPer;
+    int c[kScanPer];
+    int64_t v = 0;
+#pragma unroll
+    for (int e = 0; e < kScanPer; ++e) {
+      c[e] = i0 + e < n ? counts[i0 + e] : 0;
+      v += c[e];
+    }
+    // inclusive scan of the thread sums within the wave
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
       const int64_t u = __shfl_up(v, off, 64);
@@ -122,9 +131,14 @@ __global__ void __launch_bounds__(kScanThreads) scan_counts_kernel(const int* co
     }
     if (lane == 63) s_wsum[wave] = v;
     __syncthreads();
-    int64_t before = s_carry;
-    for (int w = 0; w < wave; ++w) before += s_wsum[w];
-    if (i < n) offsets[i + 1] = before + v;
+    int64_t run = s_carry;
+    for (int w = 0; w < wave; ++w) run += s_wsum[w];
+    run += __shfl_up(v, 1, 64) * (lane > 0);  // exclusive within the wave
+#pragma unroll
+    for (int e = 0; e < kScanPer; ++e) {
+      run += c[e];
+      if (i0 + e < n) offsets[i0 + e + 1] = run;
+    }
     __syncthreads();
     if (tid == 0) {
       int64_t t = s_carry;
