@@ -423,6 +423,7 @@ def run_refine(args):
         step()
     torch.cuda.synchronize()
     t_match = t_ref = 0.0
+    acom.profile_begin(8192)
     for _ in range(args.steps):
         t0 = time.perf_counter()
         gpl.match(pk, 4, "fp32", args.chunk, ws, out=out)
@@ -433,6 +434,13 @@ def run_refine(args):
         t_ref += time.perf_counter() - t1
         t_match += t1 - t0
     el = t_match + t_ref
+    prof = acom.profile_read()
+    acom.profile_end()
+    Z, R, N = gpl.n_zones, gpl.n_radial, gpl.n_angular
+    flop_per_pattern = 8.0 * Z * (N // 2 + 1) * R
+    b_ms = prof["bound"][0] / prof["bound"][1]
+    per_launch = min(args.chunk, n)
+    tflops = flop_per_pattern * per_launch / (b_ms * 1e-3) / 1e12
     log(f"refine: timed, {n * args.steps / el:.0f} patterns/s")
     m = m.cpu().numpy()
     init = out["orient"].reshape(n, 4, 3, 3).cpu().numpy()
@@ -461,9 +469,14 @@ def run_refine(args):
              "oracle_comparison": ext, "input_generation_s": round(t_gen, 3)}
     ccfg = {"patterns": n, "peaks": int(d["offsets"][-1]), "zones": gpl.n_zones, "n_radial": gpl.n_radial,
             "n_angular": gpl.n_angular, "candidates": 4, "max_trials": 64}
-    roof = {"kernel": "refine_kernel (continuous score and gradient, FP32 VALU)", "bound": "alu", "achieved": None,
-            "peak": None, "unit": None, "frac": None, "traffic": None,
-            "note": "latency-bound gradient ascent; see DESIGN.md"}
+    # the dominant kernel of the step is the FP32 contraction of the candidate search
+    roof = {"kernel": "bound_kernel (MFMA contraction, fp32 operands) of the top-4 search", "bound": "mfma",
+            "achieved": round(tflops, 3), "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
+            "frac": round(tflops / PEAK_TFLOPS["fp32"], 4), "traffic": None,
+            "algorithmic_flop_per_launch": flop_per_pattern * per_launch,
+            "kernel_avg_ms": {k: (round(t / c, 4) if c else None) for k, (t, c) in prof.items()},
+            "refine_kernel": "latency-bound gradient ascent (per-pattern candidate loops, a block reduction per "
+                             "iteration); its time is ms_per_step_refine"}
     return line("refine", n * args.steps / el, el * 1e3 / args.steps, args.steps, args.warmup, "f32", ccfg, roof,
                 cpu, extra)
 
@@ -601,13 +614,18 @@ def run_simulate(args):
     for _ in range(args.warmup):
         gpl.simulate(orient)
     torch.cuda.synchronize()
+    ev = [{k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for k in ("count", "fill")} for _ in range(args.steps)]
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        off, qx, qy, I = gpl.simulate(orient)
+    for i in range(args.steps):
+        off, qx, qy, I = gpl.simulate(orient, events=ev[i])
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    t_count = sum(e["count"][0].elapsed_time(e["count"][1]) for e in ev) / args.steps
+    t_fill = sum(e["fill"][0].elapsed_time(e["fill"][1]) for e in ev) / args.steps
     total = int(off[-1].item())
-    log(f"simulate: timed, {n * args.steps / el:.0f} patterns/s, {total / n:.1f} peaks per pattern")
+    log(f"simulate: timed, {n * args.steps / el:.0f} patterns/s, {total / n:.1f} peaks per pattern, "
+        f"count call {t_count:.4f} ms, fill call {t_fill:.4f} ms")
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import kinematics
@@ -622,9 +640,16 @@ def run_simulate(args):
         cel = time.perf_counter() - t0
         cpu = {"value": k / cel, "unit": "patterns/s", "cores": 1, "kind": "oracle",
                "sample": f"{k} of the same orientations; oracle/kinematics.pattern (numpy FP64, one thread)"}
-    roof = {"kernel": "simulate_kernel (per pattern: rotate, excitation error, shape factor, compaction)",
-            "bound": "alu", "achieved": None, "peak": None, "unit": None, "frac": None, "traffic": None,
-            "note": "latency-bound (one block per pattern, barriers per 256 reflections)"}
+    # per reflection: rotation 15, excitation error 14 (incl. sqrt and divide), shape factor 4 (incl. exp),
+    # cut 1 = 34 operations, for the 536 reflections of the FCC plan (|g| < 2 1/A), in the fill pass
+    n_refl = int(np.sum(np.linalg.norm(synth.load_table("fcc_a4.08")["g"], axis=1) < cfg["k_max"]))
+    flop = 34.0 * n_refl * n
+    tf = flop / (t_fill * 1e-3) / 1e12
+    roof = {"kernel": "simulate_kernel<true> (fill: rotate, excitation error, shape factor, ordered compaction)",
+            "bound": "alu", "achieved": round(tf, 3), "peak": 157.3, "unit": "TFLOP/s",
+            "frac": round(tf / 157.3, 4), "traffic": None, "algorithmic_flop_per_launch": flop,
+            "fill_call_ms": round(t_fill, 4), "count_call_ms": round(t_count, 4),
+            "note": "one wavefront per pattern; exp, sqrt and divide issue as several instructions each"}
     ccfg = {"patterns": n, "peaks_per_pattern": round(total / n, 2), "k_max": cfg["k_max"]}
     return line("simulate", n * args.steps / el, el * 1e3 / args.steps, args.steps, args.warmup, "f32", ccfg, roof,
                 cpu, {"metric": "forward kinematical patterns simulated/sec at 1 GPU"})
@@ -715,7 +740,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); patterns are independent, so a "
-              f"multi-GPU run shards the scan with no exchange (see DESIGN.md)", file=sys.stderr)
+              f"multi-GPU run shards the scan into contiguous pattern ranges with no exchange", file=sys.stderr)
         sys.exit(2)
     if args.precisions is None:
         args.precisions = "bf16,fp16,fp32" if args.workload == "hcp" else "fp32,bf16,fp16"

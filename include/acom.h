@@ -40,7 +40,7 @@ typedef enum {
   ACOM_E_INVALID = 1,     /* bad argument (see acom_last_error) */
   ACOM_E_NOMEM = 2,       /* device allocation failed (acom_build_plan only) */
   ACOM_E_HIP = 3,         /* a HIP runtime call failed */
-  ACOM_E_UNSUPPORTED = 4, /* valid request this build does not support */
+  ACOM_E_UNSUPPORTED = 4, /* valid request the library does not support */
   ACOM_E_WORKSPACE = 5    /* workspace smaller than acom_*_workspace_size */
 } acom_status_t;
 

@@ -457,25 +457,37 @@ class Plan:
                                       _stream(stream)), "acom_match_multi")
         return out
 
-    def simulate(self, orient, phase=None, rel_cut=0.01, stream=None):
+    def simulate(self, orient, phase=None, rel_cut=0.01, stream=None, events=None):
         """Forward kinematical patterns of orientations orient (n, 3, 3) on the
         plan's device (acom_simulate_count / _fill): (offsets, qx, qy, intensity)
-        device tensors, peaks in the plan's reflection order."""
+        device tensors, peaks in the plan's reflection order.  events: optional
+        dict of (start, end) torch.cuda.Event pairs under "count" and "fill",
+        recorded around the two calls on the launch stream."""
         orient = orient.reshape(-1, 9)
         n = orient.shape[0]
         dev = orient.device
         counts = torch.empty(n, dtype=torch.int32, device=dev)
         offsets = torch.empty(n + 1, dtype=torch.int64, device=dev)
         ph = _ptr(phase, torch.int32, "phase")
+        st = torch.cuda.current_stream() if stream is None else stream
+
+        def rec(key, i):
+            if events is not None and key in events:
+                events[key][i].record(st)
+
+        rec("count", 0)
         _check(lib().acom_simulate_count(self._h, n, _ptr(orient, torch.float32, "orient"), ph, float(rel_cut),
-                                         c_void_p(counts.data_ptr()), c_void_p(offsets.data_ptr()), _stream(stream)),
+                                         c_void_p(counts.data_ptr()), c_void_p(offsets.data_ptr()), _stream(st)),
                "acom_simulate_count")
+        rec("count", 1)
         total = int(offsets[-1].item())  # synchronises
         f32 = dict(dtype=torch.float32, device=dev)
         qx, qy, I = torch.empty(total, **f32), torch.empty(total, **f32), torch.empty(total, **f32)
+        rec("fill", 0)
         _check(lib().acom_simulate_fill(self._h, n, _ptr(orient, torch.float32, "orient"), ph, float(rel_cut),
                                         c_void_p(offsets.data_ptr()), c_void_p(qx.data_ptr()), c_void_p(qy.data_ptr()),
-                                        c_void_p(I.data_ptr()), _stream(stream)), "acom_simulate_fill")
+                                        c_void_p(I.data_ptr()), _stream(st)), "acom_simulate_fill")
+        rec("fill", 1)
         return offsets, qx, qy, I
 
     def autotune(self, peaks: Peaks, precision="fp32", chunk=0, workspace=None, stream=None):

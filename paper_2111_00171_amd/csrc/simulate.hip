@@ -7,8 +7,8 @@
 //
 // Two calls: acom_simulate_count writes each pattern's peak count and the
 // exclusive prefix sum (CSR offsets); acom_simulate_fill writes the peaks in
-// reflection order.  One 256-thread block per pattern, 256 reflections per
-// pass, wave ballots for the in-order compaction.
+// reflection order.  One wavefront per pattern, 64 reflections per step, wave
+// ballots for the in-order compaction.
 #include <cmath>
 
 #include "acom_internal.h"
@@ -37,16 +37,16 @@ __device__ __forceinline__ float sim_excitation(float x, float y, float z, float
   return -(2.0f * k0 * z + (x * x + y * y + z * z)) / (2.0f * sqrtf(x * x + y * y + (k0 + z) * (k0 + z)));
 }
 
-// FILL = false: count the kept reflections of pattern blockIdx.x.
-// FILL = true: write them, in reflection order, from offsets[p].
+// One wavefront per pattern (kSimThreads / 64 patterns per block), no
+// barriers: the wave reduces the phase's largest |F|^2, then walks the
+// reflections 64 at a time; a ballot and its popcount below the lane give
+// every kept reflection its rank in reflection order.
+// FILL = false: count the kept reflections; FILL = true: write them from offsets[p].
 template <bool FILL>
 __global__ void __launch_bounds__(kSimThreads) simulate_kernel(SimArgs a) {
-  __shared__ float s_red[kSimThreads / 64];
-  __shared__ int s_wcnt[kSimThreads / 64];
-  __shared__ int s_base;
-  const int p = blockIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int p = blockIdx.x * (kSimThreads / 64) + (threadIdx.x >> 6);
   if (p >= a.n) return;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int ph = a.phase ? a.phase[p] : 0;
   if (ph < 0 || ph >= a.n_phases) ph = -1;
   const int g0 = ph < 0 ? 0 : a.refl_off[ph], g1 = ph < 0 ? 0 : a.refl_off[ph + 1];
@@ -54,19 +54,15 @@ __global__ void __launch_bounds__(kSimThreads) simulate_kernel(SimArgs a) {
 #pragma unroll
   for (int i = 0; i < 9; ++i) M[i] = a.orient[(size_t)p * 9 + i];
   float fm = 0.0f;
-  for (int g = g0 + tid; g < g1; g += kSimThreads) fm = fmaxf(fm, a.F2[g]);
+  for (int g = g0 + lane; g < g1; g += 64) fm = fmaxf(fm, a.F2[g]);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) fm = fmaxf(fm, __shfl_xor(fm, off, 64));
-  if (lane == 0) s_red[wave] = fm;
-  if (tid == 0) s_base = 0;
-  __syncthreads();
-  fm = s_red[0];
-  for (int w = 1; w < kSimThreads / 64; ++w) fm = fmaxf(fm, s_red[w]);
   const float cut = a.rel_cut * fm;
   const float inv2s2 = 1.0f / (2.0f * a.sigma * a.sigma);
-  const int64_t out0 = FILL ? a.offsets[p] : 0;
-  for (int gb = g0; gb < g1; gb += kSimThreads) {
-    const int g = gb + tid;
+  int64_t o = FILL ? a.offsets[p] : 0;
+  int kept = 0;
+  for (int gb = g0; gb < g1; gb += 64) {
+    const int g = gb + lane;
     bool keep = false;
     float x = 0.0f, y = 0.0f, Ig = 0.0f;
     if (g < g1) {
@@ -79,25 +75,16 @@ __global__ void __launch_bounds__(kSimThreads) simulate_kernel(SimArgs a) {
       keep = Ig > cut;
     }
     const unsigned long long bal = __ballot(keep);
-    if (lane == 0) s_wcnt[wave] = __popcll(bal);
-    __syncthreads();
-    int before = s_base;  // kept in earlier passes and earlier waves of this pass
-    for (int w = 0; w < wave; ++w) before += s_wcnt[w];
     if (FILL && keep) {
-      const int64_t o = out0 + before + __popcll(bal & ((1ull << lane) - 1ull));
-      a.qx[o] = x;
-      a.qy[o] = y;
-      a.I[o] = Ig;
+      const int64_t q = o + __popcll(bal & ((1ull << lane) - 1ull));
+      a.qx[q] = x;
+      a.qy[q] = y;
+      a.I[q] = Ig;
     }
-    __syncthreads();
-    if (tid == 0) {
-      int t = s_base;
-      for (int w = 0; w < kSimThreads / 64; ++w) t += s_wcnt[w];
-      s_base = t;
-    }
-    __syncthreads();
+    o += __popcll(bal);
+    kept += __popcll(bal);
   }
-  if (!FILL && tid == 0) a.counts[p] = s_base;
+  if (!FILL && lane == 0) a.counts[p] = kept;
 }
 
 // offsets[0] = 0, offsets[i + 1] = offsets[i] + counts[i]: one block walks the
@@ -194,7 +181,7 @@ extern "C" acom_status_t acom_simulate_count(acom_plan_t plan, int64_t n, const 
   hipStream_t s = (hipStream_t)stream;
   a.counts = counts;
   if (n > 0) {
-    simulate_kernel<false><<<dim3((unsigned)n), kSimThreads, 0, s>>>(a);
+    simulate_kernel<false><<<dim3((unsigned)((n + kSimThreads / 64 - 1) / (kSimThreads / 64))), kSimThreads, 0, s>>>(a);
     ACOM_HIP(hipGetLastError());
   }
   ACOM_HIP(launch_scan_counts(counts, (int)n, offsets, s));
@@ -213,7 +200,8 @@ extern "C" acom_status_t acom_simulate_fill(acom_plan_t plan, int64_t n, const f
   a.qy = qy;
   a.I = intensity;
   if (n > 0) {
-    simulate_kernel<true><<<dim3((unsigned)n), kSimThreads, 0, (hipStream_t)stream>>>(a);
+    simulate_kernel<true><<<dim3((unsigned)((n + kSimThreads / 64 - 1) / (kSimThreads / 64))), kSimThreads, 0,
+                           (hipStream_t)stream>>>(a);
     ACOM_HIP(hipGetLastError());
   }
   return ACOM_OK;
