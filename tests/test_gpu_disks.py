@@ -146,12 +146,14 @@ def test_detect_edge_cases(acom):
     res = det.detect(torch.zeros((0, N, N), device="cuda"))
     assert res["offsets"].cpu().tolist() == [0]
     # flat and zero frames have no strict maximum; one disk gives one peak at its centre
-    fr = torch.zeros((3, N, N), device="cuda")
+    fr = torch.zeros((4, N, N), device="cuda")
     fr[1] += 5.0
     fr[2] = torch.tensor(100.0 * synth.probe_disk(N, 20, 30, 3.5), device="cuda")
+    fr[3] = fr[2]
+    fr[3, 40, 40] = float("nan")   # a data error spreads NaN over the whole correlation: no peaks
     res = det.detect(fr, with_pixels=True)
     torch.cuda.synchronize()
-    assert res["counts"].cpu().tolist() == [0, 0, 1]
+    assert res["counts"].cpu().tolist() == [0, 0, 1, 0]
     assert int(res["pixel"][2, 0]) == 20 * N + 30
     # invalid arguments are rejected on the host
     for bad in (dict(edge=0), dict(edge=32), dict(max_peaks=257), dict(min_rel=-1.0), dict(min_spacing=-1)):
