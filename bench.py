@@ -163,6 +163,12 @@ def cpu_baseline_match(workload, d, res_by_prec, sample_target_s=15.0, max_patte
     idx = np.concatenate([i for i, _ in batches])
     zs = {k: np.concatenate([z[k] for _, z in batches]) for k in ("score", "n", "mirror")}
     m = len(idx)
+    # the same oracle on one thread, on the first two sampled patterns
+    sub1 = synth.subset(d, np.sort(idx_all[:2]))
+    t0 = time.perf_counter()
+    directsum.zone_scores(opl, sub1["offsets"], sub1["qx"], sub1["qy"], sub1["I"], 1)
+    one_core = 2 / (time.perf_counter() - t0)
+    log(f"{workload}: oracle on one thread, {one_core:.3f} patterns/s")
     agree = {}
     for prec, res in res_by_prec.items():
         zone = res["zone"][idx, 0]
@@ -182,7 +188,19 @@ def cpu_baseline_match(workload, d, res_by_prec, sample_target_s=15.0, max_patte
     return ({"value": m / el, "unit": "patterns/s", "cores": cores, "kind": "oracle",
              "sample": f"{m} seeded patterns of the same workload; plain-C FP64 direct-sum correlation "
                        f"over all {Z} zones x 360 bins x 2 branches (OpenMP, {cores} threads); "
-                       f"plan build excluded as on the GPU"}, agree)
+                       f"plan build excluded as on the GPU",
+             "value_one_core": one_core, "cpu_model": cpu_model()}, agree)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def cpu_baseline_refine(d, init, res, sample_target_s=15.0, max_patterns=256):
