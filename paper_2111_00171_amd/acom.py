@@ -285,11 +285,15 @@ class DiskDetector:
                                        c_void_p(out["flags"].data_ptr()), _stream(stream)), "acom_detect_disks")
         return out
 
-    def gather(self, det, out=None, stream=None):
-        """CSR Peaks from the slots of detect() (reads the total: synchronises)."""
+    def gather(self, det, out=None, stream=None, sync=True):
+        """CSR Peaks from the slots of detect().  sync=True reads the total (a
+        host synchronisation) and returns arrays of exactly that length;
+        sync=False returns arrays of the slot capacity n * max_peaks (the
+        offsets bound every row, which is all acom_match needs), so the whole
+        frames -> peaks -> match sequence runs without a host round trip."""
         n = int(det["counts"].numel())
-        total = int(det["offsets"][-1].item())
         dev = det["counts"].device
+        total = int(det["offsets"][-1].item()) if sync else n * self.max_peaks
         if out is None:
             out = tuple(torch.empty(total, dtype=torch.float32, device=dev) for _ in range(3))
         qx, qy, I = out
@@ -300,8 +304,8 @@ class DiskDetector:
                                        _stream(stream)), "acom_gather_peaks")
         return Peaks(det["offsets"], qx[:total], qy[:total], I[:total], device=dev)
 
-    def peaks(self, frames, stream=None):
-        return self.gather(self.detect(frames, stream=stream), stream=stream)
+    def peaks(self, frames, stream=None, sync=True):
+        return self.gather(self.detect(frames, stream=stream), stream=stream, sync=sync)
 
 
 class Plan:

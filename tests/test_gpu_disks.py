@@ -245,3 +245,23 @@ def test_detected_peaks_index_the_frames(acom):
     mis = np.array([metrics.misorientation_deg(om[i], d["truth"][i], G) for i in range(48)])
     print("misorientation (deg): median", np.median(mis), "frac < 2:", np.mean(mis < 2.0))
     assert np.mean(mis < 2.0) >= 0.8
+
+
+def test_peaks_without_host_sync_match_identically(acom):
+    """Capacity-sized CSR arrays (no read of the total) give the matcher the
+    same rows, so its results are bit-identical to those of exact-size arrays."""
+    N = 128
+    d, fr = _frames(N, 24, seed=1010)
+    det, _ = _detector(acom, d, N, 4.0)
+    res = det.detect(fr)
+    exact = det.gather(res)
+    cap = det.gather(res, sync=False)
+    assert cap.total_peaks == 24 * det.max_peaks >= exact.total_peaks
+    plan = helpers.gpu_plan(["fcc"], k_max=2.0, n_radial=64, n_angular=180, zone_step_deg=2.0,
+                            precisions=("fp32", "bf16"))
+    for prec in ("fp32", "bf16"):
+        a = plan.match(exact, top_k=2, precision=prec)
+        b = plan.match(cap, top_k=2, precision=prec)
+        torch.cuda.synchronize()
+        for k in ("zone", "bin", "mirror", "score", "orient"):
+            assert torch.equal(a[k], b[k]), (prec, k)
