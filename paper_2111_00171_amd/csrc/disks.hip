@@ -337,24 +337,41 @@ __global__ void __launch_bounds__(DiskShape<N>::NT) disk_detect_kernel(DiskArgs 
   constexpr int RUNS = N / PIX;
   const int y = tid % N, run = tid / N, x0 = run * PIX;
   const int slot = y * RUNS + run;
-  const int xa = max(x0, a.edge), xb = min(x0 + PIX, N - a.edge);
+  // interior pixels of the run as a bit mask (rows and columns at least `edge`
+  // from the border); edge >= 1, so the rows above and below exist
+  unsigned inmask = 0u;
+  if (y >= a.edge && y < N - a.edge) {
+    const int lo = max(x0, a.edge) - x0, hi = min(x0 + PIX, N - a.edge) - x0;
+    if (hi > lo) inmask = (hi >= 32 ? 0xFFFFFFFFu : (1u << hi) - 1u) & ~((1u << lo) - 1u);
+  }
   unsigned mask = 0u;
   float vmax = -INFINITY;
-  if (y >= a.edge && y < N - a.edge && xa < xb) {
-    // column maxima of the rows above and below, slid along x
-    float v0 = fmaxf(C(y - 1, xa - 1), C(y + 1, xa - 1)), m0 = C(y, xa - 1);
-    float v1 = fmaxf(C(y - 1, xa), C(y + 1, xa)), m1 = C(y, xa);
-    const float dy = (float)y - a.cy;
-    for (int x = xa; x < xb; ++x) {
-      const float v2 = fmaxf(C(y - 1, x + 1), C(y + 1, x + 1)), m2 = C(y, x + 1);
+  if (inmask) {
+    // fully unrolled over the run: column maxima of the rows above and below
+    // slide along x; the two reads outside the frame (x0 - 1 < 0, x0 + PIX = N)
+    // are clamped and only feed pixels outside the interior mask
+    const int xl = max(x0 - 1, 0), xr = min(x0 + PIX, N - 1);
+    float v0 = fmaxf(C(y - 1, xl), C(y + 1, xl)), m0 = C(y, xl);
+    float v1 = fmaxf(C(y - 1, x0), C(y + 1, x0)), m1 = C(y, x0);
+    const float dy2 = ((float)y - a.cy) * ((float)y - a.cy);
+#pragma unroll
+    for (int i = 0; i < PIX; ++i) {
+      const int xn = i + 1 < PIX ? x0 + i + 1 : xr;
+      const float v2 = fmaxf(C(y - 1, xn), C(y + 1, xn)), m2 = C(y, xn);
       const float nb = fmaxf(fmaxf(v0, v1), fmaxf(fmaxf(v2, m0), m2));
-      const float dx = (float)x - a.cx;
-      if (m1 > nb && dy * dy + dx * dx >= a.r2_excl) {
-        mask |= 1u << (x - x0);
+      const float dx = (float)(x0 + i) - a.cx;
+      if (m1 > nb && fmaf(dx, dx, dy2) >= a.r2_excl) {
+        mask |= 1u << i;
         vmax = fmaxf(vmax, m1);
       }
       v0 = v1; m0 = m1;
       v1 = v2; m1 = m2;
+    }
+    // pixels outside the interior never count, nor does their maximum
+    if (mask & ~inmask) {
+      mask &= inmask;
+      vmax = -INFINITY;
+      for (unsigned m = mask; m; m &= m - 1u) vmax = fmaxf(vmax, C(y, x0 + __builtin_ctz(m)));
     }
   }
 #pragma unroll

@@ -109,10 +109,17 @@ def _check_all(d, res, kw, N, frames_idx):
     return diffs, worst
 
 
-@pytest.mark.parametrize("size,n,r_excl", [(128, 40, 4.0), (64, 40, 3.0)])
-def test_detect_matches_oracle(acom, size, n, r_excl):
+@pytest.mark.parametrize("size,n,r_excl,extra,diff_frac", [
+    (128, 40, 4.0, {}, 0.25),
+    (64, 40, 3.0, {}, 0.25),
+    (128, 24, 0.0, dict(min_spacing=0, max_peaks=8, min_abs=500.0), 0.25),  # beam kept, cut at 8, absolute floor
+    # noise maxima too (about 400 candidates, 256 kept): near-equal noise values make explained
+    # differences common, so only their explanation is required
+    (128, 24, 4.0, dict(min_rel=0.0005, max_peaks=256, min_spacing=2), 1.0),
+])
+def test_detect_matches_oracle(acom, size, n, r_excl, extra, diff_frac):
     d, fr = _frames(size, n)
-    det, prm = _detector(acom, d, size, r_excl)
+    det, prm = _detector(acom, d, size, r_excl, **extra)
     res = det.detect(fr, with_pixels=True)
     torch.cuda.synchronize()
     counts = res["counts"].cpu().numpy()
@@ -120,9 +127,10 @@ def test_detect_matches_oracle(acom, size, n, r_excl):
     assert off[0] == 0 and np.array_equal(np.diff(off), counts)
     assert not res["flags"].cpu().numpy().any()
     diffs, worst = _check_all(d, res, _oracle_kw(d, prm, r_excl), size, range(n))
-    print(f"size {size}: frames with explained differences {diffs}/{n}, max |dI|/max|C| {worst:.2e}")
-    assert diffs <= n // 4
-    assert counts.mean() > 10
+    print(f"size {size} {extra}: frames with explained differences {diffs}/{n}, max |dI|/max|C| {worst:.2e}, "
+          f"mean count {counts.mean():.1f}")
+    assert diffs <= int(diff_frac * n)
+    assert counts.mean() > 7
 
 
 def test_template_spectrum_is_the_conjugate_dft(acom):
