@@ -177,7 +177,7 @@ def _check_decisions(opl, d, res, pats, top_k=1, tol=1e-5):
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16", "fp16"])
-@pytest.mark.parametrize("top_k", [1, 4])
+@pytest.mark.parametrize("top_k", [1, 4, 16])
 def test_match_small_config(acom, small, precision, top_k):
     d, opl, gpl = small
     pk = acom.Peaks.from_host(d)
