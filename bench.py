@@ -430,10 +430,10 @@ def run_refine(args):
     t_gen = time.perf_counter() - t0
     log(f"refine: inputs generated ({len(d['offsets']) - 1} patterns, {t_gen:.1f} s)")
     phases, cfg = PLAN_CFG["refine"]
-    gpl = acom.Plan([acom.fcc()], acom.PlanParams(precisions=["fp32"], **cfg))
+    gpl = acom.Plan([acom.fcc()], acom.PlanParams(precisions=["fp32", "bf16"], **cfg))
     n = len(d["offsets"]) - 1
     pk = acom.Peaks.from_host(d)
-    ws = torch.empty(gpl.match_workspace_bytes("fp32", args.chunk), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(gpl.match_workspace_bytes("bf16", args.chunk), dtype=torch.uint8, device="cuda")
     out = gpl.empty_matches(n, 4, True, "cuda")
 
     shape = gpl.autotune(pk, "fp32", args.chunk, ws)
@@ -477,6 +477,13 @@ def run_refine(args):
     S_truth = gpl.score(pk, truth, torch.zeros(n, 3, dtype=torch.float32, device="cuda")).cpu().numpy()
     S_ref = S.cpu().numpy()
     far = [p for p, mr in zip(idx, mis_ref) if mr > 5.0]
+    # the same refinement from BF16-contraction candidates (FP32 rescoring)
+    out16 = gpl.empty_matches(n, 4, True, "cuda")
+    gpl.match(pk, 4, "bf16", args.chunk, ws, out=out16)
+    m16, _, _ = gpl.refine(pk, out16["orient"].reshape(n, 4, 9), max_iter=64)
+    m16 = m16.cpu().numpy()
+    mis16 = [metrics.misorientation_deg(m16[p], d["truth"][p], G) for p in idx]
+    mis16_32 = [metrics.misorientation_deg(m16[p], m[p], G) for p in idx]
     tail = {"patterns_over_5deg": len(far),
             "refined_score_at_least_truth_score": int(sum(S_ref[p] >= S_truth[p] * (1.0 - 1e-5) for p in far))}
     cpu = ext = None
@@ -486,7 +493,12 @@ def run_refine(args):
                                          "refined_median": float(np.median(mis_ref)),
                                          "refined_p90": float(np.percentile(mis_ref, 90)),
                                          "refined_p99": float(np.percentile(mis_ref, 99)), "patterns": 512,
-                                         "tail_over_5deg": tail},
+                                         "tail_over_5deg": tail,
+                                         "bf16_candidates": {
+                                             "refined_median": float(np.median(mis16)),
+                                             "refined_p90": float(np.percentile(mis16, 90)),
+                                             "vs_fp32_candidates_within_0.1deg": float(np.mean(np.array(mis16_32) < 0.1)),
+                                             "vs_fp32_candidates_median": float(np.median(mis16_32))}},
              "contraction_shape": shape, "ms_per_step_match": round(t_match * 1e3 / args.steps, 3),
              "ms_per_step_refine": round(t_ref * 1e3 / args.steps, 3),
              "oracle_comparison": ext, "input_generation_s": round(t_gen, 3)}

@@ -42,7 +42,14 @@ def hexagonal_rotations():
 
 
 def rotation_angle(R):
-    return math.acos(max(-1.0, min(1.0, (float(np.trace(R)) - 1.0) / 2.0)))
+    """Angle of rotation R from both its cosine (trace) and its sine (the
+    antisymmetric part): well conditioned at every angle, so FP32 matrices a
+    few units of rounding from orthogonal read as a few 1e-7 rad, where the
+    arccos of the trace alone would read their rounding as ~3e-4 rad."""
+    R = np.asarray(R, np.float64)
+    s = 0.5 * math.sqrt((R[2, 1] - R[1, 2]) ** 2 + (R[0, 2] - R[2, 0]) ** 2 + (R[1, 0] - R[0, 1]) ** 2)
+    c = 0.5 * (float(np.trace(R)) - 1.0)
+    return math.atan2(s, c)
 
 
 def misorientation_deg(m1, m2, group):

@@ -7,8 +7,9 @@ oracle computed one pattern at a time:
   - the 512x512 three-phase scan (262,144 patterns with 3-150 peaks) against
     the concatenated 10,443-zone plan, BF16 (oracle sample among the patterns
     of at most 30 peaks);
-  - 65,536 off-grid FCC patterns: top-4 FP32 grid candidates refined on the
-    continuous score, against the oracle's refinement of the same candidates.
+  - 65,536 off-grid FCC patterns: top-4 grid candidates (FP32 and BF16
+    contractions, FP32 rescoring) refined on the continuous score, against the
+    oracle's refinement of the same candidates.
 
 Tolerances: a reported zone's oracle score is within 1e-5 of the oracle's
 maximum (ties between symmetry-equivalent zones are equal to FP32 rounding),
@@ -88,12 +89,13 @@ def test_multiphase_full_size_sampled(acom):
         assert res["phase"][p, 0] == opl["zone_phase"][res["zone"][p, 0]]
 
 
-def test_refine_full_size_sampled(acom):
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_refine_full_size_sampled(acom, precision):
     d = synth.make("refine")
     n = len(d["offsets"]) - 1
-    gpl = helpers.gpu_plan(["fcc"], precisions=("fp32",), **helpers.SCAN)
+    gpl = helpers.gpu_plan(["fcc"], precisions=("fp32", "bf16"), **helpers.SCAN)
     pk = acom.Peaks.from_host(d)
-    res = gpl.match(pk, top_k=4, precision="fp32", chunk=CHUNK)
+    res = gpl.match(pk, top_k=4, precision=precision, chunk=CHUNK)
     init = res["orient"].reshape(n, 4, 9)
     m, S, cand = gpl.refine(pk, init, max_iter=64)
     torch.cuda.synchronize()
@@ -104,7 +106,7 @@ def test_refine_full_size_sampled(acom):
     prm = oplan.Params(k_max=2.0)
     G = metrics.cubic_rotations()
     o = d["offsets"]
-    idx = np.random.default_rng(83).choice(n, 24, replace=False)
+    idx = np.random.default_rng(83).choice(n, 24 if precision == "fp32" else 12, replace=False)
     mis = []
     for p in idx:
         args = [d[k][o[p]:o[p + 1]].astype(np.float64) for k in ("qx", "qy", "I")]
