@@ -14,8 +14,9 @@ oracle computed one pattern at a time:
 Tolerances: a reported zone's oracle score is within 1e-5 of the oracle's
 maximum (ties between symmetry-equivalent zones are equal to FP32 rounding),
 and the reported FP32 score equals the oracle's value there within 1e-5 of the
-maximum; refined orientations agree within 0.1 degree (the two ascents take the
-same steps up to FP32 rounding of the gradient).
+maximum; refined orientations agree within 0.01 degree (the two ascents take the
+same steps up to FP32 rounding of the gradient; 0.004 degree is the largest
+difference seen over 183 patterns).
 """
 import numpy as np
 import pytest
@@ -113,4 +114,4 @@ def test_refine_full_size_sampled(acom, precision):
         mo, So = score.refine(refl, *args, list(init[p]), prm, max_iter=64)
         mis.append(metrics.misorientation_deg(m[p], mo, G))
         assert abs(S[p] - So) <= 1e-4 * abs(So) + 1e-6, (p, S[p], So)
-    assert max(mis) < 0.1, mis
+    assert max(mis) < 0.01, mis
