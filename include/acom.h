@@ -373,11 +373,15 @@ acom_status_t acom_detect_disks(const float* frames, int64_t n, const float* spe
                                 int32_t* counts, int64_t* offsets, float* slot_qx, float* slot_qy, float* slot_I,
                                 int32_t* slot_pixel, int32_t* flags, void* stream);
 
-/* Compacts the slots of acom_detect_disks into CSR peak arrays (qx, qy,
- * intensity, offsets[n] entries each, device) usable as acom_peaks_t. */
+/* Compacts the slots of acom_detect_disks (counts, offsets and slots as that
+ * call wrote them) into CSR peak arrays qx, qy, intensity (device, `capacity`
+ * entries each; offsets[n] are written, n * max_peaks always suffice) usable
+ * as acom_peaks_t with these offsets.  Entries that would land outside
+ * [0, capacity) are dropped, so inconsistent offsets never write out of
+ * bounds.  Asynchronous on stream; INVALID for bad sizes or null pointers. */
 acom_status_t acom_gather_peaks(int64_t n, int32_t max_peaks, const int32_t* counts, const int64_t* offsets,
                                 const float* slot_qx, const float* slot_qy, const float* slot_I, float* qx, float* qy,
-                                float* intensity, void* stream);
+                                float* intensity, int64_t capacity, void* stream);
 
 /* ------------------------------------------------------------- errors ---- */
 const char* acom_status_string(acom_status_t s);

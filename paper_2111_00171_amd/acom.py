@@ -97,7 +97,7 @@ def lib():
             "acom_detect_disks": [c_void_p, c_int64, c_void_p, P(_DiskParams), c_void_p, c_void_p, c_void_p, c_void_p,
                                   c_void_p, c_void_p, c_void_p, c_void_p],
             "acom_gather_peaks": [c_int64, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
-                                  c_void_p, c_void_p, c_void_p],
+                                  c_void_p, c_void_p, c_int64, c_void_p],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -301,7 +301,7 @@ class DiskDetector:
                                        c_void_p(det["offsets"].data_ptr()), c_void_p(det["qx"].data_ptr()),
                                        c_void_p(det["qy"].data_ptr()), c_void_p(det["I"].data_ptr()),
                                        c_void_p(qx.data_ptr()), c_void_p(qy.data_ptr()), c_void_p(I.data_ptr()),
-                                       _stream(stream)), "acom_gather_peaks")
+                                       min(qx.numel(), qy.numel(), I.numel()), _stream(stream)), "acom_gather_peaks")
         return Peaks(det["offsets"], qx[:total], qy[:total], I[:total], device=dev)
 
     def peaks(self, frames, stream=None, sync=True):

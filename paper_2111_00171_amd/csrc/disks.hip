@@ -483,13 +483,14 @@ __global__ void __launch_bounds__(DiskShape<N>::NT) disk_detect_kernel(DiskArgs 
 
 __global__ void gather_peaks_kernel(int64_t n, int max_peaks, const int32_t* counts, const int64_t* offsets,
                                     const float* sqx, const float* sqy, const float* sI, float* qx, float* qy,
-                                    float* I) {
+                                    float* I, int64_t capacity) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n * max_peaks) return;
   const int64_t p = g / max_peaks;
   const int t = (int)(g % max_peaks);
   if (t >= counts[p]) return;
   const int64_t o = offsets[p] + t;
+  if (o < 0 || o >= capacity) return;  // inconsistent offsets: never written outside the arrays
   qx[o] = sqx[g];
   qy[o] = sqy[g];
   I[o] = sI[g];
@@ -571,16 +572,17 @@ extern "C" acom_status_t acom_detect_disks(const float* frames, int64_t n, const
 extern "C" acom_status_t acom_gather_peaks(int64_t n, int32_t max_peaks, const int32_t* counts,
                                            const int64_t* offsets, const float* slot_qx, const float* slot_qy,
                                            const float* slot_I, float* qx, float* qy, float* intensity,
-                                           void* stream) {
+                                           int64_t capacity, void* stream) {
   if (n < 0 || n > (1 << 26)) return fail(ACOM_E_INVALID, "n must be in [0, 2^26]");
   if (max_peaks < 1 || max_peaks > kDiskMaxPeaks) return fail(ACOM_E_INVALID, "max_peaks must be in [1, 256]");
+  if (capacity < 0) return fail(ACOM_E_INVALID, "negative capacity");
   if (n == 0) return ACOM_OK;
   if (!counts || !offsets || !slot_qx || !slot_qy || !slot_I || !qx || !qy || !intensity)
     return fail(ACOM_E_INVALID, "null argument");
   const int64_t total = n * max_peaks;
   const unsigned blocks = (unsigned)((total + 255) / 256);
   gather_peaks_kernel<<<blocks, 256, 0, (hipStream_t)stream>>>(n, max_peaks, counts, offsets, slot_qx, slot_qy,
-                                                             slot_I, qx, qy, intensity);
+                                                             slot_I, qx, qy, intensity, capacity);
   ACOM_HIP(hipGetLastError());
   return ACOM_OK;
 }

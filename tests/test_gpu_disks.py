@@ -217,6 +217,27 @@ def test_gather_builds_csr_peaks(acom):
         assert np.array_equal(pk.intensity.cpu().numpy()[off[i]:off[i] + c], res["I"][i, :c].cpu().numpy())
 
 
+def test_gather_keeps_to_the_given_capacity(acom):
+    """acom_gather_peaks drops entries past the arrays' capacity (a smaller
+    output than offsets[n] asks for): the first `capacity` entries are those of
+    a full gather and nothing else is written."""
+    d, fr = _frames(64, 12)
+    det, _ = _detector(acom, d, 64, 3.0)
+    res = det.detect(fr)
+    full = det.gather(res)
+    total = full.total_peaks
+    cap = total // 2
+    guard = 64
+    bufs = tuple(torch.full((cap + guard,), -7.0, device="cuda") for _ in range(3))
+    views = tuple(b[:cap] for b in bufs)
+    det.gather(res, out=views, sync=False)
+    torch.cuda.synchronize()
+    assert total > 20
+    for b, ref in zip(bufs, (full.qx, full.qy, full.intensity)):
+        assert torch.equal(b[:cap], ref[:cap])
+        assert torch.all(b[cap:] == -7.0)
+
+
 def test_detect_full_size_sampled(acom):
     """65,536 frames of 128 x 128 in one launch (tiled from 256 distinct frames):
     every copy of a frame gives bit-identical slots, and sampled frames match
