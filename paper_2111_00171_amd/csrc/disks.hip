@@ -145,6 +145,93 @@ __device__ __forceinline__ void fft_all(float2* buf, const float2* tw) {
   static_assert(S::R1 * S::R2 == N, "two passes cover the transform");
 }
 
+// The column stage without a round trip between the transforms: forward
+// pass B of the column FFT (radix R2 over positions b + r N/R2, b < R1) leaves
+// each thread the frequencies f = b + R1 r of its sequence; it multiplies them
+// by the conjugate probe spectrum and, since the inverse transform splits as
+// x[m + R2 j] = sum_b W_N^{-bm} W_R1^{-bj} Y_b[m] with
+// Y_b[m] = sum_r X[b + R1 r] W_R2^{-rm}, takes the R2-point inverse DFT over r
+// in registers and writes Y_b[m] at position m R1 + b.  Column 0 holds
+// F0 + i F_H (the DC and Nyquist columns), whose product needs X[f] and
+// X[N - f]: its threads exchange them through `xch`.
+template <int N>
+__device__ __forceinline__ void col_forward_product_inverse1(float2* buf, const float2* tw, const float2* spec,
+                                                             float2* xch) {
+  using S = DiskShape<N>;
+  constexpr int H = N / 2, P = H + 1, R1 = S::R1, R2 = S::R2, NB = N / R2, PER = H * R1 / S::NT;
+  static_assert(H * R1 % S::NT == 0 && R1 * R2 == N, "one forward pass B per thread and butterfly");
+  const int tid = threadIdx.x;
+  float2 v[PER][R2];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int idx = tid + q * S::NT, sq = idx % H, b = idx / H;
+#pragma unroll
+    for (int r = 0; r < R2; ++r) v[q][r] = buf[(b + r * NB) * P + sq];
+#pragma unroll
+    for (int r = 1; r < R2; ++r) v[q][r] = cmul(v[q][r], tw[r * b]);
+    SmallDft<R2, false>::run(v[q]);  // v[q][r] = X[b + R1 r]
+    if (sq == 0) {
+#pragma unroll
+      for (int r = 0; r < R2; ++r) xch[b + R1 * r] = v[q][r];
+    }
+  }
+  __syncthreads();  // every load above is done, and column 0's spectrum is in xch
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int idx = tid + q * S::NT, sq = idx % H, b = idx / H;
+#pragma unroll
+    for (int r = 0; r < R2; ++r) {
+      const int f = b + R1 * r;
+      if (sq == 0) {
+        // split F0 + i F_H at f and N - f, multiply each, re-pack G0 + i G_H
+        const float2 z = v[q][r], zm = xch[(N - f) & (N - 1)];
+        const float2 f0 = make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));
+        const float2 fh = make_float2(0.5f * (z.y + zm.y), -0.5f * (z.x - zm.x));
+        const float2 g0 = cmul(f0, spec[f * (H + 1)]), gh = cmul(fh, spec[f * (H + 1) + H]);
+        v[q][r] = make_float2(g0.x - gh.y, g0.y + gh.x);
+      } else {
+        v[q][r] = cmul(v[q][r], spec[f * (H + 1) + sq]);
+      }
+    }
+    SmallDft<R2, true>::run(v[q]);  // v[q][m] = Y_b[m]
+#pragma unroll
+    for (int m = 0; m < R2; ++m) buf[(m * R1 + b) * P + sq] = v[q][m];
+  }
+  __syncthreads();
+}
+
+// Second inverse stage of the column transform: for each m, the twiddles
+// W_N^{-bm} and an R1-point inverse DFT over b give x[m + R2 j], j < R1.
+template <int N>
+__device__ __forceinline__ void col_inverse2(float2* buf, const float2* tw) {
+  using S = DiskShape<N>;
+  constexpr int H = N / 2, P = H + 1, R1 = S::R1, R2 = S::R2, PER = H * R2 / S::NT;
+  static_assert(H * R2 % S::NT == 0, "inverse butterflies must split evenly over the threads");
+  const int tid = threadIdx.x;
+  float2 v[PER][R1];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int idx = tid + q * S::NT, sq = idx % H, m = idx / H;
+#pragma unroll
+    for (int b = 0; b < R1; ++b) v[q][b] = buf[(m * R1 + b) * P + sq];
+#pragma unroll
+    for (int b = 1; b < R1; ++b) {
+      float2 w = tw[b * m];
+      w.y = -w.y;
+      v[q][b] = cmul(v[q][b], w);
+    }
+    SmallDft<R1, true>::run(v[q]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int idx = tid + q * S::NT, sq = idx % H, m = idx / H;
+#pragma unroll
+    for (int j = 0; j < R1; ++j) buf[(m + R2 * j) * P + sq] = v[q][j];
+  }
+  __syncthreads();
+}
+
 // Forward twiddles exp(-2 pi i t / N), t < N.
 template <int N>
 __device__ __forceinline__ void make_twiddles(float2* tw) {
@@ -251,6 +338,7 @@ template <int N>
 struct DiskLds {
   float2 buf[N * (N / 2 + 1)];
   float2 tw[N];
+  float2 xch[N];  // column 0's spectrum during the product
   float cand_v[kDiskMaxCand];
   int32_t cand_i[kDiskMaxCand];
   int16_t order[kDiskMaxCand];
@@ -304,27 +392,10 @@ __global__ void __launch_bounds__(DiskShape<N>::NT) disk_detect_kernel(DiskArgs 
   __syncthreads();
   fft_all<N, false>(L.buf, L.tw);
   split_rows<N>(L.buf);
-  fft_all<N, false>(L.buf, L.tw);
-  // ---- times conj(probe spectrum) / N^2
-  for (int idx = tid; idx < N * H; idx += NT) {
-    const int k = idx % H, y = idx / H;
-    if (k > 0) {
-      L.buf[y * P + k] = cmul(L.buf[y * P + k], a.spec[y * (H + 1) + k]);
-    } else if (y <= H) {
-      // packed column: F0 + i F_H at y and N - y -> G0 + i G_H
-      const int ym = (N - y) & (N - 1);
-      const float2 zy = L.buf[y * P], zm = L.buf[ym * P];
-      const float2 f0 = make_float2(0.5f * (zy.x + zm.x), 0.5f * (zy.y - zm.y));
-      const float2 fh = make_float2(0.5f * (zy.y + zm.y), -0.5f * (zy.x - zm.x));
-      const float2 f0m = make_float2(f0.x, -f0.y), fhm = make_float2(fh.x, -fh.y);  // values at N - y
-      const float2 g0 = cmul(f0, a.spec[y * (H + 1)]), gh = cmul(fh, a.spec[y * (H + 1) + H]);
-      const float2 g0m = cmul(f0m, a.spec[ym * (H + 1)]), ghm = cmul(fhm, a.spec[ym * (H + 1) + H]);
-      L.buf[y * P] = make_float2(g0.x - gh.y, g0.y + gh.x);
-      if (ym != y) L.buf[ym * P] = make_float2(g0m.x - ghm.y, g0m.y + ghm.x);
-    }
-  }
-  __syncthreads();
-  fft_all<N, true>(L.buf, L.tw);
+  // ---- column transform, product with conj(probe spectrum) / N^2, inverse
+  fft_pass<N, NT, S::R1, 1, false>(L.buf, L.tw);
+  col_forward_product_inverse1<N>(L.buf, L.tw, a.spec, L.xch);
+  col_inverse2<N>(L.buf, L.tw);
   join_rows<N>(L.buf);
   fft_all<N, true>(L.buf, L.tw);
   // C(y, x) = component (y & 1) of buf[x * P + y / 2]
