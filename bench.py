@@ -70,7 +70,8 @@ DESCR = {
                "(deletion radius 0.04 1/A), BF16 contraction, 1-degree plan, 128 x 360 bins",
     "simulate": "simulate: forward kinematical patterns of 65,536 random FCC orientations (reflections with "
                 "|g| < 2.0 1/A, kept above 1% of max |F|^2 after the excitation-error shape factor), CSR output",
-    "pipeline": "pipeline: 65,536 raw 128x128 float32 frames of FCC grains (4,096 distinct, tiled) -> Bragg disk "
+    "pipeline": "pipeline: 65,536 raw 128x128 float32 frames (a 64x64 scan of 4 FCC Voronoi grains, tiled 16 times; "
+                "the grain density of the 256x256 scan) -> Bragg disk "
                 "detection (at most 64 peaks) -> CSR peaks without a host round trip -> match against the 1-degree "
                 "plan (1081 zones, 128 x 360 bins), BF16 contraction, top-1 rescored in FP32",
     "detect": "detect: Bragg disk detection on 65,536 raw 128x128 float32 frames of FCC grains (4,096 distinct "
@@ -771,7 +772,7 @@ def run_pipeline(args):
     n, U, N = 65536, 4096, 128
     prec = "bf16"
     t0 = time.perf_counter()
-    d = synth.frames(seed=1007, n=U, size=N)
+    d = synth.frames(seed=1007, size=N, grain_map=(64, 64, 4))  # a 64 x 64 scan of 4 grains
     log(f"pipeline: {U} distinct frames generated ({time.perf_counter() - t0:.1f} s)")
     fr = torch.tensor(d["frames"], device="cuda").repeat(n // U, 1, 1).contiguous()
     c = int(d["center"][0])

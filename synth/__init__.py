@@ -33,7 +33,8 @@ Configurations (name -> recipe):
           centred at its sub-pixel position, an unscattered beam of amplitude 3000 on the
           optical axis (size/2, size/2), background 2 + N(0, 3^2) + shot noise N(0, signal);
           |q| = k_max falls (size/2 - 4) px from the axis; plus the vacuum probe image
-          (the same disk on the axis, noise-free)                    (seed 1007)
+          (the same disk on the axis, noise-free); optionally the frames of a scan of Voronoi
+          grains instead of independent orientations                 (seed 1007)
 """
 import json
 import math
@@ -243,10 +244,19 @@ def probe_disk(size, cy, cx, radius=3.5):
     return np.clip(radius + 0.5 - rho, 0.0, 1.0)
 
 
-def frames(seed=1007, n=256, size=128, k_max=2.0, per_grain=40, radius=3.5):
+def frames(seed=1007, n=256, size=128, k_max=2.0, per_grain=40, radius=3.5, grain_map=None):
+    """grain_map=(ny, nx, n_grains): the frames of an ny x nx scan whose pixels take
+    the orientation of the nearest of n_grains Voronoi seeds (n = ny * nx), as in
+    'scan'; else n Haar-random orientations."""
     rng = np.random.default_rng(seed)
     t = load_table("fcc_a4.08")
-    R = haar_rotations(rng, n)
+    if grain_map is not None:
+        ny, nx, ng = grain_map
+        lab = voronoi_labels(rng, ny, nx, ng)
+        R = haar_rotations(rng, ng)[lab]
+        n = ny * nx
+    else:
+        R = haar_rotations(rng, n)
     c = size // 2
     pix = k_max / (size / 2 - 4)
     w = int(math.ceil(radius + 1.5))
