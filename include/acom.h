@@ -367,7 +367,7 @@ acom_status_t acom_disk_template(const float* probe, int32_t size, int32_t cy0, 
  * at p*max_peaks + t, slots beyond the count untouched).  flags (n, nullable):
  * 1 when more than 1024 candidates passed the threshold, in which case the
  * first 1024 in raster order were ranked.  One workgroup per frame (about
- * 76 KiB of LDS at N = 128), no workspace.  Asynchronous on stream; host
+ * 77 KiB of LDS at N = 128), no workspace.  Asynchronous on stream; host
  * checks return INVALID (sizes, ranges, nulls, alignment, n beyond 2^26). */
 acom_status_t acom_detect_disks(const float* frames, int64_t n, const float* spectrum, const acom_disk_params_t* p,
                                 int32_t* counts, int64_t* offsets, float* slot_qx, float* slot_qy, float* slot_I,
