@@ -268,6 +268,8 @@ class DiskDetector:
 
     def detect(self, frames, with_pixels=False, stream=None):
         """Per-frame slots: dict(counts, offsets, qx, qy, I (n, max_peaks), pixel, flags)."""
+        if frames.dim() != 3 or tuple(frames.shape[1:]) != (self.size, self.size):
+            raise ValueError(f"frames must be (n, {self.size}, {self.size}), got {tuple(frames.shape)}")
         n = int(frames.shape[0])
         dev = frames.device
         out = {"counts": torch.empty(n, dtype=torch.int32, device=dev),

@@ -1,11 +1,14 @@
 """Argmax agreement of the GPU matcher with the FP64 oracle on a seeded subset of
-the 65,536-pattern scan (256 x 256 FCC, 1081 zones, 128 x 360 bins).
+the 65,536-pattern scan (256 x 256 FCC, 1081 zones, 128 x 360 bins), or with
+--workload hcp of the 256 x 256 HCP scan against the 8281-zone 6/m wedge (top-8,
+one 65,536-pattern chunk per launch as the benchmark runs it).
 
 Test infrastructure: the `compare` step calls the oracle (plain-C FP64 direct
 sum over every zone, shift and branch).  The `gpu` step runs the library only.
 
-    python -m tests.argmax_agreement gpu DECISIONS.npz
+    python -m tests.argmax_agreement gpu DECISIONS.npz [--workload scan|hcp]
     python -m tests.argmax_agreement compare DECISIONS.npz REPORT.json [--patterns 4096] [--seed 4242]
+        [--workload scan|hcp]
 
 Agreement per contraction precision, over the sampled patterns:
   - strict: the GPU's (zone, bin, mirror) is the oracle's lexicographically
@@ -29,17 +32,23 @@ sys.path.insert(0, ROOT)
 PRECISIONS = ("fp32", "bf16", "fp16")
 
 
-def run_gpu(out_path):
+WORKLOADS = {"scan": ("fcc", 1, "scan: 256x256 FCC, 1081 zones, 128 radial x 360 angular bins, top-1"),
+             "hcp": ("hcp", 8, "hcp: 256x256 HCP, 8281 zones (6/m wedge at 1 degree), 128 x 360 bins, top-8, "
+                               "65,536 patterns per launch")}
+
+
+def run_gpu(out_path, workload):
     import torch
     import synth
     from paper_2111_00171_amd import acom
     from tests import helpers
-    d = synth.make("scan")
-    gpl = helpers.gpu_plan(["fcc"], **helpers.SCAN)
+    phase, top_k, _ = WORKLOADS[workload]
+    d = synth.make(workload)
+    gpl = helpers.gpu_plan([phase], **helpers.SCAN)
     pk = acom.Peaks.from_host(d)
     res = {}
     for prec in PRECISIONS:
-        r = gpl.match(pk, top_k=1, precision=prec)
+        r = gpl.match(pk, top_k=top_k, precision=prec, chunk=65536 if workload == "hcp" else 0)
         torch.cuda.synchronize()
         for k in ("zone", "bin", "mirror", "score"):
             res[f"{prec}_{k}"] = r[k][:, 0].cpu().numpy()
@@ -47,13 +56,14 @@ def run_gpu(out_path):
     np.savez(out_path, **res)
 
 
-def run_compare(dec_path, report_path, n_sample, seed):
+def run_compare(dec_path, report_path, n_sample, seed, workload):
     import synth
     from oracle import correlate, directsum
     from tests import helpers
+    phase, _, descr = WORKLOADS[workload]
     dec = np.load(dec_path)
-    d = synth.make("scan")
-    opl = helpers.oracle_plan(["fcc"], **helpers.SCAN)
+    d = synth.make(workload)
+    opl = helpers.oracle_plan([phase], **helpers.SCAN)
     n = len(d["offsets"]) - 1
     idx = np.sort(np.random.default_rng(seed).choice(n, n_sample, replace=False))
     t0 = time.perf_counter()
@@ -71,7 +81,7 @@ def run_compare(dec_path, report_path, n_sample, seed):
     ozone = np.argmax(score, axis=1)
     srt = np.sort(score, axis=1)
     near = int(np.sum(srt[:, -2] >= best - 1e-5 * np.abs(best)))
-    report = {"workload": "scan: 256x256 FCC, 1081 zones, 128 radial x 360 angular bins, top-1",
+    report = {"workload": descr,
               "patterns": int(n_sample), "seed": int(seed), "oracle": "plain-C FP64 direct sum (oracle/directsum.c)",
               "oracle_near_ties_1e-5": near, "oracle_seconds": round(time.perf_counter() - t0, 1)}
     for prec in PRECISIONS:
@@ -108,11 +118,12 @@ def main():
     ap.add_argument("report", nargs="?")
     ap.add_argument("--patterns", type=int, default=4096)
     ap.add_argument("--seed", type=int, default=4242)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="scan")
     a = ap.parse_args()
     if a.step == "gpu":
-        run_gpu(a.decisions)
+        run_gpu(a.decisions, a.workload)
     else:
-        run_compare(a.decisions, a.report, a.patterns, a.seed)
+        run_compare(a.decisions, a.report, a.patterns, a.seed, a.workload)
 
 
 if __name__ == "__main__":

@@ -170,6 +170,8 @@ def test_detect_edge_cases(acom):
             dd.detect(fr)
     with pytest.raises(acom.AcomError):
         acom.DiskDetector(torch.zeros((48, 48), device="cuda"), (0, 0), (24, 24), 0.03)
+    with pytest.raises(ValueError):  # frames of another size than the detector's
+        det.detect(torch.zeros((2, 2 * N, 2 * N), device="cuda"))
 
 
 def test_candidate_overflow_ranks_first_1024_in_raster_order(acom):
