@@ -147,6 +147,16 @@ def _ptr(t, dtype, name):
     return c_void_p(t.data_ptr())
 
 
+def _need(t, shape, name):
+    """Device arrays handed to the library by pointer must hold what the call
+    reads: check the element count against the expected shape."""
+    if t is None:
+        return
+    import math as _m
+    if t.numel() != _m.prod(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)} ({_m.prod(shape)} elements), got {tuple(t.shape)}")
+
+
 # ------------------------------------------------------------------ inputs --
 
 def cubic_triangle():
@@ -234,6 +244,10 @@ class Peaks:
         self.intensity = torch.as_tensor(intensity, dtype=torch.float32).to(device).contiguous()
         self.n_patterns = int(self.offsets.numel()) - 1
         self.total_peaks = int(self.qx.numel())
+        if self.qy.numel() != self.total_peaks or self.intensity.numel() != self.total_peaks:
+            raise ValueError("qx, qy and intensity must have the same length")
+        if self.n_patterns < 0:
+            raise ValueError("offsets needs n_patterns + 1 entries")
 
     @classmethod
     def from_host(cls, d, device="cuda"):
@@ -474,6 +488,7 @@ class Plan:
         dev = orient.device
         counts = torch.empty(n, dtype=torch.int32, device=dev)
         offsets = torch.empty(n + 1, dtype=torch.int64, device=dev)
+        _need(phase, (n,), "phase")
         ph = _ptr(phase, torch.int32, "phase")
         st = torch.cuda.current_stream() if stream is None else stream
 
@@ -572,6 +587,9 @@ class Plan:
     # ------------------------------------------------------ score / refine
     def score(self, peaks: Peaks, base, theta, phase=None, stream=None):
         n = peaks.n_patterns
+        _need(base, (n, 9), "base")
+        _need(theta, (n, 3), "theta")
+        _need(phase, (n,), "phase")
         S = torch.empty(n, dtype=torch.float32, device=peaks.offsets.device)
         pk = peaks.c()
         _check(lib().acom_score(self._h, ctypes.byref(pk), _ptr(base, torch.float32, "base"),
@@ -581,6 +599,10 @@ class Plan:
 
     def score_grad(self, peaks: Peaks, base, theta, dS=None, phase=None, peak_grads=False, stream=None):
         n = peaks.n_patterns
+        _need(base, (n, 9), "base")
+        _need(theta, (n, 3), "theta")
+        _need(dS, (n,), "dS")
+        _need(phase, (n,), "phase")
         dev = peaks.offsets.device
         dth = torch.empty(n, 3, dtype=torch.float32, device=dev)
         dqx = torch.empty(peaks.total_peaks, dtype=torch.float32, device=dev) if peak_grads else None
@@ -597,6 +619,8 @@ class Plan:
         n = peaks.n_patterns
         dev = peaks.offsets.device
         n_cand = int(init_orient.shape[1])
+        _need(init_orient, (n, n_cand, 9), "init_orient")
+        _need(cand_phase, (n, n_cand), "cand_phase")
         out = torch.empty(n, 3, 3, dtype=torch.float32, device=dev)
         S = torch.empty(n, dtype=torch.float32, device=dev)
         cand = torch.empty(n, dtype=torch.int32, device=dev)
