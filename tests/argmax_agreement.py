@@ -65,15 +65,24 @@ def run_compare(dec_path, report_path, n_sample, seed, workload):
     d = synth.make(workload)
     opl = helpers.oracle_plan([phase], **helpers.SCAN)
     n = len(d["offsets"]) - 1
-    idx = np.sort(np.random.default_rng(seed).choice(n, n_sample, replace=False))
+    # in the random order, so that a report cut short is still a uniform sample
+    idx = np.random.default_rng(seed).choice(n, n_sample, replace=False)
     t0 = time.perf_counter()
-    best = np.zeros(n_sample)
     zsc = []
     for b0 in range(0, n_sample, 64):
         sub = synth.subset(d, idx[b0:b0 + 64])
-        zs = directsum.zone_scores(opl, sub["offsets"], sub["qx"], sub["qy"], sub["I"])
-        zsc.append(zs)
-        print(f"oracle {b0 + len(sub['offsets']) - 1}/{n_sample} patterns, {time.perf_counter() - t0:.0f} s", flush=True)
+        zsc.append(directsum.zone_scores(opl, sub["offsets"], sub["qx"], sub["qy"], sub["I"]))
+        done = b0 + len(sub["offsets"]) - 1
+        print(f"oracle {done}/{n_sample} patterns, {time.perf_counter() - t0:.0f} s", flush=True)
+        # the report so far (rewritten after every batch, so a long run can be cut short)
+        _report(dec, d, opl, idx[:done], zsc, descr, seed, n_sample, time.perf_counter() - t0, report_path)
+
+
+def _report(dec, d, opl, idx, zsc, descr, seed, n_planned, seconds, report_path):
+    import synth
+    from oracle import correlate
+    from tests import helpers
+    m = len(idx)
     score = np.concatenate([z["score"] for z in zsc])
     zn = np.concatenate([z["n"] for z in zsc])
     zm = np.concatenate([z["mirror"] for z in zsc])
@@ -81,15 +90,15 @@ def run_compare(dec_path, report_path, n_sample, seed, workload):
     ozone = np.argmax(score, axis=1)
     srt = np.sort(score, axis=1)
     near = int(np.sum(srt[:, -2] >= best - 1e-5 * np.abs(best)))
-    report = {"workload": descr,
-              "patterns": int(n_sample), "seed": int(seed), "oracle": "plain-C FP64 direct sum (oracle/directsum.c)",
-              "oracle_near_ties_1e-5": near, "oracle_seconds": round(time.perf_counter() - t0, 1)}
+    report = {"workload": descr, "patterns": int(m), "patterns_planned": int(n_planned), "seed": int(seed),
+              "oracle": "plain-C FP64 direct sum (oracle/directsum.c)",
+              "oracle_near_ties_1e-5": near, "oracle_seconds": round(seconds, 1)}
     for prec in PRECISIONS:
         gz = dec[f"{prec}_zone"][idx]
         gn = dec[f"{prec}_bin"][idx]
         gm = dec[f"{prec}_mirror"][idx]
         strict = tie5 = tie9 = 0
-        for i in range(n_sample):
+        for i in range(m):
             z = int(gz[i])
             if z < 0:
                 continue
@@ -104,9 +113,8 @@ def run_compare(dec_path, report_path, n_sample, seed, workload):
                 v = (Cm if gm[i] else C)[0, int(gn[i])]
             tie5 += v >= best[i] - 1e-5 * abs(best[i])
             tie9 += v >= best[i] - 1e-9 * abs(best[i])
-        report[prec] = {"strict": strict / n_sample, "tie_aware_1e-5": tie5 / n_sample,
-                        "tie_aware_1e-9": tie9 / n_sample}
-        print(prec, report[prec], flush=True)
+        report[prec] = {"strict": strict / m, "tie_aware_1e-5": tie5 / m, "tie_aware_1e-9": tie9 / m}
+    print({p: report[p] for p in PRECISIONS}, flush=True)
     with open(report_path, "w") as f:
         json.dump(report, f, indent=1)
 
