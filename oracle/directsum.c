@@ -1,4 +1,4 @@
-/* FP64 direct-sum correlation over many patterns (plain C, OpenMP over patterns).
+/* FP64 direct-sum correlation over many patterns (plain C, OpenMP over patterns, then zones).
  *
  * TEST INFRASTRUCTURE ONLY: part of the oracle; never linked into the product.
  *
@@ -62,62 +62,116 @@ int acom_oracle_directsum(int Z, int N, int R, const double* P, const double* q_
   if (nthreads > 0) omp_set_num_threads(nthreads);
 #endif
   int fail = 0;
+  /* 1. every pattern's image and the list of its nonzero cells (b, s, X) */
+  int* nnz = (int*)calloc((size_t)(n_pat > 0 ? n_pat : 1), sizeof(int));
+  int** cb = (int**)calloc((size_t)(n_pat > 0 ? n_pat : 1), sizeof(int*));
+  int** cs = (int**)calloc((size_t)(n_pat > 0 ? n_pat : 1), sizeof(int*));
+  double** cx = (double**)calloc((size_t)(n_pat > 0 ? n_pat : 1), sizeof(double*));
+  if (!nnz || !cb || !cs || !cx) fail = 1;
+  if (!fail) {
 #pragma omp parallel
-  {
-    double* X = (double*)malloc(sizeof(double) * (size_t)N * R);
-    int* cb = (int*)malloc(sizeof(int) * (size_t)N * R);
-    int* cs = (int*)malloc(sizeof(int) * (size_t)N * R);
-    double* cx = (double*)malloc(sizeof(double) * (size_t)N * R);
-    double* C = (double*)malloc(sizeof(double) * 2 * (size_t)N);
-    if (!X || !cb || !cs || !cx || !C) {
+    {
+      double* X = (double*)malloc(sizeof(double) * (size_t)N * R);
+      if (!X) {
 #pragma omp atomic write
-      fail = 1;
-    } else {
+        fail = 1;
+      } else {
 #pragma omp for schedule(dynamic, 1)
-      for (int p = 0; p < n_pat; ++p) {
-        polar_image(N, R, q_s, (int)offsets[p], (int)offsets[p + 1], qx, qy, I, delta, gamma,
-                    omega, kind, sigma, X);
-        int J = 0;
-        for (int a = 0; a < N; ++a)
-          for (int s = 0; s < R; ++s)
-            if (X[(size_t)a * R + s] != 0.0) {
-              cb[J] = a;
-              cs[J] = s;
-              cx[J] = X[(size_t)a * R + s];
-              ++J;
-            }
-        for (int z = 0; z < Z; ++z) {
-          const double* Pz = P + (size_t)z * N * R;
-          for (int n = 0; n < 2 * N; ++n) C[n] = 0.0;
-          for (int j = 0; j < J; ++j) {
-            const int b = cb[j], s = cs[j];
-            const double x = cx[j];
-            for (int n = 0; n < N; ++n) {
-              int i0 = ((b - n) % N + N) % N;
-              int i1 = ((-b - n) % N + 2 * N) % N;
-              C[2 * n] += x * Pz[(size_t)i0 * R + s];
-              C[2 * n + 1] += x * Pz[(size_t)i1 * R + s];
-            }
+        for (int p = 0; p < n_pat; ++p) {
+          polar_image(N, R, q_s, (int)offsets[p], (int)offsets[p + 1], qx, qy, I, delta, gamma,
+                      omega, kind, sigma, X);
+          int J = 0;
+          for (size_t i = 0; i < (size_t)N * R; ++i) J += X[i] != 0.0;
+          cb[p] = (int*)malloc(sizeof(int) * (size_t)(J > 0 ? J : 1));
+          cs[p] = (int*)malloc(sizeof(int) * (size_t)(J > 0 ? J : 1));
+          cx[p] = (double*)malloc(sizeof(double) * (size_t)(J > 0 ? J : 1));
+          if (!cb[p] || !cs[p] || !cx[p]) {
+#pragma omp atomic write
+            fail = 1;
+            continue;
           }
-          int best = 0;
-          for (int i = 1; i < 2 * N; ++i)
-            if (C[i] > C[best]) best = i;
-          const int n = best / 2, mi = best % 2;
-          const size_t o = (size_t)p * Z + z;
-          zscore[o] = C[best];
-          zn[o] = n;
-          zmir[o] = mi;
-          zcm1[o] = C[2 * ((n - 1 + N) % N) + mi];
-          zcp1[o] = C[2 * ((n + 1) % N) + mi];
+          J = 0;
+          for (int a = 0; a < N; ++a)
+            for (int s = 0; s < R; ++s)
+              if (X[(size_t)a * R + s] != 0.0) {
+                cb[p][J] = a;
+                cs[p][J] = s;
+                cx[p][J] = X[(size_t)a * R + s];
+                ++J;
+              }
+          nnz[p] = J;
         }
       }
+      free(X);
     }
-    free(X);
-    free(cb);
-    free(cs);
-    free(cx);
-    free(C);
   }
+  /* 2. every (zone, pattern): the two correlograms as direct sums over the
+   * pattern's nonzero cells in raster order, then the best (n, branch).  The
+   * zone's plan is read through a copy stored [s][a], so that the sum over
+   * shifts n walks one contiguous row; the products and their order are those
+   * of the definition above. */
+  if (!fail) {
+#pragma omp parallel
+    {
+      double* PT = (double*)malloc(sizeof(double) * (size_t)N * R);
+      double* C0 = (double*)malloc(sizeof(double) * (size_t)N);
+      double* C1 = (double*)malloc(sizeof(double) * (size_t)N);
+      if (!PT || !C0 || !C1) {
+#pragma omp atomic write
+        fail = 1;
+      } else {
+#pragma omp for schedule(dynamic, 1)
+        for (int z = 0; z < Z; ++z) {
+          const double* Pz = P + (size_t)z * N * R;
+          for (int a = 0; a < N; ++a)
+            for (int s = 0; s < R; ++s) PT[(size_t)s * N + a] = Pz[(size_t)a * R + s];
+          for (int p = 0; p < n_pat; ++p) {
+            for (int n = 0; n < N; ++n) C0[n] = C1[n] = 0.0;
+            for (int j = 0; j < nnz[p]; ++j) {
+              const int b = cb[p][j];
+              const double x = cx[p][j];
+              const double* row = PT + (size_t)cs[p][j] * N;
+              int i0 = b;                 /* (b - n) mod N at n = 0 */
+              int i1 = (N - b) % N;       /* (-b - n) mod N at n = 0 */
+              for (int n = 0; n < N; ++n) {
+                C0[n] += x * row[i0];
+                C1[n] += x * row[i1];
+                i0 = i0 == 0 ? N - 1 : i0 - 1;
+                i1 = i1 == 0 ? N - 1 : i1 - 1;
+              }
+            }
+            /* best over (n, branch): the first maximum in the order n, then branch */
+            int bn = 0, bm = 0;
+            double bv = C0[0];
+            for (int n = 0; n < N; ++n) {
+              if (C0[n] > bv) { bv = C0[n]; bn = n; bm = 0; }
+              if (C1[n] > bv) { bv = C1[n]; bn = n; bm = 1; }
+            }
+            const double* Cb = bm ? C1 : C0;
+            const size_t o = (size_t)p * Z + z;
+            zscore[o] = bv;
+            zn[o] = bn;
+            zmir[o] = bm;
+            zcm1[o] = Cb[(bn - 1 + N) % N];
+            zcp1[o] = Cb[(bn + 1) % N];
+          }
+        }
+      }
+      free(PT);
+      free(C0);
+      free(C1);
+    }
+  }
+  if (cb)
+    for (int p = 0; p < n_pat; ++p) free(cb[p]);
+  if (cs)
+    for (int p = 0; p < n_pat; ++p) free(cs[p]);
+  if (cx)
+    for (int p = 0; p < n_pat; ++p) free(cx[p]);
+  free(cb);
+  free(cs);
+  free(cx);
+  free(nnz);
   return fail ? -1 : 0;
 }
 

@@ -59,6 +59,33 @@ def test_hcp_structure_factor_classes():
     assert not np.any(expect == 0)
 
 
+def test_structure_factor_with_scattering_factor_table():
+    """Two species on a simple cubic cell (a = 3 A: species 0 at the origin,
+    species 1 at the body centre), with a caller's f table of knots 0, 1, 2 1/A:
+    F_hkl = f0(|g|) + (-1)^(h+k+l) f1(|g|), each f the straight line between its
+    neighbouring knots, written out by hand here."""
+    lat = np.eye(3) * 3.0
+    r = crystal.reflections(lat, [[0, 0, 0], [0.5, 0.5, 0.5]], 1.5, species=[0, 1],
+                            f_q=[0.0, 1.0, 2.0], f_tab=[[2.0, 1.0, 0.5], [1.0, 0.8, 0.2]])
+
+    def f0(q):
+        return 2.0 - q if q <= 1.0 else 1.0 - 0.5 * (q - 1.0)
+
+    def f1(q):
+        return 1.0 - 0.2 * q if q <= 1.0 else 0.8 - 0.6 * (q - 1.0)
+
+    n_expected = sum(1 for h in range(-5, 6) for k in range(-5, 6) for l in range(-5, 6)
+                     if 0 < math.sqrt(h * h + k * k + l * l) / 3.0 < 1.5)
+    assert len(r["q"]) == n_expected
+    for (h, k, l), q, F in zip(r["hkl"], r["q"], r["F"]):
+        assert abs(q - math.sqrt(h * h + k * k + l * l) / 3.0) < 1e-14
+        expect = f0(q) + (-1) ** int(h + k + l) * f1(q)
+        assert abs(F - expect) < 1e-12, (h, k, l, F, expect)
+    # (1,0,0): 2 - 1/3 - (1 - 0.2/3); (2,2,2): |g| = 1.1547, both on the second segment
+    i100 = [i for i, t in enumerate(r["hkl"]) if tuple(t) == (1, 0, 0)][0]
+    assert abs(r["F"][i100] - (5.0 / 3.0 - (1.0 - 0.2 / 3.0))) < 1e-12
+
+
 def test_reflection_set_equals_wider_brute_force():
     lat = np.eye(3) * A_FCC
     r = crystal.reflections(lat, [[0, 0, 0]], 1.5)   # primitive cubic: no extinctions
@@ -164,6 +191,30 @@ def test_image_single_peak_closed_form():
         assert abs(X[(a0 + j) % 360, s0] - expect) < 1e-12
     far = np.abs(q_s - q) >= prm.delta
     assert np.all(X[:, far] == 0)
+
+
+def test_image_single_peak_gaussian_closed_form():
+    """Gaussian kernel option: a peak at the centre of cell (a0, s0) gives w there,
+    w exp(-d^2 / 2 sigma^2) at the cells whose distance d (radial offset, arc
+    length of the angular offset at q_s, or both) is below 3 sigma, and 0 beyond."""
+    sigma = 0.03
+    prm = plan.Params(k_max=2.0, n_radial=64, n_angular=360, kind=plan.GAUSS, sigma=sigma)
+    q_s = plan.radial_axis(plan.UNIFORM, 2.0, 64)
+    s0, a0 = 40, 101
+    q, g, I = q_s[s0], 2 * math.pi * a0 / 360, 4.0
+    X = image.polar_image([q * math.cos(g)], [q * math.sin(g)], [I], q_s, 360, prm)
+    w = q * 2.0
+    assert abs(X[a0, s0] - w) < 1e-12 * w
+    dphi = 2 * math.pi / 360
+    dq = 2.0 / 64
+    for i in range(-4, 5):
+        for j in range(-12, 13):
+            d = math.sqrt((i * dq) ** 2 + (j * dphi * q_s[s0 + i]) ** 2)
+            expect = w * math.exp(-d * d / (2 * sigma * sigma)) if d < 3 * sigma else 0.0
+            assert abs(X[(a0 + j) % 360, s0 + i] - expect) < 1e-12 * w, (i, j)
+    far = np.abs(q_s - q) >= 3 * sigma
+    assert np.all(X[:, far] == 0)
+    assert X[(a0 + 180) % 360, s0] == 0
 
 
 # ------------------------------------------------------------ correlation ----
@@ -283,8 +334,13 @@ def test_spectral_bound_is_an_upper_bound_and_tight_for_a_spike():
     assert abs(correlate.spectral_bound(P1, X1)[0] - max(C1.max(), Cm1.max())) < 1e-12
 
 
-def test_c_direct_sum_matches_numpy_oracle():
-    pl = _small_plan()
+@pytest.mark.parametrize("kind", [plan.CONE, plan.GAUSS])
+def test_c_direct_sum_matches_numpy_oracle(kind):
+    if kind == plan.CONE:
+        pl = _small_plan()
+    else:
+        prm = plan.Params(k_max=1.2, n_radial=32, n_angular=90, zone_step_deg=5.0, kind=plan.GAUSS)
+        pl = plan.build([fcc_phase()], prm)
     d = synth.make("small")
     zs = directsum.zone_scores(pl, d["offsets"][:9], d["qx"], d["qy"], d["I"], nthreads=2)
     for p in range(8):
@@ -294,7 +350,18 @@ def test_c_direct_sum_matches_numpy_oracle():
         C, Cm = correlate.correlate_direct(pl["P"], X)
         sc, n, mi = correlate.zone_best(C, Cm)
         assert np.abs(zs["score"][p] - sc).max() < 1e-12 * sc.max()
-        assert np.array_equal(zs["n"][p], n) and np.array_equal(zs["mirror"][p], mi)
+        # the chosen (n, branch) is NumPy's, or one tied with it up to FP64 summation order
+        both = np.stack([C, Cm], axis=2)
+        zi = np.arange(len(sc))
+        got = both[zi, zs["n"][p], zs["mirror"][p]]
+        assert np.all(got >= sc - 1e-12 * sc.max())
+        same = (zs["n"][p] == n) & (zs["mirror"][p] == mi)
+        assert same.mean() > 0.9 if kind == plan.GAUSS else same.all()
+        # the neighbours reported for the parabola are the correlogram's own
+        br = np.where(zs["mirror"][p][:, None] == 1, Cm, C)
+        N = C.shape[1]
+        assert np.abs(zs["cm1"][p] - br[zi, (zs["n"][p] - 1) % N]).max() < 1e-12 * sc.max()
+        assert np.abs(zs["cp1"][p] - br[zi, (zs["n"][p] + 1) % N]).max() < 1e-12 * sc.max()
 
 
 # ------------------------------------------------------------------ score ----
