@@ -195,9 +195,10 @@ acom_status_t acom_match_multi(acom_plan_t plan, const acom_peaks_t* peaks, int3
  * radii per LDS step for BF16/FP16 operands, block order) for `precision` on
  * this plan: runs the polar pass on the first chunk of `peaks`, times every
  * candidate shape of the contraction on it with HIP events (one warm-up and two
- * timed launches each), and stores the fastest in the plan, where acom_match
- * then uses it.  Results of acom_match do not depend on the shape.  Synchronous;
- * must not run while another call uses the plan.  `workspace` as for
+ * timed launches each), and keeps the fastest in the calling host thread's
+ * launch settings (see acom_set_tuning), where that thread's later calls for
+ * this precision use it.  The plan is not modified.  Results of acom_match do
+ * not depend on the shape.  Synchronous.  `workspace` as for
  * acom_match with the same `chunk`.  shape [host, 3] (tile: 0 = 64 x 64,
  * 1 = large, 3 = 128 x 128 two-group schedule (16-bit operands); radii per LDS step, 16 or 32 for FP32 operands and 32, 64 or 128
  * for 16-bit ones; order) and ms [host] (one launch of the fastest shape) may
@@ -234,10 +235,11 @@ acom_status_t acom_bound(acom_plan_t plan, const acom_peaks_t* peaks, int32_t pr
  *   v_g = |g|^gamma (|F_g|^2 exp(-s_g^2 / 2 sigma_exc^2))^(omega/2)
  *         (Eq. excitation error, Eq. shape_gaussian),
  *   K_mg = exp(-|q_m - (x_g, y_g)|^2 / (2 (delta/2)^2)), (x_g, y_g, z_g) = m^T g.
- * For omega > 0, reflections whose |s_g| at base_orient is at least
+ * For omega > 0, reflections whose |s_g| at the scored orientation is at least
  * 10 sigma_exc / sqrt(omega) + 0.035 1/A are left out (v_g below exp(-25) of its
- * peak value even after a 1 degree rotation); at most 1024 reflections per phase
- * take part.
+ * peak value even after a 1 degree rotation).  At most 1024 reflections may take
+ * part: a pattern with more gets S = NaN (and NaN gradients), never a truncated
+ * sum.  A phase index outside the plan or a malformed CSR row also gives NaN.
  * base_orient n x 9, theta n x 3, phase n (int32) or NULL (phase 0); S n. */
 acom_status_t acom_score(acom_plan_t plan, const acom_peaks_t* peaks, const float* base_orient,
                          const float* theta, const int32_t* phase, float* S, void* stream);
@@ -252,8 +254,13 @@ acom_status_t acom_score_grad(acom_plan_t plan, const acom_peaks_t* peaks, const
  * (init_orient n x n_cand x 9, cand_phase n x n_cand or NULL): per candidate,
  * steps of length l along grad S / |grad S| from the current orientation (l starts
  * at 0.25 deg, doubles after an improving step up to 0.5 deg, halves otherwise),
- * at most max_iter trials or until l < 1e-4 deg; the best candidate wins.
- * out_orient n x 9, out_score n, out_cand n (index of the winner) or NULL. */
+ * at most max_iter trials or until l < 1e-4 deg; the best candidate wins.  The
+ * reflections taking part (as for acom_score) are chosen at the start
+ * orientation and again after every accepted step.
+ * out_orient n x 9, out_score n, out_cand n (index of the winner) or NULL.
+ * A candidate with an invalid phase or non-finite matrix is skipped (out_cand
+ * = -1 and score 0 when none is left); a candidate whose reflection set exceeds
+ * 1024 makes the pattern an error: out_cand = -2, out_score = NaN. */
 acom_status_t acom_refine(acom_plan_t plan, const acom_peaks_t* peaks, int32_t n_cand,
                           const float* init_orient, const int32_t* cand_phase, int32_t max_iter,
                           float* out_orient, float* out_score, int32_t* out_cand, void* stream);
@@ -261,7 +268,8 @@ acom_status_t acom_refine(acom_plan_t plan, const acom_peaks_t* peaks, int32_t n
 /* ------------------------------------------------------------ profile ---- */
 
 /* Kernel timing with HIP events recorded on the launch stream around every
- * kernel that acom_match launches (measurement support; not thread-safe).
+ * kernel that acom_match launches (measurement support).  The records belong to
+ * the calling host thread: they cover that thread's launches only.
  * acom_profile_begin creates `capacity` event pairs and starts recording;
  * acom_profile_read synchronises the recorded events and returns, for kernel
  * kind 0 (polar image + FFT), 1 (bound contraction) or 2 (exact pass), the
@@ -272,7 +280,9 @@ acom_status_t acom_profile_begin(int32_t capacity);
 acom_status_t acom_profile_read(int32_t kind, double* total_ms, int32_t* launches);
 acom_status_t acom_profile_end(void);
 
-/* Launch-shape tuning (process-wide; results do not depend on it):
+/* Launch-shape tuning of the calling host thread (results do not depend on it;
+ * every thread starts from the defaults below, so calls made from different
+ * threads on different streams share no mutable state):
  * key 0: contraction block order, 0 = pattern tiles fastest,
  *        1 = zone tiles fastest with the tiles of one pattern group on one XCD (default);
  * key 1: radii staged per LDS step by the BF16/FP16 contraction: 32, 64 (default), 128 (the largest dividing Rp is used);
@@ -287,8 +297,11 @@ acom_status_t acom_profile_end(void);
  *        (exact: those terms are zeros; default), 0 = it runs over all radii;
  * key 6: radii staged per LDS step by the FP32 contraction: 16 (default) or 32;
  * key 7: radial columns per pass of the polar (splat + FFT) kernel: 16 or 32 (default; 16 when
- *        Rp is not a multiple of 32).  The image and spectrum are bit-identical either way.
- * A shape stored in the plan by acom_autotune takes precedence over keys 0, 1, 4 and 6. */
+ *        Rp is not a multiple of 32).  The image and spectrum are bit-identical either way;
+ * key 8: largest zone count (0 .. 32768, default 16384) whose per-pattern bound row the exact
+ *        pass copies to LDS; larger plans select zones in place in the workspace.
+ * A shape found by acom_autotune takes precedence over keys 0, 1, 4 and 6 for its precision
+ * until one of those keys is set again. */
 acom_status_t acom_set_tuning(int32_t key, int32_t value);
 
 /* Fiber-texture zone sets (the paper's alternative orientation plans: zone

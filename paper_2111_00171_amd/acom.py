@@ -513,7 +513,8 @@ class Plan:
 
     def autotune(self, peaks: Peaks, precision="fp32", chunk=0, workspace=None, stream=None):
         """Time every contraction launch shape on the first chunk of `peaks` and
-        keep the fastest for `precision` in this plan (acom_autotune)."""
+        keep the fastest for `precision` in the calling thread's launch settings
+        (acom_autotune; the plan itself is not modified)."""
         dev = peaks.offsets.device
         if workspace is None:
             workspace = torch.empty(self.match_workspace_bytes(precision, chunk), dtype=torch.uint8, device=dev)
@@ -634,13 +635,14 @@ class Plan:
 
 KERNEL_KINDS = {"polar": 0, "bound": 1, "exact": 2}
 TUNING_KEYS = {"bound_order": 0, "bound_kch16": 1, "exact_xcd": 2, "polar_xcd": 3, "bound_tile": 4, "skip_zero_radii": 5,
-               "bound_kch32": 6, "polar_cols": 7}
+               "bound_kch32": 6, "polar_cols": 7, "exact_u_lds_max": 8}
 
 
 def set_tuning(**kw):
-    """Launch-shape knobs (results do not depend on them): bound_order (0/1),
-    bound_kch16 (32/64/128), exact_xcd (0/1), polar_xcd (0/1), bound_tile (0/1/2/3),
-    skip_zero_radii (0/1), bound_kch32 (16/32), polar_cols (16/32)."""
+    """Launch-shape knobs of the calling thread (results do not depend on them):
+    bound_order (0/1), bound_kch16 (32/64/128), exact_xcd (0/1), polar_xcd (0/1),
+    bound_tile (0/1/2/3), skip_zero_radii (0/1), bound_kch32 (16/32), polar_cols
+    (16/32), exact_u_lds_max (zones whose bound row the exact pass keeps in LDS)."""
     for k, v in kw.items():
         _check(lib().acom_set_tuning(TUNING_KEYS[k], int(v)), "acom_set_tuning")
 
@@ -665,17 +667,33 @@ def profile_end():
 
 
 class ContinuousScore(torch.autograd.Function):
-    """S(theta) = acom_score(base Exp(theta)); backward through acom_score_grad."""
+    """S = acom_score at base Exp(theta) for the peaks at positions (qx, qy);
+    backward through acom_score_grad, which gives dS/dtheta and, when qx or qy
+    requires a gradient, dS/dqx and dS/dqy per peak.
+
+    S = ContinuousScore.apply(theta, qx, qy, plan, peaks, base[, phase]):
+    theta (n, 3), qx and qy (total_peaks,) float32 device tensors (the peak
+    positions; peaks supplies the CSR offsets and the intensities, its own qx /
+    qy are not read), base (n, 9)."""
 
     @staticmethod
-    def forward(ctx, theta, plan, peaks, base, phase=None):
+    def forward(ctx, theta, qx, qy, plan, peaks, base, phase=None):
         theta_c = theta.detach().contiguous()
-        ctx.plan, ctx.peaks, ctx.base, ctx.phase = plan, peaks, base, phase
+        pk = Peaks.__new__(Peaks)
+        pk.offsets, pk.intensity = peaks.offsets, peaks.intensity
+        pk.qx, pk.qy = qx.detach().contiguous(), qy.detach().contiguous()
+        pk.n_patterns, pk.total_peaks = peaks.n_patterns, peaks.total_peaks
+        if pk.qx.numel() != pk.total_peaks or pk.qy.numel() != pk.total_peaks:
+            raise ValueError("qx and qy must have one entry per peak")
+        ctx.plan, ctx.peaks, ctx.base, ctx.phase = plan, pk, base, phase
         ctx.save_for_backward(theta_c)
-        return plan.score(peaks, base, theta_c, phase)
+        return plan.score(pk, base, theta_c, phase)
 
     @staticmethod
     def backward(ctx, gS):
         (theta_c,) = ctx.saved_tensors
-        dth, _, _ = ctx.plan.score_grad(ctx.peaks, ctx.base, theta_c, gS.contiguous().float(), ctx.phase)
-        return dth, None, None, None, None
+        need_q = ctx.needs_input_grad[1] or ctx.needs_input_grad[2]
+        dth, dqx, dqy = ctx.plan.score_grad(ctx.peaks, ctx.base, theta_c, gS.contiguous().float(), ctx.phase,
+                                            peak_grads=need_q)
+        return (dth if ctx.needs_input_grad[0] else None, dqx if ctx.needs_input_grad[1] else None,
+                dqy if ctx.needs_input_grad[2] else None, None, None, None, None)

@@ -38,7 +38,6 @@ constexpr int kSChunk = 32;
 constexpr int kMaxRadices = 12;
 constexpr int kMaxAngular = 1024;
 constexpr int kMaxTopK = 16;
-constexpr int kMaxZonesExact = 16384;  // per-pattern bound row held in LDS by the exact pass
 
 // Mixed-radix factorisation of the angular length (radices 8, 9, 4, 2, 3, 5, greedily).
 struct Radices {
@@ -65,7 +64,7 @@ struct PlanDev {
   std::vector<int32_t> zone_phase;        // Z
   std::vector<int32_t> refl_off;          // n_phases + 1
   // device arrays
-  float* d_qs = nullptr;        // Rp (padding columns carry q = -1: no peak reaches them)
+  float* d_qs = nullptr;        // 2 Rp: q_s rounded to FP32 (padding columns -1: no peak reaches them), then q_s - that
   float2* d_tw = nullptr;       // N twiddles (cos, sin)(2 pi m / N)
   int32_t* d_rev = nullptr;     // N: digit-reversed position of index n (in-place FFT input order)
   float* d_M12 = nullptr;       // Z x 9 (row-major, float)
@@ -77,13 +76,11 @@ struct PlanDev {
   uint16_t* d_PR16[3] = {nullptr, nullptr, nullptr};  // tile-major 16-bit copies (index = acom_precision_t)
   uint16_t* d_PI16[3] = {nullptr, nullptr, nullptr};
   double* d_Pang = nullptr;     // optional FP64 angular plan Z x N x R
-  // contraction launch shape per operand precision (index = acom_precision_t),
-  // set by acom_autotune; unset -> the library's rules
+  // a contraction launch shape (block tile, radii per LDS step, block order)
   struct BoundShape {
     int set = 0, tile = 0, kch = 64, order = 1;
     float ms = 0.0f;
   };
-  BoundShape tuned[3];
   // reflections for the continuous score (all phases concatenated)
   int G = 0;
   float4* d_refl = nullptr;     // (gx, gy, gz, |g|)

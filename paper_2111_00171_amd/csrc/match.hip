@@ -23,6 +23,8 @@
 
 #include <climits>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -151,9 +153,11 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
   float* pf = reinterpret_cast<float*>(pac + PC);
   float* pq = pf + PC;
   float* pw = pq + PC;
-  int* plist = reinterpret_cast<int*>(pw + PC);  // cached peaks reaching the current tile
+  float* pql = pw + PC;  // q_m - pq (the radius as an FP32 pair)
+  int* plist = reinterpret_cast<int*>(pql + PC);  // cached peaks reaching the current tile
   float* sqs = reinterpret_cast<float*>(plist + PC);  // q_s of every column (-1 beyond R)
-  uint32_t* scmw = reinterpret_cast<uint32_t*>(sqs + a.Rp);  // [16-column tile][wave] column masks
+  float* sqsl = sqs + a.Rp;                           // q_s - sqs
+  uint32_t* scmw = reinterpret_cast<uint32_t*>(sqsl + a.Rp);  // [16-column tile][wave] column masks
   __shared__ int s_bad, s_nlist;
   __shared__ float s_red[kThreads / 64];
   __shared__ double s_red64[kThreads / 64];
@@ -170,8 +174,13 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
     tw[i] = a.tw[i];
     rev[i] = a.rev[i];
   }
-  for (int i = tid; i < a.Rp; i += kThreads) sqs[i] = i < a.R ? a.qs[i] : -1.0f;
+  for (int i = tid; i < a.Rp; i += kThreads) {
+    sqs[i] = i < a.R ? a.qs[i] : -1.0f;
+    sqsl[i] = i < a.R ? a.qs[a.Rp + i] : 0.0f;
+  }
   if (tid == 0) s_bad = bad_range ? 1 : 0;
+  // the flag is initialised before any wave's prep() may raise it
+  __syncthreads();
 
   const double inv_dphi = N / 6.283185307179586476925286766559;
   const float dphi = (float)(6.283185307179586476925286766559 / N);
@@ -196,7 +205,9 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
       const double tr = floor(t + 0.5);
       pac[tid] = (int)tr;
       pf[tid] = (float)(t - tr);
-      pq[tid] = (float)q;
+      const float qh = (float)q;
+      pq[tid] = qh;
+      pql[tid] = (float)(q - (double)qh);
       const float w = bad ? 0.0f : powe((float)q, a.gamma) * powe(in, 0.5f * a.omega);
       pw[tid] = w;
       if (count) wsum += w;
@@ -220,6 +231,7 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
     const float qlo = col0 < a.R ? sqs[col0] : -1.0f;
     const float qhi = col0 < a.R ? sqs[cl] : -1.0f;
     const float qs = sqs[col0 + c];
+    const float qsl = sqsl[col0 + c];
     const float dqs = dphi * qs;
     int hw = N;  // half-width of the angular window of this column
     if (qs > 0.0f) {
@@ -233,13 +245,14 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
       const int cnt = (int)min((int64_t)PC, m1 - c0);
       if (!single) prep(c0, cnt, tile == 0);
       // wave 0 lists, in peak order, the cached peaks within reach of [qlo, qhi]
-      // (the same float comparisons as the per-column test below, so no reached
-      // cell is dropped)
+      // (a reach widened by 1e-5 1/A over the per-column test below, which adds
+      // the low parts of the radii, so no reached cell is dropped)
       if (tid < 64) {
         int base = 0;
+        const float rl = a.rk + 1e-5f;
         for (int j0 = 0; j0 < cnt; j0 += 64) {
           const int j = j0 + tid;
-          const bool hit = qlo >= 0.0f && j < cnt && pw[j] != 0.0f && (pq[j] - qhi < a.rk) && (qlo - pq[j] < a.rk);
+          const bool hit = qlo >= 0.0f && j < cnt && pw[j] != 0.0f && (pq[j] - qhi < rl) && (qlo - pq[j] < rl);
           const unsigned long long m = __ballot(hit);
           if (hit) plist[base + __popcll(m & ((1ull << tid) - 1ull))] = j;
           base += __popcll(m);
@@ -252,7 +265,9 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
       if (qs >= 0.0f) {
         for (int l = 0; l < nl; ++l) {
           const int j = plist[l];
-          const float dq = pq[j] - qs;
+          // q_m - q_s: the high parts are close, so their difference is exact
+          // (Sterbenz) where it matters, and the low parts restore the rest
+          const float dq = (pq[j] - qs) + (pql[j] - qsl);
           const float w = pw[j];
           if (fabsf(dq) >= a.rk) continue;
           const int ac = pac[j];
@@ -954,8 +969,9 @@ struct ExactArgs {
   const int* rev;
   const float *xr, *xi;     // tile-major over the chunk's patterns (FP32)
   const float *pr, *pi;     // zone-major [Z][Nk][Rp] (FP32)
-  const float* U;
+  float* U;                 // bound rows (workspace); updated in place when u_lds == 0
   int ldU;
+  int u_lds;                // 1: the pattern's bound row is copied to LDS; 0: selected in place in U
   const float* xnorm2;
   const uint32_t* cmask;    // per pattern and radial tile: columns holding a nonzero X
   int ntiles;
@@ -1121,8 +1137,8 @@ __global__ void __launch_bounds__(kThreads) exact_kernel(ExactArgs a) {
   float2* H0 = reinterpret_cast<float2*>(smem_raw);
   float2* tw = H0 + kBatch * a.N;
   int* rev = reinterpret_cast<int*>(tw + a.N);
-  float* Ul = reinterpret_cast<float*>(rev + a.N);
-  int* groups = reinterpret_cast<int*>(Ul + a.Z);  // Rp / 4 entries
+  float* Us = reinterpret_cast<float*>(rev + a.N);  // the bound row in LDS (u_lds), else nothing
+  int* groups = reinterpret_cast<int*>(Us + (a.u_lds ? a.Z : 0));  // Rp / 4 entries
   __shared__ int s_ng;
   __shared__ float sv[4];
   __shared__ int si[4];
@@ -1208,7 +1224,14 @@ __global__ void __launch_bounds__(kThreads) exact_kernel(ExactArgs a) {
     return;
   }
   const float margin_abs = a.eps_abs * sqrtf(a.xnorm2[p]);
-  for (int z = tid; z < a.Z; z += kThreads) Ul[z] = a.U[(size_t)p * a.ldU + z];
+  // the bound row: copied to LDS when it fits, else selected in place in the
+  // workspace (thread 0 marks taken zones; the barriers of block_argmax order
+  // those global writes for the whole workgroup)
+  float* Ul = a.U + (size_t)p * a.ldU;
+  if (a.u_lds) {
+    for (int z = tid; z < a.Z; z += kThreads) Us[z] = Ul[z];
+    Ul = Us;
+  }
   active_groups(a, p, groups, &s_ng);
   if (tid == 0) {
     s_cnt = 0;
@@ -1497,8 +1520,13 @@ struct Tuning {
   int skip_zero_radii = 1;  // contraction: skip the leading radii where the plan is zero in every zone
   int bound_kch32 = 16;   // radii per LDS step of the FP32 contraction (16 or 32)
   int polar_cols = 32;    // radial columns per pass of the polar kernel (16 or 32)
+  int exact_u_lds_max = 16384;  // largest zone count whose bound row the exact pass copies to LDS
+  PlanDev::BoundShape tuned[3];  // contraction shape per operand precision found by acom_autotune
 };
-Tuning g_tune;
+// Launch-shape settings of the calling host thread: plans stay immutable after
+// acom_build_plan, and calls made from different threads (on different
+// streams) never share mutable library state.
+thread_local Tuning g_tune;
 
 // ---------------------------------------------------------- profiling ----
 
@@ -1508,7 +1536,7 @@ struct Profiler {
   std::vector<int> kind;
   int used = 0;
 };
-Profiler g_prof;
+thread_local Profiler g_prof;  // records the calling thread's launches only
 
 struct ProfScope {
   int slot = -1;
@@ -1559,17 +1587,25 @@ WsLayout layout(const PlanDev& d, bool lowp, int Pc) {
 
 template <int NC>
 size_t polar_lds(const PlanDev& d) {
-  return (size_t)(d.N * (NC / 2) + d.N) * sizeof(float2) + (size_t)d.N * 4 + polar_peak_cache<NC>() * (4 + 4 + 4 + 4 + 4) +
-         (size_t)d.Rp * 4 + (size_t)(d.Rp / kPolarCols) * (kThreads / 64) * 4;
+  return (size_t)(d.N * (NC / 2) + d.N) * sizeof(float2) + (size_t)d.N * 4 + polar_peak_cache<NC>() * (4 + 4 + 4 + 4 + 4 + 4) +
+         (size_t)d.Rp * 8 + (size_t)(d.Rp / kPolarCols) * (kThreads / 64) * 4;
 }
-size_t exact_lds(const PlanDev& d) {
-  return (size_t)(kBatch * d.N + d.N) * sizeof(float2) + (size_t)d.N * 4 + (size_t)d.Z * 4 + (size_t)d.Rp;
+size_t exact_lds(const PlanDev& d, int u_lds) {
+  return (size_t)(kBatch * d.N + d.N) * sizeof(float2) + (size_t)d.N * 4 + (u_lds ? (size_t)d.Z * 4 : 0) + (size_t)d.Rp;
 }
 
+// Dynamic-LDS limit of a kernel: raised (never lowered) under a lock, so that a
+// launch on another thread that relies on a larger limit set earlier still fits.
 template <class K>
 acom_status_t ensure_lds(K kernel, size_t bytes) {
   if (bytes > 160 * 1024) return fail(ACOM_E_UNSUPPORTED, "plan too large for the LDS budget of one workgroup");
+  static std::mutex mu;
+  static std::map<const void*, size_t> set_to;
+  std::lock_guard<std::mutex> lock(mu);
+  size_t& cur = set_to[(const void*)kernel];
+  if (bytes <= cur) return ACOM_OK;
   ACOM_HIP(hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  cur = bytes;
   return ACOM_OK;
 }
 
@@ -1650,9 +1686,9 @@ acom_status_t launch_polar_n(const PlanDev& d, const PolarArgs& a, hipStream_t s
 
 template <int NT>
 acom_status_t launch_exact_n(const PlanDev& d, const ExactArgs& e, dim3 grid, hipStream_t s) {
-  acom_status_t st = ensure_lds(exact_kernel<NT>, exact_lds(d));
+  acom_status_t st = ensure_lds(exact_kernel<NT>, exact_lds(d, e.u_lds));
   if (st != ACOM_OK) return st;
-  exact_kernel<NT><<<grid, kThreads, exact_lds(d), s>>>(e);
+  exact_kernel<NT><<<grid, kThreads, exact_lds(d, e.u_lds), s>>>(e);
   ACOM_HIP(hipGetLastError());
   return ACOM_OK;
 }
@@ -1725,7 +1761,7 @@ acom_status_t launch_bound_t(const PlanDev& d, int precision, BoundArgs b, int k
 acom_status_t launch_bound(const PlanDev& d, int precision, const WsLayout& L, unsigned char* ws, int np,
                            float* U, int ldU, int Zvalid, hipStream_t s) {
   BoundArgs b;
-  const PlanDev::BoundShape* t = d.tuned[precision].set ? &d.tuned[precision] : nullptr;
+  const PlanDev::BoundShape* t = g_tune.tuned[precision].set ? &g_tune.tuned[precision] : nullptr;
   b.Nk = d.Nk;
   b.Rp = d.Rp;
   b.N = d.N;
@@ -1794,8 +1830,9 @@ ExactArgs exact_args(const PlanDev& d, const WsLayout& L, unsigned char* ws, int
   e.xi = reinterpret_cast<const float*>(ws + L.xi);
   e.pr = d.d_PRz;
   e.pi = d.d_PIz;
-  e.U = reinterpret_cast<const float*>(ws + L.U);
+  e.U = reinterpret_cast<float*>(ws + L.U);
   e.ldU = d.Zp;
+  e.u_lds = d.Z <= g_tune.exact_u_lds_max ? 1 : 0;
   e.xnorm2 = reinterpret_cast<const float*>(ws + L.xn2);
   e.cmask = reinterpret_cast<const uint32_t*>(ws + L.cmask);
   e.ntiles = L.ntiles;
@@ -1829,7 +1866,6 @@ acom_status_t check_plan_precision(acom_plan_t plan, int precision) {
   if (precision < 0 || precision > 2) return fail(ACOM_E_INVALID, "precision must be ACOM_FP32, ACOM_BF16 or ACOM_FP16");
   if (precision != ACOM_FP32 && !plan->d.d_PR16[precision])
     return fail(ACOM_E_INVALID, "plan was built without this precision (acom_plan_params_t.precisions)");
-  if (plan->d.Z > kMaxZonesExact) return fail(ACOM_E_UNSUPPORTED, "more than 16384 zones");
   return ACOM_OK;
 }
 
@@ -2053,7 +2089,7 @@ extern "C" acom_status_t acom_autotune(acom_plan_t plan, const acom_peaks_t* pea
   if (st != ACOM_OK) return st;
   if ((st = check_peaks(peaks)) != ACOM_OK) return st;
   if (peaks->n_patterns == 0) return fail(ACOM_E_INVALID, "autotune needs at least one pattern");
-  PlanDev& d = plan->d;
+  const PlanDev& d = plan->d;
   const int Pc = chunk_of(chunk);
   const WsLayout L = layout(d, precision != ACOM_FP32, Pc);
   if (!workspace || workspace_bytes < L.total)
@@ -2087,12 +2123,12 @@ extern "C" acom_status_t acom_autotune(acom_plan_t plan, const acom_peaks_t* pea
     (void)hipEventDestroy(e0);
     return fail(ACOM_E_HIP, "hipEventCreate");
   }
-  const PlanDev::BoundShape saved = d.tuned[precision];
+  const PlanDev::BoundShape saved = g_tune.tuned[precision];
   int best = -1;
   float best_ms = 0.0f;
   float* U = reinterpret_cast<float*>(ws + L.U);
   for (size_t i = 0; i < cand.size() && st == ACOM_OK; ++i) {
-    d.tuned[precision] = cand[i];
+    g_tune.tuned[precision] = cand[i];
     constexpr int kReps = 2;
     st = launch_bound(d, precision, L, ws, np, U, d.Zp, d.Zp, s);  // warm-up
     if (st == ACOM_E_UNSUPPORTED) {  // a shape this plan cannot use
@@ -2114,11 +2150,11 @@ extern "C" acom_status_t acom_autotune(acom_plan_t plan, const acom_peaks_t* pea
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != ACOM_OK || best < 0) {
-    d.tuned[precision] = saved;
+    g_tune.tuned[precision] = saved;
     return st != ACOM_OK ? st : fail(ACOM_E_UNSUPPORTED, "no contraction shape ran");
   }
-  d.tuned[precision] = cand[best];
-  d.tuned[precision].ms = best_ms;
+  g_tune.tuned[precision] = cand[best];
+  g_tune.tuned[precision].ms = best_ms;
   if (shape) {
     shape[0] = cand[best].tile;
     shape[1] = cand[best].kch;
@@ -2259,6 +2295,8 @@ extern "C" acom_status_t acom_profile_end(void) {
 }
 
 extern "C" acom_status_t acom_set_tuning(int32_t key, int32_t value) {
+  if (key == 0 || key == 1 || key == 4 || key == 6)  // an explicit contraction shape replaces the autotuned ones
+    for (auto& t : g_tune.tuned) t = PlanDev::BoundShape();
   switch (key) {
     case 0:
       if (value != 0 && value != 1) return fail(ACOM_E_INVALID, "bound order must be 0 or 1");
@@ -2291,6 +2329,10 @@ extern "C" acom_status_t acom_set_tuning(int32_t key, int32_t value) {
     case 7:
       if (value != 16 && value != 32) return fail(ACOM_E_INVALID, "polar columns per pass must be 16 or 32");
       g_tune.polar_cols = value;
+      return ACOM_OK;
+    case 8:
+      if (value < 0 || value > 32768) return fail(ACOM_E_INVALID, "LDS bound-row limit must be in [0, 32768] zones");
+      g_tune.exact_u_lds_max = value;
       return ACOM_OK;
 
   }

@@ -676,15 +676,21 @@ extern "C" acom_status_t acom_build_plan(const acom_phase_t* phases, int32_t n_p
     }
     rev[n] = pos;
   }
-  std::vector<float> qsf(d.Rp, -1.0f);
-  for (int s = 0; s < d.R; ++s) qsf[s] = (float)d.q_s[s];
-  if ((st = dalloc(&d.d_M12, M12f.size())) || (st = dalloc(&d.d_zone_phase, d.Z)) || (st = dalloc(&d.d_qs, d.Rp)) ||
+  // q_s as FP32 pairs: hi (padding columns -1) then lo = q_s - hi, so that the
+  // polar pass forms q_m - q_s to FP32 precision of the difference itself
+  std::vector<float> qsf(2 * (size_t)d.Rp, 0.0f);
+  for (int s = 0; s < d.Rp; ++s) qsf[s] = -1.0f;
+  for (int s = 0; s < d.R; ++s) {
+    qsf[s] = (float)d.q_s[s];
+    qsf[d.Rp + s] = (float)(d.q_s[s] - (double)qsf[s]);
+  }
+  if ((st = dalloc(&d.d_M12, M12f.size())) || (st = dalloc(&d.d_zone_phase, d.Z)) || (st = dalloc(&d.d_qs, 2 * (size_t)d.Rp)) ||
       (st = dalloc(&d.d_tw, d.N)) || (st = dalloc(&d.d_rev, d.N)) || (st = dalloc(&d.d_refl, std::max(1, d.G))) ||
       (st = dalloc(&d.d_reflF2, std::max(1, d.G))) || (st = dalloc(&d.d_refl_off, n_phases + 1)))
     return bail(st);
   if (hipMemcpy(d.d_M12, M12f.data(), sizeof(float) * M12f.size(), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(d.d_zone_phase, d.zone_phase.data(), sizeof(int) * d.Z, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(d.d_qs, qsf.data(), sizeof(float) * d.Rp, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(d.d_qs, qsf.data(), sizeof(float) * qsf.size(), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(d.d_tw, tw32.data(), sizeof(float2) * d.N, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(d.d_rev, rev.data(), sizeof(int32_t) * d.N, hipMemcpyHostToDevice) != hipSuccess ||
       (d.G && hipMemcpy(d.d_refl, refl_f.data(), sizeof(float4) * d.G, hipMemcpyHostToDevice) != hipSuccess) ||

@@ -11,9 +11,13 @@
 // dS/dtheta uses d(Exp(theta)^T u)/dtheta = [r]x J_r(theta) (SO(3) right Jacobian).
 // One wavefront per pattern; lanes own reflections, peaks are streamed from
 // LDS.  For omega > 0, reflections with |s_g| >= 10 sigma_e / sqrt(omega) + 0.035
-// 1/A at the base orientation are dropped once per call: v_g is then below
-// exp(-25) of |g|^gamma |F_g|^omega even after a 1 degree rotation (which moves
-// s_g by at most 0.035 1/A for |g| < 2 1/A).  For omega = 0 all are kept.
+// 1/A are left out: v_g is then below exp(-25) of |g|^gamma |F_g|^omega even
+// after a 1 degree rotation (which moves s_g by at most 0.035 1/A for |g| < 2
+// 1/A).  The set is taken at the orientation being scored (acom_score,
+// acom_score_grad) and, in refinement, at the start orientation and again after
+// every accepted step, whose trials lie within 0.5 degree of it.  For omega = 0
+// all are kept.  At most kMaxKept reflections take part: a pattern whose set
+// is larger is an error, reported as NaN (never truncated).
 #include <cmath>
 
 #include "acom_internal.h"
@@ -124,7 +128,8 @@ struct Shared {
 };
 
 // Kept reflections of `ph` at orientation m (lane-cooperative, ascending order).
-__device__ void select_kept(const ScoreArgs& a, int ph, const float* m, Shared& sh) {
+// Returns false (and keeps none) when more than kMaxKept pass the filter.
+__device__ bool select_kept(const ScoreArgs& a, int ph, const float* m, Shared& sh) {
   const int lane = threadIdx.x;
   const int g0 = a.refl_off[ph], g1 = a.refl_off[ph + 1];
   const float lim = a.omega > 0.0f ? 10.0f * a.sigma_e / sqrtf(a.omega) + 0.035f : INFINITY;
@@ -144,8 +149,9 @@ __device__ void select_kept(const ScoreArgs& a, int ph, const float* m, Shared& 
     if (keep && base + before < kMaxKept) sh.kept[base + before] = g;
     base += __popcll(bal);
   }
-  if (lane == 0) sh.nkept = base < kMaxKept ? base : kMaxKept;
+  if (lane == 0) sh.nkept = base <= kMaxKept ? base : 0;
   __syncthreads();
+  return base <= kMaxKept;
 }
 
 // S, and optionally dS/dtheta (theta-Jacobian J) and the per-reflection
@@ -280,9 +286,20 @@ __global__ void __launch_bounds__(kW) score_kernel(ScoreArgs a) {
   expm3(th, E);
   matmul3(base, E, R);
   right_jac(th, J);
-  select_kept(a, ph, base, sh);
   const bool grad = a.dtheta != nullptr;
   const bool peak_grad = a.dqx != nullptr || a.dqy != nullptr;
+  if (!select_kept(a, ph, R, sh)) {  // more reflections than the cap: an error, never a truncated sum
+    if (lane == 0) {
+      if (a.S) a.S[p] = NAN;
+      if (a.dtheta)
+        for (int i = 0; i < 3; ++i) a.dtheta[(size_t)p * 3 + i] = NAN;
+    }
+    for (int64_t m = m0 + lane; m < m1; m += kW) {
+      if (a.dqx) a.dqx[m] = NAN;
+      if (a.dqy) a.dqy[m] = NAN;
+    }
+    return;
+  }
   Eval e = evaluate(a, m0, m1, R, J, grad, peak_grad, sh);
   if (!grad) {
     if (lane == 0) a.S[p] = e.S;
@@ -332,6 +349,7 @@ __global__ void __launch_bounds__(kW) refine_kernel(ScoreArgs a) {
   float best[9];
   float bestS = -INFINITY;
   int bestc = -1;
+  bool overflow = false;
   for (int i = 0; i < 9; ++i) best[i] = 0.0f;
   const float I3[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
   for (int c = 0; c < a.n_cand; ++c) {
@@ -343,7 +361,10 @@ __global__ void __launch_bounds__(kW) refine_kernel(ScoreArgs a) {
     for (int i = 0; i < 9; ++i) ok = ok && isfinite(m[i]);
     if (!ok) continue;
     __syncthreads();
-    select_kept(a, ph, m, sh);
+    if (!select_kept(a, ph, m, sh)) {
+      overflow = true;
+      break;
+    }
     Eval e = evaluate(a, m0, m1, m, I3, true, false, sh);
     float S = e.S;
     float g[3] = {e.g[0], e.g[1], e.g[2]};
@@ -362,6 +383,11 @@ __global__ void __launch_bounds__(kW) refine_kernel(ScoreArgs a) {
         for (int i = 0; i < 9; ++i) m[i] = mt[i];
         S = et.S;
         l = fminf(2.0f * l, lmax);
+        __syncthreads();
+        if (!select_kept(a, ph, m, sh)) {  // the set at the new orientation
+          overflow = true;
+          break;
+        }
         Eval eg = evaluate(a, m0, m1, m, I3, true, false, sh);
         g[0] = eg.g[0];
         g[1] = eg.g[1];
@@ -370,11 +396,20 @@ __global__ void __launch_bounds__(kW) refine_kernel(ScoreArgs a) {
         l *= 0.5f;
       }
     }
+    if (overflow) break;
     if (S > bestS) {
       bestS = S;
       bestc = c;
       for (int i = 0; i < 9; ++i) best[i] = m[i];
     }
+  }
+  if (overflow) {  // more reflections than the cap for some candidate: the pattern is an error
+    if (lane == 0) {
+      for (int i = 0; i < 9; ++i) a.out_orient[(size_t)p * 9 + i] = 0.0f;
+      if (a.out_score) a.out_score[p] = NAN;
+      if (a.out_cand) a.out_cand[p] = -2;
+    }
+    return;
   }
   if (lane == 0) {
     for (int i = 0; i < 9; ++i) a.out_orient[(size_t)p * 9 + i] = bestc >= 0 ? best[i] : 0.0f;

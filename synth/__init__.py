@@ -203,9 +203,9 @@ def multi(seed=1004, ny=512, nx=512, n_grains=200, k_max=2.0):
                                               "grain": lab, "shape": (ny, nx)})
 
 
-def refine(seed=1005, n=65536, k_max=2.0):
+def refine(seed=1005, n=65536, k_max=2.0, phase_name="fcc_a4.08"):
     rng = np.random.default_rng(seed)
-    t = load_table("fcc_a4.08")
+    t = load_table(phase_name)
     R = haar_rotations(rng, n)
     lists = []
     for i in range(n):
@@ -213,7 +213,7 @@ def refine(seed=1005, n=65536, k_max=2.0):
         keep = I > 0.01 * t["F2"].max()
         qx, qy, I = qx[keep][:60], qy[keep][:60], I[keep][:60]
         lists.append(_noisy(rng, qx, qy, I))
-    return _pack(lists, R, np.zeros(n), {"name": "refine", "k_max": k_max, "phases": ["fcc_a4.08"]})
+    return _pack(lists, R, np.zeros(n), {"name": "refine", "k_max": k_max, "phases": [phase_name]})
 
 
 def overlap(seed=1006, n=4096, k_max=2.0, second=(0.4, 0.9), per_grain=40):

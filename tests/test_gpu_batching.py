@@ -111,3 +111,107 @@ def test_autotune_keeps_results(acom, multi, precision):
     torch.cuda.synchronize()
     for k in ("zone", "bin", "mirror", "score"):
         assert np.array_equal(res[k].cpu().numpy(), ref[k]), k
+
+
+def test_concurrent_matches_on_two_streams(acom, multi):
+    """The plan is read-only after acom_build_plan and launch settings belong to
+    the calling host thread, so matches on two streams at once (interleaved
+    from one thread, then from two threads, one of which changes its own
+    launch settings meanwhile) give the sequential results bit for bit."""
+    import threading
+    d, opl, gpl = multi
+    rng = np.random.default_rng(9)
+    sets = []
+    for k in range(2):
+        ang = rng.uniform(-0.5, 0.5)
+        qx = d["qx"] * np.cos(ang) - d["qy"] * np.sin(ang)
+        qy = d["qx"] * np.sin(ang) + d["qy"] * np.cos(ang)
+        sets.append(acom.Peaks(d["offsets"], qx, qy, d["I"]))
+    ref = []
+    for pk in sets:
+        r = gpl.match(pk, 2, "bf16", 128)
+        torch.cuda.synchronize()
+        ref.append({k: v.clone() for k, v in r.items() if v is not None})
+    keys = ("zone", "bin", "mirror", "score", "phi3", "orient", "n_evaluated")
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    ws = [torch.empty(gpl.match_workspace_bytes("bf16", 128), dtype=torch.uint8, device="cuda") for _ in range(2)]
+    outs = [gpl.empty_matches(sets[0].n_patterns, 2, True, "cuda") for _ in range(2)]
+    torch.cuda.synchronize()
+    # one thread, two streams, launches interleaved
+    for rep in range(3):
+        for k in range(2):
+            with torch.cuda.stream(streams[k]):
+                gpl.match(sets[k], 2, "bf16", 128, ws[k], out=outs[k])
+        torch.cuda.synchronize()
+        for k in range(2):
+            for key in keys:
+                assert torch.equal(outs[k][key], ref[k][key]), (rep, k, key)
+    # two threads, each on its own stream
+    errors = []
+
+    def worker(k):
+        try:
+            if k == 1:
+                acom.set_tuning(polar_cols=16, bound_tile=0)  # this thread's settings only
+            for rep in range(4):
+                with torch.cuda.stream(streams[k]):
+                    gpl.match(sets[k], 2, "bf16", 128, ws[k], out=outs[k])
+                streams[k].synchronize()
+                for key in keys:
+                    if not torch.equal(outs[k][key], ref[k][key]):
+                        errors.append((k, rep, key))
+        except Exception as e:  # reported below
+            errors.append((k, repr(e)))
+
+    th = [threading.Thread(target=worker, args=(k,)) for k in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errors, errors
+
+
+def test_plan_above_16384_zones(acom):
+    """A hexagonal 6/m wedge at 0.7 degree (16,900 zones): the exact pass keeps
+    the pattern's bound row in the workspace instead of LDS.  Decisions match
+    the plain-C FP64 direct sum, and equal those of the LDS path (forced by
+    raising the limit) bit for bit; on the FCC plan the in-place path forced by
+    a zero limit equals the default LDS path."""
+    from oracle import directsum
+    cfg = dict(k_max=1.6, n_radial=32, n_angular=90, zone_step_deg=0.7)
+    opl = helpers.oracle_plan(["hcp"], **cfg)
+    gpl = helpers.gpu_plan(["hcp"], precisions=("fp32", "bf16"), **cfg)
+    assert gpl.n_zones == 16900 > 16384
+    d = synth.subset(synth.make("hcp"), np.arange(0, 65536, 1024))
+    pk = acom.Peaks.from_host(d)
+    out = {}
+    try:
+        for lim in (16384, 32768):
+            acom.set_tuning(exact_u_lds_max=lim)
+            r = gpl.match(pk, top_k=4, precision="bf16")
+            torch.cuda.synchronize()
+            out[lim] = {k: v.cpu().numpy() for k, v in r.items() if v is not None}
+    finally:
+        acom.set_tuning(exact_u_lds_max=16384)
+    for k in ("zone", "bin", "mirror", "score", "phi3", "n_evaluated"):
+        assert np.array_equal(out[16384][k], out[32768][k]), k
+    res = out[16384]
+    zs = directsum.zone_scores(opl, d["offsets"], d["qx"], d["qy"], d["I"])
+    for p in range(len(d["offsets"]) - 1):
+        sc = zs["score"][p]
+        mx = sc.max()
+        z = int(res["zone"][p, 0])
+        assert z >= 0 and sc[z] >= mx - 1e-5 * mx, (p, z)
+        assert abs(res["score"][p, 0] - sc[z]) <= 1e-5 * mx
+    # the in-place path on a plan whose rows would fit LDS
+    d2, _, gpl2 = None, None, helpers.gpu_plan(["fcc"], precisions=("fp32",), **MULTI)
+    pk2 = acom.Peaks.from_host(synth.multi(ny=8, nx=8, n_grains=6))
+    try:
+        a = gpl2.match(pk2, top_k=3, precision="fp32")
+        acom.set_tuning(exact_u_lds_max=0)
+        b = gpl2.match(pk2, top_k=3, precision="fp32")
+        torch.cuda.synchronize()
+    finally:
+        acom.set_tuning(exact_u_lds_max=16384)
+    for k in ("zone", "bin", "mirror", "score", "phi3", "n_evaluated"):
+        assert torch.equal(a[k], b[k]), k

@@ -5,8 +5,8 @@ oracle computed one pattern at a time:
   - the 256x256 HCP scan against the 8281-zone 6/m wedge plan, top-8 with
     BF16 and FP16 contractions and FP32 rescoring;
   - the 512x512 three-phase scan (262,144 patterns with 3-150 peaks) against
-    the concatenated 10,443-zone plan, BF16 (oracle sample among the patterns
-    of at most 30 peaks);
+    the concatenated 10,443-zone plan, BF16 (oracle sample over the whole
+    range of peak counts, three of them above 128 peaks);
   - 65,536 off-grid FCC patterns: top-4 grid candidates (FP32 and BF16
     contractions, FP32 rescoring) refined on the continuous score, against the
     oracle's refinement of the same candidates.
@@ -14,9 +14,10 @@ oracle computed one pattern at a time:
 Tolerances: a reported zone's oracle score is within 1e-5 of the oracle's
 maximum (ties between symmetry-equivalent zones are equal to FP32 rounding),
 and the reported FP32 score equals the oracle's value there within 1e-5 of the
-maximum; refined orientations agree within 0.01 degree (the two ascents take the
-same steps up to FP32 rounding of the gradient; 0.004 degree is the largest
-difference seen over 183 patterns).
+maximum; the refined winner is a candidate whose oracle-refined score is the
+oracle's best within 1e-4 (twins can tie), and its orientation agrees with the
+oracle's refinement of that candidate within 0.01 degree (the two ascents take
+the same steps up to FP32 rounding of the gradient).
 """
 import numpy as np
 import pytest
@@ -81,10 +82,13 @@ def test_multiphase_full_size_sampled(acom):
     res = gpl.match(acom.Peaks.from_host(d), top_k=1, precision="bf16", chunk=CHUNK)
     torch.cuda.synchronize()
     res = {k: v.cpu().numpy() for k, v in res.items() if v is not None}
-    # sampled among the patterns of at most 30 peaks, so that the oracle's
-    # slowest pattern (its cost grows with the peaks) finishes in seconds
-    small = np.nonzero(np.diff(d["offsets"]) <= 30)[0]
-    idx = np.sort(np.random.default_rng(82).choice(small, 8, replace=False))
+    # sampled over the whole 3-150 range of peak counts, with three patterns
+    # above 128 peaks (the polar pass's multi-batch path)
+    cnt = np.diff(d["offsets"])
+    rng = np.random.default_rng(82)
+    idx = np.sort(np.concatenate([rng.choice(len(cnt), 6, replace=False),
+                                  rng.choice(np.nonzero(cnt > 128)[0], 3, replace=False)]))
+    assert (cnt[idx] > 128).sum() >= 3
     _check_sampled(_oracle_scores(opl, d, idx), res, idx, 1)
     for p in idx:
         assert res["phase"][p, 0] == opl["zone_phase"][res["zone"][p, 0]]
@@ -102,6 +106,7 @@ def test_refine_full_size_sampled(acom, precision):
     torch.cuda.synchronize()
     m = m.cpu().numpy()
     S = S.cpu().numpy()
+    cand = cand.cpu().numpy()
     init = init.cpu().numpy().reshape(n, 4, 3, 3)
     refl = crystal.reflections(np.eye(3) * helpers.A_FCC, helpers.FCC_FRAC, 2.0)
     prm = oplan.Params(k_max=2.0)
@@ -111,7 +116,14 @@ def test_refine_full_size_sampled(acom, precision):
     mis = []
     for p in idx:
         args = [d[k][o[p]:o[p + 1]].astype(np.float64) for k in ("qx", "qy", "I")]
-        mo, So = score.refine(refl, *args, list(init[p]), prm, max_iter=64)
-        mis.append(metrics.misorientation_deg(m[p], mo, G))
-        assert abs(S[p] - So) <= 1e-4 * abs(So) + 1e-6, (p, S[p], So)
+        # the oracle refines every candidate; the GPU's winner must be one whose
+        # refined score is the oracle's best up to FP32 resolution (candidates
+        # of equal score, such as twins, are ties), and its orientation the
+        # oracle's refinement of that same candidate
+        ref = [score.refine_one(refl, *args, init[p, j], prm, max_iter=64)[:2] for j in range(4)]
+        So = max(r[1] for r in ref)
+        c = int(cand[p])
+        assert ref[c][1] >= So - 1e-4 * abs(So), (p, c, [r[1] for r in ref])
+        assert abs(S[p] - ref[c][1]) <= 1e-4 * abs(So) + 1e-6, (p, S[p], ref[c][1])
+        mis.append(metrics.misorientation_deg(m[p], ref[c][0], G))
     assert max(mis) < 0.01, mis

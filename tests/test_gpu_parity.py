@@ -2,9 +2,12 @@
 
 Tolerances (FP32 path), from the arithmetic:
   * plan: FP64 on both sides, 1e-12 relative;
-  * X: every cell is a few FP32 products with an FP64 angle difference:
-    1e-5 of max|X|;
-  * FFT{X}: 360-point FP32 FFT, ~log2(N) eps relative to the column sums: 1e-5 of max;
+  * X: every cell is a sum of a few FP32 kernel values; the radial offset
+    q_m - q_s is formed from FP32 (hi, lo) pairs of both radii and the angle
+    offset from an FP64 angle, so each value is within a few ulp: 1e-6 of
+    max|X| (a plain FP32 radius difference would leave ~1e-6 at q = 2, where
+    an ulp of the radius over delta = 0.08 is 1.5e-6);
+  * FFT{X}: 360-point FP32 FFT, ~log2(N) eps relative to the column sums: 1e-6 of max;
   * C: contraction over 128 radii x 181 frequencies in FP32: 1e-5 of max|C|;
   * decisions: the GPU's (zone, bin, mirror) must lie in the oracle's tie set
     {C >= max C - 1e-5 max|C|} (FP32 cannot order values closer than that),
@@ -59,6 +62,46 @@ def test_plan_variants_match_oracle(acom, radial, kernel):
     assert np.abs(P - opl["P"]).max() < 1e-12 * np.abs(opl["P"]).max()
 
 
+def test_plan_with_scattering_factor_table_matches_oracle(acom):
+    """A two-species cell (simple cubic a = 3 A, species 0 at the origin and 1 at
+    the body centre) with a caller's scattering-factor table of three knots:
+    the GPU's FP64 plan (structure factors by linear interpolation of f(|g|))
+    equals the oracle's to 1e-12, with the plan's f-table path exercised end to
+    end; matching on it agrees with the oracle's maximum."""
+    from oracle import plan as oplan
+    from oracle import zones as ozones
+    lat = np.eye(3) * 3.0
+    frac = [[0, 0, 0], [0.5, 0.5, 0.5]]
+    f_q, f_tab = [0.0, 1.0, 2.0], [[2.0, 1.0, 0.5], [1.0, 0.8, 0.2]]
+    cfg = dict(k_max=1.5, n_radial=32, n_angular=90, zone_step_deg=5.0)
+    opl = oplan.build([oplan.Phase(lat, frac, triangles=[ozones.cubic_triangle()], species=[0, 1],
+                                   f_q=f_q, f_tab=f_tab)], oplan.Params(**cfg))
+    ph = acom.Phase(lattice=lat.tolist(), frac_xyz=frac, triangles=[acom.cubic_triangle()], species=[0, 1],
+                    f_q=f_q, f_tab=f_tab)
+    gpl = acom.Plan([ph], acom.PlanParams(keep_f64=True, precisions=["fp32"], **cfg))
+    P = gpl.angular_f64()
+    assert np.abs(P - opl["P"]).max() < 1e-12 * np.abs(opl["P"]).max()
+    assert np.allclose(gpl.info()["norm_A"], opl["A"], rtol=1e-12)
+    # the species weights matter: the plan differs from the one with f == 1
+    flat = oplan.build([oplan.Phase(lat, frac, triangles=[ozones.cubic_triangle()])], oplan.Params(**cfg))
+    assert np.abs(flat["P"] - opl["P"]).max() > 1e-3 * np.abs(opl["P"]).max()
+    # matching on it: kinematical patterns of the cell at random orientations
+    from oracle import crystal, kinematics
+    refl = opl["refl"][0]
+    rng = np.random.default_rng(11)
+    lists = []
+    for m in synth.haar_rotations(rng, 24):
+        qx, qy, I = kinematics.pattern(refl, m, opl["params"].k0, k_max=1.5)
+        lists.append((qx.astype(np.float32), qy.astype(np.float32), I.astype(np.float32)))
+    off = np.concatenate([[0], np.cumsum([len(l[0]) for l in lists])]).astype(np.int64)
+    dd = {"offsets": off, "qx": np.concatenate([l[0] for l in lists]), "qy": np.concatenate([l[1] for l in lists]),
+          "I": np.concatenate([l[2] for l in lists])}
+    res = gpl.match(acom.Peaks.from_host(dd), top_k=1, precision="fp32")
+    torch.cuda.synchronize()
+    res = {k: v.cpu().numpy() for k, v in res.items() if v is not None}
+    _check_decisions(opl, dd, res, [p for p in range(24) if off[p + 1] > off[p]], top_k=1)
+
+
 def test_polar_image_and_spectrum(acom, small):
     d, opl, gpl = small
     pk = acom.Peaks.from_host(d)
@@ -68,11 +111,11 @@ def test_polar_image_and_spectrum(acom, small):
     for p in range(0, 128, 7):
         Xo = helpers.oracle_image(opl, d, p)
         sc = np.abs(Xo).max()
-        assert np.abs(X[p] - Xo).max() <= 1e-5 * sc
+        assert np.abs(X[p] - Xo).max() <= 1e-6 * sc
         F = np.fft.rfft(Xo, axis=0)
         scf = np.abs(F).max()
-        assert np.abs(Xr[p] - F.real).max() <= 1e-5 * scf
-        assert np.abs(Xi[p] - F.imag).max() <= 1e-5 * scf
+        assert np.abs(Xr[p] - F.real).max() <= 1e-6 * scf
+        assert np.abs(Xi[p] - F.imag).max() <= 1e-6 * scf
 
 
 @pytest.mark.parametrize("cfg", ["small", "ragged48", "scan"])
@@ -112,11 +155,11 @@ def test_polar_pass_widths_agree(acom, cfg):
     for p in range(0, len(d["offsets"]) - 1, 37):
         Xo = helpers.oracle_image(opl, d, p)
         sc = max(np.abs(Xo).max(), 1e-30)
-        assert np.abs(X[p] - Xo).max() <= 1e-5 * sc
+        assert np.abs(X[p] - Xo).max() <= 1e-6 * sc
         F = np.fft.rfft(Xo, axis=0)
         scf = max(np.abs(F).max(), 1e-30)
-        assert np.abs(Xr[p] - F.real).max() <= 1e-5 * scf
-        assert np.abs(Xi[p] - F.imag).max() <= 1e-5 * scf
+        assert np.abs(Xr[p] - F.real).max() <= 1e-6 * scf
+        assert np.abs(Xi[p] - F.imag).max() <= 1e-6 * scf
     _check_decisions(opl, d, out[32][3], range(0, len(d["offsets"]) - 1, 37), top_k=2)
 
 
@@ -395,10 +438,10 @@ def test_match_generic_angular_length(acom, n_angular):
     Xr, Xi = gpl.polar_spectrum(pk)
     for p in range(0, 40, 7):
         Xo = helpers.oracle_image(opl, d, p)
-        assert np.abs(X[p] - Xo).max() <= 1e-5 * np.abs(Xo).max()
+        assert np.abs(X[p] - Xo).max() <= 1e-6 * np.abs(Xo).max()
         F = np.fft.rfft(Xo, axis=0)
-        assert np.abs(Xr[p].cpu().numpy() - F.real).max() <= 1e-5 * np.abs(F).max()
-        assert np.abs(Xi[p].cpu().numpy() - F.imag).max() <= 1e-5 * np.abs(F).max()
+        assert np.abs(Xr[p].cpu().numpy() - F.real).max() <= 1e-6 * np.abs(F).max()
+        assert np.abs(Xi[p].cpu().numpy() - F.imag).max() <= 1e-6 * np.abs(F).max()
     res = gpl.match(pk, top_k=2, precision="bf16")
     torch.cuda.synchronize()
     res = {k: v.cpu().numpy() for k, v in res.items() if v is not None}
