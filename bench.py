@@ -14,6 +14,13 @@ contraction with FP32 rescoring is timed on the same inputs and reported
 beside it.  The dominant kernel's roofline uses its average duration from HIP
 events recorded on its launch stream during the timed steps.
 
+The default run also times, as extra keys of the same line ("workloads"),
+short runs of the HCP top-8 scan (BF16 / FP16 / FP32), the three-phase
+262,144-pattern scan by HIP-graph replay (BF16) and the top-4 + refinement
+workload, each with its own dominant-kernel time and a seeded oracle sample
+of at least 64 patterns (--no-extra skips them).  Their oracle plans and
+direct sums run in a worker process while the GPU is timed.
+
 Other workloads (--workload), each printing one JSON line of the same form:
   hcp     256 x 256 HCP (a = 2.95, c = 4.68) scan against the 6/m wedge at 1
           degree (8281 zones); BF16 / FP16 / FP32 contraction, top-8 FP32
@@ -305,7 +312,7 @@ def line(workload, value, ms, steps, warmup, dtype, cfg, roof, cpu, extra):
     return out
 
 
-def run_match_workload(args, workload):
+def run_match_workload(args, workload, defer_oracle=False):
     import numpy as np
     import torch
     import synth
@@ -335,7 +342,7 @@ def run_match_workload(args, workload):
                                             flop_per_pattern)
         log(f"{workload}: {prec} timed, {runs[prec]['value']:.0f} patterns/s")
     cpu = agree = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not defer_oracle:
         cpu, agree = cpu_baseline_match(workload, d, host)
         log(f"{workload}: oracle sample timed")
     main_prec = precs[0]
@@ -354,9 +361,12 @@ def run_match_workload(args, workload):
     ccfg = {"patterns": n, "peaks": int(d["offsets"][-1]), "zones": Z, "n_radial": R, "n_angular": N,
             "chunk": args.chunk, "top_k": top_k}
     r = runs[main_prec]
-    return line(workload, r["value"], r["ms_per_step"], args.steps, args.warmup,
-                {"fp32": "f32", "bf16": "bf16", "fp16": "f16"}[main_prec], ccfg,
-                roofline(runs, main_prec, per_launch, flop_per_pattern, traffic), cpu, extra)
+    out = line(workload, r["value"], r["ms_per_step"], args.steps, args.warmup,
+               {"fp32": "f32", "bf16": "bf16", "fp16": "f16"}[main_prec], ccfg,
+               roofline(runs, main_prec, per_launch, flop_per_pattern, traffic), cpu, extra)
+    if defer_oracle:
+        out["_deferred"] = (d, host)
+    return out
 
 
 def run_multi(args):
@@ -847,6 +857,230 @@ def run_pipeline(args):
     return o
 
 
+def oracle_extra_samples(n_threads, n_sample=64):
+    """Worker process (no GPU): the oracle plans of FCC, BCC and HCP and the
+    plain-C FP64 direct sum of seeded samples of the HCP scan (8281 zones) and
+    of the three-phase scan (the three plans concatenated, 10,443 zones)."""
+    import numpy as np
+    import synth
+    from oracle import directsum
+    from tests import helpers
+    os.environ["OMP_NUM_THREADS"] = str(n_threads)
+    cfg = PLAN_CFG["hcp"][1]
+    t0 = time.perf_counter()
+    plans = {k: helpers.oracle_plan([k], **cfg) for k in ("fcc", "bcc", "hcp")}
+    t_plan = time.perf_counter() - t0
+    out = {"plan_s": t_plan, "threads": n_threads}
+    for name, seed in (("hcp", 3003), ("multi", 3004)):
+        d = synth.make(name)
+        n = len(d["offsets"]) - 1
+        idx = np.sort(np.random.default_rng(seed).choice(n, n_sample, replace=False))
+        sub = synth.subset(d, idx)
+        if name == "hcp":
+            pl = plans["hcp"]
+        else:
+            pl = dict(plans["fcc"])
+            pl["P"] = np.concatenate([plans[k]["P"] for k in ("fcc", "bcc", "hcp")])
+            pl["M12"] = np.concatenate([plans[k]["M12"] for k in ("fcc", "bcc", "hcp")])
+            pl["zone_phase"] = np.concatenate([np.full(len(plans[k]["P"]), i) for i, k in enumerate(("fcc", "bcc", "hcp"))])
+        t0 = time.perf_counter()
+        zs = directsum.zone_scores(pl, sub["offsets"], sub["qx"], sub["qy"], sub["I"], n_threads)
+        el = time.perf_counter() - t0
+        # the oracle's top-1 orientation: best zone, its bin and branch, parabolic offset
+        from oracle import correlate
+        orient = []
+        for i in range(n_sample):
+            z = int(np.argmax(zs["score"][i]))
+            off = correlate.parabolic_offset(zs["cm1"][i, z], zs["score"][i, z], zs["cp1"][i, z])
+            orient.append(correlate.orientation(pl["M12"][z], int(zs["n"][i, z]), off, int(zs["mirror"][i, z]),
+                                                pl["P"].shape[1]))
+        out[name] = {"idx": idx, "score": zs["score"], "n": zs["n"], "mirror": zs["mirror"],
+                     "orient": np.array(orient), "seconds": el, "zone_phase": pl["zone_phase"],
+                     "peaks": np.diff(sub["offsets"])}
+        if name == "multi":
+            del pl
+    return out
+
+
+def _single_threaded():
+    """Pool initializer: one BLAS / OpenMP thread per worker process."""
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[k] = "1"
+
+
+def _refine_one_oracle(args):
+    """Pool task: the oracle's refinement of one pattern's candidates."""
+    import numpy as np
+    from oracle import crystal, score
+    from oracle import plan as oplan
+    from tests import helpers
+    qx, qy, I, cands = args
+    refl = crystal.reflections(np.eye(3) * helpers.A_FCC, helpers.FCC_FRAC, 2.0)
+    m, S = score.refine(refl, qx, qy, I, list(cands), oplan.Params(k_max=2.0), max_iter=64)
+    return m, S
+
+
+def _agreement(sample, res, prec):
+    """Top-1 argmax agreement of the GPU's decisions with the oracle sample
+    (tie-aware: within 1e-5 of the oracle's maximum; strict: the same zone, bin
+    and branch), and the misorientation between the two top-1 orientations."""
+    import numpy as np
+    from oracle import metrics
+    idx = sample["idx"]
+    m = len(idx)
+    ok_tie = ok_strict = 0
+    mis = []
+    zp = sample["zone_phase"]
+    for i, p in enumerate(idx):
+        sc = sample["score"][i]
+        mx = sc.max()
+        z = int(res["zone"][p, 0])
+        best = int(np.argmax(sc))
+        ok_tie += (z >= 0 and sc[z] >= mx - 1e-5 * mx)
+        ok_strict += (z == best and int(res["bin"][p, 0]) == int(sample["n"][i][best])
+                      and int(res["mirror"][p, 0]) == int(sample["mirror"][i][best]))
+        G = metrics.hexagonal_rotations() if zp[best] == 2 or sample.get("hex") else metrics.cubic_rotations()
+        if z >= 0 and zp[z] == zp[best]:
+            mis.append(metrics.misorientation_deg(res["orient"][p, 0], sample["orient"][i], G))
+    return {"tie_aware": ok_tie / m, "strict": ok_strict / m, "patterns": m,
+            "patterns_over_128_peaks": int((sample["peaks"] > 128).sum()),
+            "misorientation_vs_oracle_deg": {"median": float(np.median(mis)), "max": float(np.max(mis))},
+            "precision": prec}
+
+
+def extra_workloads(args, fut):
+    """Short runs of the HCP, three-phase and refinement workloads for the
+    default line, each summarised with its rate, kernel times and oracle check."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2111_00171_amd import acom
+    from oracle import metrics
+    from concurrent.futures import ProcessPoolExecutor
+    import multiprocessing as mp
+    out = {}
+    t_all = time.perf_counter()
+    # --- HCP top-8, three contraction precisions
+    d = synth.make("hcp")
+    n = len(d["offsets"]) - 1
+    phases, cfg = PLAN_CFG["hcp"]
+    gpl = acom.Plan([acom.hcp()], acom.PlanParams(precisions=["fp32", "bf16", "fp16"], **cfg))
+    pk = acom.Peaks.from_host(d)
+    fpp = 8.0 * gpl.n_zones * (gpl.n_angular // 2 + 1) * gpl.n_radial
+    runs, host = {}, {}
+    t0 = time.perf_counter()
+    for prec in ("bf16", "fp16", "fp32"):
+        runs[prec], host[prec] = time_match(gpl, pk, prec, 8, args.chunk, 3, 1, n, fpp)
+        log(f"hcp (extra): {prec} {runs[prec]['value']:.0f} patterns/s")
+    t_hcp = time.perf_counter() - t0
+    out["hcp"] = {"workload": DESCR["hcp"], "patterns": n, "zones": gpl.n_zones, "top_k": 8, "steps": 3,
+                  "by_precision": by_precision(runs), "timed_s": round(t_hcp, 2),
+                  "roofline_bf16": roofline(runs, "bf16", min(args.chunk, n), fpp, None)}
+    del gpl, pk
+    torch.cuda.empty_cache()
+    # --- three-phase scan, BF16, one HIP graph per step
+    d3 = synth.make("multi")
+    n3 = len(d3["offsets"]) - 1
+    phases, cfg = PLAN_CFG["multi"]
+    gpl = acom.Plan([acom.fcc(), acom.bcc(), acom.hcp()], acom.PlanParams(precisions=["bf16"], **cfg))
+    pk = acom.Peaks.from_host(d3)
+    fpp3 = 8.0 * gpl.n_zones * (gpl.n_angular // 2 + 1) * gpl.n_radial
+    t0 = time.perf_counter()
+    run3, host3 = time_match(gpl, pk, "bf16", 1, args.chunk, 1, 1, n3, fpp3)
+    ws = torch.empty(gpl.match_workspace_bytes("bf16", args.chunk), dtype=torch.uint8, device="cuda")
+    o3 = gpl.empty_matches(n3, 1, True, "cuda")
+    gpl.match(pk, 1, "bf16", args.chunk, ws, out=o3)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        gpl.match(pk, 1, "bf16", args.chunk, ws, out=o3)
+    g.replay()
+    torch.cuda.synchronize()
+    steps3 = 3
+    t1 = time.perf_counter()
+    for _ in range(steps3):
+        g.replay()
+    torch.cuda.synchronize()
+    el3 = time.perf_counter() - t1
+    same = bool(np.array_equal(o3["zone"].cpu().numpy(), host3["zone"]))
+    t_multi = time.perf_counter() - t0
+    log(f"multi (extra): graph replays {n3 * steps3 / el3:.0f} patterns/s")
+    out["multi"] = {"workload": DESCR["multi"], "patterns": n3, "zones": gpl.n_zones, "steps": steps3,
+                    "patterns_per_s": round(n3 * steps3 / el3, 1), "ms_per_step": round(el3 * 1e3 / steps3, 3),
+                    "graph_replay_matches_eager": same, "eager": by_precision({"bf16": run3})["bf16"],
+                    "timed_s": round(t_multi, 2),
+                    "roofline_bf16": roofline({"bf16": run3}, "bf16", min(args.chunk, n3), fpp3, None)}
+    del g, gpl, pk, ws, o3
+    torch.cuda.empty_cache()
+    # --- top-4 grid candidates (FP32) + refinement
+    dr = synth.make("refine")
+    nr = len(dr["offsets"]) - 1
+    gpl = acom.Plan([acom.fcc()], acom.PlanParams(precisions=["fp32"], **PLAN_CFG["refine"][1]))
+    pk = acom.Peaks.from_host(dr)
+    ws = torch.empty(gpl.match_workspace_bytes("fp32", args.chunk), dtype=torch.uint8, device="cuda")
+    orr = gpl.empty_matches(nr, 4, True, "cuda")
+    gpl.match(pk, 4, "fp32", args.chunk, ws, out=orr)
+    gpl.refine(pk, orr["orient"].reshape(nr, 4, 9), max_iter=64)
+    torch.cuda.synchronize()
+    stepsr, t_m, t_r = 3, 0.0, 0.0
+    t0 = time.perf_counter()
+    for _ in range(stepsr):
+        a = time.perf_counter()
+        gpl.match(pk, 4, "fp32", args.chunk, ws, out=orr)
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        m, S, c = gpl.refine(pk, orr["orient"].reshape(nr, 4, 9), max_iter=64)
+        torch.cuda.synchronize()
+        t_r += time.perf_counter() - b
+        t_m += b - a
+    t_ref = time.perf_counter() - t0
+    m = m.cpu().numpy()
+    init = orr["orient"].reshape(nr, 4, 3, 3).cpu().numpy()
+    G = metrics.cubic_rotations()
+    idx_t = np.random.default_rng(9).choice(nr, 512, replace=False)
+    mis_t = [metrics.misorientation_deg(m[p], dr["truth"][p], G) for p in idx_t]
+    log(f"refine (extra): {nr * stepsr / (t_m + t_r):.0f} patterns/s")
+    del gpl, pk, ws, orr
+    torch.cuda.empty_cache()
+    # --- oracle checks: HCP and three-phase samples from the worker, refinement in a pool
+    t0 = time.perf_counter()
+    samples = fut.result()
+    log(f"extra: oracle samples ready (waited {time.perf_counter() - t0:.1f} s)")
+    samples["hcp"]["hex"] = True
+    for prec in ("bf16", "fp16", "fp32"):
+        out["hcp"]["by_precision"][prec]["argmax_match_vs_oracle"] = _agreement(samples["hcp"], host[prec], prec)
+    out["multi"]["argmax_match_vs_oracle"] = _agreement(samples["multi"], host3, "bf16")
+    zp = samples["multi"]["zone_phase"]
+    out["multi"]["argmax_match_vs_oracle"]["phase_equal"] = float(np.mean(
+        [zp[int(host3["zone"][p, 0])] == zp[int(np.argmax(samples["multi"]["score"][i]))]
+         for i, p in enumerate(samples["multi"]["idx"])]))
+    out["oracle_worker"] = {"plan_build_s": round(samples["plan_s"], 1), "threads": samples["threads"],
+                            "hcp_sample_s": round(samples["hcp"]["seconds"], 1),
+                            "multi_sample_s": round(samples["multi"]["seconds"], 1)}
+    o = dr["offsets"]
+    idx_r = np.sort(np.random.default_rng(3005).choice(nr, 64, replace=False))
+    jobs = [(dr["qx"][o[p]:o[p + 1]].astype(np.float64), dr["qy"][o[p]:o[p + 1]].astype(np.float64),
+             dr["I"][o[p]:o[p + 1]].astype(np.float64), init[p]) for p in idx_r]
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=max(1, min(16, (os.cpu_count() or 2))), mp_context=mp.get_context("spawn"),
+                             initializer=_single_threaded) as ex:
+        ores = list(ex.map(_refine_one_oracle, jobs))
+    t_or = time.perf_counter() - t0
+    mis_o = [metrics.misorientation_deg(m[p], mo, G) for p, (mo, _) in zip(idx_r, ores)]
+    dS = [abs(float(S[p]) - So) / abs(So) for p, (_, So) in zip(idx_r, ores)]
+    out["refine"] = {"workload": DESCR["refine"], "patterns": nr, "steps": stepsr,
+                     "patterns_per_s": round(nr * stepsr / (t_m + t_r), 1),
+                     "ms_per_step_match": round(t_m * 1e3 / stepsr, 3), "ms_per_step_refine": round(t_r * 1e3 / stepsr, 3),
+                     "timed_s": round(t_ref, 2),
+                     "refined_vs_truth_deg": {"median": float(np.median(mis_t)), "p90": float(np.percentile(mis_t, 90)),
+                                              "patterns": 512},
+                     "refined_vs_oracle_refinement_deg": {"median": float(np.median(mis_o)), "max": float(np.max(mis_o)),
+                                                          "patterns": len(idx_r), "oracle_pool_s": round(t_or, 1)},
+                     "score_vs_oracle_refinement_rel": {"median": float(np.median(dS)), "max": float(np.max(dS))}}
+    out["extra_wall_s"] = round(time.perf_counter() - t_all, 1)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -859,6 +1093,8 @@ def main():
     ap.add_argument("--chunk", type=int, default=65536,
                     help="patterns per internal launch (65,536: one launch per step on the scan; ~19 GB of workspace)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="default run: skip the HCP, three-phase and refinement extra keys")
     ap.add_argument("--rounds", type=int, default=2,
                     help="overlap workload: orientations sought per pattern (the generator draws two grains)")
     ap.add_argument("--calibrate-copy-gib", type=float, default=0.0,
@@ -872,6 +1108,14 @@ def main():
     if args.precisions is None:
         args.precisions = "bf16,fp16,fp32" if args.workload == "hcp" else "fp32,bf16,fp16"
 
+    fut = pool = None
+    extra = args.workload == "scan" and not args.no_extra and not args.no_cpu_baseline
+    if extra:  # the oracle worker starts before this process touches the GPU
+        from concurrent.futures import ProcessPoolExecutor
+        import multiprocessing as mp
+        pool = ProcessPoolExecutor(max_workers=1, mp_context=mp.get_context("spawn"))
+        fut = pool.submit(oracle_extra_samples, max(1, min(16, os.cpu_count() or 2) - 2))
+    t_start = time.perf_counter()
     import torch
     if args.calibrate_copy_gib > 0:
         nb = int(args.calibrate_copy_gib * (1 << 30))
@@ -881,7 +1125,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if args.workload in ("scan", "hcp"):
-        out = run_match_workload(args, args.workload)
+        out = run_match_workload(args, args.workload, defer_oracle=extra)
     elif args.workload == "multi":
         out = run_multi(args)
     elif args.workload == "overlap":
@@ -894,6 +1138,15 @@ def main():
         out = run_pipeline(args)
     else:
         out = run_refine(args)
+    if extra:
+        out["workloads"] = extra_workloads(args, fut)
+        pool.shutdown()
+        # the scan's oracle baseline, timed once the worker has finished (no
+        # other CPU load on the host)
+        d, host = out.pop("_deferred")
+        out["cpu_baseline"], out["argmax_match_vs_oracle"] = cpu_baseline_match("scan", d, host)
+        log("scan: oracle sample timed")
+    out["bench_wall_s"] = round(time.perf_counter() - t_start, 1)
     print(json.dumps(out))
 
 

@@ -156,8 +156,7 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
   float* pql = pw + PC;  // q_m - pq (the radius as an FP32 pair)
   int* plist = reinterpret_cast<int*>(pql + PC);  // cached peaks reaching the current tile
   float* sqs = reinterpret_cast<float*>(plist + PC);  // q_s of every column (-1 beyond R)
-  float* sqsl = sqs + a.Rp;                           // q_s - sqs
-  uint32_t* scmw = reinterpret_cast<uint32_t*>(sqsl + a.Rp);  // [16-column tile][wave] column masks
+  uint32_t* scmw = reinterpret_cast<uint32_t*>(sqs + a.Rp);  // [16-column tile][wave] column masks
   __shared__ int s_bad, s_nlist;
   __shared__ float s_red[kThreads / 64];
   __shared__ double s_red64[kThreads / 64];
@@ -174,10 +173,7 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
     tw[i] = a.tw[i];
     rev[i] = a.rev[i];
   }
-  for (int i = tid; i < a.Rp; i += kThreads) {
-    sqs[i] = i < a.R ? a.qs[i] : -1.0f;
-    sqsl[i] = i < a.R ? a.qs[a.Rp + i] : 0.0f;
-  }
+  for (int i = tid; i < a.Rp; i += kThreads) sqs[i] = i < a.R ? a.qs[i] : -1.0f;
   if (tid == 0) s_bad = bad_range ? 1 : 0;
   // the flag is initialised before any wave's prep() may raise it
   __syncthreads();
@@ -231,7 +227,9 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
     const float qlo = col0 < a.R ? sqs[col0] : -1.0f;
     const float qhi = col0 < a.R ? sqs[cl] : -1.0f;
     const float qs = sqs[col0 + c];
-    const float qsl = sqsl[col0 + c];
+    // the low part of this thread's own column, from global memory (an LDS
+    // copy would cost the third workgroup per compute unit its room)
+    const float qsl = col0 + c < a.R ? a.qs[a.Rp + col0 + c] : 0.0f;
     const float dqs = dphi * qs;
     int hw = N;  // half-width of the angular window of this column
     if (qs > 0.0f) {
@@ -1588,7 +1586,7 @@ WsLayout layout(const PlanDev& d, bool lowp, int Pc) {
 template <int NC>
 size_t polar_lds(const PlanDev& d) {
   return (size_t)(d.N * (NC / 2) + d.N) * sizeof(float2) + (size_t)d.N * 4 + polar_peak_cache<NC>() * (4 + 4 + 4 + 4 + 4 + 4) +
-         (size_t)d.Rp * 8 + (size_t)(d.Rp / kPolarCols) * (kThreads / 64) * 4;
+         (size_t)d.Rp * 4 + (size_t)(d.Rp / kPolarCols) * (kThreads / 64) * 4;
 }
 size_t exact_lds(const PlanDev& d, int u_lds) {
   return (size_t)(kBatch * d.N + d.N) * sizeof(float2) + (size_t)d.N * 4 + (u_lds ? (size_t)d.Z * 4 : 0) + (size_t)d.Rp;
