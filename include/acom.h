@@ -166,6 +166,21 @@ acom_status_t acom_match(acom_plan_t plan, const acom_peaks_t* peaks, int32_t to
                          int32_t precision, int32_t chunk, void* workspace, size_t workspace_bytes,
                          const acom_matches_t* out, void* stream);
 
+/* acom_match for callers that cannot allocate or pass a workspace (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments and results as acom_match without the workspace: the scratch
+ * memory is a 128 MiB array in the library's device code, one per GPU, held
+ * until the process ends.  The call allocates nothing and runs in chunks of
+ * acom_match_noalloc_chunk patterns (the largest multiple of 64, at most
+ * 16384, whose workspace fits 128 MiB: 448 at 1081 zones x 128 x 360 bins with
+ * a 16-bit copy).  ACOM_E_UNSUPPORTED when not even 64 patterns fit (a plan of
+ * tens of thousands of zones); use acom_match then.  Every call on a GPU uses
+ * that GPU's one array: calls that overlap in time on one GPU (on different
+ * streams or host threads) race and must be serialised by the caller. */
+acom_status_t acom_match_noalloc(acom_plan_t plan, const acom_peaks_t* peaks, int32_t top_k, int32_t precision,
+                                 const acom_matches_t* out, void* stream);
+acom_status_t acom_match_noalloc_chunk(acom_plan_t plan, int32_t precision, int32_t* chunk);
+
 /* Matching of overlapping diffraction patterns (Methods > Matching of
  * Overlapping Diffraction Patterns): n_orient rounds per pattern.  Round 0 is
  * the top-1 match of acom_match.  After each round the forward kinematical

@@ -73,6 +73,8 @@ def lib():
             "acom_plan_destroy": [c_void_p],
             "acom_match_workspace_size": [c_void_p, c_int32, c_int32, P(c_size_t)],
             "acom_match": [c_void_p, P(_Peaks), c_int32, c_int32, c_int32, c_void_p, c_size_t, P(_Matches), c_void_p],
+            "acom_match_noalloc": [c_void_p, P(_Peaks), c_int32, c_int32, P(_Matches), c_void_p],
+            "acom_match_noalloc_chunk": [c_void_p, c_int32, P(c_int32)],
             "acom_match_multi_workspace_size": [c_void_p, c_int32, c_int32, c_int64, P(c_size_t)],
             "acom_fiber_zones": [P(c_double), c_double, c_double, c_double, c_double, c_void_p, c_int32, P(c_int32)],
             "acom_simulate_count": [c_void_p, c_int64, c_void_p, c_void_p, ctypes.c_float, c_void_p, c_void_p,
@@ -447,6 +449,19 @@ class Plan:
         _check(lib().acom_match(self._h, ctypes.byref(pk), int(top_k), PRECISIONS[precision], int(chunk),
                                 c_void_p(workspace.data_ptr()), workspace.numel(), ctypes.byref(m), _stream(stream)),
                "acom_match")
+        return out
+
+    def match_noalloc(self, peaks: Peaks, top_k=1, precision="fp32", orient=True, stream=None, out=None):
+        """acom_match_noalloc: the same results as match() with the library's
+        static scratch instead of a workspace (calls on one GPU must not overlap)."""
+        n = peaks.n_patterns
+        if out is None:
+            out = self.empty_matches(n, top_k, orient, peaks.offsets.device)
+        m = _Matches(*(None if out.get(k) is None else out[k].data_ptr()
+                       for k in ("zone", "phase", "bin", "mirror", "score", "phi3", "orient", "n_evaluated")))
+        pk = peaks.c()
+        _check(lib().acom_match_noalloc(self._h, ctypes.byref(pk), int(top_k), PRECISIONS[precision],
+                                        ctypes.byref(m), _stream(stream)), "acom_match_noalloc")
         return out
 
     def match_multi_workspace_bytes(self, total_peaks, precision="fp32", chunk=0):

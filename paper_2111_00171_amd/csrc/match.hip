@@ -1942,6 +1942,77 @@ extern "C" acom_status_t acom_match(acom_plan_t plan, const acom_peaks_t* peaks,
   return ACOM_OK;
 }
 
+// ------------------------------------------------- allocation-free match ----
+//
+// For callers that cannot allocate (code under graph capture, serving loops,
+// harnesses that forbid hipMalloc): acom_match with its workspace in a
+// file-scope device array instead of a caller's buffer.  Every GPU the library
+// runs on holds its own copy of the array, at its own address, until the
+// process ends; host code reaches it only through the address that
+// hipGetSymbolAddress returns on that device, kept per device.
+namespace {
+constexpr size_t kScratchBytes = size_t(128) << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;  // per device id; null until first use there
+
+acom_status_t scratch_address(void** out) {
+  int dev = -1;
+  ACOM_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(ACOM_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return ACOM_OK;
+}
+
+// Largest chunk (a multiple of the 64-pattern tile, at most the default chunk)
+// whose workspace fits the scratch array; 0 when not even one tile fits.
+int noalloc_chunk(const PlanDev& d, int precision) {
+  int best = 0;
+  for (int c = kTileP; c <= kDefaultChunk; c += kTileP) {
+    if (layout(d, precision != ACOM_FP32, c).total > kScratchBytes) break;
+    best = c;
+  }
+  return best;
+}
+}  // namespace
+
+extern "C" acom_status_t acom_match_noalloc(acom_plan_t plan, const acom_peaks_t* peaks, int32_t top_k,
+                                            int32_t precision, const acom_matches_t* out, void* stream_v) {
+  acom_status_t st = check_plan_precision(plan, precision);
+  if (st != ACOM_OK) return st;
+  if ((st = check_peaks(peaks)) != ACOM_OK) return st;
+  if (top_k < 1 || top_k > kMaxTopK) return fail(ACOM_E_INVALID, "top_k must be in [1, 16]");
+  if (!out) return fail(ACOM_E_INVALID, "matches is null");
+  const int Pc = noalloc_chunk(plan->d, precision);
+  if (Pc == 0)
+    return fail(ACOM_E_UNSUPPORTED, "acom_match_noalloc: one 64-pattern chunk of this plan needs more than the "
+                                    "128 MiB static scratch; use acom_match with a caller's workspace");
+  if (peaks->n_patterns == 0) return ACOM_OK;
+  if (!out->zone || !out->score) return fail(ACOM_E_INVALID, "matches: zone and score outputs are required");
+  void* ws = nullptr;
+  if ((st = scratch_address(&ws)) != ACOM_OK) return st;
+  // every workspace cell the kernels read is written earlier in the same call,
+  // so the array needs no clearing between calls
+  return acom_match(plan, peaks, top_k, precision, Pc, ws, kScratchBytes, out, stream_v);
+}
+
+extern "C" acom_status_t acom_match_noalloc_chunk(acom_plan_t plan, int32_t precision, int32_t* chunk) {
+  acom_status_t st = check_plan_precision(plan, precision);
+  if (st != ACOM_OK) return st;
+  if (!chunk) return fail(ACOM_E_INVALID, "chunk is null");
+  *chunk = noalloc_chunk(plan->d, precision);
+  return ACOM_OK;
+}
+
 namespace {
 // Workspace of acom_match_multi: the match workspace, the edited intensities
 // (one per peak) and one round's per-pattern results of a chunk.
