@@ -62,6 +62,7 @@ PLAN_CFG = {  # phases and plan parameters of each workload
     "refine": (["fcc"], dict(k_max=2.0, n_radial=128, n_angular=360, zone_step_deg=1.0)),
     "overlap": (["fcc"], dict(k_max=2.0, n_radial=128, n_angular=360, zone_step_deg=1.0)),
     "simulate": (["fcc"], dict(k_max=2.0, n_radial=128, n_angular=360, zone_step_deg=1.0)),
+    "hard": (["fcc"], dict(k_max=2.0, n_radial=128, n_angular=360, zone_step_deg=1.0)),
 }
 DESCR = {
     "scan": "scan: 256x256 FCC scan, 65,536 patterns x 10-60 peaks, 1-degree plan (1081 zones), "
@@ -70,6 +71,8 @@ DESCR = {
            "top-8 FP32 rescoring",
     "multi": "multi: 512x512 three-phase scan (FCC 4.08 + BCC 2.87 + HCP), 262,144 patterns x 3-150 peaks, "
              "10,443 zones, 128 x 360 bins, top-1, BF16 contraction, one HIP-graph replay per step",
+    "hard": "hard: the 256x256 FCC scan with degraded peak lists (20% of real peaks dropped, intensities x (1 + 0.3 "
+            "N(0,1)), 5-10 spurious peaks each), 1081 zones, 128 x 360 bins, top-1",
     "refine": "refine: 65,536 FCC patterns at random orientations, top-4 grid candidates (FP32 contraction) "
               "refined by gradient ascent on the continuous score (<= 64 trials each)",
     "overlap": "overlap: 65,536 FCC patterns, each two overlapping grains (second at 0.4-0.9 intensity), "
@@ -136,6 +139,22 @@ def measured_traffic(precision, launches_patterns):
     if not e or e.get("patterns_per_launch") != launches_patterns:
         return None
     return e["bytes_per_launch"]
+
+
+def bound_flop_per_pattern(gpl):
+    """Algorithmic FLOP per pattern of the contraction pass's split bound:
+    for every zone, the four real products of the Kc exact frequencies
+    (8 Kc N_r) and one multiply-add per block-norm entry of the rest
+    (2 (N_phi/2 + 1 - Kc) ceil(N_r / block))."""
+    kc, bb = gpl.bound_split()
+    nk, R = gpl.n_angular // 2 + 1, gpl.n_radial
+    return float(gpl.n_zones) * (8.0 * kc * R + 2.0 * (nk - kc) * (-(-R // bb)))
+
+
+def full_contraction_flop_per_pattern(gpl):
+    """8 Z (N_phi/2 + 1) N_r: every frequency's complex contraction, which the
+    split bound replaces above Kc."""
+    return 8.0 * gpl.n_zones * (gpl.n_angular // 2 + 1) * gpl.n_radial
 
 
 def _oracle_plan(workload):
@@ -328,13 +347,14 @@ def run_match_workload(args, workload, defer_oracle=False):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     gpl = acom.Plan([{"fcc": acom.fcc, "bcc": acom.bcc, "hcp": acom.hcp}[k]() for k in phases],
-                    acom.PlanParams(precisions=precs, **cfg))
+                    acom.PlanParams(precisions=precs, bound_exact_freqs=args.bound_exact_freqs,
+                                    bound_block_radii=args.bound_block_radii, **cfg))
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
     n = len(d["offsets"]) - 1
     pk = acom.Peaks.from_host(d)
     Z, R, N = gpl.n_zones, gpl.n_radial, gpl.n_angular
-    flop_per_pattern = 8.0 * Z * (N // 2 + 1) * R
+    flop_per_pattern = bound_flop_per_pattern(gpl)
     runs, host = {}, {}
     log(f"{workload}: plan built ({Z} zones, {t_plan:.1f} s)")
     for prec in precs:
@@ -358,8 +378,11 @@ def run_match_workload(args, workload, defer_oracle=False):
         mis = [metrics.misorientation_deg(host[main_prec]["orient"][p, 0], d["truth"][p], G) for p in idx]
         extra["misorientation_vs_truth_deg"] = {"median": float(np.median(mis)), "p90": float(np.percentile(mis, 90)),
                                                 "patterns": 256, "precision": main_prec}
+    kc, bb = gpl.bound_split()
     ccfg = {"patterns": n, "peaks": int(d["offsets"][-1]), "zones": Z, "n_radial": R, "n_angular": N,
-            "chunk": args.chunk, "top_k": top_k}
+            "chunk": args.chunk, "top_k": top_k, "bound_exact_freqs": kc, "bound_block_radii": bb}
+    extra["bound_flop_per_pattern"] = flop_per_pattern
+    extra["full_contraction_flop_per_pattern"] = full_contraction_flop_per_pattern(gpl)
     r = runs[main_prec]
     out = line(workload, r["value"], r["ms_per_step"], args.steps, args.warmup,
                {"fp32": "f32", "bf16": "bf16", "fp16": "f16"}[main_prec], ccfg,
@@ -391,7 +414,7 @@ def run_multi(args):
     n = len(d["offsets"]) - 1
     pk = acom.Peaks.from_host(d)
     Z, R, N = gpl.n_zones, gpl.n_radial, gpl.n_angular
-    flop_per_pattern = 8.0 * Z * (N // 2 + 1) * R
+    flop_per_pattern = bound_flop_per_pattern(gpl)
     # kernel averages and the contraction roofline from an eager profiled run
     log(f"multi: plan built ({Z} zones, {t_plan:.1f} s)")
     run, host = time_match(gpl, pk, prec, 1, args.chunk, 2, 1, n, flop_per_pattern)
@@ -474,7 +497,7 @@ def run_refine(args):
     prof = acom.profile_read()
     acom.profile_end()
     Z, R, N = gpl.n_zones, gpl.n_radial, gpl.n_angular
-    flop_per_pattern = 8.0 * Z * (N // 2 + 1) * R
+    flop_per_pattern = bound_flop_per_pattern(gpl)
     b_ms = prof["bound"][0] / prof["bound"][1]
     per_launch = min(args.chunk, n)
     tflops = flop_per_pattern * per_launch / (b_ms * 1e-3) / 1e12
@@ -592,7 +615,7 @@ def run_overlap(args):
     n = len(d["offsets"]) - 1
     pk = acom.Peaks.from_host(d)
     Z, R, N = gpl.n_zones, gpl.n_radial, gpl.n_angular
-    flop_per_pattern = 8.0 * Z * (N // 2 + 1) * R
+    flop_per_pattern = bound_flop_per_pattern(gpl)
     ws = torch.empty(gpl.match_multi_workspace_bytes(pk.total_peaks, prec, args.chunk), dtype=torch.uint8,
                      device="cuda")
     shape = gpl.autotune(pk, prec, args.chunk, ws)
@@ -791,7 +814,7 @@ def run_pipeline(args):
     phases, cfg = PLAN_CFG["scan"]
     gpl = acom.Plan([acom.fcc()], acom.PlanParams(precisions=[prec], **cfg))
     Z, R, Nphi = gpl.n_zones, gpl.n_radial, gpl.n_angular
-    flop_per_pattern = 8.0 * Z * (Nphi // 2 + 1) * R
+    flop_per_pattern = bound_flop_per_pattern(gpl)
     cap = tuple(torch.empty(n * det.max_peaks, dtype=torch.float32, device="cuda") for _ in range(3))
     ws = torch.empty(gpl.match_workspace_bytes(prec, args.chunk), dtype=torch.uint8, device="cuda")
     out = gpl.empty_matches(n, 1, True, "cuda")
@@ -871,13 +894,15 @@ def oracle_extra_samples(n_threads, n_sample=64):
     plans = {k: helpers.oracle_plan([k], **cfg) for k in ("fcc", "bcc", "hcp")}
     t_plan = time.perf_counter() - t0
     out = {"plan_s": t_plan, "threads": n_threads}
-    for name, seed in (("hcp", 3003), ("multi", 3004)):
+    for name, seed in (("hcp", 3003), ("multi", 3004), ("hard", 3008)):
         d = synth.make(name)
         n = len(d["offsets"]) - 1
         idx = np.sort(np.random.default_rng(seed).choice(n, n_sample, replace=False))
         sub = synth.subset(d, idx)
         if name == "hcp":
             pl = plans["hcp"]
+        elif name == "hard":
+            pl = plans["fcc"]
         else:
             pl = dict(plans["fcc"])
             pl["P"] = np.concatenate([plans[k]["P"] for k in ("fcc", "bcc", "hcp")])
@@ -966,7 +991,7 @@ def extra_workloads(args, fut):
     phases, cfg = PLAN_CFG["hcp"]
     gpl = acom.Plan([acom.hcp()], acom.PlanParams(precisions=["fp32", "bf16", "fp16"], **cfg))
     pk = acom.Peaks.from_host(d)
-    fpp = 8.0 * gpl.n_zones * (gpl.n_angular // 2 + 1) * gpl.n_radial
+    fpp = bound_flop_per_pattern(gpl)
     runs, host = {}, {}
     t0 = time.perf_counter()
     for prec in ("bf16", "fp16", "fp32"):
@@ -978,13 +1003,34 @@ def extra_workloads(args, fut):
                   "roofline_bf16": roofline(runs, "bf16", min(args.chunk, n), fpp, None)}
     del gpl, pk
     torch.cuda.empty_cache()
+    # --- the scan with degraded peak lists, BF16 and FP32
+    dh = synth.make("hard")
+    nh = len(dh["offsets"]) - 1
+    gpl = acom.Plan([acom.fcc()], acom.PlanParams(precisions=["fp32", "bf16"], **PLAN_CFG["hard"][1]))
+    pk = acom.Peaks.from_host(dh)
+    fpph = bound_flop_per_pattern(gpl)
+    runs_h, host_h = {}, {}
+    t0 = time.perf_counter()
+    for prec in ("bf16", "fp32"):
+        runs_h[prec], host_h[prec] = time_match(gpl, pk, prec, 1, args.chunk, 3, 1, nh, fpph)
+        log(f"hard (extra): {prec} {runs_h[prec]['value']:.0f} patterns/s")
+    out["hard"] = {"workload": DESCR["hard"], "patterns": nh, "peaks_mean": float(np.diff(dh["offsets"]).mean()),
+                   "steps": 3, "by_precision": by_precision(runs_h), "timed_s": round(time.perf_counter() - t0, 2)}
+    Gc = metrics.cubic_rotations()
+    idx_h = np.random.default_rng(7).choice(nh, 256, replace=False)
+    mis_h = [metrics.misorientation_deg(host_h["bf16"]["orient"][p, 0], dh["truth"][p], Gc) for p in idx_h]
+    out["hard"]["misorientation_vs_truth_deg"] = {"median": float(np.median(mis_h)),
+                                                  "within_2deg": float(np.mean(np.array(mis_h) < 2.0)),
+                                                  "patterns": 256, "precision": "bf16"}
+    del gpl, pk
+    torch.cuda.empty_cache()
     # --- three-phase scan, BF16, one HIP graph per step
     d3 = synth.make("multi")
     n3 = len(d3["offsets"]) - 1
     phases, cfg = PLAN_CFG["multi"]
     gpl = acom.Plan([acom.fcc(), acom.bcc(), acom.hcp()], acom.PlanParams(precisions=["bf16"], **cfg))
     pk = acom.Peaks.from_host(d3)
-    fpp3 = 8.0 * gpl.n_zones * (gpl.n_angular // 2 + 1) * gpl.n_radial
+    fpp3 = bound_flop_per_pattern(gpl)
     t0 = time.perf_counter()
     run3, host3 = time_match(gpl, pk, "bf16", 1, args.chunk, 1, 1, n3, fpp3)
     ws = torch.empty(gpl.match_workspace_bytes("bf16", args.chunk), dtype=torch.uint8, device="cuda")
@@ -1050,13 +1096,16 @@ def extra_workloads(args, fut):
     for prec in ("bf16", "fp16", "fp32"):
         out["hcp"]["by_precision"][prec]["argmax_match_vs_oracle"] = _agreement(samples["hcp"], host[prec], prec)
     out["multi"]["argmax_match_vs_oracle"] = _agreement(samples["multi"], host3, "bf16")
+    for prec in ("bf16", "fp32"):
+        out["hard"]["by_precision"][prec]["argmax_match_vs_oracle"] = _agreement(samples["hard"], host_h[prec], prec)
     zp = samples["multi"]["zone_phase"]
     out["multi"]["argmax_match_vs_oracle"]["phase_equal"] = float(np.mean(
         [zp[int(host3["zone"][p, 0])] == zp[int(np.argmax(samples["multi"]["score"][i]))]
          for i, p in enumerate(samples["multi"]["idx"])]))
     out["oracle_worker"] = {"plan_build_s": round(samples["plan_s"], 1), "threads": samples["threads"],
                             "hcp_sample_s": round(samples["hcp"]["seconds"], 1),
-                            "multi_sample_s": round(samples["multi"]["seconds"], 1)}
+                            "multi_sample_s": round(samples["multi"]["seconds"], 1),
+                            "hard_sample_s": round(samples["hard"]["seconds"], 1)}
     o = dr["offsets"]
     idx_r = np.sort(np.random.default_rng(3005).choice(nr, 64, replace=False))
     jobs = [(dr["qx"][o[p]:o[p + 1]].astype(np.float64), dr["qy"][o[p]:o[p + 1]].astype(np.float64),
@@ -1086,13 +1135,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="scan", choices=["scan", "hcp", "multi", "refine", "overlap", "simulate",
-                                                             "detect", "pipeline"])
+    ap.add_argument("--workload", default="scan", choices=["scan", "hcp", "hard", "multi", "refine", "overlap",
+                                                             "simulate", "detect", "pipeline"])
     ap.add_argument("--precisions", default=None,
                     help="comma list; the first is `value` (scan: fp32,bf16,fp16; hcp: bf16,fp16,fp32)")
     ap.add_argument("--chunk", type=int, default=65536,
                     help="patterns per internal launch (65,536: one launch per step on the scan; ~19 GB of workspace)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--bound-exact-freqs", type=int, default=0,
+                    help="plan parameter bound_exact_freqs (0: the library's default)")
+    ap.add_argument("--bound-block-radii", type=int, default=0,
+                    help="plan parameter bound_block_radii (0: the library's default)")
     ap.add_argument("--no-extra", action="store_true",
                     help="default run: skip the HCP, three-phase and refinement extra keys")
     ap.add_argument("--rounds", type=int, default=2,
@@ -1124,7 +1177,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    if args.workload in ("scan", "hcp"):
+    if args.workload in ("scan", "hcp", "hard"):
         out = run_match_workload(args, args.workload, defer_oracle=extra)
     elif args.workload == "multi":
         out = run_multi(args)

@@ -90,6 +90,10 @@ typedef struct {
   int32_t kernel;        /* acom_kernel_t */
   int32_t precisions;    /* bit mask of (1 << acom_precision_t) operand copies to build; FP32 is always built */
   int32_t keep_f64;      /* nonzero: keep the FP64 angular plan for acom_plan_copy_f64 */
+  int32_t bound_exact_freqs;  /* split bound of acom_match: frequencies k < Kc bounded by their exact
+                                 correlogram spectra; 0 -> Kc = min(N_phi/2 + 1, 32) */
+  int32_t bound_block_radii;  /* radii per block of the Cauchy-Schwarz bound for k >= Kc: 2, 4, 8 or 16
+                                 (0 -> 8) */
 } acom_plan_params_t;
 
 typedef struct acom_plan_s* acom_plan_t;
@@ -138,6 +142,11 @@ acom_status_t acom_plan_info(acom_plan_t plan, int32_t* n_zones, int32_t* n_radi
                              int32_t* n_angular, int32_t* n_phases, double* q_s, double* zones,
                              int32_t* zone_phase, double* norm_A);
 
+/* The split of the contraction pass's bound (see acom_match): Kc exact
+ * frequencies and the radii per block of the Cauchy-Schwarz part; either
+ * pointer may be NULL. */
+acom_status_t acom_plan_bound_split(acom_plan_t plan, int32_t* exact_freqs, int32_t* block_radii);
+
 /* Copy the FP64 angular plan P[z][a][s] (Z x N_phi x N_r) to host memory.
  * Requires keep_f64 at build time, else ACOM_E_UNSUPPORTED. */
 acom_status_t acom_plan_copy_f64(acom_plan_t plan, double* host_P);
@@ -155,11 +164,15 @@ acom_status_t acom_match_workspace_size(acom_plan_t plan, int32_t precision, int
  * sparse polar image X (Eq. image_polar), its FFT along phi3, the per-frequency
  * contraction sum_s FFT{P}^* FFT{X} for C and FFT{P}^* FFT{X}^* for C_mirror, the
  * inverse FFT, and the maximum over zones, in-plane bins and the two branches.
- * The contraction runs in `precision`; every reported score is recomputed in
- * FP32 from the FP32 plan, and a zone is skipped only when the upper bound
- * (1/N) sum_k max(|G_k|, |G_m,k|) of its two correlograms (computed in
- * `precision`, widened by a precision-dependent margin) is below the current
- * top_k-th exact score.
+ * Every reported score is computed exactly in FP32 from the FP32 plan; a zone is
+ * skipped only when an upper bound of both its correlograms is below the
+ * current top_k-th exact score.  The bound, computed in `precision` on MFMA
+ * and widened by a precision-dependent margin, is
+ *   U = (1/N) sum_k w_k T_k  (half spectrum; w_k = 1 at k = 0 and N/2, else 2),
+ *   T_k = max(|G_k|, |G_m,k|)                     for k < Kc,
+ *   T_k = sum_b ||FFT{P}_k,b|| ||FFT{X}_k,b||     for k >= Kc (Cauchy-Schwarz
+ *         on blocks b of bound_block_radii radii),
+ * with Kc and the block size set at plan build (acom_plan_bound_split).
  * Adds a 3-point parabolic sub-bin offset and the orientation matrix.
  * top_k in [1, 16]; `chunk` must equal the value given to the size query. */
 acom_status_t acom_match(acom_plan_t plan, const acom_peaks_t* peaks, int32_t top_k,
@@ -215,7 +228,7 @@ acom_status_t acom_match_multi(acom_plan_t plan, const acom_peaks_t* peaks, int3
  * this precision use it.  The plan is not modified.  Results of acom_match do
  * not depend on the shape.  Synchronous.  `workspace` as for
  * acom_match with the same `chunk`.  shape [host, 3] (tile: 0 = 64 x 64,
- * 1 = large, 3 = 128 x 128 two-group schedule (16-bit operands); radii per LDS step, 16 or 32 for FP32 operands and 32, 64 or 128
+ * 1 = large; radii per LDS step, 16 or 32 for FP32 operands and 32, 64 or 128
  * for 16-bit ones; order) and ms [host] (one launch of the fastest shape) may
  * be NULL. */
 acom_status_t acom_autotune(acom_plan_t plan, const acom_peaks_t* peaks, int32_t precision, int32_t chunk,
@@ -306,8 +319,7 @@ acom_status_t acom_profile_end(void);
  *        0 = pattern index fastest;
  * key 4: contraction block tile, 0 = 64 x 64, 1 = large (128 x 128; 128 x 64 for FP32 operands),
  *        2 = large for BF16/FP16 operands when it gives at least two tiles per compute unit,
- *        else 64 x 64 (default),
- *        3 = 128 x 128 on the two-group schedule (BF16/FP16 operands only; 32-radius steps);
+ *        else 64 x 64 (default);
  * key 5: 1 = the contraction skips the leading radii where the plan is zero in every zone
  *        (exact: those terms are zeros; default), 0 = it runs over all radii;
  * key 6: radii staged per LDS step by the FP32 contraction: 16 (default) or 32;

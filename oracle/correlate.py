@@ -61,19 +61,43 @@ def correlate_fft(P, X):
     return C, Cm
 
 
-def spectral_bound(P, X):
-    """U[z] = (1/N) sum_{k=0}^{N-1} max(|G_k|, |G'_k|) with
-    G_k = sum_s conj(Phat_ks) Xhat_ks and G'_k the same with Xhat^* (mirror).
+def spectral_bound(P, X, exact_freqs=None, block=8):
+    """U[z] >= max_n max(C, C_mirror)[z, n], an upper bound used to skip zones
+    that cannot win.  Not a quantity of the paper.
 
-    Not a quantity of the paper: an upper bound on max_n max(C, C_mirror)[z, n]
-    (triangle inequality on the inverse DFT of either branch, then the larger
-    modulus per frequency), used to skip zones that cannot win."""
-    Ph = np.fft.fft(np.asarray(P, dtype=np.float64), axis=1)
-    Xh = np.fft.fft(np.asarray(X, dtype=np.float64), axis=0)
-    N = Ph.shape[1]
-    G = np.sum(np.conj(Ph) * Xh[None], axis=2)
-    Gm = np.sum(np.conj(Ph) * np.conj(Xh)[None], axis=2)
-    return np.maximum(np.abs(G), np.abs(Gm)).sum(axis=1) / N
+    Over the half spectrum k = 0 .. N/2 (w_k = 1 at k = 0 and N/2, else 2, so
+    the full spectrum is counted; |G_{N-k}| = |G_k| for real P and X):
+
+      U[z] = (1/N) sum_k w_k T_k[z],
+      T_k = max(|G_k|, |G'_k|)                        for k <  exact_freqs,
+      T_k = sum_b ||Phat_{k,b}|| ||Xhat_{k,b}||       for k >= exact_freqs,
+
+    with G_k = sum_s conj(Phat_ks) Xhat_ks, G'_k the same with conj(Xhat)
+    (mirror), and b the blocks of `block` consecutive radii (the last one
+    shorter when the radial count is not a multiple).  The first form is the
+    triangle inequality on the inverse DFT of either branch with the larger
+    modulus per frequency; the second bounds both moduli by Cauchy-Schwarz on
+    each radial block.  exact_freqs = None (or >= N/2 + 1): every frequency
+    takes the first form."""
+    Ph = np.fft.rfft(np.asarray(P, dtype=np.float64), axis=1)    # [Z, Nk, R]
+    Xh = np.fft.rfft(np.asarray(X, dtype=np.float64), axis=0)    # [Nk, R]
+    N = np.asarray(P).shape[1]
+    Nk = Ph.shape[1]
+    w = np.full(Nk, 2.0)
+    w[0] = 1.0
+    if N % 2 == 0:
+        w[-1] = 1.0
+    kc = Nk if exact_freqs is None else min(int(exact_freqs), Nk)
+    G = np.sum(np.conj(Ph[:, :kc]) * Xh[None, :kc], axis=2)
+    Gm = np.sum(np.conj(Ph[:, :kc]) * np.conj(Xh)[None, :kc], axis=2)
+    U = (w[:kc] * np.maximum(np.abs(G), np.abs(Gm))).sum(axis=1)
+    if kc < Nk:
+        R = Xh.shape[1]
+        for b0 in range(0, R, block):
+            xb = np.sqrt(np.sum(np.abs(Xh[kc:, b0:b0 + block]) ** 2, axis=1))          # [Nk - kc]
+            pb = np.sqrt(np.sum(np.abs(Ph[:, kc:, b0:b0 + block]) ** 2, axis=2))     # [Z, Nk - kc]
+            U += pb @ (w[kc:] * xb)
+    return U / N
 
 
 def zone_best(C, Cm):

@@ -35,7 +35,8 @@ class _Params(ctypes.Structure):
     _fields_ = [("k_max", c_double), ("delta", c_double), ("gamma", c_double), ("omega", c_double),
                 ("accel_kV", c_double), ("zone_step_deg", c_double), ("gauss_sigma", c_double),
                 ("sigma_exc", c_double), ("n_radial", c_int32), ("n_angular", c_int32), ("radial", c_int32),
-                ("kernel", c_int32), ("precisions", c_int32), ("keep_f64", c_int32)]
+                ("kernel", c_int32), ("precisions", c_int32), ("keep_f64", c_int32),
+                ("bound_exact_freqs", c_int32), ("bound_block_radii", c_int32)]
 
 
 class _Peaks(ctypes.Structure):
@@ -70,6 +71,7 @@ def lib():
             "acom_plan_info": [c_void_p, P(c_int32), P(c_int32), P(c_int32), P(c_int32), P(c_double), P(c_double),
                                P(c_int32), P(c_double)],
             "acom_plan_copy_f64": [c_void_p, P(c_double)],
+            "acom_plan_bound_split": [c_void_p, P(c_int32), P(c_int32)],
             "acom_plan_destroy": [c_void_p],
             "acom_match_workspace_size": [c_void_p, c_int32, c_int32, P(c_size_t)],
             "acom_match": [c_void_p, P(_Peaks), c_int32, c_int32, c_int32, c_void_p, c_size_t, P(_Matches), c_void_p],
@@ -234,6 +236,8 @@ class PlanParams:
     sigma_exc: float = 0.02
     precisions: Sequence[str] = field(default_factory=lambda: ["fp32"])
     keep_f64: bool = False
+    bound_exact_freqs: int = 0      # 0: the library's default split
+    bound_block_radii: int = 0
 
 
 class Peaks:
@@ -350,6 +354,8 @@ class Plan:
         prm.kernel = params.kernel
         prm.precisions = sum(1 << PRECISIONS[p] for p in params.precisions)
         prm.keep_f64 = 1 if params.keep_f64 else 0
+        prm.bound_exact_freqs = params.bound_exact_freqs
+        prm.bound_block_radii = params.bound_block_radii
         h = c_void_p()
         _check(L.acom_build_plan(arr, len(phases), ctypes.byref(prm), _stream(stream), ctypes.byref(h)),
                "acom_build_plan")
@@ -405,6 +411,12 @@ class Plan:
         _check(lib().acom_plan_info(self._h, None, None, None, None, qs, zs, zp, A), "acom_plan_info")
         return {"q_s": np.array(qs[:]), "zones": np.array(zs[:]).reshape(Z, 3), "zone_phase": np.array(zp[:]),
                 "norm_A": np.array(A[:])}
+
+    def bound_split(self):
+        """(Kc, radii per block) of the contraction pass's split bound."""
+        kc, bb = c_int32(), c_int32()
+        _check(lib().acom_plan_bound_split(self._h, ctypes.byref(kc), ctypes.byref(bb)), "acom_plan_bound_split")
+        return kc.value, bb.value
 
     def angular_f64(self):
         import numpy as np
@@ -539,7 +551,7 @@ class Plan:
         _check(lib().acom_autotune(self._h, ctypes.byref(pk), PRECISIONS[precision], int(chunk),
                                    c_void_p(workspace.data_ptr()), workspace.numel(), _stream(stream), shape,
                                    ctypes.byref(ms)), "acom_autotune")
-        tile = {0: "64x64", 1: "large", 3: "128x128 two-group"}.get(shape[0], str(shape[0]))
+        tile = {0: "64x64", 1: "large"}.get(shape[0], str(shape[0]))
         return {"tile": tile, "radii_per_step": shape[1], "order": shape[2], "ms": ms.value}
 
     @staticmethod
@@ -656,7 +668,7 @@ TUNING_KEYS = {"bound_order": 0, "bound_kch16": 1, "exact_xcd": 2, "polar_xcd": 
 def set_tuning(**kw):
     """Launch-shape knobs of the calling thread (results do not depend on them):
     bound_order (0/1), bound_kch16 (32/64/128), exact_xcd (0/1), polar_xcd (0/1),
-    bound_tile (0/1/2/3), skip_zero_radii (0/1), bound_kch32 (16/32), polar_cols
+    bound_tile (0/1/2), skip_zero_radii (0/1), bound_kch32 (16/32), polar_cols
     (16/32), exact_u_lds_max (zones whose bound row the exact pass keeps in LDS)."""
     for k, v in kw.items():
         _check(lib().acom_set_tuning(TUNING_KEYS[k], int(v)), "acom_set_tuning")

@@ -52,6 +52,17 @@ struct PlanDev {
   int Z = 0, Zp = 0;        // zones, zones padded to kTileZ
   int R = 0, Rp = 0;        // radial bins, padded to kSChunk
   int r0 = 0;               // leading radial bins where FFT{P} is zero in every zone
+  // Split bound of the contraction pass: frequencies k < Kc are bounded by the
+  // larger modulus of the two correlogram spectra, k >= Kc by Cauchy-Schwarz on
+  // blocks of bb radii.  The block norms form a vector of L = (Nk - Kc) nb
+  // entries per zone (and per pattern) that the operand arrays carry in
+  // npseudo extra rows after the frequency rows, Sp = Rp - r0 entries in the
+  // real and Sp in the imaginary array of each row (slots r0 .. Rp-1; slots
+  // below r0 hold zeros).  Rows per 64-row tile: rows32 = Nk + npseudo for the
+  // FP32 operands (the exact pass reads rows < Nk), rows16 = Kc + npseudo for
+  // the 16-bit copies.
+  int Kc = 0, bb = 8, nb = 0, Sp = 0, npseudo = 0, rows32 = 0, rows16 = 0;
+  int64_t L = 0;
   int N = 0, Nk = 0;        // angular bins, N/2 + 1
   int n_phases = 0;
   Radices rad;

@@ -71,6 +71,18 @@ __device__ __forceinline__ uint16_t to_f16_bits(float v) {
   __half h = __float2half(v);
   return *reinterpret_cast<uint16_t*>(&h);
 }
+// Nonnegative v rounded up to the next representable 16-bit value when
+// round-to-nearest went below it: the split bound's block norms never shrink.
+__device__ __forceinline__ uint16_t to_bf16_bits_up(float v) {
+  const uint16_t b = to_bf16_bits(v);
+  return __uint_as_float((uint32_t)b << 16) < v ? (uint16_t)(b + 1) : b;
+}
+__device__ __forceinline__ uint16_t to_f16_bits_up(float v) {
+  const uint16_t b = to_f16_bits(v);
+  __half t;
+  *reinterpret_cast<uint16_t*>(&t) = b;
+  return __half2float(t) < v ? (uint16_t)(b + 1) : b;
+}
 
 // XCD-aware block order: the hardware deals workgroup b to XCD b % 8, so
 // logical work item w = (b % 8) * per + b / 8 gives every XCD a contiguous range
@@ -103,8 +115,16 @@ struct PolarArgs {
   float *xr, *xi;
   size_t ld_tile, ldk;
   int ldp, out_cols;
-  uint16_t *lr, *li;       // low-precision copies (same layout) or null
+  uint16_t *lr, *li;       // low-precision copies (rows k < Kc, then the norm rows; tile stride ld_tile16) or null
+  size_t ld_tile16;
   int lowp;                // 0 none, ACOM_BF16, ACOM_FP16
+  // split bound (workspace layout only): block norms w_k ||FFT{X}[k][b bb ..]||
+  // of the frequencies k >= Kc as entries v = (k - Kc) nb + b of the norm
+  // vector, in rows Nk + j (FP32) and Kc + j (16-bit), j = v / 2Sp, at slot
+  // r0 + v mod Sp of the real (v mod 2Sp < Sp) or imaginary array
+  int ws_layout;           // 1: the workspace's tile-major layout (norms written), 0: a caller's layout
+  int Kc, bb, nb, Sp, r0, npseudo;
+  int64_t L;
   float* scale;            // np: factor applied before the FP16 cast (else 1)
   float* xnorm2;           // np: sum of X^2 of the pattern's polar image
   int* flags;              // np: 0 ok, 1 invalid data, 2 no peaks
@@ -149,12 +169,15 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
   float2* b0 = reinterpret_cast<float2*>(smem_raw);   // [rev(a)][NS] complex: columns packed in pairs
   float2* tw = b0 + N * NS;
   int* rev = reinterpret_cast<int*>(tw + N);
-  int* pac = rev + N;
+  // per cached peak: nearest bin |ac| <= N/2 (int16), offset, radius as an
+  // FP32 pair, weight; the listed peaks as cache indices (< 256, one byte):
+  // narrow types keep the kernel small enough for three workgroups per CU
+  int16_t* pac = reinterpret_cast<int16_t*>(rev + N);
   float* pf = reinterpret_cast<float*>(pac + PC);
   float* pq = pf + PC;
   float* pw = pq + PC;
   float* pql = pw + PC;  // q_m - pq (the radius as an FP32 pair)
-  int* plist = reinterpret_cast<int*>(pql + PC);  // cached peaks reaching the current tile
+  uint8_t* plist = reinterpret_cast<uint8_t*>(pql + PC);  // cached peaks reaching the current tile
   float* sqs = reinterpret_cast<float*>(plist + PC);  // q_s of every column (-1 beyond R)
   uint32_t* scmw = reinterpret_cast<uint32_t*>(sqs + a.Rp);  // [16-column tile][wave] column masks
   __shared__ int s_bad, s_nlist;
@@ -199,7 +222,7 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
       const double q = sqrt((double)x * x + (double)y * y);
       const double t = atan2((double)y, (double)x) * inv_dphi;
       const double tr = floor(t + 0.5);
-      pac[tid] = (int)tr;
+      pac[tid] = (int16_t)tr;
       pf[tid] = (float)(t - tr);
       const float qh = (float)q;
       pq[tid] = qh;
@@ -217,6 +240,7 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
   float xx = 0.0f;  // this thread's share of sum X^2 over all tiles (fixed order)
   float* X = reinterpret_cast<float*>(b0);  // X(phi_a, column) at [rev(a)][NC]
   const size_t pbase = (size_t)(p >> 6) * a.ld_tile + (size_t)(p & 63) * a.ldp;
+  const size_t pbase16 = (size_t)(p >> 6) * a.ld_tile16 + (size_t)(p & 63) * a.ldp;
   const int npass = a.Rp / NC;
   for (int tile = 0; tile < npass; ++tile) {
     const int col0 = tile * NC;
@@ -252,7 +276,7 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
           const int j = j0 + tid;
           const bool hit = qlo >= 0.0f && j < cnt && pw[j] != 0.0f && (pq[j] - qhi < rl) && (qlo - pq[j] < rl);
           const unsigned long long m = __ballot(hit);
-          if (hit) plist[base + __popcll(m & ((1ull << tid) - 1ull))] = j;
+          if (hit) plist[base + __popcll(m & ((1ull << tid) - 1ull))] = (uint8_t)j;
           base += __popcll(m);
         }
         if (tid == 0) s_nlist = base;
@@ -315,10 +339,12 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
         for (int w = 0; w < kThreads / 64; ++w) u += s_red64[w];
         float scl = 1.0f;
         if (a.lowp == ACOM_FP16) {
-          // |FFT{X}| <= sum_a X <= N * sum_m w_m; map that bound below 2^14.
+          // |FFT{X}| <= sum_a X <= N * sum_m w_m; map that bound below 2^12,
+          // so that a weighted block norm (at most 2 sqrt(16) times it) stays
+          // below the FP16 maximum.
           const double bound = u * N;
           if (bound > 0.0) {
-            int e = (int)floor(log2(16384.0 / bound));
+            int e = (int)floor(log2(4096.0 / bound));
             e = max(-60, min(60, e));
             scl = ldexpf(1.0f, e);
           }
@@ -366,17 +392,36 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
       nzO = nzO || O.x != 0.0f || O.y != 0.0f;
       const int s0 = col0 + 2 * q;
       const size_t o = pbase + (size_t)k * a.ldk + s0;
-      if (a.out_cols == a.Rp) {  // workspace layout: the column pair is one aligned 8-byte / 4-byte store
+      if (a.ws_layout) {  // workspace layout: the column pair is one aligned 8-byte / 4-byte store
         *reinterpret_cast<float2*>(a.xr + o) = make_float2(E.x, O.x);
         *reinterpret_cast<float2*>(a.xi + o) = make_float2(E.y, O.y);
-        if (a.lowp == ACOM_BF16) {
-          *reinterpret_cast<uint32_t*>(a.lr + o) = (uint32_t)to_bf16_bits(E.x) | ((uint32_t)to_bf16_bits(O.x) << 16);
-          *reinterpret_cast<uint32_t*>(a.li + o) = (uint32_t)to_bf16_bits(E.y) | ((uint32_t)to_bf16_bits(O.y) << 16);
-        } else if (a.lowp == ACOM_FP16) {
-          *reinterpret_cast<uint32_t*>(a.lr + o) =
+        const size_t o16 = pbase16 + (size_t)k * a.ldk + s0;
+        if (a.lowp == ACOM_BF16 && k < a.Kc) {
+          *reinterpret_cast<uint32_t*>(a.lr + o16) = (uint32_t)to_bf16_bits(E.x) | ((uint32_t)to_bf16_bits(O.x) << 16);
+          *reinterpret_cast<uint32_t*>(a.li + o16) = (uint32_t)to_bf16_bits(E.y) | ((uint32_t)to_bf16_bits(O.y) << 16);
+        } else if (a.lowp == ACOM_FP16 && k < a.Kc) {
+          *reinterpret_cast<uint32_t*>(a.lr + o16) =
               (uint32_t)to_f16_bits(E.x * sc) | ((uint32_t)to_f16_bits(O.x * sc) << 16);
-          *reinterpret_cast<uint32_t*>(a.li + o) =
+          *reinterpret_cast<uint32_t*>(a.li + o16) =
               (uint32_t)to_f16_bits(E.y * sc) | ((uint32_t)to_f16_bits(O.y * sc) << 16);
+        }
+        if (a.npseudo > 0) {
+          // block norm over the bb / 2 column pairs of a radial block: they sit
+          // on consecutive lanes of one frequency (NS is a multiple of bb / 2),
+          // which are active together
+          float n2 = k >= a.Kc ? (E.x * E.x + E.y * E.y) + (O.x * O.x + O.y * O.y) : 0.0f;
+          for (int off = 1; off < a.bb / 2; off <<= 1) n2 += __shfl_xor(n2, off, 64);
+          if (k >= a.Kc && (q % (a.bb / 2)) == 0) {
+            const float nrm = wk * __builtin_amdgcn_sqrtf(n2);
+            const int64_t v = (int64_t)(k - a.Kc) * a.nb + s0 / a.bb;
+            const int j = (int)(v / (2 * a.Sp)), e = (int)(v % (2 * a.Sp));
+            const int slot = a.r0 + e % a.Sp;
+            (e < a.Sp ? a.xr : a.xi)[pbase + (size_t)(a.Nk + j) * a.ldk + slot] = nrm;
+            if (a.lowp == ACOM_BF16)
+              (e < a.Sp ? a.lr : a.li)[pbase16 + (size_t)(a.Kc + j) * a.ldk + slot] = to_bf16_bits_up(nrm);
+            else if (a.lowp == ACOM_FP16)
+              (e < a.Sp ? a.lr : a.li)[pbase16 + (size_t)(a.Kc + j) * a.ldk + slot] = to_f16_bits_up(nrm * sc);
+          }
         }
       } else {  // caller's [p][k][s] layout with s < out_cols (verification entry point)
         if (s0 < a.out_cols) {
@@ -412,6 +457,18 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
     }
     __syncthreads();
   }
+  // the norm rows' slots that hold no entry: below r0, and past the vector's end
+  if (a.ws_layout && a.npseudo > 0 && a.do_fft) {
+    auto zero = [&](int j, int part, int slot) {
+      (part ? a.xi : a.xr)[pbase + (size_t)(a.Nk + j) * a.ldk + slot] = 0.0f;
+      if (a.lowp) (part ? a.li : a.lr)[pbase16 + (size_t)(a.Kc + j) * a.ldk + slot] = 0;
+    };
+    for (int i = tid; i < a.npseudo * 2 * a.r0; i += kThreads) zero(i / (2 * a.r0), (i / a.r0) % 2, i % a.r0);
+    for (int64_t v = a.L + tid; v < (int64_t)a.npseudo * 2 * a.Sp; v += kThreads) {
+      const int j = (int)(v / (2 * a.Sp)), e = (int)(v % (2 * a.Sp));
+      zero(j, e >= a.Sp, a.r0 + e % a.Sp);
+    }
+  }
   // per pattern: sum of X^2 (fixed order) and the column masks of every tile
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) xx += __shfl_xor(xx, off, 64);
@@ -435,6 +492,10 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
 
 struct BoundArgs {
   int Nk, Rp, N;
+  // split bound: logical frequencies kk < Kc are the spectrum rows kk (the
+  // larger modulus of G_k and G'_k), kk in [Kc, nlog) the norm rows
+  // hi + kk - Kc (sum of the products of block norms); rows per 64-row tile
+  int Kc, nlog, hi, rows;
   int nP, nZ, per;          // block tiles over patterns and zones, XCD items per XCD
   int nX64, nP64;           // 64-row layout tiles of the pattern and zone operands
   int r0;                   // leading radii where the plan is zero in every zone
@@ -546,14 +607,14 @@ __global__ void __launch_bounds__(64 * WM * WN) bound_kernel(BoundArgs a) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) U[i][j][r] = 0.0f;
 
-  const size_t slab = (size_t)a.Nk * 64 * a.Rp;
+  const size_t slab = (size_t)a.rows * 64 * a.Rp;
   const T* gx[2] = {reinterpret_cast<const T*>(a.xr), reinterpret_cast<const T*>(a.xi)};
   const T* gp[2] = {reinterpret_cast<const T*>(a.pr), reinterpret_cast<const T*>(a.pi)};
   // radii below r0 are zero in every zone's plan: whole steps of them are
   // skipped, and with FP32 operands also the first 16 radii of a step
   const int s_begin = (a.r0 / KCH) * KCH;
   const int steps_per_k = (a.Rp - s_begin) / KCH;
-  const int nsteps = a.Nk * steps_per_k;
+  const int nsteps = a.nlog * steps_per_k;
   const bool skip_h0 = KIND == 0 && KCH == 32 && a.r0 - s_begin >= 16;
 
   // per-lane part of the LDS-direct copies: lane writes bytes [16 lane, +16) of
@@ -576,7 +637,8 @@ __global__ void __launch_bounds__(64 * WM * WN) bound_kernel(BoundArgs a) {
   }
   auto issue = [&](int stp, unsigned char* st) {
     const int k = stp / steps_per_k;
-    const size_t kbase = (size_t)k * 64 * a.Rp + s_begin + (size_t)(stp - k * steps_per_k) * KCH;
+    const int row = k < a.Kc ? k : a.hi + (k - a.Kc);
+    const size_t kbase = (size_t)row * 64 * a.Rp + s_begin + (size_t)(stp - k * steps_per_k) * KCH;
 #pragma unroll
     for (int arr = 0; arr < 2; ++arr)
 #pragma unroll
@@ -603,7 +665,9 @@ __global__ void __launch_bounds__(64 * WM * WN) bound_kernel(BoundArgs a) {
     const unsigned char* sPr = st + 2 * ARRX;
     const unsigned char* sPi = st + 2 * ARRX + ARRP;
     // the first step of a frequency starts its accumulators at 0 (compile-time
-    // operand); H0 = 1 skips the first half of an FP32 step (zero plan radii)
+    // operand); H0 = 1 skips the first half of an FP32 step (zero plan radii).
+    // A norm row runs the same four products (its epilogue uses two): one
+    // MFMA body keeps the register allocation of the spectrum rows.
     auto mma = [&](auto zc, auto hc) {
       constexpr bool Z = decltype(zc)::value;
       constexpr int H0 = decltype(hc)::value;
@@ -686,21 +750,31 @@ __global__ void __launch_bounds__(64 * WM * WN) bound_kernel(BoundArgs a) {
     else
       mma(std::true_type{}, std::integral_constant<int, 0>{});
     const int k = stp / steps_per_k;
-    if (stp - k * steps_per_k == steps_per_k - 1) {  // last radii of frequency k
-      const float wk = (k == 0 || 2 * k == a.N) ? 1.0f : 2.0f;
+    const bool nr = k >= a.Kc;  // a norm row
+    if (stp - k * steps_per_k == steps_per_k - 1) {  // last radii of logical frequency k
+      if (!nr) {
+        const float wk = (k == 0 || 2 * k == a.N) ? 1.0f : 2.0f;
 #pragma unroll
-      for (int i = 0; i < IM; ++i)
+        for (int i = 0; i < IM; ++i)
 #pragma unroll
-        for (int j = 0; j < JN; ++j)
+          for (int j = 0; j < JN; ++j)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const float A = acc[i][j][0][r], B = acc[i][j][1][r], C = acc[i][j][2][r], D = acc[i][j][3][r];
-            // max(|G|^2, |G_mirror|^2) = S + 2 |T|, S = A^2 + B^2 + C^2 + D^2, T = A B - C D
-            const float S = fmaf(A, A, fmaf(B, B, fmaf(C, C, D * D)));
-            const float Tm = fmaf(A, B, -(C * D));
-            // hardware square root (<= 1 ulp): the certificate's relative slack covers it
-            U[i][j][r] += wk * __builtin_amdgcn_sqrtf(fmaf(2.0f, fabsf(Tm), S));
-          }
+            for (int r = 0; r < 4; ++r) {
+              const float A = acc[i][j][0][r], B = acc[i][j][1][r], C = acc[i][j][2][r], D = acc[i][j][3][r];
+              // max(|G|^2, |G_mirror|^2) = S + 2 |T|, S = A^2 + B^2 + C^2 + D^2, T = A B - C D
+              const float S = fmaf(A, A, fmaf(B, B, fmaf(C, C, D * D)));
+              const float Tm = fmaf(A, B, -(C * D));
+              // hardware square root (<= 1 ulp): the certificate's relative slack covers it
+              U[i][j][r] += wk * __builtin_amdgcn_sqrtf(fmaf(2.0f, fabsf(Tm), S));
+            }
+      } else {  // block-norm products (the frequency weights are in the pattern's norms)
+#pragma unroll
+        for (int i = 0; i < IM; ++i)
+#pragma unroll
+          for (int j = 0; j < JN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) U[i][j][r] += acc[i][j][0][r] + acc[i][j][1][r];
+      }
     }
   };
   if (nsteps > 0) issue(0, sbuf0);
@@ -732,232 +806,6 @@ __global__ void __launch_bounds__(64 * WM * WN) bound_kernel(BoundArgs a) {
     }
 }
 
-// Contraction with 16-bit operands on a two-group ("ping-pong") schedule.
-// Block tile 128 x 128 (patterns x zones), eight waves in two groups of four:
-// the hardware places wave w on SIMD w % 4, so every SIMD holds one wave of
-// each group.  Group g computes patterns 64 g .. 64 g + 63 and wave q of a group
-// zones 32 q .. 32 q + 31 (4 x 2 MFMA blocks of 16 x 16, the same products and
-// epilogue as bound_kernel).  The contraction advances in subs of 32 radii, one
-// LDS stage each, in a ring of kStages stages.  Every wave alternates
-//   read section:  fragment reads of sub j and, on the first sub of a
-//                  frequency, the previous frequency's epilogue (square roots
-//                  into U);
-//   MFMA section:  LDS-direct copies of sub j + kStages - 1 and the 32 MFMAs
-//                  of sub j,
-// with a workgroup barrier after each section.  Group 1 passes one extra barrier
-// first, so it runs one section behind group 0: while one wave of a SIMD issues
-// MFMAs, the other reads LDS or runs its epilogue.
-//
-// Sections are numbered from the prologue's barrier: group 0 reads sub j in
-// section 2j + 1 and multiplies in 2j + 2, group 1 one section later.  Stage
-// hazards: the stage of sub j - 1 was last read in section 2j (group 1), so the
-// copies of sub j + kStages - 1 into it start in the MFMA section of sub j
-// (section 2j + 2 or 2j + 3); every wave's copies of sub j + 1 have landed by
-// the end of section 2j + 2 (group 0 waits at the end of its MFMA section of
-// sub j, group 1 at the end of its read section of sub j), before group 0
-// reads sub j + 1 in section 2j + 3.
-namespace pp {
-constexpr int kStages = 4;
-constexpr int kRB = 64;                 // 32 radii of 16-bit operands per staged row
-constexpr int kArr = 128 * kRB;         // one operand array of one stage: 8 KiB
-constexpr int kStage = 4 * kArr;        // Xr, Xi, Pr, Pi
-constexpr int kCopies = 4;              // 1 KiB LDS-direct copies per wave per stage
-// s_waitcnt immediates (gfx9 encoding: vmcnt[3:0] | expcnt << 4 | lgkmcnt << 8 | vmcnt[5:4] << 14)
-constexpr int kWaitLgkmVm0 = 0x0070;                    // lgkmcnt(0) vmcnt(0)
-constexpr int kWaitLgkmVmOne = 0x0070 | ((kStages - 3) * kCopies);  // lgkmcnt(0), later subs' copies may be in flight
-constexpr int kWaitLgkm = 0xC07F;                        // lgkmcnt(0) only
-constexpr int kWaitVm = 0x0F70;                          // | n: vmcnt(n) only
-}  // namespace pp
-
-// A workgroup barrier that orders nothing but itself: the waits it needs are
-// explicit s_waitcnt before it, and no instruction is scheduled across it.
-__device__ __forceinline__ void pp_barrier() {
-  __builtin_amdgcn_sched_barrier(0);
-  asm volatile("s_barrier" ::: "memory");
-  __builtin_amdgcn_sched_barrier(0);
-}
-
-template <int KIND>
-__global__ void __launch_bounds__(512) bound_pp_kernel(BoundArgs a) {
-  using namespace pp;
-  static_assert(KIND == 1 || KIND == 2, "16-bit operands");
-  typedef typename std::conditional<KIND == 1, bf16x8, f16x8>::type V8;
-  constexpr int TP = 128, TZ = 128, IM = 4, JN = 2;
-  // one LDS object per stage, so that the compiler sees that the copies into
-  // one stage never alias the fragment reads of another
-  static_assert(kStages >= 3 && kStages <= 5 && (kStages - 2) * kCopies < 16, "ring of 3 to 5 stages");
-  __shared__ __align__(16) unsigned char sb0[kStage];
-  __shared__ __align__(16) unsigned char sb1[kStage];
-  __shared__ __align__(16) unsigned char sb2[kStage];
-  __shared__ __align__(16) unsigned char sb3[kStages > 3 ? kStage : 16];
-  __shared__ __align__(16) unsigned char sb4[kStages > 4 ? kStage : 16];
-  unsigned char* const ring[5] = {sb0, sb1, sb2, sb3, sb4};
-
-  int tp, tz;
-  if (a.order == 0) {
-    tp = blockIdx.x % a.nP;
-    tz = blockIdx.x / a.nP;
-  } else {
-    const int w = xcd_item(a.per);
-    if (w >= a.nP * a.nZ) return;
-    tp = w / a.nZ;
-    tz = w % a.nZ;
-  }
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int grp = wave >> 2, q = wave & 3;
-  const int li = lane & 15, lg = lane >> 4;
-  const bool live = tz * TZ + q * 32 < a.Zvalid && tp * TP + grp * 64 < a.np;
-
-  float U[IM][JN][4];
-#pragma unroll
-  for (int i = 0; i < IM; ++i)
-#pragma unroll
-    for (int j = 0; j < JN; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) U[i][j][r] = 0.0f;
-
-  const uint16_t* gx0 = reinterpret_cast<const uint16_t*>(a.xr);
-  const uint16_t* gx1 = reinterpret_cast<const uint16_t*>(a.xi);
-  const uint16_t* gp0 = reinterpret_cast<const uint16_t*>(a.pr);
-  const uint16_t* gp1 = reinterpret_cast<const uint16_t*>(a.pi);
-  const size_t slab = (size_t)a.Nk * 64 * a.Rp;
-  const int s_begin = (a.r0 / 32) * 32;  // whole subs of radii that are zero in every zone
-  const int spk = (a.Rp - s_begin) / 32;
-  const int nsub = a.Nk * spk;
-
-  // this lane's 16 bytes of the wave's KiB of each operand array: block row
-  // 16 wave + lane / 4, physical chunk lane % 4, holding logical chunk
-  // phys ^ swizzle(row) of that row
-  size_t offx, offp;
-  {
-    const int row = wave * 16 + (lane >> 2), phys = lane & 3;
-    const int ch = (phys ^ chunk_swizzle<kRB>(row)) * 8;
-    offx = (size_t)min(tp * 2 + (row >> 6), a.nX64 - 1) * slab + (size_t)(row & 63) * a.Rp + ch;
-    offp = (size_t)min(tz * 2 + (row >> 6), a.nP64 - 1) * slab + (size_t)(row & 63) * a.Rp + ch;
-  }
-  auto issue = [&](int g, unsigned char* st) __attribute__((always_inline)) {
-    const int k = g / spk;
-    const size_t kb = (size_t)k * 64 * a.Rp + s_begin + (size_t)(g - k * spk) * 32;
-    typedef __attribute__((address_space(3))) void* lds_t;
-    __builtin_amdgcn_global_load_lds((const void*)(gx0 + kb + offx), (lds_t)(st + 0 * kArr + wave * 1024), 16, 0, 0);
-    __builtin_amdgcn_global_load_lds((const void*)(gx1 + kb + offx), (lds_t)(st + 1 * kArr + wave * 1024), 16, 0, 0);
-    __builtin_amdgcn_global_load_lds((const void*)(gp0 + kb + offp), (lds_t)(st + 2 * kArr + wave * 1024), 16, 0, 0);
-    __builtin_amdgcn_global_load_lds((const void*)(gp1 + kb + offp), (lds_t)(st + 3 * kArr + wave * 1024), 16, 0, 0);
-  };
-  auto at = [](int row, int chunk) { return row * kRB + ((chunk ^ chunk_swizzle<kRB>(row)) << 4); };
-
-  V8 fxr[IM], fxi[IM], fpr[JN], fpi[JN];
-  f32x4 acc[IM][JN][4];
-  auto read = [&](const unsigned char* st) __attribute__((always_inline)) {
-#pragma unroll
-    for (int i = 0; i < IM; ++i) {
-      const int rx = grp * 64 + i * 16 + li;
-      fxr[i] = *reinterpret_cast<const V8*>(st + 0 * kArr + at(rx, lg));
-      fxi[i] = *reinterpret_cast<const V8*>(st + 1 * kArr + at(rx, lg));
-    }
-#pragma unroll
-    for (int j = 0; j < JN; ++j) {
-      const int rp = q * 32 + j * 16 + li;
-      fpr[j] = *reinterpret_cast<const V8*>(st + 2 * kArr + at(rp, lg));
-      fpi[j] = *reinterpret_cast<const V8*>(st + 3 * kArr + at(rp, lg));
-    }
-  };
-  auto mma = [&](auto zc) __attribute__((always_inline)) {
-    constexpr bool Z = decltype(zc)::value;
-    const f32x4 zero4 = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-    for (int i = 0; i < IM; ++i)
-#pragma unroll
-      for (int j = 0; j < JN; ++j) {
-        if constexpr (KIND == 1) {
-          acc[i][j][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fxr[i], fpr[j], Z ? zero4 : acc[i][j][0], 0, 0, 0);
-          acc[i][j][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fxi[i], fpi[j], Z ? zero4 : acc[i][j][1], 0, 0, 0);
-          acc[i][j][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fxi[i], fpr[j], Z ? zero4 : acc[i][j][2], 0, 0, 0);
-          acc[i][j][3] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fxr[i], fpi[j], Z ? zero4 : acc[i][j][3], 0, 0, 0);
-        } else {
-          acc[i][j][0] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fxr[i], fpr[j], Z ? zero4 : acc[i][j][0], 0, 0, 0);
-          acc[i][j][1] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fxi[i], fpi[j], Z ? zero4 : acc[i][j][1], 0, 0, 0);
-          acc[i][j][2] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fxi[i], fpr[j], Z ? zero4 : acc[i][j][2], 0, 0, 0);
-          acc[i][j][3] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fxr[i], fpi[j], Z ? zero4 : acc[i][j][3], 0, 0, 0);
-        }
-      }
-  };
-  auto epilogue = [&](int k) __attribute__((always_inline)) {
-    const float wk = (k == 0 || 2 * k == a.N) ? 1.0f : 2.0f;
-#pragma unroll
-    for (int i = 0; i < IM; ++i)
-#pragma unroll
-      for (int j = 0; j < JN; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const float A = acc[i][j][0][r], B = acc[i][j][1][r], C = acc[i][j][2][r], D = acc[i][j][3][r];
-          const float S = fmaf(A, A, fmaf(B, B, fmaf(C, C, D * D)));
-          const float Tm = fmaf(A, B, -(C * D));
-          U[i][j][r] += wk * __builtin_amdgcn_sqrtf(fmaf(2.0f, fabsf(Tm), S));
-        }
-  };
-  // one sub: read section, barrier, MFMA section, barrier.  Sub g lives in stage
-  // g % kStages, and the copies of sub g + kStages - 1 go to the stage of sub g - 1.
-  auto body = [&](int g, unsigned char* st, unsigned char* st_ahead) __attribute__((always_inline)) {
-    const bool ahead = g + kStages - 1 < nsub;
-    const int k = g / spk;
-    const bool first = g == k * spk;
-    if (live) {
-      read(st);
-      if (first && g > 0) epilogue(k - 1);
-    }
-    // group 1 ends section 2g + 2 here: its copies of sub g + 1 (issued two
-    // MFMA sections ago; only those of sub g + 2 may still be in flight)
-    if (grp == 1 && g + kStages - 2 < nsub) __builtin_amdgcn_s_waitcnt(kWaitLgkmVmOne);
-    else if (grp == 1) __builtin_amdgcn_s_waitcnt(kWaitLgkmVm0);
-    else __builtin_amdgcn_s_waitcnt(kWaitLgkm);
-    pp_barrier();
-    // the stage of sub g - 1 has been read by both groups: refill it while the MFMAs run
-    if (ahead) issue(g + kStages - 1, st_ahead);
-    if (live) {
-      if (first) mma(std::true_type{});
-      else mma(std::false_type{});
-    }
-    // group 0 ends section 2g + 2 here: its copies of sub g + 1 landed
-    if (grp == 0 && ahead) __builtin_amdgcn_s_waitcnt(kWaitVm | ((kStages - 2) * kCopies));
-    else if (grp == 0) __builtin_amdgcn_s_waitcnt(kWaitVm | 0);
-    pp_barrier();
-  };
-
-  // prologue: subs 0 .. kStages - 2 in flight, then every wave's copies of sub 0 landed
-#pragma unroll
-  for (int j = 0; j < kStages - 1; ++j)
-    if (j < nsub) issue(j, ring[j]);
-  if (nsub >= kStages - 1) __builtin_amdgcn_s_waitcnt(kWaitVm | ((kStages - 2) * kCopies));
-  else __builtin_amdgcn_s_waitcnt(kWaitVm | 0);
-  pp_barrier();
-  if (grp == 1) pp_barrier();
-  for (int g = 0; g < nsub; g += kStages) {
-#pragma unroll
-    for (int j = 0; j < kStages; ++j)
-      if (g + j < nsub) body(g + j, ring[j], ring[(j + kStages - 1) % kStages]);
-  }
-  if (grp == 0) pp_barrier();
-  if (!live) return;
-  if (nsub > 0) epilogue(a.Nk - 1);
-  const float invN = 1.0f / (float)a.N;
-#pragma unroll
-  for (int i = 0; i < IM; ++i)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int p = tp * TP + grp * 64 + i * 16 + lg * 4 + r;
-      if (p >= a.np) continue;
-      const float inv = invN / a.scale[p];
-#pragma unroll
-      for (int j = 0; j < JN; ++j) {
-        const int z = tz * TZ + q * 32 + j * 16 + li;
-        if (z < a.Zvalid) a.U[(size_t)p * a.ldU + z] = U[i][j][r] * inv;
-      }
-    }
-}
-
 // ------------------------------------------------------------ 3. exact ----
 
 struct ExactArgs {
@@ -967,6 +815,7 @@ struct ExactArgs {
   const int* rev;
   const float *xr, *xi;     // tile-major over the chunk's patterns (FP32)
   const float *pr, *pi;     // zone-major [Z][Nk][Rp] (FP32)
+  int xrows;                // rows per 64-pattern tile of the FP32 spectrum (frequencies, then norm rows)
   float* U;                 // bound rows (workspace); updated in place when u_lds == 0
   int ldU;
   int u_lds;                // 1: the pattern's bound row is copied to LDS; 0: selected in place in U
@@ -1012,7 +861,7 @@ __device__ void active_groups(const ExactArgs& a, int p, int* groups, int* ng) {
 // loaded once for all nb zones.
 __device__ void contract_exact(const ExactArgs& a, int p, const int* bz, int nb, const int* rev, float2* H,
                                const int* groups, int ng) {
-  const size_t xbase = tile_off(p, 0, 0, a.Nk, a.Rp);
+  const size_t xbase = tile_off(p, 0, 0, a.xrows, a.Rp);
   const size_t xk = (size_t)64 * a.Rp;
   const int sub = threadIdx.x & 3;
   for (int base = 0; base < a.Nk; base += (int)(blockDim.x >> 2)) {
@@ -1561,7 +1410,7 @@ WsLayout layout(const PlanDev& d, bool lowp, int Pc) {
   L.Pc = Pc;
   L.lowp = lowp;
   L.ntiles = d.Rp / kPolarCols;
-  const size_t nx = (size_t)d.Nk * Pc * d.Rp;
+  const size_t nx = (size_t)d.rows32 * Pc * d.Rp, nx16 = (size_t)d.rows16 * Pc * d.Rp;
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t at = o;
@@ -1571,8 +1420,8 @@ WsLayout layout(const PlanDev& d, bool lowp, int Pc) {
   L.xr = take(nx * 4);
   L.xi = take(nx * 4);
   if (lowp) {
-    L.lr = take(nx * 2);
-    L.li = take(nx * 2);
+    L.lr = take(nx16 * 2);
+    L.li = take(nx16 * 2);
   }
   L.scale = take((size_t)Pc * 4);
   L.xn2 = take((size_t)Pc * 4);
@@ -1585,7 +1434,7 @@ WsLayout layout(const PlanDev& d, bool lowp, int Pc) {
 
 template <int NC>
 size_t polar_lds(const PlanDev& d) {
-  return (size_t)(d.N * (NC / 2) + d.N) * sizeof(float2) + (size_t)d.N * 4 + polar_peak_cache<NC>() * (4 + 4 + 4 + 4 + 4 + 4) +
+  return (size_t)(d.N * (NC / 2) + d.N) * sizeof(float2) + (size_t)d.N * 4 + polar_peak_cache<NC>() * (2 + 4 + 4 + 4 + 4 + 1) +
          (size_t)d.Rp * 4 + (size_t)(d.Rp / kPolarCols) * (kThreads / 64) * 4;
 }
 size_t exact_lds(const PlanDev& d, int u_lds) {
@@ -1644,16 +1493,27 @@ PolarArgs polar_args(const PlanDev& d, const acom_peaks_t* pk, int64_t p_begin, 
   a.Ximg = nullptr;
   a.do_fft = 1;
   a.cmask = nullptr;
+  a.ws_layout = 0;
+  a.ld_tile16 = 0;
+  a.Kc = d.Kc;
+  a.bb = d.bb;
+  a.nb = d.nb;
+  a.Sp = d.Sp;
+  a.r0 = d.r0;
+  a.npseudo = d.npseudo;
+  a.L = d.L;
   return a;
 }
 
 void set_ws(PolarArgs& a, const WsLayout& L, unsigned char* ws, const PlanDev& d) {
   a.xr = reinterpret_cast<float*>(ws + L.xr);
   a.xi = reinterpret_cast<float*>(ws + L.xi);
-  a.ld_tile = (size_t)d.Nk * 64 * d.Rp;   // tile-major, as tile_off
+  a.ld_tile = (size_t)d.rows32 * 64 * d.Rp;   // tile-major, as tile_off with rows32 rows per tile
+  a.ld_tile16 = (size_t)d.rows16 * 64 * d.Rp;
   a.ldk = (size_t)64 * d.Rp;
   a.ldp = d.Rp;
   a.out_cols = d.Rp;
+  a.ws_layout = 1;
   a.lr = L.lowp ? reinterpret_cast<uint16_t*>(ws + L.lr) : nullptr;
   a.li = L.lowp ? reinterpret_cast<uint16_t*>(ws + L.li) : nullptr;
   a.scale = reinterpret_cast<float*>(ws + L.scale);
@@ -1763,6 +1623,10 @@ acom_status_t launch_bound(const PlanDev& d, int precision, const WsLayout& L, u
   b.Nk = d.Nk;
   b.Rp = d.Rp;
   b.N = d.N;
+  b.Kc = d.Kc;
+  b.nlog = d.Kc + d.npseudo;
+  b.hi = precision == ACOM_FP32 ? d.Nk : d.Kc;
+  b.rows = precision == ACOM_FP32 ? d.rows32 : d.rows16;
   b.order = t ? t->order : g_tune.bound_order;
   b.nX64 = (np + 63) / 64;
   b.nP64 = d.Zp / 64;
@@ -1794,20 +1658,6 @@ acom_status_t launch_bound(const PlanDev& d, int precision, const WsLayout& L, u
   // A shape chosen by acom_autotune for this plan and precision takes precedence.
   const int tile = t ? t->tile : g_tune.bound_tile;
   const int kch = t ? t->kch : (precision == ACOM_FP32 ? g_tune.bound_kch32 : g_tune.bound_kch16);
-  if (tile == 3) {  // two-group schedule, 16-bit operands only
-    if (precision == ACOM_FP32) return fail(ACOM_E_UNSUPPORTED, "the two-group contraction takes 16-bit operands");
-    b.nP = (b.np + 127) / 128;
-    b.nZ = (b.Zvalid + 127) / 128;
-    const int nblocks = b.order == 0 ? b.nP * b.nZ : xcd_blocks(b.nP * b.nZ, &b.per);
-    if (b.order == 0) b.per = 0;
-    ProfScope prof(1, s);
-    if (precision == ACOM_BF16)
-      bound_pp_kernel<1><<<dim3(nblocks), 512, 0, s>>>(b);
-    else
-      bound_pp_kernel<2><<<dim3(nblocks), 512, 0, s>>>(b);
-    ACOM_HIP(hipGetLastError());
-    return ACOM_OK;
-  }
   const bool use_large = tile == 1 || (tile == 2 && precision != ACOM_FP32 && large >= 2 * 256);
   if (use_large && precision == ACOM_FP32) return launch_bound_t<4, 2, 2, 2>(d, precision, b, kch, s);
   if (use_large) return launch_bound_t<2, 4, 4, 2>(d, precision, b, kch, s);
@@ -1826,6 +1676,7 @@ ExactArgs exact_args(const PlanDev& d, const WsLayout& L, unsigned char* ws, int
   e.rev = d.d_rev;
   e.xr = reinterpret_cast<const float*>(ws + L.xr);
   e.xi = reinterpret_cast<const float*>(ws + L.xi);
+  e.xrows = d.rows32;
   e.pr = d.d_PRz;
   e.pi = d.d_PIz;
   e.U = reinterpret_cast<float*>(ws + L.U);
@@ -2171,10 +2022,9 @@ extern "C" acom_status_t acom_autotune(acom_plan_t plan, const acom_peaks_t* pea
   if ((st = launch_polar(d, pa, s)) != ACOM_OK) return st;
   // candidate shapes: block tile x radius step (16-bit operands) x block order
   std::vector<PlanDev::BoundShape> cand;
-  for (int tile = 0; tile <= 3; ++tile) {
-    if (tile == 2 || (tile == 3 && precision == ACOM_FP32)) continue;
+  for (int tile = 0; tile <= 1; ++tile) {
     const int kmin = precision == ACOM_FP32 ? 16 : 32;
-    const int kmax = precision == ACOM_FP32 ? 32 : (tile == 0 ? 128 : tile == 1 ? 64 : 32);
+    const int kmax = precision == ACOM_FP32 ? 32 : (tile == 0 ? 128 : 64);
     for (int order = 0; order <= 1; ++order)
       for (int kch = kmin; kch <= kmax; kch *= 2) {
         if (d.Rp % kch) continue;
@@ -2285,6 +2135,7 @@ extern "C" acom_status_t acom_polar_spectrum(acom_plan_t plan, const acom_peaks_
   pa.ldk = d.R;
   pa.ldp = d.Nk * d.R;
   pa.out_cols = d.R;
+  pa.ws_layout = 0;  // the caller's [p][k][s] arrays: spectrum only, no norm rows
   return launch_polar(d, pa, (hipStream_t)stream_v);
 }
 
@@ -2384,7 +2235,7 @@ extern "C" acom_status_t acom_set_tuning(int32_t key, int32_t value) {
       g_tune.polar_xcd = value;
       return ACOM_OK;
     case 4:
-      if (value < 0 || value > 3) return fail(ACOM_E_INVALID, "contraction tile must be 0, 1, 2 or 3");
+      if (value < 0 || value > 2) return fail(ACOM_E_INVALID, "contraction tile must be 0, 1 or 2");
       g_tune.bound_tile = value;
       return ACOM_OK;
     case 5:

@@ -253,11 +253,9 @@ __global__ void __launch_bounds__(kPlanThreads) plan_zone_kernel(PlanKernelArgs 
 }
 
 // FFT{P} along phi3 by a direct FP64 DFT: block (z, k), threads over s.
-// Writes the FP32 operand in tile-major and zone-major layouts and the
-// requested 16-bit copies (tile-major).
+// Writes the FP32 spectrum zone-major [Z][Nk][Rp] (the exact pass's layout).
 __global__ void plan_dft_kernel(int Z, int N, int Nk, int R, int Rp, const double* P, const double2* tw64,
-                                float* PR, float* PI, float* PRz, float* PIz, uint16_t* PRb, uint16_t* PIb,
-                                uint16_t* PRh, uint16_t* PIh) {
+                                float* PRz, float* PIz) {
   const int z = blockIdx.x;
   const int k = blockIdx.y;
   const double* Pz = P + (size_t)z * N * R;
@@ -269,22 +267,99 @@ __global__ void plan_dft_kernel(int Z, int N, int Nk, int R, int Rp, const doubl
       re += v * w.x;
       im -= v * w.y;
     }
-    const size_t o = tile_off(z, k, s, Nk, Rp);
     const size_t oz = ((size_t)z * Nk + k) * Rp + s;
-    PR[o] = (float)re;
-    PI[o] = (float)im;
     PRz[oz] = (float)re;
     PIz[oz] = (float)im;
-    if (PRb) {
-      __hip_bfloat16 br = __float2bfloat16((float)re), bi = __float2bfloat16((float)im);
-      PRb[o] = *reinterpret_cast<uint16_t*>(&br);
-      PIb[o] = *reinterpret_cast<uint16_t*>(&bi);
+  }
+}
+
+// 16-bit conversions; the _up forms round a nonnegative value up (to the
+// next representable value when round-to-nearest went below it), so that the
+// block norms of the split bound never shrink.
+__device__ __forceinline__ uint16_t bf16_bits(float v) {
+  __hip_bfloat16 b = __float2bfloat16(v);
+  return *reinterpret_cast<uint16_t*>(&b);
+}
+__device__ __forceinline__ uint16_t f16_bits(float v) {
+  __half h = __float2half(v);
+  return *reinterpret_cast<uint16_t*>(&h);
+}
+__device__ __forceinline__ uint16_t bf16_bits_up(float v) {
+  uint16_t b = bf16_bits(v);
+  __hip_bfloat16 t;
+  *reinterpret_cast<uint16_t*>(&t) = b;
+  return __bfloat162float(t) < v ? (uint16_t)(b + 1) : b;
+}
+__device__ __forceinline__ uint16_t f16_bits_up(float v) {
+  uint16_t b = f16_bits(v);
+  __half t;
+  *reinterpret_cast<uint16_t*>(&t) = b;
+  return __half2float(t) < v ? (uint16_t)(b + 1) : b;
+}
+__device__ __forceinline__ float f32_up(double v) {
+  const float f = (float)v;
+  return (double)f < v ? nextafterf(f, INFINITY) : f;
+}
+
+// Contraction operands, tile-major (64-row zone tiles), from the zone-major
+// FP32 spectrum: block (z, row), threads over the row's Rp slots.
+//   row < Nk:  FFT{P} at frequency row (FP32, tile stride rows32), and for
+//              row < Kc the 16-bit copies (tile stride rows16);
+//   row >= Nk: pseudo row j = row - Nk of the split bound's norm vector,
+//              entry v = (k - Kc) nb + b = ||FFT{P}[z][k][b bb .. b bb + bb)||,
+//              at slot r0 + v mod Sp of the real (v mod 2Sp < Sp) or
+//              imaginary array; FP32 row Nk + j, 16-bit row Kc + j; rounded
+//              up (norms of the FP32 values, taken in FP64).
+struct TileArgs {
+  int Z, Nk, Rp, Kc, bb, nb, Sp, r0, npseudo, rows32, rows16;
+  int64_t L;
+  const float *PRz, *PIz;
+  float *PR, *PI;
+  uint16_t *PRb, *PIb, *PRh, *PIh;
+};
+__global__ void plan_tile_kernel(TileArgs a) {
+  const int z = blockIdx.x;
+  const int row = blockIdx.y;
+  if (row < a.Nk) {
+    const int k = row;
+    for (int s = threadIdx.x; s < a.Rp; s += blockDim.x) {
+      const size_t oz = ((size_t)z * a.Nk + k) * a.Rp + s;
+      const float re = a.PRz[oz], im = a.PIz[oz];
+      const size_t o = tile_off(z, k, s, a.rows32, a.Rp);
+      a.PR[o] = re;
+      a.PI[o] = im;
+      if (k < a.Kc) {
+        const size_t o16 = tile_off(z, k, s, a.rows16, a.Rp);
+        if (a.PRb) {
+          a.PRb[o16] = bf16_bits(re);
+          a.PIb[o16] = bf16_bits(im);
+        }
+        if (a.PRh) {
+          a.PRh[o16] = f16_bits(re);
+          a.PIh[o16] = f16_bits(im);
+        }
+      }
     }
-    if (PRh) {
-      __half hr = __float2half((float)re), hi = __float2half((float)im);
-      PRh[o] = *reinterpret_cast<uint16_t*>(&hr);
-      PIh[o] = *reinterpret_cast<uint16_t*>(&hi);
+    return;
+  }
+  const int j = row - a.Nk;
+  for (int e = threadIdx.x; e < 2 * a.Sp; e += blockDim.x) {
+    const int64_t v = (int64_t)j * 2 * a.Sp + e;
+    if (v >= a.L) break;
+    const int k = a.Kc + (int)(v / a.nb), b = (int)(v % a.nb);
+    double n2 = 0.0;
+    for (int s = b * a.bb; s < (b + 1) * a.bb; ++s) {
+      const size_t oz = ((size_t)z * a.Nk + k) * a.Rp + s;
+      const double re = a.PRz[oz], im = a.PIz[oz];
+      n2 += re * re + im * im;
     }
+    const float nrm = f32_up(sqrt(n2) * (1.0 + 1e-15));
+    const int part = e / a.Sp, slot = a.r0 + e % a.Sp;
+    const size_t o = tile_off(z, a.Nk + j, slot, a.rows32, a.Rp);
+    (part ? a.PI : a.PR)[o] = nrm;
+    const size_t o16 = tile_off(z, a.Kc + j, slot, a.rows16, a.Rp);
+    if (a.PRb) (part ? a.PIb : a.PRb)[o16] = bf16_bits_up(nrm);
+    if (a.PRh) (part ? a.PIh : a.PRh)[o16] = f16_bits_up(nrm);
   }
 }
 
@@ -373,6 +448,10 @@ acom_status_t validate(const acom_phase_t* phases, int n_phases, const acom_plan
   if (p->kernel != ACOM_KERNEL_CONE && p->kernel != ACOM_KERNEL_GAUSS)
     return fail(ACOM_E_INVALID, "kernel must be ACOM_KERNEL_CONE or ACOM_KERNEL_GAUSS");
   if (p->precisions & ~7) return fail(ACOM_E_INVALID, "precisions: unknown bits");
+  if (p->bound_exact_freqs < 0) return fail(ACOM_E_INVALID, "bound_exact_freqs must be >= 0 (0: default)");
+  if (p->bound_block_radii != 0 && p->bound_block_radii != 2 && p->bound_block_radii != 4 &&
+      p->bound_block_radii != 8 && p->bound_block_radii != 16)
+    return fail(ACOM_E_INVALID, "bound_block_radii must be 2, 4, 8 or 16 (0: default 8)");
   for (int i = 0; i < n_phases; ++i) {
     const acom_phase_t& ph = phases[i];
     if (ph.n_atoms < 1 || !ph.frac_xyz) return fail(ACOM_E_INVALID, "phase needs n_atoms >= 1 and frac_xyz");
@@ -616,26 +695,13 @@ extern "C" acom_status_t acom_build_plan(const acom_phase_t* phases, int32_t n_p
   plan_zone_kernel<<<d.Z, kPlanThreads, 0, stream>>>(ka);
   if (hipGetLastError() != hipSuccess) return bail(fail(ACOM_E_HIP, "plan_zone_kernel launch"));
 
-  // frequency-domain operands
-  const size_t nfreq = (size_t)d.Nk * d.Zp * d.Rp;
+  // frequency-domain plan, zone-major FP32 (the exact pass's operand)
   const size_t nfz = (size_t)d.Nk * d.Z * d.Rp;
-  if ((st = dalloc(&d.d_PR, nfreq)) || (st = dalloc(&d.d_PI, nfreq)) || (st = dalloc(&d.d_PRz, nfz)) ||
-      (st = dalloc(&d.d_PIz, nfz)))
-    return bail(st);
-  if (hipMemsetAsync(d.d_PR, 0, nfreq * 4, stream) != hipSuccess || hipMemsetAsync(d.d_PI, 0, nfreq * 4, stream) != hipSuccess ||
-      hipMemsetAsync(d.d_PRz, 0, nfz * 4, stream) != hipSuccess || hipMemsetAsync(d.d_PIz, 0, nfz * 4, stream) != hipSuccess)
+  if ((st = dalloc(&d.d_PRz, nfz)) || (st = dalloc(&d.d_PIz, nfz))) return bail(st);
+  if (hipMemsetAsync(d.d_PRz, 0, nfz * 4, stream) != hipSuccess || hipMemsetAsync(d.d_PIz, 0, nfz * 4, stream) != hipSuccess)
     return bail(fail(ACOM_E_HIP, "memset plan"));
-  for (int p = 1; p <= 2; ++p)
-    if (d.precisions & (1 << p)) {
-      if ((st = dalloc(&d.d_PR16[p], nfreq)) || (st = dalloc(&d.d_PI16[p], nfreq))) return bail(st);
-      if (hipMemsetAsync(d.d_PR16[p], 0, nfreq * 2, stream) != hipSuccess ||
-          hipMemsetAsync(d.d_PI16[p], 0, nfreq * 2, stream) != hipSuccess)
-        return bail(fail(ACOM_E_HIP, "memset plan16"));
-    }
   dim3 gdft(d.Z, d.Nk);
-  plan_dft_kernel<<<gdft, 128, 0, stream>>>(d.Z, d.N, d.Nk, d.R, d.Rp, d_P, d_tw64, d.d_PR, d.d_PI, d.d_PRz,
-                                            d.d_PIz, d.d_PR16[ACOM_BF16], d.d_PI16[ACOM_BF16], d.d_PR16[ACOM_FP16],
-                                            d.d_PI16[ACOM_FP16]);
+  plan_dft_kernel<<<gdft, 128, 0, stream>>>(d.Z, d.N, d.Nk, d.R, d.Rp, d_P, d_tw64, d.d_PRz, d.d_PIz);
   if (hipGetLastError() != hipSuccess) return bail(fail(ACOM_E_HIP, "plan_dft_kernel launch"));
   // leading radii where every zone's FFT{P} is exactly zero: the contraction
   // may skip them (their terms are exact zeros)
@@ -656,6 +722,52 @@ extern "C" acom_status_t acom_build_plan(const acom_phase_t* phases, int32_t n_p
     if (!ok) return bail(fail(ACOM_E_HIP, "plan column scan"));
     d.r0 = 0;
     while (d.r0 < d.R && !colany[d.r0]) ++d.r0;
+  }
+  // ---- split bound and the contraction operands (tile-major over zones)
+  d.bb = prm->bound_block_radii > 0 ? prm->bound_block_radii : 8;
+  d.Kc = prm->bound_exact_freqs > 0 ? std::min(prm->bound_exact_freqs, d.Nk) : std::min(d.Nk, 32);
+  if (d.r0 >= d.R) d.Kc = d.Nk;  // a plan that is zero everywhere: nothing to split
+  d.nb = d.Rp / d.bb;
+  d.Sp = d.Rp - d.r0;
+  d.L = (int64_t)(d.Nk - d.Kc) * d.nb;
+  d.npseudo = d.L > 0 ? (int)((d.L + 2 * d.Sp - 1) / (2 * d.Sp)) : 0;
+  d.rows32 = d.Nk + d.npseudo;
+  d.rows16 = d.Kc + d.npseudo;
+  {
+    const size_t n32 = (size_t)d.rows32 * d.Zp * d.Rp, n16 = (size_t)d.rows16 * d.Zp * d.Rp;
+    if ((st = dalloc(&d.d_PR, n32)) || (st = dalloc(&d.d_PI, n32))) return bail(st);
+    if (hipMemsetAsync(d.d_PR, 0, n32 * 4, stream) != hipSuccess || hipMemsetAsync(d.d_PI, 0, n32 * 4, stream) != hipSuccess)
+      return bail(fail(ACOM_E_HIP, "memset plan operands"));
+    for (int p = 1; p <= 2; ++p)
+      if (d.precisions & (1 << p)) {
+        if ((st = dalloc(&d.d_PR16[p], n16)) || (st = dalloc(&d.d_PI16[p], n16))) return bail(st);
+        if (hipMemsetAsync(d.d_PR16[p], 0, n16 * 2, stream) != hipSuccess ||
+            hipMemsetAsync(d.d_PI16[p], 0, n16 * 2, stream) != hipSuccess)
+          return bail(fail(ACOM_E_HIP, "memset plan16"));
+      }
+    TileArgs ta;
+    ta.Z = d.Z;
+    ta.Nk = d.Nk;
+    ta.Rp = d.Rp;
+    ta.Kc = d.Kc;
+    ta.bb = d.bb;
+    ta.nb = d.nb;
+    ta.Sp = d.Sp;
+    ta.r0 = d.r0;
+    ta.npseudo = d.npseudo;
+    ta.rows32 = d.rows32;
+    ta.rows16 = d.rows16;
+    ta.L = d.L;
+    ta.PRz = d.d_PRz;
+    ta.PIz = d.d_PIz;
+    ta.PR = d.d_PR;
+    ta.PI = d.d_PI;
+    ta.PRb = d.d_PR16[ACOM_BF16];
+    ta.PIb = d.d_PI16[ACOM_BF16];
+    ta.PRh = d.d_PR16[ACOM_FP16];
+    ta.PIh = d.d_PI16[ACOM_FP16];
+    plan_tile_kernel<<<dim3(d.Z, d.rows32), 128, 0, stream>>>(ta);
+    if (hipGetLastError() != hipSuccess) return bail(fail(ACOM_E_HIP, "plan_tile_kernel launch"));
   }
 
   // small tables
@@ -718,6 +830,13 @@ extern "C" acom_status_t acom_plan_info(acom_plan_t plan, int32_t* n_zones, int3
   if (zones) std::memcpy(zones, d.zones.data(), sizeof(double) * 3 * d.Z);
   if (zone_phase) std::memcpy(zone_phase, d.zone_phase.data(), sizeof(int32_t) * d.Z);
   if (norm_A) std::memcpy(norm_A, d.normA.data(), sizeof(double) * d.Z);
+  return ACOM_OK;
+}
+
+extern "C" acom_status_t acom_plan_bound_split(acom_plan_t plan, int32_t* exact_freqs, int32_t* block_radii) {
+  if (!plan) return fail(ACOM_E_INVALID, "plan is null");
+  if (exact_freqs) *exact_freqs = plan->d.Kc;
+  if (block_radii) *block_radii = plan->d.bb;
   return ACOM_OK;
 }
 

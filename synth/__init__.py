@@ -180,6 +180,34 @@ def scan(seed=1002, ny=256, nx=256, n_grains=50, k_max=2.0, phase_name="fcc_a4.0
                                                      "grain": lab, "shape": (ny, nx)})
 
 
+def hard(seed=1008, ny=256, nx=256, n_grains=50, k_max=2.0, drop=0.2, inoise=0.3, spurious=(5, 10)):
+    """The scan's geometry with degraded peak lists (the regime of the paper's
+    dynamical and experimental patterns, where intensities depart from the
+    kinematical ones and peaks are missed or spurious): each real peak is
+    dropped with probability `drop`, intensities are multiplied by
+    (1 + inoise N(0, 1)) (clipped at 0), and 5-10 spurious peaks (positions
+    area-uniform in |q| < k_max, intensities U(0.1, 1) of the median) are
+    added."""
+    rng = np.random.default_rng(seed)
+    t = load_table("fcc_a4.08")
+    lab = voronoi_labels(rng, ny, nx, n_grains)
+    R, base = _grain_patterns(rng, [t], np.zeros(n_grains, dtype=np.int64), k_max, 10, 60, 0.01)
+    lists = []
+    for p in range(ny * nx):
+        bx, by, bI = base[lab[p]]
+        keep = rng.random(len(bx)) >= drop
+        qx, qy, I = _noisy(rng, bx[keep], by[keep], bI[keep], inoise=inoise)
+        I = np.maximum(I, 0.0)
+        cnt = int(rng.integers(spurious[0], spurious[1] + 1))
+        r = k_max * np.sqrt(rng.random(cnt))
+        a = 2.0 * math.pi * rng.random(cnt)
+        med = float(np.median(bI)) if len(bI) else 1.0
+        lists.append((np.concatenate([qx, r * np.cos(a)]), np.concatenate([qy, r * np.sin(a)]),
+                      np.concatenate([I, rng.uniform(0.1, 1.0, cnt) * med])))
+    return _pack(lists, R[lab], np.zeros(ny * nx), {"name": "hard", "k_max": k_max, "phases": ["fcc_a4.08"],
+                                                     "grain": lab, "shape": (ny, nx)})
+
+
 def hcp(seed=1003, ny=256, nx=256, n_grains=50, k_max=2.0):
     d = scan(seed, ny, nx, n_grains, k_max, "hcp_a2.95_c4.68")
     d["name"] = "hcp"
@@ -300,7 +328,7 @@ def subset(d, idx):
 
 
 CONFIGS = {"small": small, "scan": scan, "hcp": hcp, "multi": multi, "refine": refine, "overlap": overlap,
-           "frames": frames}
+           "frames": frames, "hard": hard}
 
 
 def make(name, **kw):

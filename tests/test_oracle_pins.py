@@ -319,19 +319,43 @@ def test_parabolic_offset_exact_vertex():
     assert correlate.parabolic_offset(0.0, 1.0, 1.0) == 0.5      # clamped
 
 
-def test_spectral_bound_is_an_upper_bound_and_tight_for_a_spike():
+@pytest.mark.parametrize("N", [32, 33])
+def test_spectral_bound_is_an_upper_bound_and_tight_for_a_spike(N):
     rng = np.random.default_rng(2)
-    P = _rand_sparse(rng, (6, 32, 5), 0.3)
-    X = _rand_sparse(rng, (32, 5), 0.3)
+    R = 20
+    P = _rand_sparse(rng, (6, N, R), 0.3)
+    X = _rand_sparse(rng, (N, R), 0.3)
     C, Cm = correlate.correlate_direct(P, X)
+    best = np.maximum(C.max(1), Cm.max(1))
+    # the all-exact form equals (1/N) sum over the FULL spectrum of the larger modulus
+    Ph, Xh = np.fft.fft(P, axis=1), np.fft.fft(X, axis=0)
+    full = np.maximum(np.abs(np.sum(np.conj(Ph) * Xh[None], axis=2)),
+                      np.abs(np.sum(np.conj(Ph) * np.conj(Xh)[None], axis=2))).sum(1) / N
     U = correlate.spectral_bound(P, X)
-    assert np.all(U >= np.maximum(C.max(1), Cm.max(1)) - 1e-12)
-    P1 = np.zeros((1, 32, 5))
+    assert np.allclose(U, full, rtol=1e-12)
+    assert np.all(U >= best - 1e-12)
+    Nk = N // 2 + 1
+    assert np.array_equal(correlate.spectral_bound(P, X, exact_freqs=Nk + 3), U)
+    # split forms: every split and block size is still an upper bound; finer
+    # blocks (and more exact frequencies) never loosen it
+    for kc in (0, 1, 4, 9, Nk - 1):
+        for blk in (3, 8):
+            Ub = correlate.spectral_bound(P, X, exact_freqs=kc, block=blk)
+            assert np.all(Ub >= best - 1e-12), (kc, blk)
+            assert np.all(Ub >= U - 1e-12), (kc, blk)
+        nested = [correlate.spectral_bound(P, X, exact_freqs=kc, block=blk) for blk in (1, 2, 4, R)]
+        for lo, hi in zip(nested, nested[1:]):     # each partition refines the next
+            assert np.all(hi >= lo - 1e-12), kc
+        if kc > 0:
+            assert np.all(correlate.spectral_bound(P, X, exact_freqs=kc - 1, block=4) >= nested[2] - 1e-12)
+    # tight for a single spike in plan and image at the same radius, in both forms
+    P1 = np.zeros((1, N, 5))
     P1[0, 3, 2] = 2.0
-    X1 = np.zeros((32, 5))
+    X1 = np.zeros((N, 5))
     X1[9, 2] = 1.5
     C1, Cm1 = correlate.correlate_direct(P1, X1)
-    assert abs(correlate.spectral_bound(P1, X1)[0] - max(C1.max(), Cm1.max())) < 1e-12
+    for kc, blk in ((None, 8), (0, 5), (0, 1), (5, 2)):
+        assert abs(correlate.spectral_bound(P1, X1, exact_freqs=kc, block=blk)[0] - max(C1.max(), Cm1.max())) < 1e-12
 
 
 @pytest.mark.parametrize("kind", [plan.CONE, plan.GAUSS])
