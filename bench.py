@@ -141,12 +141,27 @@ def measured_traffic(precision, launches_patterns):
     return e["bytes_per_launch"]
 
 
-def bound_flop_per_pattern(gpl):
-    """Algorithmic FLOP per pattern of the contraction pass's split bound:
-    for every zone, the four real products of the Kc exact frequencies
-    (8 Kc N_r) and one multiply-add per block-norm entry of the rest
-    (2 (N_phi/2 + 1 - Kc) ceil(N_r / block))."""
-    kc, bb = gpl.bound_split()
+def refine_roofline(work, ms):
+    """ALU roofline of refine_kernel from its own work counts (acom_refine's
+    out_work: (peak, reflection) pairs evaluated for S alone and with the
+    gradient): 8 FLOP per pair for S (two differences, the squared distance,
+    its scaling, the exponential, the weight and the sum) and 12 with the
+    gradient (two more multiply-adds), against the FP32 vector peak without
+    packed instructions (78.6 TFLOP/s)."""
+    w = work.double().sum(0).cpu().numpy()
+    flop = 8.0 * w[0] + 12.0 * w[1]
+    tf = flop / (ms * 1e-3) / 1e12
+    return {"kernel": "refine_kernel (one wavefront per pattern)", "bound": "alu", "achieved": round(tf, 3),
+            "peak": 78.6, "unit": "TFLOP/s", "frac": round(tf / 78.6, 4), "flop_per_launch": flop,
+            "pairs_score": float(w[0]), "pairs_score_and_gradient": float(w[1]), "refine_ms": round(ms, 3)}
+
+
+def bound_flop_per_pattern(gpl, prec):
+    """Algorithmic FLOP per pattern of the contraction pass's split bound with
+    operands of `prec`: for every zone, the four real products of the Kc exact
+    frequencies (8 Kc N_r) and one multiply-add per block-norm entry of the
+    rest (2 (N_phi/2 + 1 - Kc) ceil(N_r / block))."""
+    kc, bb = gpl.bound_split(prec)
     nk, R = gpl.n_angular // 2 + 1, gpl.n_radial
     return float(gpl.n_zones) * (8.0 * kc * R + 2.0 * (nk - kc) * (-(-R // bb)))
 
@@ -291,9 +306,11 @@ def time_match(gpl, pk, prec, top_k, chunk, steps, warmup, n, flop_per_pattern, 
     kern = {k: {"avg_ms": (t / c if c else None), "launches": c} for k, (t, c) in prof.items()}
     b = prof["bound"]
     per_launch = min(chunk, n)
+    flop_per_pattern = bound_flop_per_pattern(gpl, prec)  # the split depends on the operand precision
     achieved = flop_per_pattern * per_launch / (b[0] / b[1] * 1e-3) / 1e12
     nev = out["n_evaluated"].float()
     run = {"value": n * steps / el, "ms_per_step": el * 1e3 / steps, "kernels": kern, "contraction_shape": shape,
+           "flop_per_pattern": flop_per_pattern,
            "bound_tflops": achieved, "bound_frac": achieved / PEAK_TFLOPS[prec],
            "zones_evaluated_mean": float(nev.mean()), "zones_evaluated_max": int(nev.max())}
     host = {k: out[k].cpu().numpy() for k in ("zone", "phase", "bin", "mirror", "score")}
@@ -319,7 +336,7 @@ def roofline(runs, prec, per_launch, flop_per_pattern, traffic):
     return {"kernel": "bound_kernel (MFMA contraction, %s operands)" % prec, "bound": "mfma",
             "achieved": round(r["bound_tflops"], 3), "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
             "frac": round(r["bound_frac"], 4), "traffic": traffic,
-            "algorithmic_flop_per_launch": flop_per_pattern * per_launch, "dominant_kernel_of_step": dominant}
+            "algorithmic_flop_per_launch": r["flop_per_pattern"] * per_launch, "dominant_kernel_of_step": dominant}
 
 
 def line(workload, value, ms, steps, warmup, dtype, cfg, roof, cpu, extra):
@@ -348,13 +365,14 @@ def run_match_workload(args, workload, defer_oracle=False):
     t0 = time.perf_counter()
     gpl = acom.Plan([{"fcc": acom.fcc, "bcc": acom.bcc, "hcp": acom.hcp}[k]() for k in phases],
                     acom.PlanParams(precisions=precs, bound_exact_freqs=args.bound_exact_freqs,
-                                    bound_block_radii=args.bound_block_radii, **cfg))
+                                    bound_block_radii=args.bound_block_radii,
+                                    bound_exact_freqs_16bit=args.bound_exact_freqs_16bit, **cfg))
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
     n = len(d["offsets"]) - 1
     pk = acom.Peaks.from_host(d)
     Z, R, N = gpl.n_zones, gpl.n_radial, gpl.n_angular
-    flop_per_pattern = bound_flop_per_pattern(gpl)
+    flop_per_pattern = bound_flop_per_pattern(gpl, precs[0])
     runs, host = {}, {}
     log(f"{workload}: plan built ({Z} zones, {t_plan:.1f} s)")
     for prec in precs:
@@ -378,9 +396,10 @@ def run_match_workload(args, workload, defer_oracle=False):
         mis = [metrics.misorientation_deg(host[main_prec]["orient"][p, 0], d["truth"][p], G) for p in idx]
         extra["misorientation_vs_truth_deg"] = {"median": float(np.median(mis)), "p90": float(np.percentile(mis, 90)),
                                                 "patterns": 256, "precision": main_prec}
-    kc, bb = gpl.bound_split()
+    kc, bb = gpl.bound_split(main_prec)
     ccfg = {"patterns": n, "peaks": int(d["offsets"][-1]), "zones": Z, "n_radial": R, "n_angular": N,
-            "chunk": args.chunk, "top_k": top_k, "bound_exact_freqs": kc, "bound_block_radii": bb}
+            "chunk": args.chunk, "top_k": top_k, "bound_exact_freqs": kc, "bound_block_radii": bb,
+            "bound_exact_freqs_by_precision": {p: gpl.bound_split(p)[0] for p in precs}}
     extra["bound_flop_per_pattern"] = flop_per_pattern
     extra["full_contraction_flop_per_pattern"] = full_contraction_flop_per_pattern(gpl)
     r = runs[main_prec]
@@ -414,7 +433,7 @@ def run_multi(args):
     n = len(d["offsets"]) - 1
     pk = acom.Peaks.from_host(d)
     Z, R, N = gpl.n_zones, gpl.n_radial, gpl.n_angular
-    flop_per_pattern = bound_flop_per_pattern(gpl)
+    flop_per_pattern = bound_flop_per_pattern(gpl, prec)
     # kernel averages and the contraction roofline from an eager profiled run
     log(f"multi: plan built ({Z} zones, {t_plan:.1f} s)")
     run, host = time_match(gpl, pk, prec, 1, args.chunk, 2, 1, n, flop_per_pattern)
@@ -474,6 +493,7 @@ def run_refine(args):
     out = gpl.empty_matches(n, 4, True, "cuda")
 
     shape = gpl.autotune(pk, "fp32", args.chunk, ws)
+    work = torch.zeros(n, 2, dtype=torch.int32, device="cuda")
 
     def step():
         gpl.match(pk, 4, "fp32", args.chunk, ws, out=out)
@@ -489,7 +509,7 @@ def run_refine(args):
         gpl.match(pk, 4, "fp32", args.chunk, ws, out=out)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        m, S, c = gpl.refine(pk, out["orient"].reshape(n, 4, 9), max_iter=64)
+        m, S, c = gpl.refine(pk, out["orient"].reshape(n, 4, 9), max_iter=64, work=work)
         torch.cuda.synchronize()
         t_ref += time.perf_counter() - t1
         t_match += t1 - t0
@@ -497,7 +517,7 @@ def run_refine(args):
     prof = acom.profile_read()
     acom.profile_end()
     Z, R, N = gpl.n_zones, gpl.n_radial, gpl.n_angular
-    flop_per_pattern = bound_flop_per_pattern(gpl)
+    flop_per_pattern = bound_flop_per_pattern(gpl, "fp32")
     b_ms = prof["bound"][0] / prof["bound"][1]
     per_launch = min(args.chunk, n)
     tflops = flop_per_pattern * per_launch / (b_ms * 1e-3) / 1e12
@@ -536,6 +556,7 @@ def run_refine(args):
                                              "refined_p90": float(np.percentile(mis16, 90)),
                                              "vs_fp32_candidates_within_0.1deg": float(np.mean(np.array(mis16_32) < 0.1)),
                                              "vs_fp32_candidates_median": float(np.median(mis16_32))}},
+             "refine_roofline": refine_roofline(work, t_ref * 1e3 / args.steps),
              "contraction_shape": shape, "ms_per_step_match": round(t_match * 1e3 / args.steps, 3),
              "ms_per_step_refine": round(t_ref * 1e3 / args.steps, 3),
              "oracle_comparison": ext, "input_generation_s": round(t_gen, 3)}
@@ -615,7 +636,7 @@ def run_overlap(args):
     n = len(d["offsets"]) - 1
     pk = acom.Peaks.from_host(d)
     Z, R, N = gpl.n_zones, gpl.n_radial, gpl.n_angular
-    flop_per_pattern = bound_flop_per_pattern(gpl)
+    flop_per_pattern = bound_flop_per_pattern(gpl, prec)
     ws = torch.empty(gpl.match_multi_workspace_bytes(pk.total_peaks, prec, args.chunk), dtype=torch.uint8,
                      device="cuda")
     shape = gpl.autotune(pk, prec, args.chunk, ws)
@@ -780,9 +801,20 @@ def run_detect(args):
     alg = n * per_frame + total * 12                # + the kept peaks' slots
     gbs = alg / (t_det * 1e-3) / 1e9
     traffic = measured_disk_traffic(n)
-    roof = {"kernel": "disk_detect_kernel<128> (+ the one-block counts scan in the same call)", "bound": "hbm",
-            "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s", "frac": round(gbs / 8000.0, 4),
+    # the kernel is bound by VALU issue (its counters: 68 % of SIMD cycles issue
+    # VALU work), so the roof is the vector rate: the correlation's algorithmic
+    # FLOP, two real 2-D FFTs (2.5 N^2 log2 N^2 each) and the spectrum product
+    # (6 N (N/2 + 1)), against the FP32 vector peak without packed instructions
+    # (256 CU x 4 SIMD x 16 lanes x 2 FLOP x 2.4 GHz = 78.6 TFLOP/s; the 157.3
+    # TFLOP/s figure counts packed FP32, which this build does not emit)
+    import math
+    fft_flop = 2 * 2.5 * N * N * math.log2(N * N) + 6 * N * (N // 2 + 1)
+    tf = fft_flop * n / (t_det * 1e-3) / 1e12
+    roof = {"kernel": "disk_detect_kernel<128> (+ the one-block counts scan in the same call)", "bound": "alu",
+            "achieved": round(tf, 2), "peak": 78.6, "unit": "TFLOP/s", "frac": round(tf / 78.6, 4),
+            "peak_with_packed_fp32": 157.3, "algorithmic_flop_per_frame": fft_flop,
             "traffic": traffic, "algorithmic_bytes_per_launch": alg,
+            "hbm_GBps": round(gbs, 1), "hbm_frac": round(gbs / 8000.0, 4),
             "detect_call_ms": round(t_det, 4)}
     ccfg = {"frames": n, "frame": [N, N], "distinct_frames": U, "peaks_per_frame": round(total / n, 2),
             "max_peaks": prm["max_peaks"]}
@@ -814,7 +846,7 @@ def run_pipeline(args):
     phases, cfg = PLAN_CFG["scan"]
     gpl = acom.Plan([acom.fcc()], acom.PlanParams(precisions=[prec], **cfg))
     Z, R, Nphi = gpl.n_zones, gpl.n_radial, gpl.n_angular
-    flop_per_pattern = bound_flop_per_pattern(gpl)
+    flop_per_pattern = bound_flop_per_pattern(gpl, prec)
     cap = tuple(torch.empty(n * det.max_peaks, dtype=torch.float32, device="cuda") for _ in range(3))
     ws = torch.empty(gpl.match_workspace_bytes(prec, args.chunk), dtype=torch.uint8, device="cuda")
     out = gpl.empty_matches(n, 1, True, "cuda")
@@ -991,7 +1023,7 @@ def extra_workloads(args, fut):
     phases, cfg = PLAN_CFG["hcp"]
     gpl = acom.Plan([acom.hcp()], acom.PlanParams(precisions=["fp32", "bf16", "fp16"], **cfg))
     pk = acom.Peaks.from_host(d)
-    fpp = bound_flop_per_pattern(gpl)
+    fpp = bound_flop_per_pattern(gpl, "bf16")
     runs, host = {}, {}
     t0 = time.perf_counter()
     for prec in ("bf16", "fp16", "fp32"):
@@ -1008,7 +1040,7 @@ def extra_workloads(args, fut):
     nh = len(dh["offsets"]) - 1
     gpl = acom.Plan([acom.fcc()], acom.PlanParams(precisions=["fp32", "bf16"], **PLAN_CFG["hard"][1]))
     pk = acom.Peaks.from_host(dh)
-    fpph = bound_flop_per_pattern(gpl)
+    fpph = bound_flop_per_pattern(gpl, "bf16")
     runs_h, host_h = {}, {}
     t0 = time.perf_counter()
     for prec in ("bf16", "fp32"):
@@ -1030,7 +1062,7 @@ def extra_workloads(args, fut):
     phases, cfg = PLAN_CFG["multi"]
     gpl = acom.Plan([acom.fcc(), acom.bcc(), acom.hcp()], acom.PlanParams(precisions=["bf16"], **cfg))
     pk = acom.Peaks.from_host(d3)
-    fpp3 = bound_flop_per_pattern(gpl)
+    fpp3 = bound_flop_per_pattern(gpl, "bf16")
     t0 = time.perf_counter()
     run3, host3 = time_match(gpl, pk, "bf16", 1, args.chunk, 1, 1, n3, fpp3)
     ws = torch.empty(gpl.match_workspace_bytes("bf16", args.chunk), dtype=torch.uint8, device="cuda")
@@ -1069,13 +1101,14 @@ def extra_workloads(args, fut):
     gpl.refine(pk, orr["orient"].reshape(nr, 4, 9), max_iter=64)
     torch.cuda.synchronize()
     stepsr, t_m, t_r = 3, 0.0, 0.0
+    work = torch.zeros(nr, 2, dtype=torch.int32, device="cuda")
     t0 = time.perf_counter()
     for _ in range(stepsr):
         a = time.perf_counter()
         gpl.match(pk, 4, "fp32", args.chunk, ws, out=orr)
         torch.cuda.synchronize()
         b = time.perf_counter()
-        m, S, c = gpl.refine(pk, orr["orient"].reshape(nr, 4, 9), max_iter=64)
+        m, S, c = gpl.refine(pk, orr["orient"].reshape(nr, 4, 9), max_iter=64, work=work)
         torch.cuda.synchronize()
         t_r += time.perf_counter() - b
         t_m += b - a
@@ -1120,6 +1153,7 @@ def extra_workloads(args, fut):
     out["refine"] = {"workload": DESCR["refine"], "patterns": nr, "steps": stepsr,
                      "patterns_per_s": round(nr * stepsr / (t_m + t_r), 1),
                      "ms_per_step_match": round(t_m * 1e3 / stepsr, 3), "ms_per_step_refine": round(t_r * 1e3 / stepsr, 3),
+                     "refine_roofline": refine_roofline(work, t_r * 1e3 / stepsr),
                      "timed_s": round(t_ref, 2),
                      "refined_vs_truth_deg": {"median": float(np.median(mis_t)), "p90": float(np.percentile(mis_t, 90)),
                                               "patterns": 512},
@@ -1146,6 +1180,8 @@ def main():
                     help="plan parameter bound_exact_freqs (0: the library's default)")
     ap.add_argument("--bound-block-radii", type=int, default=0,
                     help="plan parameter bound_block_radii (0: the library's default)")
+    ap.add_argument("--bound-exact-freqs-16bit", type=int, default=0,
+                    help="plan parameter bound_exact_freqs_16bit (0: the library's default)")
     ap.add_argument("--no-extra", action="store_true",
                     help="default run: skip the HCP, three-phase and refinement extra keys")
     ap.add_argument("--rounds", type=int, default=2,

@@ -90,10 +90,11 @@ typedef struct {
   int32_t kernel;        /* acom_kernel_t */
   int32_t precisions;    /* bit mask of (1 << acom_precision_t) operand copies to build; FP32 is always built */
   int32_t keep_f64;      /* nonzero: keep the FP64 angular plan for acom_plan_copy_f64 */
-  int32_t bound_exact_freqs;  /* split bound of acom_match: frequencies k < Kc bounded by their exact
-                                 correlogram spectra; 0 -> Kc = min(N_phi/2 + 1, 32) */
+  int32_t bound_exact_freqs;  /* split bound of acom_match with FP32 operands: frequencies k < Kc bounded
+                                 by their exact correlogram spectra; 0 -> Kc = min(N_phi/2 + 1, 24) */
   int32_t bound_block_radii;  /* radii per block of the Cauchy-Schwarz bound for k >= Kc: 2, 4, 8 or 16
                                  (0 -> 8) */
+  int32_t bound_exact_freqs_16bit;  /* Kc for BF16 / FP16 operands; 0 -> min(N_phi/2 + 1, 48) */
 } acom_plan_params_t;
 
 typedef struct acom_plan_s* acom_plan_t;
@@ -142,10 +143,10 @@ acom_status_t acom_plan_info(acom_plan_t plan, int32_t* n_zones, int32_t* n_radi
                              int32_t* n_angular, int32_t* n_phases, double* q_s, double* zones,
                              int32_t* zone_phase, double* norm_A);
 
-/* The split of the contraction pass's bound (see acom_match): Kc exact
- * frequencies and the radii per block of the Cauchy-Schwarz part; either
- * pointer may be NULL. */
-acom_status_t acom_plan_bound_split(acom_plan_t plan, int32_t* exact_freqs, int32_t* block_radii);
+/* The split of the contraction pass's bound (see acom_match) for operands of
+ * `precision`: Kc exact frequencies and the radii per block of the
+ * Cauchy-Schwarz part; either pointer may be NULL. */
+acom_status_t acom_plan_bound_split(acom_plan_t plan, int32_t precision, int32_t* exact_freqs, int32_t* block_radii);
 
 /* Copy the FP64 angular plan P[z][a][s] (Z x N_phi x N_r) to host memory.
  * Requires keep_f64 at build time, else ACOM_E_UNSUPPORTED. */
@@ -172,7 +173,8 @@ acom_status_t acom_match_workspace_size(acom_plan_t plan, int32_t precision, int
  *   T_k = max(|G_k|, |G_m,k|)                     for k < Kc,
  *   T_k = sum_b ||FFT{P}_k,b|| ||FFT{X}_k,b||     for k >= Kc (Cauchy-Schwarz
  *         on blocks b of bound_block_radii radii),
- * with Kc and the block size set at plan build (acom_plan_bound_split).
+ * with Kc (per operand precision) and the block size set at plan build
+ * (acom_plan_bound_split).
  * Adds a 3-point parabolic sub-bin offset and the orientation matrix.
  * top_k in [1, 16]; `chunk` must equal the value given to the size query. */
 acom_status_t acom_match(acom_plan_t plan, const acom_peaks_t* peaks, int32_t top_k,
@@ -185,8 +187,8 @@ acom_status_t acom_match(acom_plan_t plan, const acom_peaks_t* peaks, int32_t to
  * memory is a 128 MiB array in the library's device code, one per GPU, held
  * until the process ends.  The call allocates nothing and runs in chunks of
  * acom_match_noalloc_chunk patterns (the largest multiple of 64, at most
- * 16384, whose workspace fits 128 MiB: 448 at 1081 zones x 128 x 360 bins with
- * a 16-bit copy).  ACOM_E_UNSUPPORTED when not even 64 patterns fit (a plan of
+ * 16384, whose workspace fits 128 MiB: several hundred at 1081 zones x 128 x
+ * 360 bins).  ACOM_E_UNSUPPORTED when not even 64 patterns fit (a plan of
  * tens of thousands of zones); use acom_match then.  Every call on a GPU uses
  * that GPU's one array: calls that overlap in time on one GPU (on different
  * streams or host threads) race and must be serialised by the caller. */
@@ -288,10 +290,14 @@ acom_status_t acom_score_grad(acom_plan_t plan, const acom_peaks_t* peaks, const
  * out_orient n x 9, out_score n, out_cand n (index of the winner) or NULL.
  * A candidate with an invalid phase or non-finite matrix is skipped (out_cand
  * = -1 and score 0 when none is left); a candidate whose reflection set exceeds
- * 1024 makes the pattern an error: out_cand = -2, out_score = NaN. */
+ * 1024 makes the pattern an error: out_cand = -2, out_score = NaN.
+ * out_work (n x 2, or NULL) counts the kernel's work per pattern: the (peak,
+ * reflection) pairs evaluated for S alone (trial steps) and for S with its
+ * gradient (start and accepted orientations). */
 acom_status_t acom_refine(acom_plan_t plan, const acom_peaks_t* peaks, int32_t n_cand,
                           const float* init_orient, const int32_t* cand_phase, int32_t max_iter,
-                          float* out_orient, float* out_score, int32_t* out_cand, void* stream);
+                          float* out_orient, float* out_score, int32_t* out_cand, int32_t* out_work,
+                          void* stream);
 
 /* ------------------------------------------------------------ profile ---- */
 
@@ -326,7 +332,9 @@ acom_status_t acom_profile_end(void);
  * key 7: radial columns per pass of the polar (splat + FFT) kernel: 16 or 32 (default; 16 when
  *        Rp is not a multiple of 32).  The image and spectrum are bit-identical either way;
  * key 8: largest zone count (0 .. 32768, default 16384) whose per-pattern bound row the exact
- *        pass copies to LDS; larger plans select zones in place in the workspace.
+ *        pass copies to LDS; larger plans select zones in place in the workspace;
+ * key 9: 1 = the exact pass runs on persistent workgroups that take patterns from XCD-local
+ *        work queues in the workspace (default), 0 = one workgroup per pattern.
  * A shape found by acom_autotune takes precedence over keys 0, 1, 4 and 6 for its precision
  * until one of those keys is set again. */
 acom_status_t acom_set_tuning(int32_t key, int32_t value);

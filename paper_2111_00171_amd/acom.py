@@ -36,7 +36,8 @@ class _Params(ctypes.Structure):
                 ("accel_kV", c_double), ("zone_step_deg", c_double), ("gauss_sigma", c_double),
                 ("sigma_exc", c_double), ("n_radial", c_int32), ("n_angular", c_int32), ("radial", c_int32),
                 ("kernel", c_int32), ("precisions", c_int32), ("keep_f64", c_int32),
-                ("bound_exact_freqs", c_int32), ("bound_block_radii", c_int32)]
+                ("bound_exact_freqs", c_int32), ("bound_block_radii", c_int32),
+                ("bound_exact_freqs_16bit", c_int32)]
 
 
 class _Peaks(ctypes.Structure):
@@ -71,7 +72,7 @@ def lib():
             "acom_plan_info": [c_void_p, P(c_int32), P(c_int32), P(c_int32), P(c_int32), P(c_double), P(c_double),
                                P(c_int32), P(c_double)],
             "acom_plan_copy_f64": [c_void_p, P(c_double)],
-            "acom_plan_bound_split": [c_void_p, P(c_int32), P(c_int32)],
+            "acom_plan_bound_split": [c_void_p, c_int32, P(c_int32), P(c_int32)],
             "acom_plan_destroy": [c_void_p],
             "acom_match_workspace_size": [c_void_p, c_int32, c_int32, P(c_size_t)],
             "acom_match": [c_void_p, P(_Peaks), c_int32, c_int32, c_int32, c_void_p, c_size_t, P(_Matches), c_void_p],
@@ -96,7 +97,7 @@ def lib():
             "acom_score_grad": [c_void_p, P(_Peaks), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                 c_void_p, c_void_p],
             "acom_refine": [c_void_p, P(_Peaks), c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p,
-                            c_void_p],
+                            c_void_p, c_void_p],
             "acom_disk_template": [c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p],
             "acom_detect_disks": [c_void_p, c_int64, c_void_p, P(_DiskParams), c_void_p, c_void_p, c_void_p, c_void_p,
                                   c_void_p, c_void_p, c_void_p, c_void_p],
@@ -236,8 +237,9 @@ class PlanParams:
     sigma_exc: float = 0.02
     precisions: Sequence[str] = field(default_factory=lambda: ["fp32"])
     keep_f64: bool = False
-    bound_exact_freqs: int = 0      # 0: the library's default split
+    bound_exact_freqs: int = 0      # 0: the library's default split (FP32 operands)
     bound_block_radii: int = 0
+    bound_exact_freqs_16bit: int = 0
 
 
 class Peaks:
@@ -356,6 +358,7 @@ class Plan:
         prm.keep_f64 = 1 if params.keep_f64 else 0
         prm.bound_exact_freqs = params.bound_exact_freqs
         prm.bound_block_radii = params.bound_block_radii
+        prm.bound_exact_freqs_16bit = params.bound_exact_freqs_16bit
         h = c_void_p()
         _check(L.acom_build_plan(arr, len(phases), ctypes.byref(prm), _stream(stream), ctypes.byref(h)),
                "acom_build_plan")
@@ -412,10 +415,11 @@ class Plan:
         return {"q_s": np.array(qs[:]), "zones": np.array(zs[:]).reshape(Z, 3), "zone_phase": np.array(zp[:]),
                 "norm_A": np.array(A[:])}
 
-    def bound_split(self):
+    def bound_split(self, precision="fp32"):
         """(Kc, radii per block) of the contraction pass's split bound."""
         kc, bb = c_int32(), c_int32()
-        _check(lib().acom_plan_bound_split(self._h, ctypes.byref(kc), ctypes.byref(bb)), "acom_plan_bound_split")
+        _check(lib().acom_plan_bound_split(self._h, PRECISIONS[precision], ctypes.byref(kc), ctypes.byref(bb)),
+               "acom_plan_bound_split")
         return kc.value, bb.value
 
     def angular_f64(self):
@@ -643,12 +647,13 @@ class Plan:
                                      _stream(stream)), "acom_score_grad")
         return dth, dqx, dqy
 
-    def refine(self, peaks: Peaks, init_orient, cand_phase=None, max_iter=64, stream=None):
+    def refine(self, peaks: Peaks, init_orient, cand_phase=None, max_iter=64, stream=None, work=None):
         n = peaks.n_patterns
         dev = peaks.offsets.device
         n_cand = int(init_orient.shape[1])
         _need(init_orient, (n, n_cand, 9), "init_orient")
         _need(cand_phase, (n, n_cand), "cand_phase")
+        _need(work, (n, 2), "work")
         out = torch.empty(n, 3, 3, dtype=torch.float32, device=dev)
         S = torch.empty(n, dtype=torch.float32, device=dev)
         cand = torch.empty(n, dtype=torch.int32, device=dev)
@@ -656,20 +661,21 @@ class Plan:
         _check(lib().acom_refine(self._h, ctypes.byref(pk), n_cand, _ptr(init_orient, torch.float32, "init_orient"),
                                  _ptr(cand_phase, torch.int32, "cand_phase"), int(max_iter),
                                  _ptr(out, torch.float32, "out"), _ptr(S, torch.float32, "S"),
-                                 _ptr(cand, torch.int32, "cand"), _stream(stream)), "acom_refine")
+                                 _ptr(cand, torch.int32, "cand"), _ptr(work, torch.int32, "work"), _stream(stream)),
+               "acom_refine")
         return out, S, cand
 
 
 KERNEL_KINDS = {"polar": 0, "bound": 1, "exact": 2}
 TUNING_KEYS = {"bound_order": 0, "bound_kch16": 1, "exact_xcd": 2, "polar_xcd": 3, "bound_tile": 4, "skip_zero_radii": 5,
-               "bound_kch32": 6, "polar_cols": 7, "exact_u_lds_max": 8}
+               "bound_kch32": 6, "polar_cols": 7, "exact_u_lds_max": 8, "exact_persist": 9}
 
 
 def set_tuning(**kw):
     """Launch-shape knobs of the calling thread (results do not depend on them):
     bound_order (0/1), bound_kch16 (32/64/128), exact_xcd (0/1), polar_xcd (0/1),
     bound_tile (0/1/2), skip_zero_radii (0/1), bound_kch32 (16/32), polar_cols
-    (16/32), exact_u_lds_max (zones whose bound row the exact pass keeps in LDS)."""
+    (16/32), exact_u_lds_max (zones whose bound row the exact pass keeps in LDS), exact_persist (0/1)."""
     for k, v in kw.items():
         _check(lib().acom_set_tuning(TUNING_KEYS[k], int(v)), "acom_set_tuning")
 

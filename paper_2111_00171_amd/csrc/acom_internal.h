@@ -38,6 +38,8 @@ constexpr int kSChunk = 32;
 constexpr int kMaxRadices = 12;
 constexpr int kMaxAngular = 1024;
 constexpr int kMaxTopK = 16;
+// default exact frequencies of the split bound, FP32 / 16-bit operands
+constexpr int kDefaultExactFreqs[2] = {24, 48};
 
 // Mixed-radix factorisation of the angular length (radices 8, 9, 4, 2, 3, 5, greedily).
 struct Radices {
@@ -54,15 +56,17 @@ struct PlanDev {
   int r0 = 0;               // leading radial bins where FFT{P} is zero in every zone
   // Split bound of the contraction pass: frequencies k < Kc are bounded by the
   // larger modulus of the two correlogram spectra, k >= Kc by Cauchy-Schwarz on
-  // blocks of bb radii.  The block norms form a vector of L = (Nk - Kc) nb
+  // blocks of bb radii.  Kc is set per operand precision (index 0: FP32, 1:
+  // the 16-bit copies).  The block norms form a vector of L = (Nk - Kc) nb
   // entries per zone (and per pattern) that the operand arrays carry in
-  // npseudo extra rows after the frequency rows, Sp = Rp - r0 entries in the
+  // npseudo extra rows after the spectrum rows, Sp = Rp - r0 entries in the
   // real and Sp in the imaginary array of each row (slots r0 .. Rp-1; slots
-  // below r0 hold zeros).  Rows per 64-row tile: rows32 = Nk + npseudo for the
-  // FP32 operands (the exact pass reads rows < Nk), rows16 = Kc + npseudo for
-  // the 16-bit copies.
-  int Kc = 0, bb = 8, nb = 0, Sp = 0, npseudo = 0, rows32 = 0, rows16 = 0;
-  int64_t L = 0;
+  // below r0 hold zeros).  Rows per 64-row tile: rows32 = Nk + npseudo[0] for
+  // the FP32 operands (the exact pass reads rows < Nk), rows16 = Kc[1] +
+  // npseudo[1] for the 16-bit copies.
+  int Kc[2] = {0, 0}, npseudo[2] = {0, 0};
+  int64_t L[2] = {0, 0};
+  int bb = 8, nb = 0, Sp = 0, rows32 = 0, rows16 = 0;
   int N = 0, Nk = 0;        // angular bins, N/2 + 1
   int n_phases = 0;
   Radices rad;

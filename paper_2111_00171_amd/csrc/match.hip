@@ -118,12 +118,14 @@ struct PolarArgs {
   uint16_t *lr, *li;       // low-precision copies (rows k < Kc, then the norm rows; tile stride ld_tile16) or null
   size_t ld_tile16;
   int lowp;                // 0 none, ACOM_BF16, ACOM_FP16
-  // split bound (workspace layout only): block norms w_k ||FFT{X}[k][b bb ..]||
-  // of the frequencies k >= Kc as entries v = (k - Kc) nb + b of the norm
-  // vector, in rows Nk + j (FP32) and Kc + j (16-bit), j = v / 2Sp, at slot
-  // r0 + v mod Sp of the real (v mod 2Sp < Sp) or imaginary array
+  // split bound (workspace layout only), for the operands of the precision
+  // matched: block norms w_k ||FFT{X}[k][b bb ..]|| of the frequencies k >= Kn
+  // as entries v = (k - Kn) nb + b of the norm vector, j = v / 2Sp, at slot
+  // r0 + v mod Sp of the real (v mod 2Sp < Sp) or imaginary array of FP32 row
+  // Nk + j (lowp == 0) or 16-bit row Kc16 + j
   int ws_layout;           // 1: the workspace's tile-major layout (norms written), 0: a caller's layout
-  int Kc, bb, nb, Sp, r0, npseudo;
+  int Kc16;                // 16-bit spectrum rows kept
+  int Kn, bb, nb, Sp, r0, npseudo;
   int64_t L;
   float* scale;            // np: factor applied before the FP16 cast (else 1)
   float* xnorm2;           // np: sum of X^2 of the pattern's polar image
@@ -133,6 +135,7 @@ struct PolarArgs {
   int ntiles;              // radial tiles of kPolarCols columns (column-mask words per pattern)
   int per;                 // > 0: XCD-grouped block order with this many items per XCD
   uint32_t* cmask;         // np x ntiles: bit c set when column c of the tile holds a nonzero X (or null)
+  int* queue;              // kXcds counters of the persistent exact pass, zeroed here (or null)
 };
 
 // One workgroup per pattern, looping over its radial tiles of NC columns (16 or
@@ -188,6 +191,7 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
   const int tid = threadIdx.x;
   const int p = a.per > 0 ? xcd_item(a.per) : (int)blockIdx.x;
   if (p >= a.np) return;
+  if (p == 0 && a.queue && tid < kXcds) a.queue[tid] = 0;  // read only by the next kernels on the stream
   const int64_t P = a.p_begin + p;
   int64_t m0 = a.offsets[P], m1 = a.offsets[P + 1];
   const bool bad_range = m0 < 0 || m1 < m0 || m1 > a.total_peaks;
@@ -396,10 +400,10 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
         *reinterpret_cast<float2*>(a.xr + o) = make_float2(E.x, O.x);
         *reinterpret_cast<float2*>(a.xi + o) = make_float2(E.y, O.y);
         const size_t o16 = pbase16 + (size_t)k * a.ldk + s0;
-        if (a.lowp == ACOM_BF16 && k < a.Kc) {
+        if (a.lowp == ACOM_BF16 && k < a.Kc16) {
           *reinterpret_cast<uint32_t*>(a.lr + o16) = (uint32_t)to_bf16_bits(E.x) | ((uint32_t)to_bf16_bits(O.x) << 16);
           *reinterpret_cast<uint32_t*>(a.li + o16) = (uint32_t)to_bf16_bits(E.y) | ((uint32_t)to_bf16_bits(O.y) << 16);
-        } else if (a.lowp == ACOM_FP16 && k < a.Kc) {
+        } else if (a.lowp == ACOM_FP16 && k < a.Kc16) {
           *reinterpret_cast<uint32_t*>(a.lr + o16) =
               (uint32_t)to_f16_bits(E.x * sc) | ((uint32_t)to_f16_bits(O.x * sc) << 16);
           *reinterpret_cast<uint32_t*>(a.li + o16) =
@@ -409,18 +413,19 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
           // block norm over the bb / 2 column pairs of a radial block: they sit
           // on consecutive lanes of one frequency (NS is a multiple of bb / 2),
           // which are active together
-          float n2 = k >= a.Kc ? (E.x * E.x + E.y * E.y) + (O.x * O.x + O.y * O.y) : 0.0f;
+          float n2 = k >= a.Kn ? (E.x * E.x + E.y * E.y) + (O.x * O.x + O.y * O.y) : 0.0f;
           for (int off = 1; off < a.bb / 2; off <<= 1) n2 += __shfl_xor(n2, off, 64);
-          if (k >= a.Kc && (q % (a.bb / 2)) == 0) {
+          if (k >= a.Kn && (q % (a.bb / 2)) == 0) {
             const float nrm = wk * __builtin_amdgcn_sqrtf(n2);
-            const int64_t v = (int64_t)(k - a.Kc) * a.nb + s0 / a.bb;
+            const int64_t v = (int64_t)(k - a.Kn) * a.nb + s0 / a.bb;
             const int j = (int)(v / (2 * a.Sp)), e = (int)(v % (2 * a.Sp));
             const int slot = a.r0 + e % a.Sp;
-            (e < a.Sp ? a.xr : a.xi)[pbase + (size_t)(a.Nk + j) * a.ldk + slot] = nrm;
-            if (a.lowp == ACOM_BF16)
-              (e < a.Sp ? a.lr : a.li)[pbase16 + (size_t)(a.Kc + j) * a.ldk + slot] = to_bf16_bits_up(nrm);
-            else if (a.lowp == ACOM_FP16)
-              (e < a.Sp ? a.lr : a.li)[pbase16 + (size_t)(a.Kc + j) * a.ldk + slot] = to_f16_bits_up(nrm * sc);
+            if (a.lowp == 0)
+              (e < a.Sp ? a.xr : a.xi)[pbase + (size_t)(a.Nk + j) * a.ldk + slot] = nrm;
+            else if (a.lowp == ACOM_BF16)
+              (e < a.Sp ? a.lr : a.li)[pbase16 + (size_t)(a.Kc16 + j) * a.ldk + slot] = to_bf16_bits_up(nrm);
+            else
+              (e < a.Sp ? a.lr : a.li)[pbase16 + (size_t)(a.Kc16 + j) * a.ldk + slot] = to_f16_bits_up(nrm * sc);
           }
         }
       } else {  // caller's [p][k][s] layout with s < out_cols (verification entry point)
@@ -460,8 +465,10 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
   // the norm rows' slots that hold no entry: below r0, and past the vector's end
   if (a.ws_layout && a.npseudo > 0 && a.do_fft) {
     auto zero = [&](int j, int part, int slot) {
-      (part ? a.xi : a.xr)[pbase + (size_t)(a.Nk + j) * a.ldk + slot] = 0.0f;
-      if (a.lowp) (part ? a.li : a.lr)[pbase16 + (size_t)(a.Kc + j) * a.ldk + slot] = 0;
+      if (a.lowp == 0)
+        (part ? a.xi : a.xr)[pbase + (size_t)(a.Nk + j) * a.ldk + slot] = 0.0f;
+      else
+        (part ? a.li : a.lr)[pbase16 + (size_t)(a.Kc16 + j) * a.ldk + slot] = 0;
     };
     for (int i = tid; i < a.npseudo * 2 * a.r0; i += kThreads) zero(i / (2 * a.r0), (i / a.r0) % 2, i % a.r0);
     for (int64_t v = a.L + tid; v < (int64_t)a.npseudo * 2 * a.Sp; v += kThreads) {
@@ -816,6 +823,7 @@ struct ExactArgs {
   const float *xr, *xi;     // tile-major over the chunk's patterns (FP32)
   const float *pr, *pi;     // zone-major [Z][Nk][Rp] (FP32)
   int xrows;                // rows per 64-pattern tile of the FP32 spectrum (frequencies, then norm rows)
+  int* queue;               // kXcds pattern counters of the persistent exact pass (workspace)
   float* U;                 // bound rows (workspace); updated in place when u_lds == 0
   int ldU;
   int u_lds;                // 1: the pattern's bound row is copied to LDS; 0: selected in place in U
@@ -840,16 +848,27 @@ struct ExactArgs {
 };
 
 // The 4-radius groups of pattern p whose columns hold any nonzero X, in
-// increasing order (the others contribute exact zeros to every contraction).
+// increasing order (the others contribute exact zeros to every contraction):
+// wave 0 reads the column masks in parallel, one group per lane, and compacts
+// the active groups in order by ballot.
 __device__ void active_groups(const ExactArgs& a, int p, int* groups, int* ng) {
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    constexpr int GPT = kPolarCols / 4;  // groups per mask word
+    const int total = a.ntiles * GPT;
     int n = 0;
-    for (int t = 0; t < a.ntiles; ++t) {
-      const uint32_t m = a.cmask ? a.cmask[(size_t)p * a.ntiles + t] : 0xFFFFu;
-      for (int j = 0; j < kPolarCols / 4; ++j)
-        if ((m >> (4 * j)) & 0xFu) groups[n++] = t * (kPolarCols / 4) + j;
+    for (int g0 = 0; g0 < total; g0 += 64) {
+      const int g = g0 + lane;
+      bool act = false;
+      if (g < total) {
+        const uint32_t m = a.cmask ? a.cmask[(size_t)p * a.ntiles + g / GPT] : 0xFFFFu;
+        act = ((m >> (4 * (g % GPT))) & 0xFu) != 0u;
+      }
+      const unsigned long long bal = __ballot(act);
+      if (act) groups[n + __popcll(bal & ((1ull << lane) - 1ull))] = g;
+      n += __popcll(bal);
     }
-    *ng = n;
+    if (lane == 0) *ng = n;
   }
   __syncthreads();
 }
@@ -978,7 +997,13 @@ __device__ __forceinline__ int exact_stride(int nb) {
   return (NT > 0 && nb == 3) ? 4 : nb;
 }
 
-template <int NT>
+// PERSIST: a persistent grid (a few workgroups per compute unit) in which the
+// workgroups of XCD x take the patterns of the x-th eighth of the chunk one by
+// one from that XCD's counter in the workspace (zeroed by the polar pass), so
+// neighbouring patterns still share an XCD's L2, the FFT tables are loaded
+// once per workgroup, and a pattern that evaluates many zones holds up only
+// its own workgroup.  Every workgroup leaves once its range is exhausted.
+template <int NT, bool PERSIST>
 __global__ void __launch_bounds__(kThreads) exact_kernel(ExactArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   float2* H0 = reinterpret_cast<float2*>(smem_raw);
@@ -1051,8 +1076,7 @@ __global__ void __launch_bounds__(kThreads) exact_kernel(ExactArgs a) {
     return;
   }
 
-  const int p = a.per < 0 ? (int)blockIdx.x : xcd_item(a.per);
-  if (p >= a.np) return;
+  auto one = [&](const int p) {
   const int64_t P = a.p_begin + p;
   const int fl = a.flags[p];
   if (fl != 0) {
@@ -1227,6 +1251,25 @@ __global__ void __launch_bounds__(kThreads) exact_kernel(ExactArgs a) {
     }
   }
   if (a.n_eval && tid == 0) a.n_eval[P - a.out_p0] = s_eval;
+  };  // one pattern
+
+  if constexpr (!PERSIST) {
+    const int p = a.per < 0 ? (int)blockIdx.x : xcd_item(a.per);
+    if (p >= a.np) return;
+    one(p);
+  } else {
+    __shared__ int s_next;
+    const int x = (int)(blockIdx.x % kXcds);
+    const int lo = x * a.per, hi = min(a.np, lo + a.per);
+    while (true) {
+      __syncthreads();  // the previous pattern is done with every LDS array and s_next
+      if (tid == 0) s_next = lo + atomicAdd(a.queue + x, 1);
+      __syncthreads();
+      const int p = s_next;
+      if (p >= hi) break;
+      one(p);
+    }
+  }
 }
 
 // --------------------------------------------- 4. overlapping patterns ----
@@ -1368,6 +1411,7 @@ struct Tuning {
   int bound_kch32 = 16;   // radii per LDS step of the FP32 contraction (16 or 32)
   int polar_cols = 32;    // radial columns per pass of the polar kernel (16 or 32)
   int exact_u_lds_max = 16384;  // largest zone count whose bound row the exact pass copies to LDS
+  int exact_persist = 1;         // exact pass: persistent workgroups on XCD-local work queues
   PlanDev::BoundShape tuned[3];  // contraction shape per operand precision found by acom_autotune
 };
 // Launch-shape settings of the calling host thread: plans stay immutable after
@@ -1400,7 +1444,7 @@ struct ProfScope {
 };
 
 struct WsLayout {
-  size_t xr = 0, xi = 0, lr = 0, li = 0, scale = 0, xn2 = 0, cmask = 0, flags = 0, U = 0, total = 0;
+  size_t xr = 0, xi = 0, lr = 0, li = 0, scale = 0, xn2 = 0, cmask = 0, flags = 0, U = 0, queue = 0, total = 0;
   int Pc = 0, ntiles = 0;
   bool lowp = false;
 };
@@ -1428,6 +1472,7 @@ WsLayout layout(const PlanDev& d, bool lowp, int Pc) {
   L.cmask = take((size_t)Pc * L.ntiles * 4);
   L.flags = take((size_t)Pc * 4);
   L.U = take((size_t)Pc * d.Zp * 4);
+  L.queue = take(kXcds * 4);
   L.total = o;
   return L;
 }
@@ -1495,13 +1540,16 @@ PolarArgs polar_args(const PlanDev& d, const acom_peaks_t* pk, int64_t p_begin, 
   a.cmask = nullptr;
   a.ws_layout = 0;
   a.ld_tile16 = 0;
-  a.Kc = d.Kc;
+  a.queue = nullptr;
+  const int c = lowp ? 1 : 0;
+  a.Kc16 = d.Kc[1];
+  a.Kn = d.Kc[c];
   a.bb = d.bb;
   a.nb = d.nb;
   a.Sp = d.Sp;
   a.r0 = d.r0;
-  a.npseudo = d.npseudo;
-  a.L = d.L;
+  a.npseudo = d.npseudo[c];
+  a.L = d.L[c];
   return a;
 }
 
@@ -1520,6 +1568,7 @@ void set_ws(PolarArgs& a, const WsLayout& L, unsigned char* ws, const PlanDev& d
   a.xnorm2 = reinterpret_cast<float*>(ws + L.xn2);
   a.cmask = reinterpret_cast<uint32_t*>(ws + L.cmask);
   a.flags = reinterpret_cast<int*>(ws + L.flags);
+  a.queue = reinterpret_cast<int*>(ws + L.queue);
 }
 
 template <int NT, int NC>
@@ -1543,21 +1592,37 @@ acom_status_t launch_polar_n(const PlanDev& d, const PolarArgs& a, hipStream_t s
 }
 
 template <int NT>
-acom_status_t launch_exact_n(const PlanDev& d, const ExactArgs& e, dim3 grid, hipStream_t s) {
-  acom_status_t st = ensure_lds(exact_kernel<NT>, exact_lds(d, e.u_lds));
+acom_status_t launch_exact_n(const PlanDev& d, const ExactArgs& e, dim3 grid, hipStream_t s, bool persist) {
+  const size_t lds = exact_lds(d, e.u_lds);
+  if (!persist) {
+    acom_status_t st = ensure_lds(exact_kernel<NT, false>, lds);
+    if (st != ACOM_OK) return st;
+    exact_kernel<NT, false><<<grid, kThreads, lds, s>>>(e);
+    ACOM_HIP(hipGetLastError());
+    return ACOM_OK;
+  }
+  // persistent: the workgroups that fit the device at once, in XCD-local ranges
+  acom_status_t st = ensure_lds(exact_kernel<NT, true>, lds);
   if (st != ACOM_OK) return st;
-  exact_kernel<NT><<<grid, kThreads, exact_lds(d, e.u_lds), s>>>(e);
+  int dev = 0, cus = 0, per_cu = 0;
+  ACOM_HIP(hipGetDevice(&dev));
+  ACOM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  ACOM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, exact_kernel<NT, true>, kThreads, lds));
+  ExactArgs p = e;
+  p.per = (p.np + kXcds - 1) / kXcds;
+  const int nblk = std::max(kXcds, (std::max(1, cus * std::max(1, per_cu)) / kXcds) * kXcds);
+  exact_kernel<NT, true><<<dim3(nblk), kThreads, lds, s>>>(p);
   ACOM_HIP(hipGetLastError());
   return ACOM_OK;
 }
-acom_status_t launch_exact(const PlanDev& d, const ExactArgs& e, dim3 grid, hipStream_t s) {
+acom_status_t launch_exact(const PlanDev& d, const ExactArgs& e, dim3 grid, hipStream_t s, bool persist = false) {
   switch (d.N) {  // the same compile-time FFT lengths as the polar pass
-    case 90: return launch_exact_n<90>(d, e, grid, s);
-    case 120: return launch_exact_n<120>(d, e, grid, s);
-    case 180: return launch_exact_n<180>(d, e, grid, s);
-    case 360: return launch_exact_n<360>(d, e, grid, s);
-    case 720: return launch_exact_n<720>(d, e, grid, s);
-    default: return launch_exact_n<0>(d, e, grid, s);
+    case 90: return launch_exact_n<90>(d, e, grid, s, persist);
+    case 120: return launch_exact_n<120>(d, e, grid, s, persist);
+    case 180: return launch_exact_n<180>(d, e, grid, s, persist);
+    case 360: return launch_exact_n<360>(d, e, grid, s, persist);
+    case 720: return launch_exact_n<720>(d, e, grid, s, persist);
+    default: return launch_exact_n<0>(d, e, grid, s, persist);
   }
 }
 
@@ -1623,9 +1688,10 @@ acom_status_t launch_bound(const PlanDev& d, int precision, const WsLayout& L, u
   b.Nk = d.Nk;
   b.Rp = d.Rp;
   b.N = d.N;
-  b.Kc = d.Kc;
-  b.nlog = d.Kc + d.npseudo;
-  b.hi = precision == ACOM_FP32 ? d.Nk : d.Kc;
+  const int c = precision == ACOM_FP32 ? 0 : 1;
+  b.Kc = d.Kc[c];
+  b.nlog = d.Kc[c] + d.npseudo[c];
+  b.hi = precision == ACOM_FP32 ? d.Nk : d.Kc[1];
   b.rows = precision == ACOM_FP32 ? d.rows32 : d.rows16;
   b.order = t ? t->order : g_tune.bound_order;
   b.nX64 = (np + 63) / 64;
@@ -1680,6 +1746,7 @@ ExactArgs exact_args(const PlanDev& d, const WsLayout& L, unsigned char* ws, int
   e.pr = d.d_PRz;
   e.pi = d.d_PIz;
   e.U = reinterpret_cast<float*>(ws + L.U);
+  e.queue = reinterpret_cast<int*>(ws + L.queue);
   e.ldU = d.Zp;
   e.u_lds = d.Z <= g_tune.exact_u_lds_max ? 1 : 0;
   e.xnorm2 = reinterpret_cast<const float*>(ws + L.xn2);
@@ -1747,7 +1814,7 @@ acom_status_t match_chunk(const PlanDev& d, const acom_peaks_t* peaks, int64_t c
   else
     e.per = -1;
   ProfScope prof(2, s);
-  return launch_exact(d, e, dim3(nblk), s);
+  return launch_exact(d, e, dim3(nblk), s, g_tune.exact_persist != 0);
 }
 
 int chunk_of(int chunk) {
@@ -2253,6 +2320,10 @@ extern "C" acom_status_t acom_set_tuning(int32_t key, int32_t value) {
     case 8:
       if (value < 0 || value > 32768) return fail(ACOM_E_INVALID, "LDS bound-row limit must be in [0, 32768] zones");
       g_tune.exact_u_lds_max = value;
+      return ACOM_OK;
+    case 9:
+      if (value != 0 && value != 1) return fail(ACOM_E_INVALID, "persistent exact pass must be 0 or 1");
+      g_tune.exact_persist = value;
       return ACOM_OK;
 
   }

@@ -304,15 +304,17 @@ __device__ __forceinline__ float f32_up(double v) {
 // Contraction operands, tile-major (64-row zone tiles), from the zone-major
 // FP32 spectrum: block (z, row), threads over the row's Rp slots.
 //   row < Nk:  FFT{P} at frequency row (FP32, tile stride rows32), and for
-//              row < Kc the 16-bit copies (tile stride rows16);
-//   row >= Nk: pseudo row j = row - Nk of the split bound's norm vector,
-//              entry v = (k - Kc) nb + b = ||FFT{P}[z][k][b bb .. b bb + bb)||,
+//              row < Kc[1] the 16-bit copies (tile stride rows16);
+//   row >= Nk: norm row j = row - Nk of the split bound of each precision c
+//              (0: FP32, 1: 16-bit) that has one: entry
+//              v = (k - Kc[c]) nb + b = ||FFT{P}[z][k][b bb .. b bb + bb)||
 //              at slot r0 + v mod Sp of the real (v mod 2Sp < Sp) or
-//              imaginary array; FP32 row Nk + j, 16-bit row Kc + j; rounded
-//              up (norms of the FP32 values, taken in FP64).
+//              imaginary array, FP32 row Nk + j or 16-bit row Kc[1] + j;
+//              rounded up (norms of the FP32 values, taken in FP64).
 struct TileArgs {
-  int Z, Nk, Rp, Kc, bb, nb, Sp, r0, npseudo, rows32, rows16;
-  int64_t L;
+  int Z, Nk, Rp, bb, nb, Sp, r0, rows32, rows16;
+  int Kc[2], npseudo[2];
+  int64_t L[2];
   const float *PRz, *PIz;
   float *PR, *PI;
   uint16_t *PRb, *PIb, *PRh, *PIh;
@@ -328,7 +330,7 @@ __global__ void plan_tile_kernel(TileArgs a) {
       const size_t o = tile_off(z, k, s, a.rows32, a.Rp);
       a.PR[o] = re;
       a.PI[o] = im;
-      if (k < a.Kc) {
+      if (k < a.Kc[1]) {
         const size_t o16 = tile_off(z, k, s, a.rows16, a.Rp);
         if (a.PRb) {
           a.PRb[o16] = bf16_bits(re);
@@ -343,23 +345,28 @@ __global__ void plan_tile_kernel(TileArgs a) {
     return;
   }
   const int j = row - a.Nk;
-  for (int e = threadIdx.x; e < 2 * a.Sp; e += blockDim.x) {
-    const int64_t v = (int64_t)j * 2 * a.Sp + e;
-    if (v >= a.L) break;
-    const int k = a.Kc + (int)(v / a.nb), b = (int)(v % a.nb);
-    double n2 = 0.0;
-    for (int s = b * a.bb; s < (b + 1) * a.bb; ++s) {
-      const size_t oz = ((size_t)z * a.Nk + k) * a.Rp + s;
-      const double re = a.PRz[oz], im = a.PIz[oz];
-      n2 += re * re + im * im;
+  for (int c = 0; c < 2; ++c) {
+    if (j >= a.npseudo[c] || (c == 1 && !a.PRb && !a.PRh)) continue;
+    for (int e = threadIdx.x; e < 2 * a.Sp; e += blockDim.x) {
+      const int64_t v = (int64_t)j * 2 * a.Sp + e;
+      if (v >= a.L[c]) break;
+      const int k = a.Kc[c] + (int)(v / a.nb), b = (int)(v % a.nb);
+      double n2 = 0.0;
+      for (int s = b * a.bb; s < (b + 1) * a.bb; ++s) {
+        const size_t oz = ((size_t)z * a.Nk + k) * a.Rp + s;
+        const double re = a.PRz[oz], im = a.PIz[oz];
+        n2 += re * re + im * im;
+      }
+      const float nrm = f32_up(sqrt(n2) * (1.0 + 1e-15));
+      const int part = e / a.Sp, slot = a.r0 + e % a.Sp;
+      if (c == 0) {
+        (part ? a.PI : a.PR)[tile_off(z, a.Nk + j, slot, a.rows32, a.Rp)] = nrm;
+      } else {
+        const size_t o16 = tile_off(z, a.Kc[1] + j, slot, a.rows16, a.Rp);
+        if (a.PRb) (part ? a.PIb : a.PRb)[o16] = bf16_bits_up(nrm);
+        if (a.PRh) (part ? a.PIh : a.PRh)[o16] = f16_bits_up(nrm);
+      }
     }
-    const float nrm = f32_up(sqrt(n2) * (1.0 + 1e-15));
-    const int part = e / a.Sp, slot = a.r0 + e % a.Sp;
-    const size_t o = tile_off(z, a.Nk + j, slot, a.rows32, a.Rp);
-    (part ? a.PI : a.PR)[o] = nrm;
-    const size_t o16 = tile_off(z, a.Kc + j, slot, a.rows16, a.Rp);
-    if (a.PRb) (part ? a.PIb : a.PRb)[o16] = bf16_bits_up(nrm);
-    if (a.PRh) (part ? a.PIh : a.PRh)[o16] = f16_bits_up(nrm);
   }
 }
 
@@ -448,7 +455,8 @@ acom_status_t validate(const acom_phase_t* phases, int n_phases, const acom_plan
   if (p->kernel != ACOM_KERNEL_CONE && p->kernel != ACOM_KERNEL_GAUSS)
     return fail(ACOM_E_INVALID, "kernel must be ACOM_KERNEL_CONE or ACOM_KERNEL_GAUSS");
   if (p->precisions & ~7) return fail(ACOM_E_INVALID, "precisions: unknown bits");
-  if (p->bound_exact_freqs < 0) return fail(ACOM_E_INVALID, "bound_exact_freqs must be >= 0 (0: default)");
+  if (p->bound_exact_freqs < 0 || p->bound_exact_freqs_16bit < 0)
+    return fail(ACOM_E_INVALID, "bound_exact_freqs(_16bit) must be >= 0 (0: default)");
   if (p->bound_block_radii != 0 && p->bound_block_radii != 2 && p->bound_block_radii != 4 &&
       p->bound_block_radii != 8 && p->bound_block_radii != 16)
     return fail(ACOM_E_INVALID, "bound_block_radii must be 2, 4, 8 or 16 (0: default 8)");
@@ -725,14 +733,20 @@ extern "C" acom_status_t acom_build_plan(const acom_phase_t* phases, int32_t n_p
   }
   // ---- split bound and the contraction operands (tile-major over zones)
   d.bb = prm->bound_block_radii > 0 ? prm->bound_block_radii : 8;
-  d.Kc = prm->bound_exact_freqs > 0 ? std::min(prm->bound_exact_freqs, d.Nk) : std::min(d.Nk, 32);
-  if (d.r0 >= d.R) d.Kc = d.Nk;  // a plan that is zero everywhere: nothing to split
   d.nb = d.Rp / d.bb;
   d.Sp = d.Rp - d.r0;
-  d.L = (int64_t)(d.Nk - d.Kc) * d.nb;
-  d.npseudo = d.L > 0 ? (int)((d.L + 2 * d.Sp - 1) / (2 * d.Sp)) : 0;
-  d.rows32 = d.Nk + d.npseudo;
-  d.rows16 = d.Kc + d.npseudo;
+  {
+    const int want[2] = {prm->bound_exact_freqs > 0 ? prm->bound_exact_freqs : kDefaultExactFreqs[0],
+                         prm->bound_exact_freqs_16bit > 0 ? prm->bound_exact_freqs_16bit : kDefaultExactFreqs[1]};
+    for (int c = 0; c < 2; ++c) {
+      d.Kc[c] = std::min(want[c], d.Nk);
+      if (d.r0 >= d.R) d.Kc[c] = d.Nk;  // a plan that is zero everywhere: nothing to split
+      d.L[c] = (int64_t)(d.Nk - d.Kc[c]) * d.nb;
+      d.npseudo[c] = d.L[c] > 0 ? (int)((d.L[c] + 2 * d.Sp - 1) / (2 * d.Sp)) : 0;
+    }
+  }
+  d.rows32 = d.Nk + d.npseudo[0];
+  d.rows16 = d.Kc[1] + d.npseudo[1];
   {
     const size_t n32 = (size_t)d.rows32 * d.Zp * d.Rp, n16 = (size_t)d.rows16 * d.Zp * d.Rp;
     if ((st = dalloc(&d.d_PR, n32)) || (st = dalloc(&d.d_PI, n32))) return bail(st);
@@ -749,15 +763,17 @@ extern "C" acom_status_t acom_build_plan(const acom_phase_t* phases, int32_t n_p
     ta.Z = d.Z;
     ta.Nk = d.Nk;
     ta.Rp = d.Rp;
-    ta.Kc = d.Kc;
     ta.bb = d.bb;
     ta.nb = d.nb;
     ta.Sp = d.Sp;
     ta.r0 = d.r0;
-    ta.npseudo = d.npseudo;
     ta.rows32 = d.rows32;
     ta.rows16 = d.rows16;
-    ta.L = d.L;
+    for (int c = 0; c < 2; ++c) {
+      ta.Kc[c] = d.Kc[c];
+      ta.npseudo[c] = d.npseudo[c];
+      ta.L[c] = d.L[c];
+    }
     ta.PRz = d.d_PRz;
     ta.PIz = d.d_PIz;
     ta.PR = d.d_PR;
@@ -766,7 +782,7 @@ extern "C" acom_status_t acom_build_plan(const acom_phase_t* phases, int32_t n_p
     ta.PIb = d.d_PI16[ACOM_BF16];
     ta.PRh = d.d_PR16[ACOM_FP16];
     ta.PIh = d.d_PI16[ACOM_FP16];
-    plan_tile_kernel<<<dim3(d.Z, d.rows32), 128, 0, stream>>>(ta);
+    plan_tile_kernel<<<dim3(d.Z, d.Nk + std::max(d.npseudo[0], d.npseudo[1])), 128, 0, stream>>>(ta);
     if (hipGetLastError() != hipSuccess) return bail(fail(ACOM_E_HIP, "plan_tile_kernel launch"));
   }
 
@@ -833,9 +849,11 @@ extern "C" acom_status_t acom_plan_info(acom_plan_t plan, int32_t* n_zones, int3
   return ACOM_OK;
 }
 
-extern "C" acom_status_t acom_plan_bound_split(acom_plan_t plan, int32_t* exact_freqs, int32_t* block_radii) {
+extern "C" acom_status_t acom_plan_bound_split(acom_plan_t plan, int32_t precision, int32_t* exact_freqs,
+                                              int32_t* block_radii) {
   if (!plan) return fail(ACOM_E_INVALID, "plan is null");
-  if (exact_freqs) *exact_freqs = plan->d.Kc;
+  if (precision < 0 || precision > 2) return fail(ACOM_E_INVALID, "precision must be ACOM_FP32, ACOM_BF16 or ACOM_FP16");
+  if (exact_freqs) *exact_freqs = plan->d.Kc[precision == ACOM_FP32 ? 0 : 1];
   if (block_radii) *block_radii = plan->d.bb;
   return ACOM_OK;
 }

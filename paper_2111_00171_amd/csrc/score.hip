@@ -54,6 +54,7 @@ struct ScoreArgs {
   float* out_orient;
   float* out_score;
   int* out_cand;
+  int* out_work;           // n x 2 or null: (peak, reflection) pairs evaluated for S alone and with its gradient
 };
 
 __device__ __forceinline__ float wsum(float v) {
@@ -350,6 +351,8 @@ __global__ void __launch_bounds__(kW) refine_kernel(ScoreArgs a) {
   float bestS = -INFINITY;
   int bestc = -1;
   bool overflow = false;
+  const int npk = (int)max((int64_t)0, m1 - m0);
+  int work_s = 0, work_g = 0;  // pair evaluations (reported when out_work is given)
   for (int i = 0; i < 9; ++i) best[i] = 0.0f;
   const float I3[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
   for (int c = 0; c < a.n_cand; ++c) {
@@ -366,6 +369,7 @@ __global__ void __launch_bounds__(kW) refine_kernel(ScoreArgs a) {
       break;
     }
     Eval e = evaluate(a, m0, m1, m, I3, true, false, sh);
+    work_g += sh.nkept * npk;
     float S = e.S;
     float g[3] = {e.g[0], e.g[1], e.g[2]};
     float l = 0.25f * deg;
@@ -378,6 +382,7 @@ __global__ void __launch_bounds__(kW) refine_kernel(ScoreArgs a) {
       expm3(th, E);
       matmul3(m, E, mt);
       Eval et = evaluate(a, m0, m1, mt, I3, false, false, sh);
+      work_s += sh.nkept * npk;
       ++it;
       if (et.S > S) {
         for (int i = 0; i < 9; ++i) m[i] = mt[i];
@@ -389,6 +394,7 @@ __global__ void __launch_bounds__(kW) refine_kernel(ScoreArgs a) {
           break;
         }
         Eval eg = evaluate(a, m0, m1, m, I3, true, false, sh);
+        work_g += sh.nkept * npk;
         g[0] = eg.g[0];
         g[1] = eg.g[1];
         g[2] = eg.g[2];
@@ -402,6 +408,10 @@ __global__ void __launch_bounds__(kW) refine_kernel(ScoreArgs a) {
       bestc = c;
       for (int i = 0; i < 9; ++i) best[i] = m[i];
     }
+  }
+  if (lane == 0 && a.out_work) {
+    a.out_work[2 * (size_t)p] = work_s;
+    a.out_work[2 * (size_t)p + 1] = work_g;
   }
   if (overflow) {  // more reflections than the cap for some candidate: the pattern is an error
     if (lane == 0) {
@@ -488,7 +498,8 @@ extern "C" acom_status_t acom_score_grad(acom_plan_t plan, const acom_peaks_t* p
 
 extern "C" acom_status_t acom_refine(acom_plan_t plan, const acom_peaks_t* peaks, int32_t n_cand,
                                      const float* init_orient, const int32_t* cand_phase, int32_t max_iter,
-                                     float* out_orient, float* out_score, int32_t* out_cand, void* stream) {
+                                     float* out_orient, float* out_score, int32_t* out_cand, int32_t* out_work,
+                                     void* stream) {
   ScoreArgs a;
   acom_status_t st = common_args(plan, peaks, &a);
   if (st != ACOM_OK) return st;
@@ -503,6 +514,7 @@ extern "C" acom_status_t acom_refine(acom_plan_t plan, const acom_peaks_t* peaks
   a.out_orient = out_orient;
   a.out_score = out_score;
   a.out_cand = out_cand;
+  a.out_work = out_work;
   refine_kernel<<<a.n, kW, 0, (hipStream_t)stream>>>(a);
   ACOM_HIP(hipGetLastError());
   return ACOM_OK;

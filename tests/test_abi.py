@@ -71,8 +71,10 @@ def test_invalid_arguments_return_status_codes():
     assert L.acom_build_plan(ph, 1, ctypes.byref(prm), None, None) == 1
     # null plan handles
     assert L.acom_match(None, None, 1, 0, 0, None, 0, None, None) == 1
-    assert L.acom_refine(None, None, 1, None, None, 10, None, None, None, None) == 1
+    assert L.acom_refine(None, None, 1, None, None, 10, None, None, None, None, None) == 1
     assert L.acom_score(None, None, None, None, None, None, None) == 1
+    assert L.acom_match_noalloc(None, None, 1, 0, None, None) == 1
+    assert L.acom_plan_bound_split(None, 0, None, None) == 1
     assert L.acom_plan_destroy(None) == 0
     assert L.acom_status_string(5) == b"workspace too small"
 

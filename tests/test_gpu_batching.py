@@ -215,3 +215,28 @@ def test_plan_above_16384_zones(acom):
         acom.set_tuning(exact_u_lds_max=16384)
     for k in ("zone", "bin", "mirror", "score", "phi3", "n_evaluated"):
         assert torch.equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_persistent_exact_pass_equals_grid_launch(acom, multi, precision):
+    """The exact pass on persistent workgroups (XCD-local work queues) gives the
+    grid launch's results bit for bit: on the three-phase plan, and on 20,000
+    scan patterns in chunks of 8,192 (a ragged last chunk, queues reset per
+    chunk by the polar pass)."""
+    d, opl, gpl = multi
+    cases = [(gpl, acom.Peaks.from_host(d), 0)]
+    scan_plan = helpers.gpu_plan(["fcc"], precisions=("fp32", "bf16"), **helpers.SCAN)
+    cases.append((scan_plan, acom.Peaks.from_host(synth.subset(synth.make("scan"), np.arange(20000) * 3)), 8192))
+    for pl, pk, chunk in cases:
+        out = {}
+        try:
+            for persist in (0, 1):
+                acom.set_tuning(exact_persist=persist)
+                r = pl.match(pk, top_k=3, precision=precision, chunk=chunk)
+                torch.cuda.synchronize()
+                out[persist] = {k: v.cpu().numpy() for k, v in r.items() if v is not None}
+        finally:
+            acom.set_tuning(exact_persist=1)
+        for k in ("zone", "phase", "bin", "mirror", "score", "phi3", "orient", "n_evaluated"):
+            assert np.array_equal(out[0][k], out[1][k]), (chunk, k)
+        assert (out[1]["zone"][:, 0] >= 0).mean() > 0.95

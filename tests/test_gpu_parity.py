@@ -174,7 +174,7 @@ def test_correlogram_and_bound(acom, small):
         sc = max(np.abs(Co).max(), np.abs(Cmo).max())
         assert np.abs(C[p, :, 0] - Co).max() <= 1e-5 * sc
         assert np.abs(C[p, :, 1] - Cmo).max() <= 1e-5 * sc
-        kc, bb = gpl.bound_split()
+        kc, bb = gpl.bound_split("fp32")
         Uo = correlate.spectral_bound(opl["P"], Xo, exact_freqs=kc, block=bb)
         assert np.abs(U[p] - Uo).max() <= 1e-5 * Uo.max()
         assert np.all(U[p] >= np.maximum(Co.max(1), Cmo.max(1)) - 1e-5 * sc)
@@ -189,7 +189,7 @@ def test_low_precision_bound_within_rigorous_margin(acom, small, precision, u):
     d, opl, gpl = small
     pk = acom.Peaks.from_host(d)
     U = gpl.bound(pk, precision).cpu().numpy()
-    kc, bb = gpl.bound_split()
+    kc, bb = gpl.bound_split(precision)
     for p in range(0, 128, 5):
         Xo = helpers.oracle_image(opl, d, p)
         Uo = correlate.spectral_bound(opl["P"], Xo, exact_freqs=kc, block=bb)
@@ -384,7 +384,7 @@ def test_contraction_shapes_agree_on_scan(acom, scan, precision):
     for sh in shapes[1:]:
         assert np.array_equal(U[shapes[0]], U[sh]), sh
     u = 2 ** -8 if precision == "bf16" else 2 ** -11
-    kc, bb = gpl.bound_split()
+    kc, bb = gpl.bound_split(precision)
     for p in (0, 127, 128, 16383, 16384 + 299):
         Xo = helpers.oracle_image(opl, sub, p)
         Uo = correlate.spectral_bound(opl["P"], Xo, exact_freqs=kc, block=bb)

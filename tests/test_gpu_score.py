@@ -168,8 +168,14 @@ def test_refinement_matches_oracle_and_truth(setup):
     far = synth.haar_rotations(rng, 96)
     cands = np.stack([base, far], axis=1)            # the right basin first, a wrong one second
     init = torch.tensor(cands.reshape(96, 2, 9), dtype=torch.float32, device="cuda")
-    m, S, c = gpl.refine(pk, init, max_iter=64)
+    work = torch.zeros(96, 2, dtype=torch.int32, device="cuda")
+    m, S, c = gpl.refine(pk, init, max_iter=64, work=work)
     m, S, c = m.cpu().numpy(), S.cpu().numpy(), c.cpu().numpy()
+    # the work counts: every pattern evaluated its candidates with the gradient
+    # at least once, and took trial steps (pairs = peaks x kept reflections)
+    w = work.cpu().numpy()
+    npk = np.diff(d["offsets"])
+    assert np.all(w[:, 1] >= 2 * npk) and np.all(w[:, 0] > 0)
     G = metrics.cubic_rotations()
     mis_truth, mis_oracle = [], []
     for p in range(96):

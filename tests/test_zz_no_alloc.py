@@ -30,9 +30,13 @@ def _call_noalloc(acom, gpl, pk, top_k, precision):
 def test_match_noalloc_equals_match_twice():
     from paper_2111_00171_amd import acom
     gpl = helpers.gpu_plan(["fcc"], precisions=("fp32", "bf16"), **helpers.SCAN)
-    chunk = ctypes.c_int32()
-    assert acom.lib().acom_match_noalloc_chunk(gpl._h, acom.PRECISIONS["bf16"], ctypes.byref(chunk)) == 0
-    assert chunk.value == 448
+    # the chunk is the largest multiple of 64 (at most 16384) whose workspace,
+    # as acom_match_workspace_size reports it, fits the 128 MiB scratch
+    for prec in ("bf16", "fp32"):
+        chunk = ctypes.c_int32()
+        assert acom.lib().acom_match_noalloc_chunk(gpl._h, acom.PRECISIONS[prec], ctypes.byref(chunk)) == 0
+        fits = [c for c in range(64, 16385, 64) if gpl.match_workspace_bytes(prec, c) <= 128 << 20]
+        assert fits and chunk.value == max(fits), (prec, chunk.value)
     d = synth.make("scan")
     for precision, n in (("bf16", 3000), ("bf16", 700), ("fp32", 1000), ("fp32", 130)):
         sub = synth.subset(d, np.arange(n) * 7 % 65536)
