@@ -84,6 +84,13 @@ __device__ __forceinline__ uint16_t to_f16_bits_up(float v) {
   return __half2float(t) < v ? (uint16_t)(b + 1) : b;
 }
 
+// v of the lane that DPP control CTRL selects (a quad permutation or a
+// half-row mirror: the source lane is always within the same 8 lanes)
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
 // XCD-aware block order: the hardware deals workgroup b to XCD b % 8, so
 // logical work item w = (b % 8) * per + b / 8 gives every XCD a contiguous range
 // of logical items (neighbouring tiles then share that XCD's L2).  The grid has
@@ -125,8 +132,9 @@ struct PolarArgs {
   // Nk + j (lowp == 0) or 16-bit row Kc16 + j
   int ws_layout;           // 1: the workspace's tile-major layout (norms written), 0: a caller's layout
   int Kc16;                // 16-bit spectrum rows kept
-  int Kn, bb, nb, Sp, r0, npseudo;
+  int Kn, bb, bb_log2, nb, Sp, r0, npseudo;
   int64_t L;
+  float inv2sp;            // 1 / (2 Sp) in FP32: the row of an entry by a corrected FP32 quotient
   float* scale;            // np: factor applied before the FP16 cast (else 1)
   float* xnorm2;           // np: sum of X^2 of the pattern's polar image
   int* flags;              // np: 0 ok, 1 invalid data, 2 no peaks
@@ -383,52 +391,111 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
     // half spectrum counted twice except k = 0 and N/2), and which columns have
     // a nonzero spectrum (a thread always holds pair q = tid % NS)
     bool nzE = false, nzO = false;
-    for (int it = tid; it < a.Nk * NS; it += kThreads) {
-      const int k = it / NS, q = it % NS;
+    // the spectra (E, O) of column pair q at frequency k; the Parseval sum and
+    // the nonzero flags are taken on the way; returns the half-spectrum weight
+    auto pair_at = [&](int k, int q, float2& E, float2& O) {
       const float2 Zk = F[k * NS + q];
       const float2 Zn = F[(k == 0 ? 0 : N - k) * NS + q];
-      float2 E = make_float2(0.5f * (Zk.x + Zn.x), 0.5f * (Zk.y - Zn.y));
-      float2 O = make_float2(0.5f * (Zk.y + Zn.y), -0.5f * (Zk.x - Zn.x));
+      E = make_float2(0.5f * (Zk.x + Zn.x), 0.5f * (Zk.y - Zn.y));
+      O = make_float2(0.5f * (Zk.y + Zn.y), -0.5f * (Zk.x - Zn.x));
       if (bad) E = O = make_float2(0.0f, 0.0f);
       const float wk = (k == 0 || 2 * k == N) ? 1.0f : 2.0f;
       xx += wk * ((E.x * E.x + E.y * E.y) + (O.x * O.x + O.y * O.y));
       nzE = nzE || E.x != 0.0f || E.y != 0.0f;
       nzO = nzO || O.x != 0.0f || O.y != 0.0f;
-      const int s0 = col0 + 2 * q;
-      const size_t o = pbase + (size_t)k * a.ldk + s0;
-      if (a.ws_layout) {  // workspace layout: the column pair is one aligned 8-byte / 4-byte store
-        *reinterpret_cast<float2*>(a.xr + o) = make_float2(E.x, O.x);
-        *reinterpret_cast<float2*>(a.xi + o) = make_float2(E.y, O.y);
-        const size_t o16 = pbase16 + (size_t)k * a.ldk + s0;
-        if (a.lowp == ACOM_BF16 && k < a.Kc16) {
-          *reinterpret_cast<uint32_t*>(a.lr + o16) = (uint32_t)to_bf16_bits(E.x) | ((uint32_t)to_bf16_bits(O.x) << 16);
-          *reinterpret_cast<uint32_t*>(a.li + o16) = (uint32_t)to_bf16_bits(E.y) | ((uint32_t)to_bf16_bits(O.y) << 16);
-        } else if (a.lowp == ACOM_FP16 && k < a.Kc16) {
-          *reinterpret_cast<uint32_t*>(a.lr + o16) =
-              (uint32_t)to_f16_bits(E.x * sc) | ((uint32_t)to_f16_bits(O.x * sc) << 16);
-          *reinterpret_cast<uint32_t*>(a.li + o16) =
-              (uint32_t)to_f16_bits(E.y * sc) | ((uint32_t)to_f16_bits(O.y * sc) << 16);
-        }
-        if (a.npseudo > 0) {
-          // block norm over the bb / 2 column pairs of a radial block: they sit
-          // on consecutive lanes of one frequency (NS is a multiple of bb / 2),
-          // which are active together
-          float n2 = k >= a.Kn ? (E.x * E.x + E.y * E.y) + (O.x * O.x + O.y * O.y) : 0.0f;
-          for (int off = 1; off < a.bb / 2; off <<= 1) n2 += __shfl_xor(n2, off, 64);
-          if (k >= a.Kn && (q % (a.bb / 2)) == 0) {
-            const float nrm = wk * __builtin_amdgcn_sqrtf(n2);
-            const int64_t v = (int64_t)(k - a.Kn) * a.nb + s0 / a.bb;
-            const int j = (int)(v / (2 * a.Sp)), e = (int)(v % (2 * a.Sp));
-            const int slot = a.r0 + e % a.Sp;
-            if (a.lowp == 0)
-              (e < a.Sp ? a.xr : a.xi)[pbase + (size_t)(a.Nk + j) * a.ldk + slot] = nrm;
-            else if (a.lowp == ACOM_BF16)
-              (e < a.Sp ? a.lr : a.li)[pbase16 + (size_t)(a.Kc16 + j) * a.ldk + slot] = to_bf16_bits_up(nrm);
-            else
-              (e < a.Sp ? a.lr : a.li)[pbase16 + (size_t)(a.Kc16 + j) * a.ldk + slot] = to_f16_bits_up(nrm * sc);
+      return wk;
+    };
+    if (a.ws_layout) {
+      // workspace layout: the column pair is one aligned 8-byte / 4-byte store.
+      // Frequencies k < Kn carry the spectrum (FP32, and the 16-bit copy: Kn is
+      // Kc16 then); k >= Kn the FP32 spectrum and the block norms. Offsets
+      // inside one pattern's rows fit 32 bits. The operand precision is a
+      // compile-time choice: no per-launch branch or argument inside the loops.
+      auto unpack = [&](auto lp_c) {
+        constexpr int LP = decltype(lp_c)::value;
+        float* const xr_p = a.xr + pbase;
+        float* const xi_p = a.xi + pbase;
+        uint16_t* const lr_p = LP ? a.lr + pbase16 : nullptr;
+        uint16_t* const li_p = LP ? a.li + pbase16 : nullptr;
+        const int ldk = (int)a.ldk;
+        for (int it = tid; it < a.Kn * NS; it += kThreads) {
+          const int k = it / NS, q = it % NS;
+          float2 E, O;
+          pair_at(k, q, E, O);
+          const int o = k * ldk + col0 + 2 * q;
+          *reinterpret_cast<float2*>(xr_p + o) = make_float2(E.x, O.x);
+          *reinterpret_cast<float2*>(xi_p + o) = make_float2(E.y, O.y);
+          if constexpr (LP == ACOM_BF16) {
+            *reinterpret_cast<uint32_t*>(lr_p + o) = (uint32_t)to_bf16_bits(E.x) | ((uint32_t)to_bf16_bits(O.x) << 16);
+            *reinterpret_cast<uint32_t*>(li_p + o) = (uint32_t)to_bf16_bits(E.y) | ((uint32_t)to_bf16_bits(O.y) << 16);
+          } else if constexpr (LP == ACOM_FP16) {
+            *reinterpret_cast<uint32_t*>(lr_p + o) =
+                (uint32_t)to_f16_bits(E.x * sc) | ((uint32_t)to_f16_bits(O.x * sc) << 16);
+            *reinterpret_cast<uint32_t*>(li_p + o) =
+                (uint32_t)to_f16_bits(E.y * sc) | ((uint32_t)to_f16_bits(O.y * sc) << 16);
           }
         }
-      } else {  // caller's [p][k][s] layout with s < out_cols (verification entry point)
+        // the norm rows: FP32 rows Nk + j, or 16-bit rows Kc16 + j
+        float* const nr32 = xr_p + a.Nk * ldk;
+        float* const ni32 = xi_p + a.Nk * ldk;
+        uint16_t* const nr16 = LP ? lr_p + a.Kc16 * ldk : nullptr;
+        uint16_t* const ni16 = LP ? li_p + a.Kc16 * ldk : nullptr;
+        const int hb = a.bb / 2, sp2 = 2 * a.Sp;
+        // it - tid stays a multiple of NS: a thread keeps its column pair
+        for (int it = a.Kn * NS + tid; it < a.Nk * NS; it += kThreads) {
+          const int k = it / NS, q = it % NS;
+          float2 E, O;
+          const float wk = pair_at(k, q, E, O);
+          const int s0 = col0 + 2 * q;
+          const int o = k * ldk + s0;
+          *reinterpret_cast<float2*>(xr_p + o) = make_float2(E.x, O.x);
+          *reinterpret_cast<float2*>(xi_p + o) = make_float2(E.y, O.y);
+          // block norm over the hb = bb / 2 column pairs of a radial block:
+          // they sit on consecutive lanes of one frequency (NS is a multiple of
+          // hb and of the loop's start), which are active together; the sum
+          // runs over DPP lane moves
+          float n2 = (E.x * E.x + E.y * E.y) + (O.x * O.x + O.y * O.y);
+          if (hb >= 2) n2 += dpp_move<0xB1>(n2);   // lanes 2i <-> 2i + 1
+          if (hb >= 4) n2 += dpp_move<0x4E>(n2);   // lane pairs of a quad
+          if (hb >= 8) n2 += dpp_move<0x141>(n2);  // the two quads of 8 lanes
+          if ((q & (hb - 1)) == 0) {
+            const float nrm = wk * __builtin_amdgcn_sqrtf(n2);
+            // entry v: row j = v / 2Sp from an FP32 quotient, off by at most
+            // one (v < 2^24), then corrected; no integer division, no table
+            const int v = (k - a.Kn) * a.nb + (s0 >> a.bb_log2);
+            int j = (int)((float)v * a.inv2sp);
+            int e = v - j * sp2;
+            if (e < 0) {
+              --j;
+              e += sp2;
+            } else if (e >= sp2) {
+              ++j;
+              e -= sp2;
+            }
+            const bool im = e >= a.Sp;
+            const int no = j * ldk + a.r0 + (im ? e - a.Sp : e);
+            if constexpr (LP == 0)
+              (im ? ni32 : nr32)[no] = nrm;
+            else if constexpr (LP == ACOM_BF16)
+              (im ? ni16 : nr16)[no] = to_bf16_bits_up(nrm);
+            else
+              (im ? ni16 : nr16)[no] = to_f16_bits_up(nrm * sc);
+          }
+        }
+      };
+      if (a.lowp == ACOM_BF16)
+        unpack(std::integral_constant<int, ACOM_BF16>{});
+      else if (a.lowp == ACOM_FP16)
+        unpack(std::integral_constant<int, ACOM_FP16>{});
+      else
+        unpack(std::integral_constant<int, 0>{});
+    } else {  // caller's [p][k][s] layout with s < out_cols (verification entry point)
+      for (int it = tid; it < a.Nk * NS; it += kThreads) {
+        const int k = it / NS, q = it % NS;
+        float2 E, O;
+        pair_at(k, q, E, O);
+        const int s0 = col0 + 2 * q;
+        const size_t o = pbase + (size_t)k * a.ldk + s0;
         if (s0 < a.out_cols) {
           a.xr[o] = E.x;
           a.xi[o] = E.y;
@@ -464,17 +531,18 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
   }
   // the norm rows' slots that hold no entry: below r0, and past the vector's end
   if (a.ws_layout && a.npseudo > 0 && a.do_fft) {
-    auto zero = [&](int j, int part, int slot) {
-      if (a.lowp == 0)
-        (part ? a.xi : a.xr)[pbase + (size_t)(a.Nk + j) * a.ldk + slot] = 0.0f;
-      else
-        (part ? a.li : a.lr)[pbase16 + (size_t)(a.Kc16 + j) * a.ldk + slot] = 0;
-    };
-    for (int i = tid; i < a.npseudo * 2 * a.r0; i += kThreads) zero(i / (2 * a.r0), (i / a.r0) % 2, i % a.r0);
-    for (int64_t v = a.L + tid; v < (int64_t)a.npseudo * 2 * a.Sp; v += kThreads) {
-      const int j = (int)(v / (2 * a.Sp)), e = (int)(v % (2 * a.Sp));
-      zero(j, e >= a.Sp, a.r0 + e % a.Sp);
-    }
+    // entry v = j 2Sp + part Sp + (slot - r0) of row j; slots below r0 and
+    // entries past L hold no norm
+    for (int j = 0; j < a.npseudo; ++j)
+      for (int e = tid; e < 2 * a.Rp; e += kThreads) {
+        const int part = e >= a.Rp, slot = e - part * a.Rp;
+        const int64_t v = (int64_t)j * 2 * a.Sp + part * a.Sp + (slot - a.r0);
+        if (slot >= a.r0 && v < a.L) continue;
+        if (a.lowp == 0)
+          (part ? a.xi : a.xr)[pbase + (size_t)(a.Nk + j) * a.ldk + slot] = 0.0f;
+        else
+          (part ? a.li : a.lr)[pbase16 + (size_t)(a.Kc16 + j) * a.ldk + slot] = 0;
+      }
   }
   // per pattern: sum of X^2 (fixed order) and the column masks of every tile
 #pragma unroll
@@ -1544,6 +1612,8 @@ PolarArgs polar_args(const PlanDev& d, const acom_peaks_t* pk, int64_t p_begin, 
   const int c = lowp ? 1 : 0;
   a.Kc16 = d.Kc[1];
   a.Kn = d.Kc[c];
+  a.inv2sp = d.Sp > 0 ? 1.0f / (float)(2 * d.Sp) : 0.0f;
+  a.bb_log2 = __builtin_ctz(d.bb);
   a.bb = d.bb;
   a.nb = d.nb;
   a.Sp = d.Sp;
