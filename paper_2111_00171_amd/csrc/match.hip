@@ -84,6 +84,14 @@ __device__ __forceinline__ uint16_t to_f16_bits_up(float v) {
   return __half2float(t) < v ? (uint16_t)(b + 1) : b;
 }
 
+// Store at a byte offset from a base: with a wave-uniform base and a 32-bit
+// offset the compiler uses the scalar-base form of the global store (no
+// 64-bit address arithmetic per lane).
+template <class T, class V>
+__device__ __forceinline__ void store_at(T* base, uint32_t byte_off, V v) {
+  *reinterpret_cast<V*>(reinterpret_cast<char*>(base) + byte_off) = v;
+}
+
 // v of the lane that DPP control CTRL selects (a quad permutation or a
 // half-row mirror: the source lane is always within the same 8 lanes)
 template <int CTRL>
@@ -135,6 +143,7 @@ struct PolarArgs {
   int Kn, bb, bb_log2, nb, Sp, r0, npseudo;
   int64_t L;
   float inv2sp;            // 1 / (2 Sp) in FP32: the row of an entry by a corrected FP32 quotient
+  int inc_j, inc_e;        // (kThreads / NS) nb = inc_j 2Sp + inc_e: the norm position's advance per unpack step
   float* scale;            // np: factor applied before the FP16 cast (else 1)
   float* xnorm2;           // np: sum of X^2 of the pattern's polar image
   int* flags;              // np: 0 ok, 1 invalid data, 2 no peaks
@@ -240,7 +249,9 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
       pq[tid] = qh;
       pql[tid] = (float)(q - (double)qh);
       const float w = bad ? 0.0f : powe((float)q, a.gamma) * powe(in, 0.5f * a.omega);
-      pw[tid] = w;
+      // the splat accumulates X / 2 (an exact scaling): the unpack's
+      // (Z_k + conj Z_{N-k}) / 2 then needs no multiplication
+      pw[tid] = 0.5f * w;
       if (count) wsum += w;
     }
     __syncthreads();
@@ -372,7 +383,7 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
     if (a.Ximg) {
       for (int i = tid; i < N * NC; i += kThreads) {
         const int ai = i / NC, cc = i % NC;
-        if (col0 + cc < a.R) a.Ximg[((size_t)p * N + ai) * a.R + col0 + cc] = bad ? 0.0f : X[rev[ai] * NC + cc];
+        if (col0 + cc < a.R) a.Ximg[((size_t)p * N + ai) * a.R + col0 + cc] = bad ? 0.0f : 2.0f * X[rev[ai] * NC + cc];
       }
     }
     if (!a.do_fft) {
@@ -390,81 +401,128 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
     // On the way: sum X^2 by Parseval (sum_a X_a^2 = (1/N) sum_k |Xhat_k|^2, the
     // half spectrum counted twice except k = 0 and N/2), and which columns have
     // a nonzero spectrum (a thread always holds pair q = tid % NS)
+    // which columns have a nonzero spectrum: X >= 0, so a column is nonzero
+    // exactly when its sum, the k = 0 term, is (column 2q is the real part of
+    // sequence q, column 2q + 1 its imaginary part)
     bool nzE = false, nzO = false;
-    // the spectra (E, O) of column pair q at frequency k; the Parseval sum and
-    // the nonzero flags are taken on the way; returns the half-spectrum weight
-    auto pair_at = [&](int k, int q, float2& E, float2& O) {
-      const float2 Zk = F[k * NS + q];
-      const float2 Zn = F[(k == 0 ? 0 : N - k) * NS + q];
-      E = make_float2(0.5f * (Zk.x + Zn.x), 0.5f * (Zk.y - Zn.y));
-      O = make_float2(0.5f * (Zk.y + Zn.y), -0.5f * (Zk.x - Zn.x));
-      if (bad) E = O = make_float2(0.0f, 0.0f);
-      const float wk = (k == 0 || 2 * k == N) ? 1.0f : 2.0f;
-      xx += wk * ((E.x * E.x + E.y * E.y) + (O.x * O.x + O.y * O.y));
-      nzE = nzE || E.x != 0.0f || E.y != 0.0f;
-      nzO = nzO || O.x != 0.0f || O.y != 0.0f;
-      return wk;
+    if (tid < NS && !bad) {
+      nzE = F[tid].x != 0.0f;
+      nzO = F[tid].y != 0.0f;
+    }
+    // Z_k and Z_{N-k} of column pair q; k is clamped to Nk - 1 so that a
+    // prefetch one loop step past the end stays inside the LDS buffer
+    auto load_pair = [&](int k, int q, float2& Zk, float2& Zn) {
+      k = min(k, a.Nk - 1);
+      Zk = F[k * NS + q];
+      Zn = F[(k == 0 ? 0 : N - k) * NS + q];
     };
-    if (a.ws_layout) {
+    // the spectra of the pair: E = (Z_k + conj Z_{N-k}) / 2 for column 2q,
+    // O = -i (Z_k - conj Z_{N-k}) / 2 for column 2q + 1 (the LDS holds the
+    // transform of X / 2)
+    auto pair_of = [](float2 Zk, float2 Zn, float2& E, float2& O) {
+      E = make_float2(Zk.x + Zn.x, Zk.y - Zn.y);
+      O = make_float2(Zk.y + Zn.y, Zn.x - Zk.x);
+    };
+    // weight of frequency k in the half spectrum (Parseval; the block norms)
+    auto wk_of = [&](int k) { return (k == 0 || 2 * k == N) ? 1.0f : 2.0f; };
+    if (a.ws_layout && bad) {
+      // a flagged pattern: zero spectrum rows (the contraction reads them) and norms
+      const int rows = a.lowp ? a.Kc16 : a.Nk;
+      for (int it = tid; it < a.Nk * NS; it += kThreads) {
+        const int k = it / NS, q = it % NS;
+        const size_t o = pbase + (size_t)k * a.ldk + col0 + 2 * q;
+        *reinterpret_cast<float2*>(a.xr + o) = make_float2(0.0f, 0.0f);
+        *reinterpret_cast<float2*>(a.xi + o) = make_float2(0.0f, 0.0f);
+        if (a.lowp && k < rows) {
+          const size_t o16 = pbase16 + (size_t)k * a.ldk + col0 + 2 * q;
+          *reinterpret_cast<uint32_t*>(a.lr + o16) = 0u;
+          *reinterpret_cast<uint32_t*>(a.li + o16) = 0u;
+        }
+      }
+      if (a.npseudo > 0 && tile == 0)
+        for (int i = tid; i < a.npseudo * a.Rp; i += kThreads) {
+          const int j = i / a.Rp, slot = i % a.Rp;
+          if (a.lowp == 0) {
+            a.xr[pbase + (size_t)(a.Nk + j) * a.ldk + slot] = 0.0f;
+            a.xi[pbase + (size_t)(a.Nk + j) * a.ldk + slot] = 0.0f;
+          } else {
+            a.lr[pbase16 + (size_t)(a.Kc16 + j) * a.ldk + slot] = 0;
+            a.li[pbase16 + (size_t)(a.Kc16 + j) * a.ldk + slot] = 0;
+          }
+        }
+    } else if (a.ws_layout) {
       // workspace layout: the column pair is one aligned 8-byte / 4-byte store.
       // Frequencies k < Kn carry the spectrum (FP32, and the 16-bit copy: Kn is
-      // Kc16 then); k >= Kn the FP32 spectrum and the block norms. Offsets
-      // inside one pattern's rows fit 32 bits. The operand precision is a
-      // compile-time choice: no per-launch branch or argument inside the loops.
+      // Kc16 then); k >= Kn the FP32 spectrum and the block norms. The stores
+      // go through buffer resources over this pattern's rows (32-bit offsets,
+      // the base in scalar registers), and the operand precision is a
+      // compile-time choice: no per-launch branch inside the loops.
+      //
+      // Steps it = it0 + tid + kThreads m (it0 a multiple of NS, so a thread
+      // keeps its column pair q = tid % NS): two register sets alternate, the
+      // next step's pair loading while the current one is processed.
+      const int q = tid % NS, dk = kThreads / NS;
+      auto steps = [&](int it0, int it1, auto&& body) {
+        float2 ak, an, bk, bn;
+        load_pair((it0 + tid) / NS, q, ak, an);
+        for (int it = it0 + tid; it < it1; it += 2 * kThreads) {
+          const int k = (int)((unsigned)it / NS);
+          load_pair(k + dk, q, bk, bn);
+          __builtin_amdgcn_sched_barrier(0);  // the loads issue here, not next to their use
+          body(k, ak, an);
+          if (it + kThreads < it1) {  // the same for all NS lanes of frequency k
+            load_pair(k + 2 * dk, q, ak, an);
+            __builtin_amdgcn_sched_barrier(0);
+            body(k + dk, bk, bn);
+          }
+        }
+      };
       auto unpack = [&](auto lp_c) {
         constexpr int LP = decltype(lp_c)::value;
+        const int ldk = (int)a.ldk;
+        // this pattern's rows: a base in scalar registers and 32-bit byte
+        // offsets per lane (a 64-pattern tile of rows stays below 2 GiB)
         float* const xr_p = a.xr + pbase;
         float* const xi_p = a.xi + pbase;
         uint16_t* const lr_p = LP ? a.lr + pbase16 : nullptr;
         uint16_t* const li_p = LP ? a.li + pbase16 : nullptr;
-        const int ldk = (int)a.ldk;
-        for (int it = tid; it < a.Kn * NS; it += kThreads) {
-          const int k = it / NS, q = it % NS;
+        const int c2 = col0 + 2 * q;
+        steps(0, a.Kn * NS, [&](int k, float2 ck, float2 cn) {
           float2 E, O;
-          pair_at(k, q, E, O);
-          const int o = k * ldk + col0 + 2 * q;
-          *reinterpret_cast<float2*>(xr_p + o) = make_float2(E.x, O.x);
-          *reinterpret_cast<float2*>(xi_p + o) = make_float2(E.y, O.y);
+          pair_of(ck, cn, E, O);
+          xx += wk_of(k) * ((E.x * E.x + E.y * E.y) + (O.x * O.x + O.y * O.y));
+          const uint32_t o = (uint32_t)(k * ldk + c2);
+          store_at(xr_p, o * 4u, make_float2(E.x, O.x));
+          store_at(xi_p, o * 4u, make_float2(E.y, O.y));
           if constexpr (LP == ACOM_BF16) {
-            *reinterpret_cast<uint32_t*>(lr_p + o) = (uint32_t)to_bf16_bits(E.x) | ((uint32_t)to_bf16_bits(O.x) << 16);
-            *reinterpret_cast<uint32_t*>(li_p + o) = (uint32_t)to_bf16_bits(E.y) | ((uint32_t)to_bf16_bits(O.y) << 16);
+            store_at(lr_p, o * 2u, (uint32_t)to_bf16_bits(E.x) | ((uint32_t)to_bf16_bits(O.x) << 16));
+            store_at(li_p, o * 2u, (uint32_t)to_bf16_bits(E.y) | ((uint32_t)to_bf16_bits(O.y) << 16));
           } else if constexpr (LP == ACOM_FP16) {
-            *reinterpret_cast<uint32_t*>(lr_p + o) =
-                (uint32_t)to_f16_bits(E.x * sc) | ((uint32_t)to_f16_bits(O.x * sc) << 16);
-            *reinterpret_cast<uint32_t*>(li_p + o) =
-                (uint32_t)to_f16_bits(E.y * sc) | ((uint32_t)to_f16_bits(O.y * sc) << 16);
+            store_at(lr_p, o * 2u, (uint32_t)to_f16_bits(E.x * sc) | ((uint32_t)to_f16_bits(O.x * sc) << 16));
+            store_at(li_p, o * 2u, (uint32_t)to_f16_bits(E.y * sc) | ((uint32_t)to_f16_bits(O.y * sc) << 16));
           }
-        }
-        // the norm rows: FP32 rows Nk + j, or 16-bit rows Kc16 + j
-        float* const nr32 = xr_p + a.Nk * ldk;
-        float* const ni32 = xi_p + a.Nk * ldk;
-        uint16_t* const nr16 = LP ? lr_p + a.Kc16 * ldk : nullptr;
-        uint16_t* const ni16 = LP ? li_p + a.Kc16 * ldk : nullptr;
-        const int hb = a.bb / 2, sp2 = 2 * a.Sp;
-        // it - tid stays a multiple of NS: a thread keeps its column pair
-        for (int it = a.Kn * NS + tid; it < a.Nk * NS; it += kThreads) {
-          const int k = it / NS, q = it % NS;
-          float2 E, O;
-          const float wk = pair_at(k, q, E, O);
-          const int s0 = col0 + 2 * q;
-          const int o = k * ldk + s0;
-          *reinterpret_cast<float2*>(xr_p + o) = make_float2(E.x, O.x);
-          *reinterpret_cast<float2*>(xi_p + o) = make_float2(E.y, O.y);
-          // block norm over the hb = bb / 2 column pairs of a radial block:
-          // they sit on consecutive lanes of one frequency (NS is a multiple of
-          // hb and of the loop's start), which are active together; the sum
-          // runs over DPP lane moves
-          float n2 = (E.x * E.x + E.y * E.y) + (O.x * O.x + O.y * O.y);
-          if (hb >= 2) n2 += dpp_move<0xB1>(n2);   // lanes 2i <-> 2i + 1
-          if (hb >= 4) n2 += dpp_move<0x4E>(n2);   // lane pairs of a quad
-          if (hb >= 8) n2 += dpp_move<0x141>(n2);  // the two quads of 8 lanes
-          if ((q & (hb - 1)) == 0) {
-            const float nrm = wk * __builtin_amdgcn_sqrtf(n2);
-            // entry v: row j = v / 2Sp from an FP32 quotient, off by at most
-            // one (v < 2^24), then corrected; no integer division, no table
-            const int v = (k - a.Kn) * a.nb + (s0 >> a.bb_log2);
-            int j = (int)((float)v * a.inv2sp);
-            int e = v - j * sp2;
+        });
+        if (a.Kn >= a.Nk) return;
+        // block norms over the HB = bb / 2 column pairs of a radial block: they
+        // sit on consecutive lanes of one frequency (NS is a multiple of HB),
+        // which are active together; the sum runs over DPP lane moves. The
+        // entry of (k, block b) is v = (k - Kn) nb + b, at slot r0 + e of the
+        // real (e < Sp) or, with e - Sp, the imaginary half of norm row
+        // j = v / 2Sp, e = v mod 2Sp. (j, e) start from a corrected FP32
+        // quotient and advance by dk nb = inc_j 2Sp + inc_e per step.
+        auto norms = [&](auto hb_c) {
+          constexpr int HB = decltype(hb_c)::value;
+          const int sp2 = 2 * a.Sp;
+          float* const nr32 = xr_p + a.Nk * ldk + a.r0;
+          float* const ni32 = xi_p + a.Nk * ldk + a.r0 - a.Sp;  // indexed by e >= Sp
+          uint16_t* const nr16 = LP ? lr_p + a.Kc16 * ldk + a.r0 : nullptr;
+          uint16_t* const ni16 = LP ? li_p + a.Kc16 * ldk + a.r0 - a.Sp : nullptr;
+          const bool lead = (q & (HB - 1)) == 0;
+          int j, e;
+          {
+            const int v = (tid / NS) * a.nb + (c2 >> a.bb_log2);
+            j = (int)((float)v * a.inv2sp);
+            e = v - j * sp2;
             if (e < 0) {
               --j;
               e += sp2;
@@ -472,15 +530,43 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
               ++j;
               e -= sp2;
             }
-            const bool im = e >= a.Sp;
-            const int no = j * ldk + a.r0 + (im ? e - a.Sp : e);
-            if constexpr (LP == 0)
-              (im ? ni32 : nr32)[no] = nrm;
-            else if constexpr (LP == ACOM_BF16)
-              (im ? ni16 : nr16)[no] = to_bf16_bits_up(nrm);
-            else
-              (im ? ni16 : nr16)[no] = to_f16_bits_up(nrm * sc);
           }
+          steps(a.Kn * NS, a.Nk * NS, [&](int k, float2 ck, float2 cn) {
+            float2 E, O;
+            pair_of(ck, cn, E, O);
+            const float wk = 2 * k == N ? 1.0f : 2.0f;  // k >= Kn > 0
+            float n2 = (E.x * E.x + E.y * E.y) + (O.x * O.x + O.y * O.y);
+            xx += wk * n2;
+            const uint32_t o = (uint32_t)(k * ldk + c2);
+            store_at(xr_p, o * 4u, make_float2(E.x, O.x));
+            store_at(xi_p, o * 4u, make_float2(E.y, O.y));
+            if constexpr (HB >= 2) n2 += dpp_move<0xB1>(n2);   // lanes 2i <-> 2i + 1
+            if constexpr (HB >= 4) n2 += dpp_move<0x4E>(n2);   // lane pairs of a quad
+            if constexpr (HB >= 8) n2 += dpp_move<0x141>(n2);  // the two quads of 8 lanes
+            if (lead) {
+              const float nrm = wk * __builtin_amdgcn_sqrtf(n2);
+              const bool im = e >= a.Sp;
+              const int no = j * ldk + e;
+              if constexpr (LP == 0)
+                (im ? ni32 : nr32)[no] = nrm;
+              else if constexpr (LP == ACOM_BF16)
+                (im ? ni16 : nr16)[no] = to_bf16_bits_up(nrm);
+              else
+                (im ? ni16 : nr16)[no] = to_f16_bits_up(nrm * sc);
+            }
+            e += a.inc_e;
+            j += a.inc_j;
+            if (e >= sp2) {
+              e -= sp2;
+              ++j;
+            }
+          });
+        };
+        switch (a.bb) {
+          case 2: norms(std::integral_constant<int, 1>{}); break;
+          case 4: norms(std::integral_constant<int, 2>{}); break;
+          case 16: norms(std::integral_constant<int, 8>{}); break;
+          default: norms(std::integral_constant<int, 4>{}); break;
         }
       };
       if (a.lowp == ACOM_BF16)
@@ -492,8 +578,11 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
     } else {  // caller's [p][k][s] layout with s < out_cols (verification entry point)
       for (int it = tid; it < a.Nk * NS; it += kThreads) {
         const int k = it / NS, q = it % NS;
-        float2 E, O;
-        pair_at(k, q, E, O);
+        float2 Zk, Zn, E, O;
+        load_pair(k, q, Zk, Zn);
+        pair_of(Zk, Zn, E, O);
+        if (bad) E = O = make_float2(0.0f, 0.0f);
+        xx += wk_of(k) * ((E.x * E.x + E.y * E.y) + (O.x * O.x + O.y * O.y));
         const int s0 = col0 + 2 * q;
         const size_t o = pbase + (size_t)k * a.ldk + s0;
         if (s0 < a.out_cols) {
@@ -1613,6 +1702,7 @@ PolarArgs polar_args(const PlanDev& d, const acom_peaks_t* pk, int64_t p_begin, 
   a.Kc16 = d.Kc[1];
   a.Kn = d.Kc[c];
   a.inv2sp = d.Sp > 0 ? 1.0f / (float)(2 * d.Sp) : 0.0f;
+  a.inc_j = a.inc_e = 0;
   a.bb_log2 = __builtin_ctz(d.bb);
   a.bb = d.bb;
   a.nb = d.nb;
@@ -1648,6 +1738,11 @@ acom_status_t launch_polar_nc(const PlanDev& d, const PolarArgs& a, hipStream_t 
   PolarArgs b = a;
   b.ntiles = d.Rp / kPolarCols;
   b.per = 0;
+  if (d.Sp > 0) {  // advance of a norm entry per unpack step of kThreads / (NC / 2) frequencies
+    const int adv = kThreads / (NC / 2) * d.nb;
+    b.inc_j = adv / (2 * d.Sp);
+    b.inc_e = adv % (2 * d.Sp);
+  }
   const int nblocks = g_tune.polar_xcd ? xcd_blocks(b.np, &b.per) : b.np;
   ProfScope prof(0, s);
   polar_kernel<NT, NC><<<dim3(nblocks), kThreads, polar_lds<NC>(d), s>>>(b);

@@ -13,6 +13,7 @@
 #include <hip/hip_fp16.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -747,6 +748,9 @@ extern "C" acom_status_t acom_build_plan(const acom_phase_t* phases, int32_t n_p
   }
   d.rows32 = d.Nk + d.npseudo[0];
   d.rows16 = d.Kc[1] + d.npseudo[1];
+  // the polar pass addresses one 64-pattern tile of spectrum rows with 32-bit byte offsets
+  if ((size_t)d.rows32 * 64 * d.Rp * 4 > (size_t)INT_MAX)
+    return bail(fail(ACOM_E_UNSUPPORTED, "plan too large: a 64-pattern tile of spectrum rows exceeds 2 GiB"));
   {
     const size_t n32 = (size_t)d.rows32 * d.Zp * d.Rp, n16 = (size_t)d.rows16 * d.Zp * d.Rp;
     if ((st = dalloc(&d.d_PR, n32)) || (st = dalloc(&d.d_PI, n32))) return bail(st);
