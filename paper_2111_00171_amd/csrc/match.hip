@@ -1035,58 +1035,76 @@ __device__ void active_groups(const ExactArgs& a, int p, int* groups, int* ng) {
 // the in-place inverse FFT: H[rev(n) * nb + b].  Four consecutive lanes share a
 // frequency k and take every fourth active radius group; each group of X is
 // loaded once for all nb zones.
-__device__ void contract_exact(const ExactArgs& a, int p, const int* bz, int nb, const int* rev, float2* H,
-                               const int* groups, int ng) {
+template <int NB>
+__device__ void contract_exact_nb(const ExactArgs& a, int p, const int* bz, const int* rev, float2* H,
+                                  const int* groups, int ng) {
   const size_t xbase = tile_off(p, 0, 0, a.xrows, a.Rp);
   const size_t xk = (size_t)64 * a.Rp;
   const int sub = threadIdx.x & 3;
   for (int base = 0; base < a.Nk; base += (int)(blockDim.x >> 2)) {
     const int k = base + (int)(threadIdx.x >> 2);
-    float A[kBatch], B[kBatch], C[kBatch], D[kBatch];
+    float A[NB], B[NB], C[NB], D[NB];
 #pragma unroll
-    for (int b = 0; b < kBatch; ++b) A[b] = B[b] = C[b] = D[b] = 0.0f;
+    for (int b = 0; b < NB; ++b) A[b] = B[b] = C[b] = D[b] = 0.0f;
     if (k < a.Nk) {
       const float* xr = a.xr + xbase + (size_t)k * xk;
       const float* xi = a.xi + xbase + (size_t)k * xk;
-      size_t po[kBatch];
+      const float* pr[NB];
+      const float* pi[NB];
 #pragma unroll
-      for (int b = 0; b < kBatch; ++b) po[b] = ((size_t)bz[b] * a.Nk + k) * a.Rp;
+      for (int b = 0; b < NB; ++b) {
+        pr[b] = a.pr + ((size_t)bz[b] * a.Nk + k) * a.Rp;
+        pi[b] = a.pi + ((size_t)bz[b] * a.Nk + k) * a.Rp;
+      }
+      // every zone of the batch is a compile-time slot: no branch separates
+      // the loads of one group, so they are all in flight together
 #pragma unroll 2
       for (int g = sub; g < ng; g += 4) {
         const int s = groups[g] * 4;
         const float4 vr = *reinterpret_cast<const float4*>(xr + s);
         const float4 vi = *reinterpret_cast<const float4*>(xi + s);
+        float4 wr[NB], wi[NB];
 #pragma unroll
-        for (int b = 0; b < kBatch; ++b) {
-          if (b < nb) {
-            const float4 wr = *reinterpret_cast<const float4*>(a.pr + po[b] + s);
-            const float4 wi = *reinterpret_cast<const float4*>(a.pi + po[b] + s);
-            A[b] += vr.x * wr.x + vr.y * wr.y + vr.z * wr.z + vr.w * wr.w;
-            B[b] += vi.x * wi.x + vi.y * wi.y + vi.z * wi.z + vi.w * wi.w;
-            C[b] += vi.x * wr.x + vi.y * wr.y + vi.z * wr.z + vi.w * wr.w;
-            D[b] += vr.x * wi.x + vr.y * wi.y + vr.z * wi.z + vr.w * wi.w;
-          }
+        for (int b = 0; b < NB; ++b) {
+          wr[b] = *reinterpret_cast<const float4*>(pr[b] + s);
+          wi[b] = *reinterpret_cast<const float4*>(pi[b] + s);
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          A[b] += vr.x * wr[b].x + vr.y * wr[b].y + vr.z * wr[b].z + vr.w * wr[b].w;
+          B[b] += vi.x * wi[b].x + vi.y * wi[b].y + vi.z * wi[b].z + vi.w * wi[b].w;
+          C[b] += vi.x * wr[b].x + vi.y * wr[b].y + vi.z * wr[b].z + vi.w * wr[b].w;
+          D[b] += vr.x * wi[b].x + vr.y * wi[b].y + vr.z * wi[b].z + vr.w * wi[b].w;
         }
       }
     }
 #pragma unroll
-    for (int b = 0; b < kBatch; ++b) {
-      if (b < nb) {
+    for (int b = 0; b < NB; ++b) {
 #pragma unroll
-        for (int off = 1; off <= 2; off <<= 1) {
-          A[b] += __shfl_xor(A[b], off, 64);
-          B[b] += __shfl_xor(B[b], off, 64);
-          C[b] += __shfl_xor(C[b], off, 64);
-          D[b] += __shfl_xor(D[b], off, 64);
-        }
-        if (k < a.Nk && sub == 0) {
-          H[rev[k] * nb + b] = make_float2((A[b] + B[b]) + (C[b] + D[b]), (C[b] - D[b]) + (A[b] - B[b]));
-          if (k > 0 && 2 * k < a.N)
-            H[rev[a.N - k] * nb + b] = make_float2((A[b] + B[b]) - (C[b] + D[b]), (A[b] - B[b]) - (C[b] - D[b]));
-        }
+      for (int off = 1; off <= 2; off <<= 1) {
+        A[b] += __shfl_xor(A[b], off, 64);
+        B[b] += __shfl_xor(B[b], off, 64);
+        C[b] += __shfl_xor(C[b], off, 64);
+        D[b] += __shfl_xor(D[b], off, 64);
+      }
+      if (k < a.Nk && sub == 0) {
+        H[rev[k] * NB + b] = make_float2((A[b] + B[b]) + (C[b] + D[b]), (C[b] - D[b]) + (A[b] - B[b]));
+        if (k > 0 && 2 * k < a.N)
+          H[rev[a.N - k] * NB + b] = make_float2((A[b] + B[b]) - (C[b] + D[b]), (A[b] - B[b]) - (C[b] - D[b]));
       }
     }
   }
+}
+// nb zones (1, 2 or 4; a batch of 3 is padded by its caller to 4 with its
+// last zone repeated)
+__device__ void contract_exact(const ExactArgs& a, int p, const int* bz, int nb, const int* rev, float2* H,
+                               const int* groups, int ng) {
+  if (nb == 1)
+    contract_exact_nb<1>(a, p, bz, rev, H, groups, ng);
+  else if (nb == 2)
+    contract_exact_nb<2>(a, p, bz, rev, H, groups, ng);
+  else
+    contract_exact_nb<4>(a, p, bz, rev, H, groups, ng);
 }
 
 __device__ void block_argmax(const float* v, int n, float* out_v, int* out_i, float* sv, int* si) {
@@ -1133,9 +1151,9 @@ __device__ __forceinline__ float parabolic(float cm1, float c0, float cp1) {
   return fminf(0.5f, fmaxf(-0.5f, 0.5f * (cm1 - cp1) / den));
 }
 
-// Inverse FFT of the batch's sequences (stride nbp in H): with the angular
-// length known at compile time, the specialised schedule for 1, 2 or 4
-// sequences (a batch of 3 is padded to 4 by its caller).
+// Inverse FFT of the batch's sequences (stride nbp in H: 1, 2 or 4, a batch
+// of 3 padded to 4 by its caller): with the angular length known at compile
+// time, the specialised schedule.
 template <int NT>
 __device__ __forceinline__ void exact_ifft(float2* H, const float2* tw, const ExactArgs& a, int nbp) {
   if constexpr (NT > 0) {
@@ -1151,7 +1169,7 @@ __device__ __forceinline__ void exact_ifft(float2* H, const float2* tw, const Ex
 }
 template <int NT>
 __device__ __forceinline__ int exact_stride(int nb) {
-  return (NT > 0 && nb == 3) ? 4 : nb;
+  return nb == 3 ? 4 : nb;  // the contraction is specialised for 1, 2 and 4 sequences
 }
 
 // PERSIST: a persistent grid (a few workgroups per compute unit) in which the
