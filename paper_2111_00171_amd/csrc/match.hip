@@ -1032,17 +1032,17 @@ __device__ void active_groups(const ExactArgs& a, int p, int* groups, int* ng) {
 
 // H for nb zones of local pattern p: H_k = G_k + i G_mirror,k (k <= N/2) and
 // H_{N-k} = conj(G_k) + i conj(G_mirror,k), stored in digit-reversed order for
-// the in-place inverse FFT: H[rev(n) * nb + b].  Four consecutive lanes share a
-// frequency k and take every fourth active radius group; each group of X is
-// loaded once for all nb zones.
+// the in-place inverse FFT: H[rev(n) * nb + b].  Eight consecutive lanes share a
+// frequency k and take every eighth active radius group (consecutive groups
+// fill whole 128-byte lines); each group of X is loaded once for all nb zones.
 template <int NB>
 __device__ void contract_exact_nb(const ExactArgs& a, int p, const int* bz, const int* rev, float2* H,
                                   const int* groups, int ng) {
   const size_t xbase = tile_off(p, 0, 0, a.xrows, a.Rp);
   const size_t xk = (size_t)64 * a.Rp;
-  const int sub = threadIdx.x & 3;
-  for (int base = 0; base < a.Nk; base += (int)(blockDim.x >> 2)) {
-    const int k = base + (int)(threadIdx.x >> 2);
+  const int sub = threadIdx.x & 7;
+  for (int base = 0; base < a.Nk; base += (int)(blockDim.x >> 3)) {
+    const int k = base + (int)(threadIdx.x >> 3);
     float A[NB], B[NB], C[NB], D[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) A[b] = B[b] = C[b] = D[b] = 0.0f;
@@ -1059,7 +1059,7 @@ __device__ void contract_exact_nb(const ExactArgs& a, int p, const int* bz, cons
       // every zone of the batch is a compile-time slot: no branch separates
       // the loads of one group, so they are all in flight together
 #pragma unroll 2
-      for (int g = sub; g < ng; g += 4) {
+      for (int g = sub; g < ng; g += 8) {
         const int s = groups[g] * 4;
         const float4 vr = *reinterpret_cast<const float4*>(xr + s);
         const float4 vi = *reinterpret_cast<const float4*>(xi + s);
@@ -1081,7 +1081,7 @@ __device__ void contract_exact_nb(const ExactArgs& a, int p, const int* bz, cons
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
 #pragma unroll
-      for (int off = 1; off <= 2; off <<= 1) {
+      for (int off = 1; off <= 4; off <<= 1) {
         A[b] += __shfl_xor(A[b], off, 64);
         B[b] += __shfl_xor(B[b], off, 64);
         C[b] += __shfl_xor(C[b], off, 64);
