@@ -98,10 +98,17 @@ def log(msg):
 
 
 def kernel_source_hash():
+    """Hash of the contraction kernel's source: the bound section of match.hip
+    (from its section marker to the next) and the shared header, so that the
+    stored counters stay valid across changes to the other passes."""
     h = hashlib.sha256()
-    for f in ("match.hip", "fft_device.h", "acom_internal.h"):
-        with open(os.path.join(ROOT, "paper_2111_00171_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    with open(os.path.join(ROOT, "paper_2111_00171_amd", "csrc", "match.hip"), "rb") as fh:
+        src = fh.read()
+    a = src.index(b"// " + b"-" * 60 + b" 2. bound ----")
+    b = src.index(b"// " + b"-" * 60 + b" 3. exact ----")
+    h.update(src[a:b])
+    with open(os.path.join(ROOT, "paper_2111_00171_amd", "csrc", "acom_internal.h"), "rb") as fh:
+        h.update(fh.read())
     return h.hexdigest()[:16]
 
 

@@ -334,7 +334,8 @@ acom_status_t acom_profile_end(void);
  * key 8: largest zone count (0 .. 32768, default 16384) whose per-pattern bound row the exact
  *        pass copies to LDS; larger plans select zones in place in the workspace;
  * key 9: 1 = the exact pass runs on persistent workgroups that take patterns from XCD-local
- *        work queues in the workspace (default), 0 = one workgroup per pattern.
+ *        work queues in the workspace, 0 = one workgroup per pattern (default).  Results are
+ *        identical either way.
  * A shape found by acom_autotune takes precedence over keys 0, 1, 4 and 6 for its precision
  * until one of those keys is set again. */
 acom_status_t acom_set_tuning(int32_t key, int32_t value);

@@ -1586,7 +1586,7 @@ struct Tuning {
   int bound_kch32 = 16;   // radii per LDS step of the FP32 contraction (16 or 32)
   int polar_cols = 32;    // radial columns per pass of the polar kernel (16 or 32)
   int exact_u_lds_max = 16384;  // largest zone count whose bound row the exact pass copies to LDS
-  int exact_persist = 1;         // exact pass: persistent workgroups on XCD-local work queues
+  int exact_persist = 0;         // exact pass: persistent workgroups on XCD-local work queues (1) or one per pattern
   PlanDev::BoundShape tuned[3];  // contraction shape per operand precision found by acom_autotune
 };
 // Launch-shape settings of the calling host thread: plans stay immutable after

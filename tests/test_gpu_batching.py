@@ -236,7 +236,7 @@ def test_persistent_exact_pass_equals_grid_launch(acom, multi, precision):
                 torch.cuda.synchronize()
                 out[persist] = {k: v.cpu().numpy() for k, v in r.items() if v is not None}
         finally:
-            acom.set_tuning(exact_persist=1)
+            acom.set_tuning(exact_persist=0)
         for k in ("zone", "phase", "bin", "mirror", "score", "phi3", "orient", "n_evaluated"):
             assert np.array_equal(out[0][k], out[1][k]), (chunk, k)
         assert (out[1]["zone"][:, 0] >= 0).mean() > 0.95
