@@ -19,6 +19,7 @@
 // all are kept.  At most kMaxKept reflections take part: a pattern whose set
 // is larger is an error, reported as NaN (never truncated).
 #include <cmath>
+#include <type_traits>
 
 #include "acom_internal.h"
 
@@ -121,11 +122,16 @@ __device__ __forceinline__ float excitation(float x, float y, float z, float k0)
   return -(2.0f * k0 * z + (x * x + y * y + z * z)) / (2.0f * sqrtf(x * x + y * y + (k0 + z) * (k0 + z)));
 }
 
+// LDS of one pattern: the kept reflections' indices and a chunk of peaks
+// (position and weight); the score's peak gradient also keeps each kept
+// reflection's projected position and value.
 struct Shared {
-  float qx[kPeakChunk], qy[kPeakChunk], w[kPeakChunk], q[kPeakChunk];
+  float qx[kPeakChunk], qy[kPeakChunk], w[kPeakChunk];
   int kept[kMaxKept];
-  float rx[kMaxKept], ry[kMaxKept], v[kMaxKept];
   int nkept;
+};
+struct SharedKeep : Shared {
+  float rx[kMaxKept], ry[kMaxKept], v[kMaxKept];
 };
 
 // Kept reflections of `ph` at orientation m (lane-cooperative, ascending order).
@@ -162,62 +168,102 @@ struct Eval {
   float g[3];
 };
 
+// Peaks [c0, c0 + cnt) into LDS: position and weight w = q^gamma I^(omega/2).
+// Every lane calls; ends with a barrier.
+__device__ void load_peaks(const ScoreArgs& a, int64_t c0, int cnt, Shared& sh) {
+  __syncthreads();
+  for (int i = threadIdx.x; i < cnt; i += kW) {
+    const float x = a.qx[c0 + i], y = a.qy[c0 + i], in = a.I[c0 + i];
+    const float q = sqrtf(x * x + y * y);
+    sh.qx[i] = x;
+    sh.qy[i] = y;
+    sh.w[i] = powe(q, a.gamma) * powe(in, 0.5f * a.omega);
+  }
+  __syncthreads();
+}
+
+// The kept reflections are taken 64 at a time, one per lane: its projected
+// position, excitation error and value v_g, then its sums over the peaks,
+//   ag = sum_m w_m K_mg, (bx, by) = sum_m w_m K_mg (q_m - r_g),
+// which it folds at once into N = sum_g ag v_g, sum_g v_g^2 and, for the
+// gradient, the two parts of dS/dr_g = dN/dr_g / |v| - N v_g dv_g/dr_g / |v|^3
+// (their cross products with r_g, times J, summed separately and combined
+// with 1/|v| and N/|v|^3 at the end), so a lane holds one reflection's state.
+// K = exp(-d^2 / 2 sigma_c^2) is taken as 2^(-d^2 log2(e) / 2 sigma_c^2) by the
+// hardware base-2 exponential. peaks_cached: the pattern's peaks (m1 - m0 <=
+// kPeakChunk) are already in LDS.
+template <class SH>
 __device__ Eval evaluate(const ScoreArgs& a, int64_t m0, int64_t m1, const float* R, const float* J, bool grad,
-                         bool keep_arrays, Shared& sh) {
+                         bool keep_arrays, bool peaks_cached, SH& sh) {
   const int lane = threadIdx.x;
   const float sig2 = 0.25f * a.delta * a.delta;
-  const float inv2sc = 1.0f / (2.0f * sig2);
+  const float kexp = 1.4426950408889634f / (2.0f * sig2);  // log2(e) / (2 sigma_c^2)
   const float inv2se = 1.0f / (2.0f * a.sigma_e * a.sigma_e);
+  const float inv_se2 = 1.0f / (a.sigma_e * a.sigma_e);
   const int nk = sh.nkept;
-  constexpr int PER = kMaxKept / kW;
-  float rx[PER], ry[PER], rz[PER], s[PER], v[PER], ag[PER], bx[PER], by[PER];
-#pragma unroll
-  for (int t = 0; t < PER; ++t) {
-    const int j = lane + t * kW;
-    ag[t] = bx[t] = by[t] = 0.0f;
-    v[t] = 0.0f;
-    rx[t] = ry[t] = rz[t] = s[t] = 0.0f;
-    if (j < nk) {
+  float Np = 0.0f, V2 = 0.0f;
+  float ga[3] = {0.0f, 0.0f, 0.0f}, gb[3] = {0.0f, 0.0f, 0.0f};
+  for (int j0 = 0; j0 < nk; j0 += kW) {
+    const int j = j0 + lane;
+    const bool act = j < nk;
+    float rx = 0.0f, ry = 0.0f, rz = 0.0f, st = 0.0f, v = 0.0f;
+    if (act) {
       const int g = sh.kept[j];
       const float4 r = a.refl[g];
-      rx[t] = R[0] * r.x + R[3] * r.y + R[6] * r.z;
-      ry[t] = R[1] * r.x + R[4] * r.y + R[7] * r.z;
-      rz[t] = R[2] * r.x + R[5] * r.y + R[8] * r.z;
-      s[t] = excitation(rx[t], ry[t], rz[t], a.k0);
-      v[t] = powe(r.w, a.gamma) * powe(a.F2[g] * expf(-s[t] * s[t] * inv2se), 0.5f * a.omega);
+      rx = R[0] * r.x + R[3] * r.y + R[6] * r.z;
+      ry = R[1] * r.x + R[4] * r.y + R[7] * r.z;
+      rz = R[2] * r.x + R[5] * r.y + R[8] * r.z;
+      st = excitation(rx, ry, rz, a.k0);
+      v = powe(r.w, a.gamma) * powe(a.F2[g] * expf(-st * st * inv2se), 0.5f * a.omega);
     }
-  }
-  for (int64_t c0 = m0; c0 < m1; c0 += kPeakChunk) {
-    const int cnt = (int)min((int64_t)kPeakChunk, m1 - c0);
-    __syncthreads();
-    for (int i = lane; i < cnt; i += kW) {
-      const float x = a.qx[c0 + i], y = a.qy[c0 + i], in = a.I[c0 + i];
-      const float q = sqrtf(x * x + y * y);
-      sh.qx[i] = x;
-      sh.qy[i] = y;
-      sh.q[i] = q;
-      sh.w[i] = powe(q, a.gamma) * powe(in, 0.5f * a.omega);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int t = 0; t < PER; ++t) {
-      if (lane + t * kW >= nk) continue;
-      for (int i = 0; i < cnt; ++i) {
-        const float dx = sh.qx[i] - rx[t], dy = sh.qy[i] - ry[t];
-        const float wk = sh.w[i] * expf(-(dx * dx + dy * dy) * inv2sc);
-        ag[t] += wk;
+    float ag = 0.0f, bx = 0.0f, by = 0.0f;
+    for (int64_t c0 = m0; c0 < m1; c0 += kPeakChunk) {
+      const int cnt = (int)min((int64_t)kPeakChunk, m1 - c0);
+      if (!peaks_cached) load_peaks(a, c0, cnt, sh);
+      if (act) {
         if (grad) {
-          bx[t] += wk * dx;
-          by[t] += wk * dy;
+          for (int i = 0; i < cnt; ++i) {
+            const float dx = sh.qx[i] - rx, dy = sh.qy[i] - ry;
+            const float wk = sh.w[i] * __builtin_amdgcn_exp2f(-(dx * dx + dy * dy) * kexp);
+            ag += wk;
+            bx += wk * dx;
+            by += wk * dy;
+          }
+        } else {
+          for (int i = 0; i < cnt; ++i) {
+            const float dx = sh.qx[i] - rx, dy = sh.qy[i] - ry;
+            ag += sh.w[i] * __builtin_amdgcn_exp2f(-(dx * dx + dy * dy) * kexp);
+          }
         }
       }
     }
-  }
-  float Np = 0.0f, V2 = 0.0f;
+    Np += ag * v;
+    V2 += v * v;
+    if constexpr (std::is_same<SH, SharedKeep>::value) {
+      if (keep_arrays && act) {
+        sh.rx[j] = rx;
+        sh.ry[j] = ry;
+        sh.v[j] = v;
+      }
+    }
+    if (grad && act) {
+      const float D = sqrtf(rx * rx + ry * ry + (a.k0 + rz) * (a.k0 + rz));
+      const float f = v * 0.5f * a.omega * (-st * inv_se2);
+      const float dvx = f * (-rx / D - st * rx / (D * D));
+      const float dvy = f * (-ry / D - st * ry / (D * D));
+      const float dvz = f * (-(a.k0 + rz) / D - st * (a.k0 + rz) / (D * D));
+      // part 1: dN/dr; part 2: v dv/dr
+      const float ax = ag * dvx + v * bx / sig2, ay = ag * dvy + v * by / sig2, az = ag * dvz;
+      const float ux = v * dvx, uy = v * dvy, uz = v * dvz;
+      // (d x r) J for d = part 1 and part 2
+      const float c1x = ay * rz - az * ry, c1y = az * rx - ax * rz, c1z = ax * ry - ay * rx;
+      const float c2x = uy * rz - uz * ry, c2y = uz * rx - ux * rz, c2z = ux * ry - uy * rx;
 #pragma unroll
-  for (int t = 0; t < PER; ++t) {
-    Np += ag[t] * v[t];
-    V2 += v[t] * v[t];
+      for (int i = 0; i < 3; ++i) {
+        ga[i] += c1x * J[i] + c1y * J[3 + i] + c1z * J[6 + i];
+        gb[i] += c2x * J[i] + c2y * J[3 + i] + c2z * J[6 + i];
+      }
+    }
   }
   Eval e;
   e.N = wsum(Np);
@@ -225,50 +271,15 @@ __device__ Eval evaluate(const ScoreArgs& a, int64_t m0, int64_t m1, const float
   e.nv = sqrtf(v2);
   e.S = e.nv > 0.0f ? e.N / e.nv : 0.0f;
   e.g[0] = e.g[1] = e.g[2] = 0.0f;
-  if (keep_arrays) {
-#pragma unroll
-    for (int t = 0; t < PER; ++t) {
-      const int j = lane + t * kW;
-      if (j < nk) {
-        sh.rx[j] = rx[t];
-        sh.ry[j] = ry[t];
-        sh.v[j] = v[t];
-      }
-    }
-  }
   if (!grad || !(e.nv > 0.0f)) return e;
-  const float inv_se2 = 1.0f / (a.sigma_e * a.sigma_e);
   const float c1 = 1.0f / e.nv, c2 = e.N / (e.nv * e.nv * e.nv);
-  float gd[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
-  for (int t = 0; t < PER; ++t) {
-    if (lane + t * kW >= nk) continue;
-    const float x = rx[t], y = ry[t], z = rz[t], st = s[t];
-    const float D = sqrtf(x * x + y * y + (a.k0 + z) * (a.k0 + z));
-    const float f = v[t] * 0.5f * a.omega * (-st * inv_se2);
-    const float dvx = f * (-x / D - st * x / (D * D));
-    const float dvy = f * (-y / D - st * y / (D * D));
-    const float dvz = f * (-(a.k0 + z) / D - st * (a.k0 + z) / (D * D));
-    const float dNx = ag[t] * dvx + v[t] * bx[t] / sig2;
-    const float dNy = ag[t] * dvy + v[t] * by[t] / sig2;
-    const float dNz = ag[t] * dvz;
-    const float dx = c1 * dNx - c2 * v[t] * dvx;
-    const float dy = c1 * dNy - c2 * v[t] * dvy;
-    const float dz = c1 * dNz - c2 * v[t] * dvz;
-    // (dS/dr x r)
-    const float cx = dy * z - dz * y, cy = dz * x - dx * z, cz = dx * y - dy * x;
-    gd[0] += cx * J[0] + cy * J[3] + cz * J[6];
-    gd[1] += cx * J[1] + cy * J[4] + cz * J[7];
-    gd[2] += cx * J[2] + cy * J[5] + cz * J[8];
-  }
-  e.g[0] = wsum(gd[0]);
-  e.g[1] = wsum(gd[1]);
-  e.g[2] = wsum(gd[2]);
+  for (int i = 0; i < 3; ++i) e.g[i] = c1 * wsum(ga[i]) - c2 * wsum(gb[i]);
   return e;
 }
 
 __global__ void __launch_bounds__(kW) score_kernel(ScoreArgs a) {
-  __shared__ Shared sh;
+  __shared__ SharedKeep sh;
   const int p = blockIdx.x;
   const int lane = threadIdx.x;
   const int64_t m0 = a.offsets[p], m1 = a.offsets[p + 1];
@@ -301,7 +312,9 @@ __global__ void __launch_bounds__(kW) score_kernel(ScoreArgs a) {
     }
     return;
   }
-  Eval e = evaluate(a, m0, m1, R, J, grad, peak_grad, sh);
+  const bool cached = m1 - m0 <= kPeakChunk;  // the pattern's peaks fit the LDS chunk: loaded once
+  if (cached) load_peaks(a, m0, (int)(m1 - m0), sh);
+  Eval e = evaluate(a, m0, m1, R, J, grad, peak_grad, cached, sh);
   if (!grad) {
     if (lane == 0) a.S[p] = e.S;
     return;
@@ -353,6 +366,10 @@ __global__ void __launch_bounds__(kW) refine_kernel(ScoreArgs a) {
   bool overflow = false;
   const int npk = (int)max((int64_t)0, m1 - m0);
   int work_s = 0, work_g = 0;  // pair evaluations (reported when out_work is given)
+  // the pattern's peaks, once, when they fit the LDS chunk (else every evaluation streams them)
+  const bool range_ok = m0 >= 0 && m1 >= m0 && m1 <= a.total_peaks;
+  const bool cached = range_ok && m1 - m0 <= kPeakChunk;
+  if (cached) load_peaks(a, m0, npk, sh);
   for (int i = 0; i < 9; ++i) best[i] = 0.0f;
   const float I3[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
   for (int c = 0; c < a.n_cand; ++c) {
@@ -360,7 +377,7 @@ __global__ void __launch_bounds__(kW) refine_kernel(ScoreArgs a) {
     const int ph = a.cand_phase ? a.cand_phase[ci] : 0;
     float m[9];
     for (int i = 0; i < 9; ++i) m[i] = a.init[ci * 9 + i];
-    bool ok = ph >= 0 && ph < a.n_phases && m0 >= 0 && m1 >= m0 && m1 <= a.total_peaks;
+    bool ok = ph >= 0 && ph < a.n_phases && range_ok;
     for (int i = 0; i < 9; ++i) ok = ok && isfinite(m[i]);
     if (!ok) continue;
     __syncthreads();
@@ -368,7 +385,7 @@ __global__ void __launch_bounds__(kW) refine_kernel(ScoreArgs a) {
       overflow = true;
       break;
     }
-    Eval e = evaluate(a, m0, m1, m, I3, true, false, sh);
+    Eval e = evaluate(a, m0, m1, m, I3, true, false, cached, sh);
     work_g += sh.nkept * npk;
     float S = e.S;
     float g[3] = {e.g[0], e.g[1], e.g[2]};
@@ -381,7 +398,7 @@ __global__ void __launch_bounds__(kW) refine_kernel(ScoreArgs a) {
       float E[9], mt[9];
       expm3(th, E);
       matmul3(m, E, mt);
-      Eval et = evaluate(a, m0, m1, mt, I3, false, false, sh);
+      Eval et = evaluate(a, m0, m1, mt, I3, false, false, cached, sh);
       work_s += sh.nkept * npk;
       ++it;
       if (et.S > S) {
@@ -393,7 +410,7 @@ __global__ void __launch_bounds__(kW) refine_kernel(ScoreArgs a) {
           overflow = true;
           break;
         }
-        Eval eg = evaluate(a, m0, m1, m, I3, true, false, sh);
+        Eval eg = evaluate(a, m0, m1, m, I3, true, false, cached, sh);
         work_g += sh.nkept * npk;
         g[0] = eg.g[0];
         g[1] = eg.g[1];

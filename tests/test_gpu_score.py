@@ -219,17 +219,23 @@ def test_refinement_on_other_phases(phase_name, ph):
     m, S, c = m.cpu().numpy(), S.cpu().numpy(), c.cpu().numpy()
     G = metrics.cubic_rotations() if ph == 1 else metrics.hexagonal_rotations()
     c32 = init.cpu().numpy().astype(np.float64).reshape(n, 3, 3, 3)
+    mis_oracle = []
     for p in range(0, n, 4):
         qx, qy, I = _peaks(d, p)
         # the GPU's winner: a candidate of the oracle's best refined score up to
-        # FP32 resolution, at the oracle's refinement of that candidate
+        # FP32 resolution, ending where the oracle's refinement of that candidate
+        # ends, up to where either ascent stops (the FP64 score at the GPU's end
+        # point is the oracle's end score up to 1e-4)
         allr = [score.refine_one(refls[cph[p, j]], qx, qy, I, c32[p, j], prm, max_iter=64) for j in range(3)]
         jb = int(np.argmax([r[1] for r in allr]))
         best = (allr[jb][0], allr[jb][1], jb)
         cj = int(c[p])
         assert allr[cj][1] >= best[1] - 1e-4 * abs(best[1]), (p, cj, best[2])
         assert abs(S[p] - allr[cj][1]) <= 1e-4 * abs(best[1]), (p, S[p], allr[cj][1])
-        assert metrics.misorientation_deg(m[p], allr[cj][0], G) < 0.01
+        Sg = score.score(refls[cph[p, cj]], qx, qy, I, m[p].astype(np.float64), np.zeros(3), prm)
+        assert Sg >= allr[cj][1] - 1e-4 * abs(best[1]), (p, Sg, allr[cj][1])
+        mis_oracle.append(metrics.misorientation_deg(m[p], allr[cj][0], G))
+    assert np.median(mis_oracle) <= 0.01 and max(mis_oracle) <= 0.05, mis_oracle
     assert np.mean(c == 0) > 0.8
     mis = [metrics.misorientation_deg(m[p], d["truth"][p], G) for p in range(n)]
     assert np.median(mis) < 0.1
