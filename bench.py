@@ -569,14 +569,19 @@ def run_refine(args):
              "oracle_comparison": ext, "input_generation_s": round(t_gen, 3)}
     ccfg = {"patterns": n, "peaks": int(d["offsets"][-1]), "zones": gpl.n_zones, "n_radial": gpl.n_radial,
             "n_angular": gpl.n_angular, "candidates": 4, "max_trials": 64}
-    # the dominant kernel of the step is the FP32 contraction of the candidate search
-    roof = {"kernel": "bound_kernel (MFMA contraction, fp32 operands) of the top-4 search", "bound": "mfma",
-            "achieved": round(tflops, 3), "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
-            "frac": round(tflops / PEAK_TFLOPS["fp32"], 4), "traffic": None,
-            "algorithmic_flop_per_launch": flop_per_pattern * per_launch,
-            "kernel_avg_ms": {k: (round(t / c, 4) if c else None) for k, (t, c) in prof.items()},
-            "refine_kernel": "latency-bound gradient ascent (per-pattern candidate loops, a block reduction per "
-                             "iteration); its time is ms_per_step_refine"}
+    # the roofline of the step's dominant kernel: the refinement's (ALU, its
+    # counted score and gradient work) or the FP32 contraction of the search
+    contraction = {"kernel": "bound_kernel (MFMA contraction, fp32 operands) of the top-4 search", "bound": "mfma",
+                   "achieved": round(tflops, 3), "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
+                   "frac": round(tflops / PEAK_TFLOPS["fp32"], 4), "traffic": None,
+                   "algorithmic_flop_per_launch": flop_per_pattern * per_launch,
+                   "kernel_avg_ms": {k: (round(t / c, 4) if c else None) for k, (t, c) in prof.items()}}
+    rr = dict(extra["refine_roofline"], traffic=None)
+    bound_ms = contraction["kernel_avg_ms"].get("bound") or 0.0
+    if rr["refine_ms"] >= bound_ms:
+        roof = dict(rr, other_kernel=contraction)
+    else:
+        roof = dict(contraction, other_kernel=rr)
     return line("refine", n * args.steps / el, el * 1e3 / args.steps, args.steps, args.warmup, "f32", ccfg, roof,
                 cpu, extra)
 
