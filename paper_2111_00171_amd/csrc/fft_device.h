@@ -265,6 +265,77 @@ __device__ __forceinline__ void fft_level_ct(float2* buf, const float2* tw, floa
   if constexpr (LEVEL > 0) fft_level_ct<N, NSEQ, LEVEL - 1>(buf, tw, sg);
 }
 
+// Forward 360-point DFT (exp(-2 pi i n k / 360)) of NSEQ interleaved
+// sequences in natural order, buf[n * NSEQ + q], in two LDS passes instead of
+// three: 360 = 24 x 15 by Cooley-Tukey over n = n1 + 24 n2, k = k2 + 15 k1,
+//   X[k2 + 15 k1] = sum_n1 W24^(n1 k1) W360^(n1 k2) sum_n2 W15^(n2 k2) x[n1 + 24 n2],
+// each factor in registers by Good's prime-factor maps (15 = 3 x 5 with input
+// (5 i + 3 j) mod 15 and output (10 i + 6 j) mod 15; 24 = 3 x 8 with input
+// (8 i + 3 j) mod 24 and output (16 i + 9 j) mod 24: no inner twiddles).
+// Pass 1 writes the twiddled 15-point spectra over n2 in place; pass 2 the
+// 24-point spectra over n1, so frequency k ends at position
+// (k / 15) + 24 (k % 15). tw[i] = exp(+2 pi i i / 360). Every thread calls;
+// ends with a barrier.
+template <int NSEQ>
+__device__ __forceinline__ void block_fft360_fwd(float2* buf, const float2* tw) {
+  for (int it = threadIdx.x; it < 24 * NSEQ; it += blockDim.x) {
+    const int q = it % NSEQ, n1 = it / NSEQ;
+    float2 a[3][5];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 5; ++j) a[i][j] = buf[(n1 + 24 * ((5 * i + 3 * j) % 15)) * NSEQ + q];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      float2 t[3] = {a[0][j], a[1][j], a[2][j]};
+      dft_small(t, 3, 1.0f);
+      a[0][j] = t[0];
+      a[1][j] = t[1];
+      a[2][j] = t[2];
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) dft_small(a[i], 5, 1.0f);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 5; ++j) {
+        const int k2 = (10 * i + 6 * j) % 15;
+        float2 y = a[i][j];
+        if (k2 > 0 && n1 > 0) {
+          const float2 w = tw[n1 * k2];  // n1 k2 <= 23 * 14 < 360
+          y = cmul(y, make_float2(w.x, -w.y));
+        }
+        buf[(n1 + 24 * k2) * NSEQ + q] = y;
+      }
+  }
+  __syncthreads();
+  for (int it = threadIdx.x; it < 15 * NSEQ; it += blockDim.x) {
+    const int q = it % NSEQ, k2 = it / NSEQ;
+    float2 a[3][8];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) a[i][j] = buf[((8 * i + 3 * j) % 24 + 24 * k2) * NSEQ + q];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      float2 t[3] = {a[0][j], a[1][j], a[2][j]};
+      dft_small(t, 3, 1.0f);
+      a[0][j] = t[0];
+      a[1][j] = t[1];
+      a[2][j] = t[2];
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) dft_small(a[i], 8, 1.0f);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) buf[((16 * i + 9 * j) % 24 + 24 * k2) * NSEQ + q] = a[i][j];
+  }
+  __syncthreads();
+}
+// Position of frequency k in the output of block_fft360_fwd.
+__device__ __forceinline__ int fft360_pos(int k) { return k / 15 + 24 * (k % 15); }
+
 template <int N, int NSEQ>
 __device__ __forceinline__ void block_fft_inplace_ct(float2* buf, const float2* tw, float sg) {
   constexpr RadixPlan P = make_radix_plan(N);

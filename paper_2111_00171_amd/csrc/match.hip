@@ -178,7 +178,7 @@ constexpr int polar_peak_cache() {
   return NC == 32 ? 128 : kPeakCache;
 }
 template <int NT, int NC>
-__global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
+__global__ void __launch_bounds__(kThreads, 3) polar_kernel(PolarArgs a) {
   static_assert(NC == 16 || NC == 32, "16 or 32 columns per pass");
   constexpr int PC = polar_peak_cache<NC>();
   constexpr int kParts = kThreads / NC;  // angular partitions of the splat
@@ -204,6 +204,13 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
   __shared__ float s_red[kThreads / 64];
   __shared__ double s_red64[kThreads / 64];
   __shared__ float s_sc;
+
+  // N = 360: X in natural angular order for the two-pass transform, whose
+  // frequency k sits at fft360_pos(k); other lengths: digit-reversed input,
+  // natural output
+  constexpr bool kNat360 = NT == 360;
+  auto xrow = [&](int ai) { return kNat360 ? ai : rev[ai]; };
+  auto fpos = [&](int k) { return kNat360 ? fft360_pos(k) : k; };
 
   const int tid = threadIdx.x;
   const int p = a.per > 0 ? xcd_item(a.per) : (int)blockIdx.x;
@@ -328,7 +335,7 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
               if (xa < -pi_f) xa += 2.0f * pi_f;
               const float dp = xa * qs;
               const float k = kern32(__builtin_amdgcn_sqrtf(dq2 + dp * dp), a.delta, kinv, sig3, a.kernel);
-              if (k > 0.0f) X[rev[ai] * NC + c] += w * k;
+              if (k > 0.0f) X[xrow(ai) * NC + c] += w * k;
             }
           } else {
             // window [ac - hw, ac + hw] in unwrapped bins; fewer than N bins, so each
@@ -342,7 +349,7 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
               for (int u = first; u < u1; u += kParts) {
                 const float dp = ((float)(u - ac) - f) * dqs;
                 const float k = kern32(__builtin_amdgcn_sqrtf(dq2 + dp * dp), a.delta, kinv, sig3, a.kernel);
-                if (k > 0.0f) X[rev[u - sh] * NC + c] += w * k;
+                if (k > 0.0f) X[xrow(u - sh) * NC + c] += w * k;
               }
             }
           }
@@ -383,7 +390,7 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
     if (a.Ximg) {
       for (int i = tid; i < N * NC; i += kThreads) {
         const int ai = i / NC, cc = i % NC;
-        if (col0 + cc < a.R) a.Ximg[((size_t)p * N + ai) * a.R + col0 + cc] = bad ? 0.0f : 2.0f * X[rev[ai] * NC + cc];
+        if (col0 + cc < a.R) a.Ximg[((size_t)p * N + ai) * a.R + col0 + cc] = bad ? 0.0f : 2.0f * X[xrow(ai) * NC + cc];
       }
     }
     if (!a.do_fft) {
@@ -391,7 +398,9 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
       continue;
     }
     if (listed) {  // a tile of zeros has a zero spectrum: its LDS already holds it
-      if constexpr (NT > 0)
+      if constexpr (kNat360)
+        block_fft360_fwd<NS>(b0, tw);
+      else if constexpr (NT > 0)
         block_fft_inplace_ct<NT, NS>(b0, tw, 1.0f);
       else
         block_fft_inplace(b0, tw, N, NS, a.rad, a.nrad, 1.0f);
@@ -413,8 +422,8 @@ __global__ void __launch_bounds__(kThreads) polar_kernel(PolarArgs a) {
     // prefetch one loop step past the end stays inside the LDS buffer
     auto load_pair = [&](int k, int q, float2& Zk, float2& Zn) {
       k = min(k, a.Nk - 1);
-      Zk = F[k * NS + q];
-      Zn = F[(k == 0 ? 0 : N - k) * NS + q];
+      Zk = F[fpos(k) * NS + q];
+      Zn = F[fpos(k == 0 ? 0 : N - k) * NS + q];
     };
     // the spectra of the pair: E = (Z_k + conj Z_{N-k}) / 2 for column 2q,
     // O = -i (Z_k - conj Z_{N-k}) / 2 for column 2q + 1 (the LDS holds the
