@@ -91,9 +91,9 @@ typedef struct {
   int32_t precisions;    /* bit mask of (1 << acom_precision_t) operand copies to build; FP32 is always built */
   int32_t keep_f64;      /* nonzero: keep the FP64 angular plan for acom_plan_copy_f64 */
   int32_t bound_exact_freqs;  /* split bound of acom_match with FP32 operands: frequencies k < Kc bounded
-                                 by their exact correlogram spectra; 0 -> Kc = min(N_phi/2 + 1, 24) */
+                                 by their exact correlogram spectra; 0 -> Kc = min(N_phi/2 + 1, 28) */
   int32_t bound_block_radii;  /* radii per block of the Cauchy-Schwarz bound for k >= Kc: 2, 4, 8 or 16
-                                 (0 -> 8) */
+                                 (0 -> 16) */
   int32_t bound_exact_freqs_16bit;  /* Kc for BF16 / FP16 operands; 0 -> min(N_phi/2 + 1, 48) */
 } acom_plan_params_t;
 

@@ -39,7 +39,7 @@ constexpr int kMaxRadices = 12;
 constexpr int kMaxAngular = 1024;
 constexpr int kMaxTopK = 16;
 // default exact frequencies of the split bound, FP32 / 16-bit operands
-constexpr int kDefaultExactFreqs[2] = {24, 48};
+constexpr int kDefaultExactFreqs[2] = {28, 48};
 
 // Mixed-radix factorisation of the angular length (radices 8, 9, 4, 2, 3, 5, greedily).
 struct Radices {

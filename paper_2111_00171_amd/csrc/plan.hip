@@ -733,7 +733,7 @@ extern "C" acom_status_t acom_build_plan(const acom_phase_t* phases, int32_t n_p
     while (d.r0 < d.R && !colany[d.r0]) ++d.r0;
   }
   // ---- split bound and the contraction operands (tile-major over zones)
-  d.bb = prm->bound_block_radii > 0 ? prm->bound_block_radii : 8;
+  d.bb = prm->bound_block_radii > 0 ? prm->bound_block_radii : 16;
   d.nb = d.Rp / d.bb;
   d.Sp = d.Rp - d.r0;
   {
