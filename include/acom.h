@@ -335,7 +335,11 @@ acom_status_t acom_profile_end(void);
  *        pass copies to LDS; larger plans select zones in place in the workspace;
  * key 9: 1 = the exact pass runs on persistent workgroups that take patterns from XCD-local
  *        work queues in the workspace, 0 = one workgroup per pattern (default).  Results are
- *        identical either way.
+ *        identical either way;
+ * key 10: with key 2 = 1, the exact pass's patterns per XCD run (0 .. 2^20, default 1024):
+ *        XCD x takes the x-th run of that many consecutive patterns out of each group of
+ *        8 runs, so the device works on neighbouring patterns; 0 = one contiguous range
+ *        per XCD.  Results are identical for every value.
  * A shape found by acom_autotune takes precedence over keys 0, 1, 4 and 6 for its precision
  * until one of those keys is set again. */
 acom_status_t acom_set_tuning(int32_t key, int32_t value);

@@ -668,14 +668,16 @@ class Plan:
 
 KERNEL_KINDS = {"polar": 0, "bound": 1, "exact": 2}
 TUNING_KEYS = {"bound_order": 0, "bound_kch16": 1, "exact_xcd": 2, "polar_xcd": 3, "bound_tile": 4, "skip_zero_radii": 5,
-               "bound_kch32": 6, "polar_cols": 7, "exact_u_lds_max": 8, "exact_persist": 9}
+               "bound_kch32": 6, "polar_cols": 7, "exact_u_lds_max": 8, "exact_persist": 9,
+               "exact_xcd_block": 10}
 
 
 def set_tuning(**kw):
     """Launch-shape knobs of the calling thread (results do not depend on them):
     bound_order (0/1), bound_kch16 (32/64/128), exact_xcd (0/1), polar_xcd (0/1),
     bound_tile (0/1/2), skip_zero_radii (0/1), bound_kch32 (16/32), polar_cols
-    (16/32), exact_u_lds_max (zones whose bound row the exact pass keeps in LDS), exact_persist (0/1)."""
+    (16/32), exact_u_lds_max (zones whose bound row the exact pass keeps in LDS), exact_persist (0/1),
+    exact_xcd_block (patterns per XCD run of the exact pass's order; 0 = one range per XCD)."""
     for k, v in kw.items():
         _check(lib().acom_set_tuning(TUNING_KEYS[k], int(v)), "acom_set_tuning")
 

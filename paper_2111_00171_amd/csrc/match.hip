@@ -109,6 +109,22 @@ inline int xcd_blocks(int total, int* per) {
   *per = (total + kXcds - 1) / kXcds;
   return *per * kXcds;
 }
+// The same with the items dealt out in groups: XCD x takes the x-th run of B
+// consecutive items of each group of 8 B (the whole device then works on 8 B
+// neighbouring items at a time, each XCD still on consecutive ones), and the
+// last, partial group is split into 8 ranges of `per` items.  B = 0 gives the
+// single range per XCD of xcd_item.
+__device__ __forceinline__ int xcd_item_grouped(int B, int nfull, int per) {
+  const int j = (int)(blockIdx.x / kXcds), x = (int)(blockIdx.x % kXcds);
+  if (j < nfull * B) return (j / B) * (kXcds * B) + x * B + j % B;
+  return nfull * kXcds * B + x * per + (j - nfull * B);
+}
+inline int xcd_blocks_grouped(int total, int B, int* nfull, int* per) {
+  *nfull = B > 0 ? total / (kXcds * B) : 0;
+  const int rem = total - *nfull * kXcds * B;
+  *per = (rem + kXcds - 1) / kXcds;
+  return kXcds * (*nfull * B + *per);
+}
 
 // ------------------------------------------------------------ 1. polar ----
 
@@ -1000,7 +1016,8 @@ struct ExactArgs {
   const float* M12;
   const int* zone_phase;
   float eps_rel, eps_abs;
-  int top_k, per;
+  int top_k;
+  int per, xblk, xfull;  // pattern order: per < 0 plain, else xcd_item_grouped(xblk, xfull, per)
   int64_t p_begin;
   int np;
   int *zone, *phase, *bin, *mirror, *n_eval;
@@ -1238,7 +1255,7 @@ __global__ void __launch_bounds__(kThreads) exact_kernel(ExactArgs a) {
   }
 
   if (a.force_zone) {  // one given (zone, bin, branch) per pattern
-    const int p = a.per < 0 ? (int)blockIdx.x : xcd_item(a.per);
+    const int p = a.per < 0 ? (int)blockIdx.x : xcd_item_grouped(a.xblk, a.xfull, a.per);
     if (p >= a.np) return;
     const int64_t P = a.p_begin + p;
     const int z = a.force_zone[P - a.out_p0];
@@ -1438,7 +1455,7 @@ __global__ void __launch_bounds__(kThreads) exact_kernel(ExactArgs a) {
   };  // one pattern
 
   if constexpr (!PERSIST) {
-    const int p = a.per < 0 ? (int)blockIdx.x : xcd_item(a.per);
+    const int p = a.per < 0 ? (int)blockIdx.x : xcd_item_grouped(a.xblk, a.xfull, a.per);
     if (p >= a.np) return;
     one(p);
   } else {
@@ -1596,6 +1613,7 @@ struct Tuning {
   int polar_cols = 32;    // radial columns per pass of the polar kernel (16 or 32)
   int exact_u_lds_max = 16384;  // largest zone count whose bound row the exact pass copies to LDS
   int exact_persist = 0;         // exact pass: persistent workgroups on XCD-local work queues (1) or one per pattern
+  int exact_xcd_block = 1024;    // exact pass, XCD-grouped order: patterns per run (0 = one range per XCD)
   PlanDev::BoundShape tuned[3];  // contraction shape per operand precision found by acom_autotune
 };
 // Launch-shape settings of the calling host thread: plans stay immutable after
@@ -1802,6 +1820,7 @@ acom_status_t launch_exact_n(const PlanDev& d, const ExactArgs& e, dim3 grid, hi
   ACOM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, exact_kernel<NT, true>, kThreads, lds));
   ExactArgs p = e;
   p.per = (p.np + kXcds - 1) / kXcds;
+  p.xblk = p.xfull = 0;
   const int nblk = std::max(kXcds, (std::max(1, cus * std::max(1, per_cu)) / kXcds) * kXcds);
   exact_kernel<NT, true><<<dim3(nblk), kThreads, lds, s>>>(p);
   ACOM_HIP(hipGetLastError());
@@ -1958,6 +1977,8 @@ ExactArgs exact_args(const PlanDev& d, const WsLayout& L, unsigned char* ws, int
   e.out_p0 = 0;
   e.force_zone = e.force_bin = e.force_mirror = nullptr;
   e.force_score = nullptr;
+  e.per = -1;
+  e.xblk = e.xfull = 0;
   return e;
 }
 
@@ -2001,10 +2022,13 @@ acom_status_t match_chunk(const PlanDev& d, const acom_peaks_t* peaks, int64_t c
   e.orient = out.orient;
   e.n_eval = out.n_evaluated;
   int nblk = np;
-  if (g_tune.exact_xcd)
-    nblk = xcd_blocks(np, &e.per);
-  else
+  e.xblk = e.xfull = 0;
+  if (g_tune.exact_xcd) {
+    e.xblk = g_tune.exact_xcd_block;
+    nblk = xcd_blocks_grouped(np, e.xblk, &e.xfull, &e.per);
+  } else {
     e.per = -1;
+  }
   ProfScope prof(2, s);
   return launch_exact(d, e, dim3(nblk), s, g_tune.exact_persist != 0);
 }
@@ -2516,6 +2540,10 @@ extern "C" acom_status_t acom_set_tuning(int32_t key, int32_t value) {
     case 9:
       if (value != 0 && value != 1) return fail(ACOM_E_INVALID, "persistent exact pass must be 0 or 1");
       g_tune.exact_persist = value;
+      return ACOM_OK;
+    case 10:
+      if (value < 0 || value > (1 << 20)) return fail(ACOM_E_INVALID, "exact-pass XCD run must be in [0, 2^20] patterns");
+      g_tune.exact_xcd_block = value;
       return ACOM_OK;
 
   }

@@ -217,26 +217,35 @@ def test_plan_above_16384_zones(acom):
         assert torch.equal(a[k], b[k]), k
 
 
+# exact-pass launch orders: the default grid (XCD runs of 1024 patterns), one
+# range per XCD, runs of 3 and 100 (partial last groups), plain order, and the
+# persistent workgroups on XCD-local queues
+EXACT_ORDERS = [dict(), dict(exact_xcd_block=0), dict(exact_xcd_block=3), dict(exact_xcd_block=100),
+                dict(exact_xcd=0), dict(exact_persist=1)]
+
+
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
-def test_persistent_exact_pass_equals_grid_launch(acom, multi, precision):
-    """The exact pass on persistent workgroups (XCD-local work queues) gives the
-    grid launch's results bit for bit: on the three-phase plan, and on 20,000
-    scan patterns in chunks of 8,192 (a ragged last chunk, queues reset per
+def test_exact_pass_orders_and_persistent_launch_agree(acom, multi, precision):
+    """Every launch order of the exact pass gives the default grid launch's
+    results bit for bit: on the three-phase plan, and on 20,000 scan patterns in
+    chunks of 8,192 (a ragged last chunk; the persistent queues are reset per
     chunk by the polar pass)."""
     d, opl, gpl = multi
     cases = [(gpl, acom.Peaks.from_host(d), 0)]
     scan_plan = helpers.gpu_plan(["fcc"], precisions=("fp32", "bf16"), **helpers.SCAN)
     cases.append((scan_plan, acom.Peaks.from_host(synth.subset(synth.make("scan"), np.arange(20000) * 3)), 8192))
     for pl, pk, chunk in cases:
-        out = {}
+        out = []
         try:
-            for persist in (0, 1):
-                acom.set_tuning(exact_persist=persist)
+            for tune in EXACT_ORDERS:
+                acom.set_tuning(**tune)
                 r = pl.match(pk, top_k=3, precision=precision, chunk=chunk)
                 torch.cuda.synchronize()
-                out[persist] = {k: v.cpu().numpy() for k, v in r.items() if v is not None}
+                out.append({k: v.cpu().numpy() for k, v in r.items() if v is not None})
+                acom.set_tuning(exact_persist=0, exact_xcd=1, exact_xcd_block=1024)
         finally:
-            acom.set_tuning(exact_persist=0)
-        for k in ("zone", "phase", "bin", "mirror", "score", "phi3", "orient", "n_evaluated"):
-            assert np.array_equal(out[0][k], out[1][k]), (chunk, k)
-        assert (out[1]["zone"][:, 0] >= 0).mean() > 0.95
+            acom.set_tuning(exact_persist=0, exact_xcd=1, exact_xcd_block=1024)
+        for tune, o in zip(EXACT_ORDERS[1:], out[1:]):
+            for k in ("zone", "phase", "bin", "mirror", "score", "phi3", "orient", "n_evaluated"):
+                assert np.array_equal(out[0][k], o[k]), (chunk, tune, k)
+        assert (out[0]["zone"][:, 0] >= 0).mean() > 0.95
