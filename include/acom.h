@@ -321,8 +321,8 @@ acom_status_t acom_profile_end(void);
  *        1 = zone tiles fastest with the tiles of one pattern group on one XCD (default);
  * key 1: radii staged per LDS step by the BF16/FP16 contraction: 32, 64 (default), 128 (the largest dividing Rp is used);
  * key 2: exact-pass pattern order, 1 = XCD-grouped (default), 0 = plain;
- * key 3: polar-pass order, 1 = consecutive patterns grouped on one XCD (default),
- *        0 = pattern index fastest;
+ * key 3: polar-pass order, 1 = consecutive patterns grouped on one XCD,
+ *        0 = pattern index fastest (default);
  * key 4: contraction block tile, 0 = 64 x 64, 1 = large (128 x 128; 128 x 64 for FP32 operands),
  *        2 = large for BF16/FP16 operands when it gives at least two tiles per compute unit,
  *        else 64 x 64 (default);

@@ -1606,7 +1606,7 @@ struct Tuning {
   int bound_order = 1;    // 0: pattern tiles fastest, 1: XCD-grouped zone tiles fastest
   int bound_kch16 = 64;   // radii per LDS step of the 16-bit contraction (32, 64 or 128)
   int exact_xcd = 1;      // exact pass: XCD-grouped pattern order
-  int polar_xcd = 1;      // polar pass: consecutive patterns grouped on one XCD
+  int polar_xcd = 0;      // polar pass: consecutive patterns grouped on one XCD (1) or pattern index fastest
   int bound_tile = 2;     // contraction block tile: 0 = 64 x 64, 1 = 128 x 128, 2 = by problem size
   int skip_zero_radii = 1;  // contraction: skip the leading radii where the plan is zero in every zone
   int bound_kch32 = 16;   // radii per LDS step of the FP32 contraction (16 or 32)

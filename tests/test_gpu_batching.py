@@ -217,17 +217,18 @@ def test_plan_above_16384_zones(acom):
         assert torch.equal(a[k], b[k]), k
 
 
-# exact-pass launch orders: the default grid (XCD runs of 1024 patterns), one
+# launch orders: the exact pass's default grid (XCD runs of 1024 patterns), one
 # range per XCD, runs of 3 and 100 (partial last groups), plain order, and the
-# persistent workgroups on XCD-local queues
-EXACT_ORDERS = [dict(), dict(exact_xcd_block=0), dict(exact_xcd_block=3), dict(exact_xcd_block=100),
-                dict(exact_xcd=0), dict(exact_persist=1)]
+# persistent workgroups on XCD-local queues; the polar pass XCD-grouped
+LAUNCH_ORDERS = [dict(), dict(exact_xcd_block=0), dict(exact_xcd_block=3), dict(exact_xcd_block=100),
+                 dict(exact_xcd=0), dict(exact_persist=1), dict(polar_xcd=1)]
+DEFAULT_ORDER = dict(exact_persist=0, exact_xcd=1, exact_xcd_block=1024, polar_xcd=0)
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
-def test_exact_pass_orders_and_persistent_launch_agree(acom, multi, precision):
-    """Every launch order of the exact pass gives the default grid launch's
-    results bit for bit: on the three-phase plan, and on 20,000 scan patterns in
+def test_launch_orders_and_persistent_exact_pass_agree(acom, multi, precision):
+    """Every launch order of the exact and polar passes gives the default
+    launch's results bit for bit: on the three-phase plan, and on 20,000 scan patterns in
     chunks of 8,192 (a ragged last chunk; the persistent queues are reset per
     chunk by the polar pass)."""
     d, opl, gpl = multi
@@ -237,15 +238,15 @@ def test_exact_pass_orders_and_persistent_launch_agree(acom, multi, precision):
     for pl, pk, chunk in cases:
         out = []
         try:
-            for tune in EXACT_ORDERS:
+            for tune in LAUNCH_ORDERS:
                 acom.set_tuning(**tune)
                 r = pl.match(pk, top_k=3, precision=precision, chunk=chunk)
                 torch.cuda.synchronize()
                 out.append({k: v.cpu().numpy() for k, v in r.items() if v is not None})
-                acom.set_tuning(exact_persist=0, exact_xcd=1, exact_xcd_block=1024)
+                acom.set_tuning(**DEFAULT_ORDER)
         finally:
-            acom.set_tuning(exact_persist=0, exact_xcd=1, exact_xcd_block=1024)
-        for tune, o in zip(EXACT_ORDERS[1:], out[1:]):
+            acom.set_tuning(**DEFAULT_ORDER)
+        for tune, o in zip(LAUNCH_ORDERS[1:], out[1:]):
             for k in ("zone", "phase", "bin", "mirror", "score", "phi3", "orient", "n_evaluated"):
                 assert np.array_equal(out[0][k], o[k]), (chunk, tune, k)
         assert (out[0]["zone"][:, 0] >= 0).mean() > 0.95
