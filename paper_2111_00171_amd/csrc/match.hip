@@ -92,11 +92,45 @@ __device__ __forceinline__ void store_at(T* base, uint32_t byte_off, V v) {
   *reinterpret_cast<V*>(reinterpret_cast<char*>(base) + byte_off) = v;
 }
 
-// v of the lane that DPP control CTRL selects (a quad permutation or a
-// half-row mirror: the source lane is always within the same 8 lanes)
+// v of the lane that DPP control CTRL selects (a quad permutation, a half-row
+// or a row mirror: the source lane is always within the same 16 lanes)
 template <int CTRL>
 __device__ __forceinline__ float dpp_move(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp_move_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+
+// (value, index) maximum over the wavefront, ties to the smaller index, the
+// same pair in every lane (every lane active).  Within each row of 16 lanes by
+// DPP moves (lanes 2i <-> 2i + 1, the lane pairs of a quad, then the mirrored
+// half-row and row, whose lanes hold equal pairs by then); then the four row
+// results, read by scalar lane reads.  The selection is a total order, so the
+// result does not depend on the order of the comparisons.
+__device__ __forceinline__ void wave_argmax(float& bv, int& bi) {
+  auto take = [&](float ov, int oi) {
+    if (ov > bv || (ov == bv && oi < bi)) {
+      bv = ov;
+      bi = oi;
+    }
+  };
+  take(dpp_move<0xB1>(bv), dpp_move_i<0xB1>(bi));
+  take(dpp_move<0x4E>(bv), dpp_move_i<0x4E>(bi));
+  take(dpp_move<0x141>(bv), dpp_move_i<0x141>(bi));
+  take(dpp_move<0x140>(bv), dpp_move_i<0x140>(bi));
+  float rv[4];
+  int ri[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    rv[r] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bv), 16 * r));
+    ri[r] = __builtin_amdgcn_readlane(bi, 16 * r);
+  }
+  bv = rv[0];
+  bi = ri[0];
+#pragma unroll
+  for (int r = 1; r < 4; ++r) take(rv[r], ri[r]);
 }
 
 // XCD-aware block order: the hardware deals workgroup b to XCD b % 8, so
@@ -1104,15 +1138,20 @@ __device__ void contract_exact_nb(const ExactArgs& a, int p, const int* bz, cons
         }
       }
     }
+    // sums over the eight lanes of k by DPP moves: lanes 2i <-> 2i + 1, the lane
+    // pairs of a quad, then the mirrored half-row (the other quad, whose lanes
+    // all hold its sum): the butterfly's values, bit for bit
+    auto sum8 = [](float& v) {
+      v += dpp_move<0xB1>(v);
+      v += dpp_move<0x4E>(v);
+      v += dpp_move<0x141>(v);
+    };
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-#pragma unroll
-      for (int off = 1; off <= 4; off <<= 1) {
-        A[b] += __shfl_xor(A[b], off, 64);
-        B[b] += __shfl_xor(B[b], off, 64);
-        C[b] += __shfl_xor(C[b], off, 64);
-        D[b] += __shfl_xor(D[b], off, 64);
-      }
+      sum8(A[b]);
+      sum8(B[b]);
+      sum8(C[b]);
+      sum8(D[b]);
       if (k < a.Nk && sub == 0) {
         H[rev[k] * NB + b] = make_float2((A[b] + B[b]) + (C[b] + D[b]), (C[b] - D[b]) + (A[b] - B[b]));
         if (k > 0 && 2 * k < a.N)
@@ -1143,15 +1182,7 @@ __device__ void block_argmax(const float* v, int n, float* out_v, int* out_i, fl
       bi = i;
     }
   }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const float ov = __shfl_xor(bv, off, 64);
-    const int oi = __shfl_xor(bi, off, 64);
-    if (ov > bv || (ov == bv && oi < bi)) {
-      bv = ov;
-      bi = oi;
-    }
-  }
+  wave_argmax(bv, bi);
   if ((threadIdx.x & 63) == 0) {
     sv[threadIdx.x >> 6] = bv;
     si[threadIdx.x >> 6] = bi;
@@ -1358,15 +1389,7 @@ __global__ void __launch_bounds__(kThreads) exact_kernel(ExactArgs a) {
           bi = t;
         }
       }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const float ov = __shfl_xor(bv, off, 64);
-        const int oi = __shfl_xor(bi, off, 64);
-        if (ov > bv || (ov == bv && oi < bi)) {
-          bv = ov;
-          bi = oi;
-        }
-      }
+      wave_argmax(bv, bi);
       if (lane == 0) {
         const int n = bi >> 1, m = bi & 1;
         const float2 vm = Fr[(n == 0 ? a.N - 1 : n - 1) * nbp + b];

@@ -58,10 +58,24 @@ struct ScoreArgs {
   int* out_work;           // n x 2 or null: (peak, reflection) pairs evaluated for S alone and with its gradient
 };
 
+// v of the lane that DPP control CTRL selects within the same row of 16 lanes
+template <int CTRL>
+__device__ __forceinline__ float dpp_row(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// Sum over the wavefront (every lane active), the same value in every lane:
+// within each row of 16 lanes by DPP moves (lanes 2i <-> 2i + 1, the lane pairs
+// of a quad, then the mirrored half-row and row, whose lanes hold equal sums by
+// then), then the four row sums, read by scalar lane reads, in a fixed order.
 __device__ __forceinline__ float wsum(float v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  v += dpp_row<0xB1>(v);
+  v += dpp_row<0x4E>(v);
+  v += dpp_row<0x141>(v);
+  v += dpp_row<0x140>(v);
+  const int b = __float_as_int(v);
+  return (__int_as_float(__builtin_amdgcn_readlane(b, 0)) + __int_as_float(__builtin_amdgcn_readlane(b, 16))) +
+         (__int_as_float(__builtin_amdgcn_readlane(b, 32)) + __int_as_float(__builtin_amdgcn_readlane(b, 48)));
 }
 
 __device__ __forceinline__ float powe(float x, float e) {
@@ -222,6 +236,7 @@ __device__ Eval evaluate(const ScoreArgs& a, int64_t m0, int64_t m1, const float
       if (!peaks_cached) load_peaks(a, c0, cnt, sh);
       if (act) {
         if (grad) {
+#pragma unroll 4
           for (int i = 0; i < cnt; ++i) {
             const float dx = sh.qx[i] - rx, dy = sh.qy[i] - ry;
             const float wk = sh.w[i] * __builtin_amdgcn_exp2f(-(dx * dx + dy * dy) * kexp);
@@ -230,6 +245,7 @@ __device__ Eval evaluate(const ScoreArgs& a, int64_t m0, int64_t m1, const float
             by += wk * dy;
           }
         } else {
+#pragma unroll 4
           for (int i = 0; i < cnt; ++i) {
             const float dx = sh.qx[i] - rx, dy = sh.qy[i] - ry;
             ag += sh.w[i] * __builtin_amdgcn_exp2f(-(dx * dx + dy * dy) * kexp);
