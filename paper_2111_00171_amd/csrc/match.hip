@@ -1117,8 +1117,12 @@ __device__ void contract_exact_nb(const ExactArgs& a, int p, const int* bz, cons
         pi[b] = a.pi + ((size_t)bz[b] * a.Nk + k) * a.Rp;
       }
       // every zone of the batch is a compile-time slot: no branch separates
-      // the loads of one group, so they are all in flight together
-#pragma unroll 2
+      // the loads of one group, so they are all in flight together.  Batches
+      // of up to two zones also overlap two groups' loads; a batch of four
+      // (ten 16-byte loads per group) does not: measured on the degraded-peak
+      // scan, more loads in flight per lane made the pass slower
+      constexpr int kGroupsInFlight = NB == 4 ? 1 : 2;
+#pragma unroll kGroupsInFlight
       for (int g = sub; g < ng; g += 8) {
         const int s = groups[g] * 4;
         const float4 vr = *reinterpret_cast<const float4*>(xr + s);
