@@ -238,6 +238,9 @@ __global__ void __launch_bounds__(kThreads, 3) polar_kernel(PolarArgs a) {
   const int N = NT > 0 ? NT : a.N;
   float2* b0 = reinterpret_cast<float2*>(smem_raw);   // [rev(a)][NS] complex: columns packed in pairs
   float2* tw = b0 + N * NS;
+  // the digit-reversed order of the input (other lengths), or for N = 360 the
+  // output position of each frequency (a table lookup in place of two integer
+  // divisions per spectrum value read by the unpack)
   int* rev = reinterpret_cast<int*>(tw + N);
   // per cached peak: nearest bin |ac| <= N/2 (int16), offset, radius as an
   // FP32 pair, weight; the listed peaks as cache indices (< 256, one byte):
@@ -260,7 +263,7 @@ __global__ void __launch_bounds__(kThreads, 3) polar_kernel(PolarArgs a) {
   // natural output
   constexpr bool kNat360 = NT == 360;
   auto xrow = [&](int ai) { return kNat360 ? ai : rev[ai]; };
-  auto fpos = [&](int k) { return kNat360 ? fft360_pos(k) : k; };
+  auto fpos = [&](int k) { return kNat360 ? rev[k] : k; };
 
   const int tid = threadIdx.x;
   const int p = a.per > 0 ? xcd_item(a.per) : (int)blockIdx.x;
@@ -272,7 +275,7 @@ __global__ void __launch_bounds__(kThreads, 3) polar_kernel(PolarArgs a) {
   if (bad_range) m0 = m1 = 0;  // malformed CSR row: a data error, nothing is read
   for (int i = tid; i < N; i += kThreads) {
     tw[i] = a.tw[i];
-    rev[i] = a.rev[i];
+    rev[i] = kNat360 ? fft360_pos(i) : a.rev[i];
   }
   for (int i = tid; i < a.Rp; i += kThreads) sqs[i] = i < a.R ? a.qs[i] : -1.0f;
   if (tid == 0) s_bad = bad_range ? 1 : 0;
