@@ -227,7 +227,7 @@ template <int NC>
 constexpr int polar_peak_cache() {
   return NC == 32 ? 128 : kPeakCache;
 }
-template <int NT, int NC>
+template <int NT, int NC, int KIND>
 __global__ void __launch_bounds__(kThreads, 3) polar_kernel(PolarArgs a) {
   static_assert(NC == 16 || NC == 32, "16 or 32 columns per pass");
   constexpr int PC = polar_peak_cache<NC>();
@@ -289,7 +289,7 @@ __global__ void __launch_bounds__(kThreads, 3) polar_kernel(PolarArgs a) {
   // whole columns, so the waves whose columns no listed peak reaches skip the
   // splat loop as a whole instead of idling lanes in every wave
   const int c = tid / kParts, part = tid % kParts;
-  const float kinv = a.kernel == ACOM_KERNEL_CONE ? 1.0f / a.delta : 1.0f / (2.0f * a.sigma * a.sigma);
+  const float kinv = KIND == ACOM_KERNEL_CONE ? 1.0f / a.delta : 1.0f / (2.0f * a.sigma * a.sigma);
   const float sig3 = 3.0f * a.sigma;
   const bool single = (m1 - m0) <= PC;
   double wsum = 0.0;  // this thread's share of sum_m w_m (first pass over the peaks only)
@@ -367,6 +367,8 @@ __global__ void __launch_bounds__(kThreads, 3) polar_kernel(PolarArgs a) {
       __syncthreads();
       const int nl = s_nlist;
       listed = listed || nl > 0;
+      // the kernel shape (KIND) is a compile-time constant; a cell adds w k
+      // even where k = 0 (X >= 0, so X + 0 is X exactly)
       if (qs >= 0.0f) {
         for (int l = 0; l < nl; ++l) {
           const int j = plist[l];
@@ -387,8 +389,7 @@ __global__ void __launch_bounds__(kThreads, 3) polar_kernel(PolarArgs a) {
               if (xa > pi_f) xa -= 2.0f * pi_f;
               if (xa < -pi_f) xa += 2.0f * pi_f;
               const float dp = xa * qs;
-              const float k = kern32(__builtin_amdgcn_sqrtf(dq2 + dp * dp), a.delta, kinv, sig3, a.kernel);
-              if (k > 0.0f) X[xrow(ai) * NC + c] += w * k;
+              X[xrow(ai) * NC + c] += w * kern32(__builtin_amdgcn_sqrtf(dq2 + dp * dp), a.delta, kinv, sig3, KIND);
             }
           } else {
             // window [ac - hw, ac + hw] in unwrapped bins; fewer than N bins, so each
@@ -401,8 +402,7 @@ __global__ void __launch_bounds__(kThreads, 3) polar_kernel(PolarArgs a) {
               const int first = u0 + (part - (u0 - sh) % kParts + kParts) % kParts;
               for (int u = first; u < u1; u += kParts) {
                 const float dp = ((float)(u - ac) - f) * dqs;
-                const float k = kern32(__builtin_amdgcn_sqrtf(dq2 + dp * dp), a.delta, kinv, sig3, a.kernel);
-                if (k > 0.0f) X[xrow(u - sh) * NC + c] += w * k;
+                X[xrow(u - sh) * NC + c] += w * kern32(__builtin_amdgcn_sqrtf(dq2 + dp * dp), a.delta, kinv, sig3, KIND);
               }
             }
           }
@@ -1808,7 +1808,10 @@ void set_ws(PolarArgs& a, const WsLayout& L, unsigned char* ws, const PlanDev& d
 
 template <int NT, int NC>
 acom_status_t launch_polar_nc(const PlanDev& d, const PolarArgs& a, hipStream_t s) {
-  acom_status_t st = ensure_lds(polar_kernel<NT, NC>, polar_lds<NC>(d));
+  // one instantiation per kernel shape: the splat's cell loops hold no branch on it
+  const bool cone = a.kernel == ACOM_KERNEL_CONE;
+  auto kern = cone ? polar_kernel<NT, NC, ACOM_KERNEL_CONE> : polar_kernel<NT, NC, ACOM_KERNEL_GAUSS>;
+  acom_status_t st = ensure_lds(kern, polar_lds<NC>(d));
   if (st != ACOM_OK) return st;
   PolarArgs b = a;
   b.ntiles = d.Rp / kPolarCols;
@@ -1820,7 +1823,7 @@ acom_status_t launch_polar_nc(const PlanDev& d, const PolarArgs& a, hipStream_t 
   }
   const int nblocks = g_tune.polar_xcd ? xcd_blocks(b.np, &b.per) : b.np;
   ProfScope prof(0, s);
-  polar_kernel<NT, NC><<<dim3(nblocks), kThreads, polar_lds<NC>(d), s>>>(b);
+  kern<<<dim3(nblocks), kThreads, polar_lds<NC>(d), s>>>(b);
   ACOM_HIP(hipGetLastError());
   return ACOM_OK;
 }

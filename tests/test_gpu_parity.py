@@ -118,6 +118,29 @@ def test_polar_image_and_spectrum(acom, small):
         assert np.abs(Xi[p] - F.imag).max() <= 1e-6 * scf
 
 
+def test_polar_image_gaussian_kernel(acom):
+    """The splat with the Gaussian kernel (its own compile-time cell loop):
+    the image and spectrum match the oracle's cell by cell on the small
+    configuration, at the cone's tolerance."""
+    cfg = dict(helpers.SMALL, kernel=1)
+    d = synth.make("small")
+    opl = helpers.oracle_plan(["fcc"], **cfg)
+    gpl = helpers.gpu_plan(["fcc"], precisions=("fp32",), **cfg)
+    pk = acom.Peaks.from_host(d)
+    X = gpl.polar_image(pk).cpu().numpy()
+    Xr, Xi = gpl.polar_spectrum(pk)
+    Xr, Xi = Xr.cpu().numpy(), Xi.cpu().numpy()
+    for p in range(0, 128, 5):
+        Xo = helpers.oracle_image(opl, d, p)
+        sc = np.abs(Xo).max()
+        assert sc > 0.0
+        assert np.abs(X[p] - Xo).max() <= 1e-6 * sc, p
+        F = np.fft.rfft(Xo, axis=0)
+        scf = np.abs(F).max()
+        assert np.abs(Xr[p] - F.real).max() <= 1e-6 * scf, p
+        assert np.abs(Xi[p] - F.imag).max() <= 1e-6 * scf, p
+
+
 @pytest.mark.parametrize("cfg", ["small", "ragged48", "scan"])
 def test_polar_pass_widths_agree(acom, cfg):
     """The polar kernel's 32-column passes compute every cell and every
