@@ -892,11 +892,14 @@ __global__ void __launch_bounds__(64 * WM * WN) bound_kernel(BoundArgs a) {
     const unsigned char* sPi = st + 2 * ARRX + ARRP;
     // the first step of a frequency starts its accumulators at 0 (compile-time
     // operand); H0 = 1 skips the first half of an FP32 step (zero plan radii).
-    // A norm row runs the same four products (its epilogue uses two): one
-    // MFMA body keeps the register allocation of the spectrum rows.
-    auto mma = [&](auto zc, auto hc) {
+    // NR: a norm row with FP32 operands runs only the two products its
+    // epilogue reads (A + B); C and D keep the last spectrum row's values,
+    // which no norm row reads.  The 16-bit kernels keep one body (their
+    // registers are full).
+    auto mma = [&](auto zc, auto hc, auto nc) {
       constexpr bool Z = decltype(zc)::value;
       constexpr int H0 = decltype(hc)::value;
+      constexpr bool NR = decltype(nc)::value && KIND == 0;
       const f32x4 zero4 = {0.0f, 0.0f, 0.0f, 0.0f};
       if constexpr (KIND == 0) {
         // two halves of 16 radii; lane quarter lg holds radii 16 h + 4 lg .. + 3 (chunk 4 h + lg)
@@ -928,8 +931,10 @@ __global__ void __launch_bounds__(64 * WM * WN) bound_kernel(BoundArgs a) {
                 const bool z = Z && h == H0 && t == 0;
                 acc[i][j][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxr[i][t], fpr[j][t], z ? zero4 : acc[i][j][0], 0, 0, 0);
                 acc[i][j][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxi[i][t], fpi[j][t], z ? zero4 : acc[i][j][1], 0, 0, 0);
-                acc[i][j][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxi[i][t], fpr[j][t], z ? zero4 : acc[i][j][2], 0, 0, 0);
-                acc[i][j][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxr[i][t], fpi[j][t], z ? zero4 : acc[i][j][3], 0, 0, 0);
+                if constexpr (!NR) {
+                  acc[i][j][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxi[i][t], fpr[j][t], z ? zero4 : acc[i][j][2], 0, 0, 0);
+                  acc[i][j][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(fxr[i][t], fpi[j][t], z ? zero4 : acc[i][j][3], 0, 0, 0);
+                }
               }
         }
       } else {
@@ -969,12 +974,18 @@ __global__ void __launch_bounds__(64 * WM * WN) bound_kernel(BoundArgs a) {
         }
       }
     };
-    if (stp % steps_per_k != 0)
-      mma(std::false_type{}, std::integral_constant<int, 0>{});
-    else if (skip_h0)
-      mma(std::true_type{}, std::integral_constant<int, 1>{});
+    auto mma_at = [&](auto nc) {
+      if (stp % steps_per_k != 0)
+        mma(std::false_type{}, std::integral_constant<int, 0>{}, nc);
+      else if (skip_h0)
+        mma(std::true_type{}, std::integral_constant<int, 1>{}, nc);
+      else
+        mma(std::true_type{}, std::integral_constant<int, 0>{}, nc);
+    };
+    if (KIND == 0 && stp / steps_per_k >= a.Kc)
+      mma_at(std::true_type{});
     else
-      mma(std::true_type{}, std::integral_constant<int, 0>{});
+      mma_at(std::false_type{});
     const int k = stp / steps_per_k;
     const bool nr = k >= a.Kc;  // a norm row
     if (stp - k * steps_per_k == steps_per_k - 1) {  // last radii of logical frequency k
