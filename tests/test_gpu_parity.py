@@ -141,6 +141,23 @@ def test_polar_image_gaussian_kernel(acom):
         assert np.abs(Xi[p] - F.imag).max() <= 1e-6 * scf, p
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_match_gaussian_kernel_plan(acom, precision):
+    """Matching on a Gaussian-kernel plan (the Gaussian instantiation of the
+    polar kernel, the contraction and the exact pass on its spectra): top-2
+    decisions and exact scores equal the FP64 oracle's, tie-aware, on every
+    fourth pattern of the small configuration."""
+    cfg = dict(helpers.SMALL, kernel=1)
+    d = synth.make("small")
+    opl = helpers.oracle_plan(["fcc"], **cfg)
+    gpl = helpers.gpu_plan(["fcc"], precisions=("fp32", "bf16"), **cfg)
+    pk = acom.Peaks.from_host(d)
+    res = gpl.match(pk, top_k=2, precision=precision)
+    res = {k: v.cpu().numpy() for k, v in res.items() if v is not None}
+    off = d["offsets"]
+    _check_decisions(opl, d, res, [p for p in range(0, 128, 4) if off[p + 1] > off[p]], top_k=2)
+
+
 @pytest.mark.parametrize("cfg", ["small", "ragged48", "scan"])
 def test_polar_pass_widths_agree(acom, cfg):
     """The polar kernel's 32-column passes compute every cell and every
