@@ -286,7 +286,9 @@ acom_status_t acom_score_grad(acom_plan_t plan, const acom_peaks_t* peaks, const
  * at 0.25 deg, doubles after an improving step up to 0.5 deg, halves otherwise),
  * at most max_iter trials or until l < 1e-4 deg; the best candidate wins.  The
  * reflections taking part (as for acom_score) are chosen at the start
- * orientation and again after every accepted step.
+ * orientation and again whenever the next trial could lie more than 1 deg from
+ * the orientation they were chosen at (the accepted steps since then plus the
+ * trial's own step bound that rotation).
  * out_orient n x 9, out_score n, out_cand n (index of the winner) or NULL.
  * A candidate with an invalid phase or non-finite matrix is skipped (out_cand
  * = -1 and score 0 when none is left); a candidate whose reflection set exceeds

@@ -14,8 +14,10 @@
 // 1/A are left out: v_g is then below exp(-25) of |g|^gamma |F_g|^omega even
 // after a 1 degree rotation (which moves s_g by at most 0.035 1/A for |g| < 2
 // 1/A).  The set is taken at the orientation being scored (acom_score,
-// acom_score_grad) and, in refinement, at the start orientation and again after
-// every accepted step, whose trials lie within 0.5 degree of it.  For omega = 0
+// acom_score_grad) and, in refinement, at the start orientation and again
+// whenever the next trial could lie more than 1 degree from the orientation it
+// was taken at (the bound: the accepted steps since then plus the trial's own,
+// each a rotation by its step length).  For omega = 0
 // all are kept.  At most kMaxKept reflections take part: a pattern whose set
 // is larger is an error, reported as NaN (never truncated).
 #include <cmath>
@@ -376,6 +378,7 @@ __global__ void __launch_bounds__(kW) refine_kernel(ScoreArgs a) {
   const int64_t m0 = a.offsets[p], m1 = a.offsets[p + 1];
   const float deg = 0.017453292519943295f;
   const float lmax = 0.5f * deg, lmin = 1e-4f * deg;
+  const float reach = 1.0f * deg;  // rotation within which a kept set stays valid
   float best[9];
   float bestS = -INFINITY;
   int bestc = -1;
@@ -406,10 +409,19 @@ __global__ void __launch_bounds__(kW) refine_kernel(ScoreArgs a) {
     float S = e.S;
     float g[3] = {e.g[0], e.g[1], e.g[2]};
     float l = 0.25f * deg;
+    float drift = 0.0f;  // bound on the rotation from where the kept set was taken to m
     int it = 0;
     while (it < a.max_iter && l >= lmin) {
       const float gn = sqrtf(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
       if (!(gn > 0.0f)) break;
+      if (drift + l > reach) {  // the trial could leave the set's range: take it again at m
+        __syncthreads();
+        if (!select_kept(a, ph, m, sh)) {
+          overflow = true;
+          break;
+        }
+        drift = 0.0f;
+      }
       float th[3] = {l * g[0] / gn, l * g[1] / gn, l * g[2] / gn};
       float E[9], mt[9];
       expm3(th, E);
@@ -420,12 +432,8 @@ __global__ void __launch_bounds__(kW) refine_kernel(ScoreArgs a) {
       if (et.S > S) {
         for (int i = 0; i < 9; ++i) m[i] = mt[i];
         S = et.S;
+        drift += l;  // within reach: checked before the trial
         l = fminf(2.0f * l, lmax);
-        __syncthreads();
-        if (!select_kept(a, ph, m, sh)) {  // the set at the new orientation
-          overflow = true;
-          break;
-        }
         Eval eg = evaluate(a, m0, m1, m, I3, true, false, cached, sh);
         work_g += sh.nkept * npk;
         g[0] = eg.g[0];
